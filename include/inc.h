@@ -1,0 +1,160 @@
+/*
+ * inc.h — C ABI of the MI355X (gfx950) intranuclear cascade + evaporation
+ * library.
+ *
+ * The library generates proton–nucleus non-elastic events at 20–250 MeV
+ * following Wan Chan Tseung & Beltran, "A graphics processor-based intranuclear
+ * cascade and evaporation simulation" (arXiv:1309.7963): a Bertini-type
+ * cascade in a 15-shell Fermi-gas nucleus (Sec. 2.2, Eq. (1); Sec. 2.3)
+ * followed by evaporation of n, p, d, t, 3He and alpha (Sec. 2.4).  Inputs are
+ * incident protons (kinetic energy, target) and a random seed; outputs are the
+ * escaping and evaporated particles and the residual nucleus (Sec. 3.2, 3.3).
+ *
+ * Conventions
+ *   Units: MeV, MeV/c, fm.  Incident protons move along +z.  Directions are
+ *   unit vectors in the target rest frame; T is the asymptotic kinetic energy.
+ *   Species codes: 0 n, 1 p, 2 d, 3 t, 4 3He, 5 alpha.  Stage 0 = cascade,
+ *   1 = evaporation.
+ *   Event identity: event i of a batch uses the Philox4x32-10 stream with
+ *   key = seed and counter = (block, id lo, id hi, 0), id = first_event_id + i,
+ *   so results depend only on (seed, id, target, T0), never on batching.
+ *   All functions return 0 (INC_OK) or a negative error code; no exception
+ *   crosses the ABI.  Pointers documented as "device" must be device memory
+ *   of the current HIP device; "host" pointers are ordinary host memory.
+ */
+#ifndef INC_H
+#define INC_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---------------------------------------------------------------- errors */
+#define INC_OK 0
+#define INC_ERR_ARG -1        /* invalid argument (target, sizes, pointers)   */
+#define INC_ERR_RANGE -2      /* an incident energy outside [20, 250] MeV     */
+#define INC_ERR_CAPACITY -3   /* secondary buffer too small; n_sec holds the
+                                 required total, residuals are valid          */
+#define INC_ERR_NO_DEVICE -4  /* no usable gfx950 device                      */
+#define INC_ERR_OOM -5        /* device allocation failed                     */
+#define INC_ERR_DEVICE -6     /* a HIP call or kernel launch failed           */
+
+const char* inc_strerror(int code);
+
+/* ------------------------------------------------------------- targets */
+typedef struct {
+  int A; /* mass number, 4 <= A <= 250 */
+  int Z; /* charge, 1 <= Z <= A - 1    */
+} inc_nucleus;
+
+/* Options.  Zero-initialised = the method as specified, default launch. */
+typedef struct {
+  /* test hooks (special cases with closed-form answers) */
+  int uniform_density;   /* every shell at A / (4/3 pi R^3)                  */
+  int zero_fermi;        /* p_F = E_F = 0                                    */
+  int zero_binding;      /* E_B = E_C = 0                                    */
+  int no_pauli;          /* no Pauli test                                    */
+  int no_evaporation;    /* stop after the cascade                           */
+  int stop_after_first;  /* end the cascade at the first allowed collision  */
+  float const_sigma_mb;  /* > 0: every NN cross-section is this constant     */
+  int fixed_b_on;        /* 1: every pass enters at impact parameter fixed_b */
+  float fixed_b;         /* fm, 0 <= fixed_b < R                             */
+  /* launch policy (0 = library default) */
+  int block_size;        /* threads per block: 64..256, multiple of 64       */
+  int evap_threshold;    /* persistent kernel: lanes in evaporation that make
+                            a wave run an evaporation step (1..64)           */
+  int waves_per_cu;      /* persistent kernel: resident waves per CU         */
+} inc_options;
+
+/* One residual nucleus per event, 32 bytes. */
+typedef struct {
+  uint16_t A_f, Z_f;     /* final residual                                   */
+  uint16_t n_sec;        /* secondaries of this event                        */
+  uint16_t flags;        /* 1 stack guard, 2 segment guard, 4 empty residual */
+  float Ex_casc;         /* excitation energy after the cascade (MeV)        */
+  float Ex_f;            /* excitation energy left after evaporation (MeV)   */
+  float p_f[3];          /* final residual momentum (MeV/c)                  */
+  uint16_t n_coll;       /* allowed NN collisions in the cascade             */
+  uint16_t n_retry;      /* transparent passes before the event (Sec. 2.1)   */
+} inc_residual;
+
+/* Device-side output buffers, owned by the caller. */
+typedef struct {
+  inc_residual* res;      /* device, n entries (event order)                 */
+  uint32_t* sec_event;    /* device, sec_capacity entries: index in batch    */
+  uint8_t* sec_species;   /* device, sec_capacity                            */
+  uint8_t* sec_stage;     /* device, sec_capacity                            */
+  float* sec_T;           /* device, sec_capacity: kinetic energy (MeV)      */
+  float* sec_ux;          /* device, sec_capacity: direction cosines         */
+  float* sec_uy;
+  float* sec_uz;
+  size_t sec_capacity;
+  unsigned long long* counters; /* device, >= 4 entries, caller-owned:
+                            [0] secondaries produced (may exceed capacity:
+                                only the first sec_capacity are stored),
+                            [1] flagged events, [2] work-queue head,
+                            [3] reserved.  Reset by the call.               */
+} inc_output;
+
+/* A batch of incident protons, in device memory. */
+typedef struct {
+  size_t n;                 /* events, 1 <= n < 2^32                         */
+  const uint8_t* target_idx;/* device, n entries into the context's targets;
+                               NULL = every event on target 0               */
+  const float* T0;          /* device, n kinetic energies in [20, 250] MeV   */
+  uint64_t seed;
+  uint64_t first_event_id;
+} inc_batch;
+
+typedef struct inc_ctx inc_ctx;
+
+/* Build a context on the current device: nucleus shell tables (Sec. 2.2),
+ * the NN cross-section table (Sec. 2.3) and the binding-energy table used by
+ * the evaporation (Sec. 2.4) are computed by setup kernels and stay resident.
+ * targets: host array of n_targets (1..16) nuclei.  opt: host, may be NULL.
+ * The context is not thread-safe: calls on one context must be serialised. */
+int inc_ctx_create(const inc_nucleus* targets, int n_targets, const inc_options* opt, inc_ctx** out);
+int inc_ctx_destroy(inc_ctx* ctx);
+
+/* Copy the context's shell tables to host memory: for target t, 15 shells x
+ * {r_outer, rho_n, rho_p, pF_n, pF_p, EF_n, EF_p} floats, then E_B, E_C, R
+ * (108 floats per target).  host_out must hold 108 * n_targets floats. */
+int inc_ctx_tables(const inc_ctx* ctx, float* host_out);
+
+/* Launch modes */
+#define INC_MODE_PLAIN 0      /* one event per thread; cascade kernel then
+                                 evaporation kernel (the paper's Sec. 3 shape) */
+#define INC_MODE_PERSISTENT 1 /* one fused persistent kernel: lanes refill
+                                 from a global work queue                     */
+
+/* Generate batch->n non-elastic events asynchronously on `stream` (a
+ * hipStream_t; NULL = the default stream).  All batch and output pointers
+ * are device pointers.  Incident energies are validated on the device:
+ * out-of-range events are skipped and counted in counters[1] with
+ * flags = 0x8000 in their residual record; the host wrapper inc_simulate
+ * turns that into INC_ERR_RANGE.  Returns INC_ERR_ARG for bad sizes or
+ * pointers, INC_ERR_DEVICE if a launch fails. */
+int inc_simulate_dev(inc_ctx* ctx, const inc_batch* batch, const inc_output* out, void* stream, int mode);
+
+/* Convenience form (the spec call shape): synchronous, host arrays.
+ * energies_MeV: host, n_events floats.  Results are copied to host arrays
+ * res (n_events) and the secondary arrays (sec_capacity each); *n_sec
+ * receives the number of secondaries produced.  Returns INC_ERR_CAPACITY when
+ * *n_sec > sec_capacity (residuals are still valid), INC_ERR_RANGE when an
+ * energy is outside [20, 250] MeV (nothing is simulated). */
+int inc_simulate(int target_A, int target_Z, const float* energies_MeV, size_t n_events,
+                 uint64_t seed, inc_residual* res, uint32_t* sec_event, uint8_t* sec_species,
+                 uint8_t* sec_stage, float* sec_T, float* sec_ux, float* sec_uy, float* sec_uz,
+                 size_t sec_capacity, size_t* n_sec);
+
+/* Library version of the frozen physics readings (changes when any reading
+ * that affects results changes). */
+int inc_contract_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

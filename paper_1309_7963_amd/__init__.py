@@ -1,0 +1,206 @@
+"""MI355X (gfx950) intranuclear cascade + evaporation event generator
+(arXiv:1309.7963).  Python surface over the C ABI of include/inc.h; PyTorch
+provides device memory and streams, every step of the method runs in the HIP
+kernels of ``csrc/``.
+
+    import torch, paper_1309_7963_amd as inc
+    ctx = inc.Context([(16, 8)])
+    T0 = torch.full((10000,), 200.0, device="cuda")
+    out = ctx.simulate(T0, seed=1)
+    host = out.to_numpy()
+"""
+from __future__ import annotations
+
+from dataclasses import dataclass
+from typing import Optional, Sequence
+
+import ctypes as C
+
+import numpy as np
+
+from . import _lib
+from ._lib import (  # noqa: F401
+    INC_ERR_ARG, INC_ERR_CAPACITY, INC_ERR_DEVICE, INC_ERR_NO_DEVICE, INC_ERR_OOM, INC_ERR_RANGE,
+    MODE_PERSISTENT, MODE_PLAIN, RESIDUAL_DTYPE, IncError,
+)
+
+FLAG_STACK, FLAG_SEGMENTS, FLAG_EMPTY, FLAG_RANGE = 1, 2, 4, 0x8000
+
+
+def _torch():
+    import torch
+
+    return torch
+
+
+@dataclass
+class DeviceOutput:
+    """Caller-owned device buffers of one batch (torch tensors)."""
+
+    n: int
+    res: "object"          # uint8 [n * 32] (RESIDUAL_DTYPE records)
+    sec_event: "object"    # int32 [cap] (uint32 values)
+    sec_species: "object"  # uint8 [cap]
+    sec_stage: "object"    # uint8 [cap]
+    sec_T: "object"        # float32 [cap]
+    sec_ux: "object"
+    sec_uy: "object"
+    sec_uz: "object"
+    counters: "object"     # int64 [4]
+
+    @property
+    def capacity(self) -> int:
+        return int(self.sec_T.shape[0])
+
+    @classmethod
+    def allocate(cls, n: int, capacity: int, device="cuda"):
+        torch = _torch()
+        cap = max(int(capacity), 1)
+        e = lambda dt: torch.empty(cap, dtype=dt, device=device)
+        return cls(
+            n=n,
+            res=torch.empty(n * 32, dtype=torch.uint8, device=device),
+            sec_event=e(torch.int32), sec_species=e(torch.uint8), sec_stage=e(torch.uint8),
+            sec_T=e(torch.float32), sec_ux=e(torch.float32), sec_uy=e(torch.float32), sec_uz=e(torch.float32),
+            counters=torch.zeros(4, dtype=torch.int64, device=device),
+        )
+
+    def c_struct(self, capacity: Optional[int] = None) -> _lib.Output:
+        o = _lib.Output()
+        o.res = self.res.data_ptr()
+        o.sec_event = self.sec_event.data_ptr()
+        o.sec_species = self.sec_species.data_ptr()
+        o.sec_stage = self.sec_stage.data_ptr()
+        o.sec_T = self.sec_T.data_ptr()
+        o.sec_ux = self.sec_ux.data_ptr()
+        o.sec_uy = self.sec_uy.data_ptr()
+        o.sec_uz = self.sec_uz.data_ptr()
+        o.sec_capacity = self.capacity if capacity is None else int(capacity)
+        o.counters = self.counters.data_ptr()
+        return o
+
+    def n_sec(self) -> int:
+        """Secondaries produced (synchronises with the device)."""
+        return int(self.counters[0].item())
+
+    def n_flagged(self) -> int:
+        return int(self.counters[1].item())
+
+    def to_numpy(self) -> dict:
+        """Copy everything to host numpy arrays (synchronising)."""
+        k = min(self.n_sec(), self.capacity)
+        res = self.res.cpu().numpy().view(RESIDUAL_DTYPE)
+        return dict(
+            res=res,
+            n_sec_total=self.n_sec(),
+            sec_event=self.sec_event[:k].cpu().numpy().view(np.uint32),
+            sec_species=self.sec_species[:k].cpu().numpy(),
+            sec_stage=self.sec_stage[:k].cpu().numpy(),
+            sec_T=self.sec_T[:k].cpu().numpy(),
+            sec_u=np.stack(
+                [self.sec_ux[:k].cpu().numpy(), self.sec_uy[:k].cpu().numpy(), self.sec_uz[:k].cpu().numpy()], axis=1
+            ),
+        )
+
+
+class Context:
+    """Resident nucleus, cross-section and binding tables for a set of target
+    nuclei on the current device (inc_ctx_create)."""
+
+    def __init__(self, targets: Sequence[Sequence[int]], **options):
+        L = _lib.load()
+        self.targets = [(int(a), int(z)) for a, z in targets]
+        arr = (_lib.Nucleus * len(self.targets))(*[_lib.Nucleus(a, z) for a, z in self.targets])
+        opt = _lib.Options()
+        for k, v in options.items():
+            if k == "fixed_b" and v is not None:
+                opt.fixed_b_on = 1
+                opt.fixed_b = float(v)
+            elif v is not None:
+                setattr(opt, k, v)
+        self.options = dict(options)
+        h = C.c_void_p()
+        _lib.check(L.inc_ctx_create(arr, len(self.targets), C.byref(opt), C.byref(h)), "inc_ctx_create")
+        self._h = h
+        self.max_A = max(a for a, _ in self.targets)
+
+    def close(self):
+        if getattr(self, "_h", None) and self._h.value:
+            _lib.load().inc_ctx_destroy(self._h)
+            self._h = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def tables(self) -> np.ndarray:
+        """Shell tables per target: (n_targets, 108) floats (see inc.h)."""
+        out = np.zeros((len(self.targets), 108), dtype=np.float32)
+        _lib.check(_lib.load().inc_ctx_tables(self._h, out.ctypes.data), "inc_ctx_tables")
+        return out
+
+    def default_capacity(self, n: int) -> int:
+        # at most A + 1 secondaries per event; the mean is far lower
+        return int(n * min(self.max_A + 1, 12)) + 4096
+
+    def simulate(self, T0, seed: int, target_idx=None, first_event_id: int = 0, mode: str = "persistent",
+                 out: Optional[DeviceOutput] = None, capacity: Optional[int] = None, stream=None) -> DeviceOutput:
+        """Generate len(T0) non-elastic events asynchronously on `stream`
+        (default: torch's current stream).  T0: float32 cuda tensor (MeV);
+        target_idx: uint8 cuda tensor or None."""
+        torch = _torch()
+        if not (torch.is_tensor(T0) and T0.is_cuda and T0.dtype == torch.float32 and T0.is_contiguous()):
+            raise TypeError("T0 must be a contiguous float32 CUDA tensor")
+        n = int(T0.shape[0])
+        if target_idx is not None:
+            if not (target_idx.is_cuda and target_idx.dtype == torch.uint8 and target_idx.shape[0] == n
+                    and target_idx.is_contiguous()):
+                raise TypeError("target_idx must be a contiguous uint8 CUDA tensor of len(T0)")
+        if out is None:
+            out = DeviceOutput.allocate(n, self.default_capacity(n) if capacity is None else capacity, T0.device)
+        elif out.n < n:
+            raise ValueError("output buffers hold %d events, batch has %d" % (out.n, n))
+        b = _lib.Batch()
+        b.n = n
+        b.target_idx = target_idx.data_ptr() if target_idx is not None else None
+        b.T0 = T0.data_ptr()
+        b.seed = int(seed)
+        b.first_event_id = int(first_event_id)
+        o = out.c_struct(capacity)
+        s = stream if stream is not None else torch.cuda.current_stream()
+        m = {"plain": _lib.MODE_PLAIN, "persistent": _lib.MODE_PERSISTENT}[mode]
+        _lib.check(_lib.load().inc_simulate_dev(self._h, C.byref(b), C.byref(o), C.c_void_p(s.cuda_stream), m),
+                   "inc_simulate_dev")
+        return out
+
+
+def simulate_host(A: int, Z: int, energies: np.ndarray, seed: int, capacity: Optional[int] = None) -> dict:
+    """The synchronous host-array call inc_simulate(target_A, target_Z,
+    energies, n_events, seed, out...).  Raises IncError on failure."""
+    L = _lib.load()
+    e = np.ascontiguousarray(energies, dtype=np.float32)
+    n = e.shape[0]
+    cap = n * min(A + 1, 12) + 4096 if capacity is None else int(capacity)
+    res = np.zeros(n, dtype=RESIDUAL_DTYPE)
+    ev = np.zeros(max(cap, 1), dtype=np.uint32)
+    sp = np.zeros(max(cap, 1), dtype=np.uint8)
+    st = np.zeros(max(cap, 1), dtype=np.uint8)
+    T = np.zeros(max(cap, 1), dtype=np.float32)
+    ux, uy, uz = (np.zeros(max(cap, 1), dtype=np.float32) for _ in range(3))
+    nsec = C.c_size_t(0)
+    rc = L.inc_simulate(A, Z, e.ctypes.data, n, seed, res.ctypes.data, ev.ctypes.data, sp.ctypes.data,
+                        st.ctypes.data, T.ctypes.data, ux.ctypes.data, uy.ctypes.data, uz.ctypes.data, cap,
+                        C.byref(nsec))
+    k = min(nsec.value, cap)
+    out = dict(res=res, n_sec_total=nsec.value, sec_event=ev[:k], sec_species=sp[:k], sec_stage=st[:k],
+               sec_T=T[:k], sec_u=np.stack([ux[:k], uy[:k], uz[:k]], axis=1))
+    if rc != _lib.INC_OK and rc != _lib.INC_ERR_CAPACITY:
+        _lib.check(rc, "inc_simulate")
+    out["rc"] = rc
+    return out
+
+
+def contract_version() -> int:
+    return _lib.load().inc_contract_version()

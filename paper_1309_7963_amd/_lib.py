@@ -1,0 +1,109 @@
+"""ctypes binding of include/inc.h (argument marshalling only)."""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libinc.so")
+
+INC_OK = 0
+INC_ERR_ARG = -1
+INC_ERR_RANGE = -2
+INC_ERR_CAPACITY = -3
+INC_ERR_NO_DEVICE = -4
+INC_ERR_OOM = -5
+INC_ERR_DEVICE = -6
+MODE_PLAIN = 0
+MODE_PERSISTENT = 1
+
+# exported symbols, in the order include/inc.h declares them
+SYMBOLS = (
+    "inc_strerror", "inc_ctx_create", "inc_ctx_destroy", "inc_ctx_tables",
+    "inc_simulate_dev", "inc_simulate", "inc_contract_version",
+)
+
+
+class Nucleus(C.Structure):
+    _fields_ = [("A", C.c_int), ("Z", C.c_int)]
+
+
+class Options(C.Structure):
+    _fields_ = [
+        ("uniform_density", C.c_int), ("zero_fermi", C.c_int), ("zero_binding", C.c_int),
+        ("no_pauli", C.c_int), ("no_evaporation", C.c_int), ("stop_after_first", C.c_int),
+        ("const_sigma_mb", C.c_float), ("fixed_b_on", C.c_int), ("fixed_b", C.c_float),
+        ("block_size", C.c_int), ("evap_threshold", C.c_int), ("waves_per_cu", C.c_int),
+    ]
+
+
+class Output(C.Structure):
+    _fields_ = [
+        ("res", C.c_void_p), ("sec_event", C.c_void_p), ("sec_species", C.c_void_p),
+        ("sec_stage", C.c_void_p), ("sec_T", C.c_void_p), ("sec_ux", C.c_void_p),
+        ("sec_uy", C.c_void_p), ("sec_uz", C.c_void_p), ("sec_capacity", C.c_size_t),
+        ("counters", C.c_void_p),
+    ]
+
+
+class Batch(C.Structure):
+    _fields_ = [
+        ("n", C.c_size_t), ("target_idx", C.c_void_p), ("T0", C.c_void_p),
+        ("seed", C.c_uint64), ("first_event_id", C.c_uint64),
+    ]
+
+
+RESIDUAL_DTYPE = np.dtype(
+    [("A_f", "<u2"), ("Z_f", "<u2"), ("n_sec", "<u2"), ("flags", "<u2"),
+     ("Ex_casc", "<f4"), ("Ex_f", "<f4"), ("p_f", "<f4", 3),
+     ("n_coll", "<u2"), ("n_retry", "<u2")]
+)
+assert RESIDUAL_DTYPE.itemsize == 32
+
+_lib = None
+
+
+class IncError(RuntimeError):
+    def __init__(self, code: int, what: str = ""):
+        self.code = code
+        msg = load().inc_strerror(code).decode() if _lib is not None else str(code)
+        super().__init__("%s: %s (%d)" % (what, msg, code) if what else "%s (%d)" % (msg, code))
+
+
+def load():
+    """Load the HIP library; raises if it has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(
+                "libinc.so is not built: run `python -m paper_1309_7963_amd.build` "
+                "(the GPU path has no fallback)"
+            )
+        L = C.CDLL(LIB_PATH)
+        L.inc_strerror.argtypes = [C.c_int]
+        L.inc_strerror.restype = C.c_char_p
+        L.inc_ctx_create.argtypes = [C.POINTER(Nucleus), C.c_int, C.POINTER(Options), C.POINTER(C.c_void_p)]
+        L.inc_ctx_create.restype = C.c_int
+        L.inc_ctx_destroy.argtypes = [C.c_void_p]
+        L.inc_ctx_destroy.restype = C.c_int
+        L.inc_ctx_tables.argtypes = [C.c_void_p, C.c_void_p]
+        L.inc_ctx_tables.restype = C.c_int
+        L.inc_simulate_dev.argtypes = [C.c_void_p, C.POINTER(Batch), C.POINTER(Output), C.c_void_p, C.c_int]
+        L.inc_simulate_dev.restype = C.c_int
+        L.inc_simulate.argtypes = [
+            C.c_int, C.c_int, C.c_void_p, C.c_size_t, C.c_uint64, C.c_void_p,
+            C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
+            C.c_size_t, C.POINTER(C.c_size_t),
+        ]
+        L.inc_simulate.restype = C.c_int
+        L.inc_contract_version.argtypes = []
+        L.inc_contract_version.restype = C.c_int
+        _lib = L
+    return _lib
+
+
+def check(code: int, what: str = ""):
+    if code != INC_OK:
+        raise IncError(code, what)

@@ -1,0 +1,290 @@
+// api.hip — the C ABI declared in include/inc.h: context with resident
+// tables, argument validation, launch policy and the synchronous host
+// convenience call.
+#include <string.h>
+
+#include <new>
+
+#include "kernels.h"
+
+using namespace incdev;
+
+struct inc_ctx {
+  int device;
+  int n_targets;
+  int AZ[2 * kMaxTargets];
+  inc_options opt;
+  bool fixed_b_set;
+  NucTab* d_nuc;
+  XsTab* d_xs;
+  double* d_B;
+  int amax, zmax;
+  EvapTab evap;
+  MidState* d_mid;
+  size_t mid_cap;
+  int n_cu;
+  int block, evap_threshold, waves_per_cu;
+};
+
+namespace {
+
+int map_err(hipError_t e) {
+  if (e == hipSuccess) return INC_OK;
+  if (e == hipErrorOutOfMemory) return INC_ERR_OOM;
+  if (e == hipErrorNoDevice || e == hipErrorInvalidDevice) return INC_ERR_NO_DEVICE;
+  return INC_ERR_DEVICE;
+}
+
+bool valid_target(int A, int Z) { return A >= 4 && A <= 250 && Z >= 1 && Z <= A - 1; }
+
+int current_gfx950(int* dev, int* n_cu) {
+  int count = 0;
+  if (hipGetDeviceCount(&count) != hipSuccess || count < 1) return INC_ERR_NO_DEVICE;
+  if (hipGetDevice(dev) != hipSuccess) return INC_ERR_NO_DEVICE;
+  hipDeviceProp_t p;
+  if (hipGetDeviceProperties(&p, *dev) != hipSuccess) return INC_ERR_NO_DEVICE;
+  if (strncmp(p.gcnArchName, "gfx950", 6) != 0) return INC_ERR_NO_DEVICE;
+  *n_cu = p.multiProcessorCount;
+  return INC_OK;
+}
+
+void release(inc_ctx* c) {
+  if (!c) return;
+  if (c->d_nuc) (void)hipFree(c->d_nuc);
+  if (c->d_xs) (void)hipFree(c->d_xs);
+  if (c->d_B) (void)hipFree(c->d_B);
+  if (c->d_mid) (void)hipFree(c->d_mid);
+  delete c;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* inc_strerror(int code) {
+  switch (code) {
+    case INC_OK: return "ok";
+    case INC_ERR_ARG: return "invalid argument";
+    case INC_ERR_RANGE: return "incident energy outside [20, 250] MeV";
+    case INC_ERR_CAPACITY: return "secondary buffer too small";
+    case INC_ERR_NO_DEVICE: return "no gfx950 device";
+    case INC_ERR_OOM: return "device out of memory";
+    case INC_ERR_DEVICE: return "HIP error";
+    default: return "unknown error";
+  }
+}
+
+int inc_contract_version(void) { return 1; }
+
+int inc_ctx_create(const inc_nucleus* targets, int n_targets, const inc_options* opt, inc_ctx** out) {
+  if (!out) return INC_ERR_ARG;
+  *out = nullptr;
+  if (!targets || n_targets < 1 || n_targets > kMaxTargets) return INC_ERR_ARG;
+  for (int t = 0; t < n_targets; ++t)
+    if (!valid_target(targets[t].A, targets[t].Z)) return INC_ERR_ARG;
+  inc_options o;
+  memset(&o, 0, sizeof(o));
+  if (opt) o = *opt;
+  if (o.block_size && (o.block_size < 64 || o.block_size > 256 || o.block_size % 64)) return INC_ERR_ARG;
+  if (o.evap_threshold < 0 || o.evap_threshold > 64 || o.waves_per_cu < 0 || o.waves_per_cu > 32) return INC_ERR_ARG;
+  if (!(o.const_sigma_mb >= 0.0f) || o.const_sigma_mb > 1e5f) return INC_ERR_ARG;
+  if (o.fixed_b_on && !(o.fixed_b >= 0.0f && o.fixed_b < 20.0f)) return INC_ERR_ARG;
+  int dev = 0, n_cu = 0;
+  int rc = current_gfx950(&dev, &n_cu);
+  if (rc) return rc;
+
+  inc_ctx* c = new (std::nothrow) inc_ctx;
+  if (!c) return INC_ERR_OOM;
+  memset(c, 0, sizeof(*c));
+  c->device = dev;
+  c->n_cu = n_cu;
+  c->n_targets = n_targets;
+  c->opt = o;
+  c->fixed_b_set = o.fixed_b_on != 0;
+  c->block = o.block_size ? o.block_size : 256;
+  c->evap_threshold = o.evap_threshold ? o.evap_threshold : 32;
+  c->waves_per_cu = o.waves_per_cu ? o.waves_per_cu : 8;
+  int amax = 0, zmax = 0;
+  for (int t = 0; t < n_targets; ++t) {
+    c->AZ[2 * t] = targets[t].A;
+    c->AZ[2 * t + 1] = targets[t].Z;
+    amax = targets[t].A + 1 > amax ? targets[t].A + 1 : amax;
+    zmax = targets[t].Z + 1 > zmax ? targets[t].Z + 1 : zmax;
+  }
+  c->amax = amax;
+  c->zmax = zmax;
+
+  int* d_AZ = nullptr;
+  EvapTab* d_evap = nullptr;
+  hipError_t e = hipSuccess;
+  do {
+    if ((e = hipMalloc(&c->d_nuc, sizeof(NucTab) * n_targets)) != hipSuccess) break;
+    if ((e = hipMalloc(&c->d_xs, sizeof(XsTab))) != hipSuccess) break;
+    if ((e = hipMalloc(&c->d_B, sizeof(double) * (amax + 1) * (zmax + 1))) != hipSuccess) break;
+    if ((e = hipMalloc(&d_AZ, sizeof(int) * 2 * n_targets)) != hipSuccess) break;
+    if ((e = hipMalloc(&d_evap, sizeof(EvapTab))) != hipSuccess) break;
+    if ((e = hipMemcpy(d_AZ, c->AZ, sizeof(int) * 2 * n_targets, hipMemcpyHostToDevice)) != hipSuccess) break;
+    if ((e = inc_launch_setup(d_AZ, n_targets, c->d_nuc, c->d_xs, c->d_B, amax, zmax, d_evap, o, nullptr)) !=
+        hipSuccess)
+      break;
+    if ((e = hipDeviceSynchronize()) != hipSuccess) break;
+    e = hipMemcpy(&c->evap, d_evap, sizeof(EvapTab), hipMemcpyDeviceToHost);
+  } while (false);
+  if (d_AZ) (void)hipFree(d_AZ);
+  if (d_evap) (void)hipFree(d_evap);
+  if (e != hipSuccess) {
+    release(c);
+    return map_err(e);
+  }
+  *out = c;
+  return INC_OK;
+}
+
+int inc_ctx_destroy(inc_ctx* ctx) {
+  if (!ctx) return INC_ERR_ARG;
+  release(ctx);
+  return INC_OK;
+}
+
+int inc_ctx_tables(const inc_ctx* ctx, float* host_out) {
+  if (!ctx || !host_out) return INC_ERR_ARG;
+  NucTab tabs[kMaxTargets];
+  hipError_t e = hipMemcpy(tabs, ctx->d_nuc, sizeof(NucTab) * ctx->n_targets, hipMemcpyDeviceToHost);
+  if (e != hipSuccess) return map_err(e);
+  for (int t = 0; t < ctx->n_targets; ++t) {
+    float* o = host_out + 108 * t;
+    for (int i = 0; i < kShells; ++i) {
+      o[7 * i + 0] = sqrtf(tabs[t].r2[i + 1]);
+      o[7 * i + 1] = tabs[t].rho[0][i];
+      o[7 * i + 2] = tabs[t].rho[1][i];
+      o[7 * i + 3] = tabs[t].pF[0][i];
+      o[7 * i + 4] = tabs[t].pF[1][i];
+      o[7 * i + 5] = tabs[t].EF[0][i];
+      o[7 * i + 6] = tabs[t].EF[1][i];
+    }
+    o[105] = tabs[t].EB;
+    o[106] = tabs[t].EC;
+    o[107] = tabs[t].R;
+  }
+  return INC_OK;
+}
+
+int inc_simulate_dev(inc_ctx* ctx, const inc_batch* b, const inc_output* out, void* stream, int mode) {
+  if (!ctx || !b || !out) return INC_ERR_ARG;
+  if (mode != INC_MODE_PLAIN && mode != INC_MODE_PERSISTENT) return INC_ERR_ARG;
+  if (b->n < 1 || b->n >= (1ull << 32) || !b->T0) return INC_ERR_ARG;
+  if (!out->res || !out->counters) return INC_ERR_ARG;
+  if (out->sec_capacity && (!out->sec_event || !out->sec_species || !out->sec_stage || !out->sec_T ||
+                            !out->sec_ux || !out->sec_uy || !out->sec_uz))
+    return INC_ERR_ARG;
+  hipStream_t s = (hipStream_t)stream;
+  if (mode == INC_MODE_PLAIN && ctx->mid_cap < b->n) {
+    if (ctx->d_mid) (void)hipFree(ctx->d_mid);
+    ctx->d_mid = nullptr;
+    ctx->mid_cap = 0;
+    hipError_t e = hipMalloc(&ctx->d_mid, sizeof(MidState) * b->n);
+    if (e != hipSuccess) return map_err(e);
+    ctx->mid_cap = b->n;
+  }
+  LaunchDesc L;
+  memset(&L, 0, sizeof(L));
+  L.mode = mode;
+  L.block = ctx->block;
+  L.persistent_blocks = ctx->n_cu * ctx->waves_per_cu / (ctx->block / 64);
+  if (L.persistent_blocks < 1) L.persistent_blocks = 1;
+  L.evap_threshold = ctx->evap_threshold;
+  L.nuc = ctx->d_nuc;
+  L.n_targets = ctx->n_targets;
+  L.xs = ctx->d_xs;
+  L.bind = ctx->d_B;
+  L.amax = ctx->amax;
+  L.zmax = ctx->zmax;
+  L.evap = ctx->evap;
+  L.opt = ctx->opt;
+  L.fixed_b_set = ctx->fixed_b_set;
+  L.n = b->n;
+  L.tidx = b->target_idx;
+  L.T0 = b->T0;
+  L.seed = b->seed;
+  L.first_id = b->first_event_id;
+  L.res = out->res;
+  L.sec_event = out->sec_event;
+  L.sec_species = out->sec_species;
+  L.sec_stage = out->sec_stage;
+  L.sec_T = out->sec_T;
+  L.sec_ux = out->sec_ux;
+  L.sec_uy = out->sec_uy;
+  L.sec_uz = out->sec_uz;
+  L.sec_capacity = out->sec_capacity;
+  L.counters = out->counters;
+  L.mid = ctx->d_mid;
+  return map_err(inc_launch_events(L, s));
+}
+
+int inc_simulate(int target_A, int target_Z, const float* energies, size_t n, uint64_t seed, inc_residual* res,
+                 uint32_t* sec_event, uint8_t* sec_species, uint8_t* sec_stage, float* sec_T, float* sec_ux,
+                 float* sec_uy, float* sec_uz, size_t cap, size_t* n_sec) {
+  if (!energies || !res || !n_sec || n < 1 || n >= (1ull << 32)) return INC_ERR_ARG;
+  if (!valid_target(target_A, target_Z)) return INC_ERR_ARG;
+  if (cap && (!sec_event || !sec_species || !sec_stage || !sec_T || !sec_ux || !sec_uy || !sec_uz))
+    return INC_ERR_ARG;
+  for (size_t i = 0; i < n; ++i)
+    if (!(energies[i] >= 20.0f && energies[i] <= 250.0f)) return INC_ERR_RANGE;
+  inc_nucleus t = {target_A, target_Z};
+  inc_ctx* ctx = nullptr;
+  int rc = inc_ctx_create(&t, 1, nullptr, &ctx);
+  if (rc) return rc;
+  const size_t dcap = cap ? cap : 1;
+  float* d_T0 = nullptr;
+  inc_residual* d_res = nullptr;
+  unsigned long long* d_cnt = nullptr;
+  char* d_sec = nullptr;
+  hipError_t e = hipSuccess;
+  unsigned long long cnt[4] = {0, 0, 0, 0};
+  const size_t sec_bytes = dcap * (4 + 1 + 1 + 4 * 4);
+  do {
+    if ((e = hipMalloc(&d_T0, sizeof(float) * n)) != hipSuccess) break;
+    if ((e = hipMalloc(&d_res, sizeof(inc_residual) * n)) != hipSuccess) break;
+    if ((e = hipMalloc(&d_cnt, sizeof(unsigned long long) * 4)) != hipSuccess) break;
+    if ((e = hipMalloc(&d_sec, sec_bytes)) != hipSuccess) break;
+    if ((e = hipMemcpy(d_T0, energies, sizeof(float) * n, hipMemcpyHostToDevice)) != hipSuccess) break;
+    inc_output o;
+    o.res = d_res;
+    o.sec_T = (float*)d_sec;
+    o.sec_ux = o.sec_T + dcap;
+    o.sec_uy = o.sec_ux + dcap;
+    o.sec_uz = o.sec_uy + dcap;
+    o.sec_event = (uint32_t*)(o.sec_uz + dcap);
+    o.sec_species = (uint8_t*)(o.sec_event + dcap);
+    o.sec_stage = o.sec_species + dcap;
+    o.sec_capacity = cap;
+    o.counters = d_cnt;
+    inc_batch bt = {n, nullptr, d_T0, seed, 0};
+    rc = inc_simulate_dev(ctx, &bt, &o, nullptr, INC_MODE_PERSISTENT);
+    if (rc) break;
+    if ((e = hipDeviceSynchronize()) != hipSuccess) break;
+    if ((e = hipMemcpy(cnt, d_cnt, sizeof(cnt), hipMemcpyDeviceToHost)) != hipSuccess) break;
+    if ((e = hipMemcpy(res, d_res, sizeof(inc_residual) * n, hipMemcpyDeviceToHost)) != hipSuccess) break;
+    const size_t k = cnt[0] < cap ? (size_t)cnt[0] : cap;
+    if (k) {
+      if ((e = hipMemcpy(sec_T, o.sec_T, 4 * k, hipMemcpyDeviceToHost)) != hipSuccess) break;
+      if ((e = hipMemcpy(sec_ux, o.sec_ux, 4 * k, hipMemcpyDeviceToHost)) != hipSuccess) break;
+      if ((e = hipMemcpy(sec_uy, o.sec_uy, 4 * k, hipMemcpyDeviceToHost)) != hipSuccess) break;
+      if ((e = hipMemcpy(sec_uz, o.sec_uz, 4 * k, hipMemcpyDeviceToHost)) != hipSuccess) break;
+      if ((e = hipMemcpy(sec_event, o.sec_event, 4 * k, hipMemcpyDeviceToHost)) != hipSuccess) break;
+      if ((e = hipMemcpy(sec_species, o.sec_species, k, hipMemcpyDeviceToHost)) != hipSuccess) break;
+      if ((e = hipMemcpy(sec_stage, o.sec_stage, k, hipMemcpyDeviceToHost)) != hipSuccess) break;
+    }
+  } while (false);
+  if (d_T0) (void)hipFree(d_T0);
+  if (d_res) (void)hipFree(d_res);
+  if (d_cnt) (void)hipFree(d_cnt);
+  if (d_sec) (void)hipFree(d_sec);
+  inc_ctx_destroy(ctx);
+  if (rc) return rc;
+  if (e != hipSuccess) return map_err(e);
+  *n_sec = (size_t)cnt[0];
+  return cnt[0] > cap ? INC_ERR_CAPACITY : INC_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,384 @@
+// device.h — device-side building blocks of the gfx950 cascade + evaporation
+// kernels (arXiv:1309.7963, Sec. 2 and 3).  Everything here is FP32 IEEE
+// arithmetic (Sec. 3.1 computes in single precision) except the binding-energy
+// differences of the evaporation, which come from a double table so that no
+// nuclear total energy is ever formed in FP32.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace incdev {
+
+constexpr int kShells = 15;
+constexpr int kMaxTargets = 16;
+constexpr int kStackDepth = 64;      // LIFO guard (depth 64)
+constexpr int kMaxSegments = 10000;  // flight-segment guard per event
+constexpr int kXsNodes = 512;        // log-spaced p_lab nodes
+constexpr float kPi = 3.14159265358979323846f;
+constexpr float kMassN = 939.565420f;
+constexpr float kMassP = 938.272088f;
+constexpr float kE2 = 1.44f;         // e^2, MeV fm
+constexpr float kMbToFm2 = 0.1f;
+constexpr float kPlo = 0.1374f;      // GeV/c; NN argument floor (T_lab ~ 10 MeV)
+constexpr float kPhi = 1.5f;         // GeV/c; NN argument ceiling
+
+constexpr uint16_t kFlagStack = 1, kFlagSegments = 2, kFlagEmpty = 4, kFlagRange = 0x8000;
+
+// --------------------------------------------------------------- tables
+// One target nucleus: 15 shells (Sec. 2.2).  Index [species][shell], species
+// 0 = neutron, 1 = proton; r2[i] = (i R / 15)^2 for i = 0..15.
+struct NucTab {
+  float r2[16];
+  float rho[2][16];  // fm^-3
+  float pF[2][16];   // MeV/c
+  float EF[2][16];   // MeV
+  float R, EB, EC;
+  float EFmin[2];    // smallest E_F per species (outermost shell)
+  float pFmax[2];    // largest p_F per species (innermost shell)
+  int A, Z;
+  float pad[7];
+};
+static_assert(sizeof(NucTab) % 16 == 0, "NucTab must stay 16-byte aligned");
+
+// NN elastic table on a log grid of p_lab in [kPlo, kPhi] (Sec. 2.3, 3.1):
+// columns [like] = sigma (mb), sigma_hat suffix maximum (mb), slope b
+// ((GeV/c)^-2); like = 1 for pp/nn, 0 for np/pn.
+struct XsTab {
+  float sig[2][kXsNodes];
+  float hat[2][kXsNodes];
+  float slope[2][kXsNodes];
+};
+
+// Evaporation constants (Sec. 2.4): fragment masses, mass numbers, charges,
+// spin factors, a^(1/3), binding energies.
+struct EvapTab {
+  float m[6];
+  float a13[6];
+  double B[6];
+};
+
+// Per-call constants shared by the kernels.
+struct Opts {
+  int no_pauli, no_evaporation, stop_after_first;
+  float const_sigma_mb;  // > 0 overrides every NN cross-section
+  float fixed_b;         // >= 0 fixes the impact parameter
+  int evap_threshold;
+};
+
+// Binding energies B(A, Z) in double for A <= amax, Z <= zmax.
+struct BindTab {
+  const double* B;
+  int zstride;  // zmax + 1
+  int amax, zmax;
+};
+
+// --------------------------------------------------------------- Philox
+// Philox4x32-10 (Salmon et al., SC'11).
+__device__ __forceinline__ void philox4x32_10(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3,
+                                              uint32_t k0, uint32_t k1, uint32_t out[4]) {
+#pragma unroll
+  for (int r = 0; r < 10; ++r) {
+    if (r) {
+      k0 += 0x9E3779B9u;
+      k1 += 0xBB67AE85u;
+    }
+    const uint32_t hi0 = __umulhi(0xD2511F53u, c0), lo0 = 0xD2511F53u * c0;
+    const uint32_t hi1 = __umulhi(0xCD9E8D57u, c2), lo1 = 0xCD9E8D57u * c2;
+    const uint32_t n0 = hi1 ^ c1 ^ k0;
+    const uint32_t n2 = hi0 ^ c3 ^ k1;
+    c0 = n0;
+    c1 = lo1;
+    c2 = n2;
+    c3 = lo0;
+  }
+  out[0] = c0;
+  out[1] = c1;
+  out[2] = c2;
+  out[3] = c3;
+}
+
+// Per-event stream: key = seed, counter = (block, id lo, id hi, 0); the four
+// words of a block are used in order; u = ((w >> 9) + 1/2) 2^-23, exact in
+// FP32 and strictly inside (0, 1).
+struct Rng {
+  uint32_t k0, k1, id0, id1;
+  uint32_t blk;    // next block to generate
+  uint32_t w[4];
+  uint32_t pos;    // next word (4 = buffer empty)
+
+  __device__ __forceinline__ void init(uint64_t seed, uint64_t id) {
+    k0 = (uint32_t)seed;
+    k1 = (uint32_t)(seed >> 32);
+    id0 = (uint32_t)id;
+    id1 = (uint32_t)(id >> 32);
+    blk = 0;
+    pos = 4;
+  }
+  // Resume after `drawn` uniforms.
+  __device__ __forceinline__ void seek(uint32_t drawn) {
+    blk = drawn >> 2;
+    pos = drawn & 3u;
+    if (pos) {
+      philox4x32_10(blk, id0, id1, 0u, k0, k1, w);
+      ++blk;
+    } else {
+      pos = 4;
+    }
+  }
+  __device__ __forceinline__ uint32_t drawn() const { return pos == 4 ? blk * 4u : (blk - 1u) * 4u + pos; }
+  __device__ __forceinline__ float next() {
+    if (pos >= 4) {
+      philox4x32_10(blk, id0, id1, 0u, k0, k1, w);
+      ++blk;
+      pos = 0;
+    }
+    const uint32_t v = pos == 0 ? w[0] : pos == 1 ? w[1] : pos == 2 ? w[2] : w[3];
+    ++pos;
+    return (float)(v >> 9) * 0x1p-23f + 0x1p-24f;
+  }
+};
+
+// ------------------------------------------------------------ small math
+__device__ __forceinline__ float nucleon_mass(int sp) { return sp ? kMassP : kMassN; }
+__device__ __forceinline__ float kinetic_of(float p, float m) { return p * p / (sqrtf(p * p + m * m) + m); }
+
+struct V3 {
+  float x, y, z;
+};
+__device__ __forceinline__ float dot3(V3 a, V3 b) { return a.x * b.x + a.y * b.y + a.z * b.z; }
+__device__ __forceinline__ V3 axpy(float s, V3 a, V3 b) { return {s * a.x + b.x, s * a.y + b.y, s * a.z + b.z}; }
+__device__ __forceinline__ V3 scale(float s, V3 a) { return {s * a.x, s * a.y, s * a.z}; }
+__device__ __forceinline__ V3 unit(V3 a) {
+  const float r = 1.0f / sqrtf(dot3(a, a));
+  return scale(r, a);
+}
+
+// Unit vector at polar angle (cos c, sin s) and azimuth 2 pi u_phi from a.
+__device__ __forceinline__ V3 rotate(V3 a, float c, float s, float u_phi) {
+  float sp, cp;
+  sincospif(2.0f * u_phi, &sp, &cp);
+  const float st = sqrtf(a.x * a.x + a.y * a.y);
+  if (st > 1e-6f) {
+    const float inv = 1.0f / st;
+    const V3 e1 = {a.x * a.z * inv, a.y * a.z * inv, -st};
+    const V3 e2 = {-a.y * inv, a.x * inv, 0.0f};
+    return {c * a.x + s * (cp * e1.x + sp * e2.x), c * a.y + s * (cp * e1.y + sp * e2.y),
+            c * a.z + s * (cp * e1.z + sp * e2.z)};
+  }
+  return {s * cp, s * sp, a.z >= 0.0f ? c : -c};
+}
+
+// Boost a momentum q of mass m from a frame with gamma*beta = u, gamma = g.
+__device__ __forceinline__ void boost_out(V3 q, float m, V3 u, float g, V3& p, float& T) {
+  const float q2 = dot3(q, q);
+  const float E = sqrtf(q2 + m * m);
+  const float uq = dot3(u, q);
+  p = axpy(uq / (g + 1.0f) + E, u, q);
+  T = g * (q2 / (E + m)) + dot3(u, u) / (g + 1.0f) * m + uq;
+}
+
+// -------------------------------------------------------- cross-sections
+__device__ __forceinline__ void xs_coord(float p_GeV, int& k, float& f) {
+  const float pc = fminf(fmaxf(p_GeV, kPlo), kPhi);
+  const float scale = (float)(kXsNodes - 1) / logf(kPhi / kPlo);
+  float x = logf(pc * (1.0f / kPlo)) * scale;
+  x = fminf(fmaxf(x, 0.0f), (float)(kXsNodes - 1));
+  k = min((int)x, kXsNodes - 2);
+  f = x - (float)k;
+}
+__device__ __forceinline__ float xs_lerp(const float* col, int k, float f) {
+  const float a = col[k], b = col[k + 1];
+  return a + f * (b - a);
+}
+
+// Majorant flight cross-sections (fm^2) for a particle of species sp with
+// excess energy eps: smallest own momentum (at the smallest E_F) against the
+// largest Fermi momentum of each target species.
+__device__ __forceinline__ void majorant(const NucTab& nt, const XsTab& xs, const Opts& o, int sp, float eps,
+                                         float& sh0, float& sh1) {
+  const float mx = nucleon_mass(sp);
+  const float T = eps + nt.EFmin[sp];
+  const float p = sqrtf(T * T + 2.0f * T * mx);
+  const float Ex = T + mx;
+  float sh[2];
+#pragma unroll
+  for (int y = 0; y < 2; ++y) {
+    const float my = nucleon_mass(y);
+    const float pF = nt.pFmax[y];
+    const float EFy = sqrtf(pF * pF + my * my);
+    const float pmin = fmaxf(0.0f, (p * EFy - Ex * pF) / my) * 1e-3f;
+    float s;
+    if (o.const_sigma_mb > 0.0f) {
+      s = o.const_sigma_mb;
+    } else {
+      int k;
+      float f;
+      xs_coord(pmin, k, f);
+      s = xs_lerp(xs.hat[sp == y], k, f);
+    }
+    sh[y] = s * kMbToFm2;
+  }
+  sh0 = sh[0];
+  sh1 = sh[1];
+}
+
+// Classical refraction at a potential step (reading of Chen et al., Sec. 2.3):
+// tangential momentum kept, T - V conserved, reflection when the normal
+// component cannot be formed.  Returns true when transmitted.
+__device__ __forceinline__ bool refract(V3& d, V3 n, float T_from, float T_to, float m) {
+  const float p_from = sqrtf(T_from * T_from + 2.0f * T_from * m);
+  const float dn = dot3(d, n);
+  const float pn = p_from * dn;
+  if (T_to > 0.0f) {
+    const float pn2 = pn * pn + (T_to - T_from) * (T_to + T_from + 2.0f * m);
+    if (pn2 > 0.0f) {
+      const float pnn = copysignf(sqrtf(pn2), pn);
+      const V3 q = {p_from * d.x + (pnn - pn) * n.x, p_from * d.y + (pnn - pn) * n.y,
+                    p_from * d.z + (pnn - pn) * n.z};
+      d = unit(q);
+      return true;
+    }
+  }
+  d = axpy(-2.0f * dn, n, d);
+  return false;
+}
+
+// ------------------------------------------------------------ evaporation
+// ln I(a, U), I = int_0^U x exp(2 sqrt(a (U - x))) dx
+//   = [e^Y (2Y^2 - 6Y + 6) + Y^2 - 6] / (8 a^2),  Y = 2 sqrt(a U),
+// with the all-positive series (1/4a^2) sum_{n>=4} (n-1)(n-3) Y^n/n! below Y = 2.
+__device__ __forceinline__ float log_width_integral(float a, float U) {
+  const float Y = 2.0f * sqrtf(a * U);
+  if (Y < 2.0f) {
+    float term = Y * Y * Y * Y * (1.0f / 24.0f);
+    float sum = 0.0f;
+#pragma unroll
+    for (int n = 4; n < 22; ++n) {
+      sum += (float)((n - 1) * (n - 3)) * term;
+      term *= Y / (float)(n + 1);
+    }
+    return logf(sum) - logf(4.0f * a * a);
+  }
+  const float k = (2.0f * Y - 6.0f) * Y + 6.0f + expf(-Y) * (Y * Y - 6.0f);
+  return Y + logf(k) - logf(8.0f * a * a);
+}
+
+// Kinetic-energy excess x in [0, U] with density ~ x exp(2 sqrt(a (U - x))).
+// With Y = 2 sqrt(a U), t = Y - 2 sqrt(a (U - x)) and s = t / Y in [0, 1]:
+// x = U s (2 - s), U - x = U (1 - s)^2, and the CDF in s is K(s) / K(1) with
+// dK/ds ~ s (2 - s) (1 - s) e^{-Y s}.  K is integrated in closed form
+// (large Y) or by its series in s (small Y); the root of K(s) = u K(1) is found
+// by bracketed Newton iteration.  Returns s.
+__device__ __forceinline__ float spectrum_K(float Y, float s) {
+  if (Y < 1.0f) {
+    // sum_m (-Y)^m / m! [2 s^{m+2}/(m+2) - 3 s^{m+3}/(m+3) + s^{m+4}/(m+4)]
+    float c = 1.0f, sm = s * s, sum = 0.0f;
+#pragma unroll
+    for (int m = 0; m < 12; ++m) {
+      sum += c * sm * (2.0f / (float)(m + 2) - 3.0f * s / (float)(m + 3) + s * s / (float)(m + 4));
+      c *= -Y / (float)(m + 1);
+      sm *= s;
+    }
+    return sum;
+  }
+  const float t = Y * s;
+  const float C = (2.0f * Y - 6.0f) * Y + 6.0f;
+  const float Q = 2.0f * Y * Y * (1.0f + t) - 3.0f * Y * ((t + 2.0f) * t + 2.0f) + ((t + 3.0f) * t + 6.0f) * t + 6.0f;
+  return C - expf(-t) * Q;
+}
+__device__ __forceinline__ float spectrum_dK(float Y, float s) {
+  const float core = s * (2.0f - s) * (1.0f - s) * expf(-Y * s);
+  if (Y < 1.0f) return core;
+  const float Y2 = Y * Y;
+  return Y2 * Y2 * core;
+}
+__device__ __forceinline__ float spectrum_sample_s(float Y, float u) {
+  const float K1 = spectrum_K(Y, 1.0f);
+  const float target = u * K1;
+  float lo = 0.0f, hi = 1.0f;
+  float s = Y > 4.0f ? fminf(0.5f, 2.0f / Y) : 0.5f;
+  for (int it = 0; it < 40; ++it) {
+    const float F = spectrum_K(Y, s) - target;
+    if (F < 0.0f) lo = s; else hi = s;
+    const float dF = spectrum_dK(Y, s);
+    float sn = (dF > 0.0f) ? s - F / dF : 0.5f * (lo + hi);
+    if (!(sn > lo && sn < hi)) sn = 0.5f * (lo + hi);
+    const float step = fabsf(sn - s);
+    s = sn;
+    if (step <= 2e-7f || hi - lo <= 2e-7f) break;
+  }
+  return fminf(fmaxf(s, 0.0f), 1.0f);
+}
+
+// ------------------------------------------------------------- writer
+// Wave-compacted writer (Sec. 3.3 writes evaporated particles uncoalesced):
+// lanes that emit a record this iteration append it to the wave's LDS buffer
+// at (fill + rank among emitting lanes); when the buffer could overflow, the
+// wave reserves space with one global atomic and all 64 lanes copy the
+// buffer out contiguously into the SoA arrays.
+constexpr int kWriterCap = 128;  // records per wave buffer
+constexpr int kRecWords = 6;     // event, species | stage << 8, T, ux, uy, uz
+
+struct OutPtrs {
+  uint32_t* ev;
+  uint8_t* species;
+  uint8_t* stage;
+  float* T;
+  float* ux;
+  float* uy;
+  float* uz;
+  unsigned long long* counter;
+  unsigned long long cap;
+};
+
+__device__ __forceinline__ int lane_id() { return __lane_id(); }
+
+__device__ __forceinline__ uint32_t rank_in(uint64_t mask) {
+  return __builtin_amdgcn_mbcnt_hi((uint32_t)(mask >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)mask, 0u));
+}
+
+// Must be called by all lanes of the wave.
+__device__ __forceinline__ void writer_flush(uint32_t* buf, int& fill, const OutPtrs& o) {
+  if (fill == 0) return;
+  __builtin_amdgcn_wave_barrier();
+  unsigned long long base = 0;
+  if (lane_id() == 0) base = atomicAdd(o.counter, (unsigned long long)fill);
+  base = __shfl(base, 0);
+  for (int i = lane_id(); i < fill; i += 64) {
+    const unsigned long long k = base + (unsigned long long)i;
+    if (k < o.cap) {
+      const uint32_t* r = buf + i * kRecWords;
+      o.ev[k] = r[0];
+      o.species[k] = (uint8_t)(r[1] & 0xFFu);
+      o.stage[k] = (uint8_t)(r[1] >> 8);
+      o.T[k] = __uint_as_float(r[2]);
+      o.ux[k] = __uint_as_float(r[3]);
+      o.uy[k] = __uint_as_float(r[4]);
+      o.uz[k] = __uint_as_float(r[5]);
+    }
+  }
+  __builtin_amdgcn_wave_barrier();
+  fill = 0;
+}
+
+// Must be called by all lanes of the wave.
+__device__ __forceinline__ void writer_append(uint32_t* buf, int& fill, const OutPtrs& o, bool emit, uint32_t ev,
+                                              uint32_t kind, float T, V3 u) {
+  const uint64_t m = __ballot(emit);
+  if (m == 0) return;
+  const int cnt = __popcll(m);
+  if (fill + cnt > kWriterCap) writer_flush(buf, fill, o);
+  if (emit) {
+    uint32_t* r = buf + (fill + (int)rank_in(m)) * kRecWords;
+    r[0] = ev;
+    r[1] = kind;
+    r[2] = __float_as_uint(T);
+    r[3] = __float_as_uint(u.x);
+    r[4] = __float_as_uint(u.y);
+    r[5] = __float_as_uint(u.z);
+  }
+  fill += cnt;
+}
+
+}  // namespace incdev

@@ -1,0 +1,404 @@
+// event.h — per-lane state machines of one non-elastic event: the
+// intranuclear cascade (Sec. 2.3) and the evaporation (Sec. 2.4).  A lane
+// advances by one bounded step per call so that the calling kernels keep the
+// whole wave converged at the writer after every step.
+#pragma once
+
+#include "device.h"
+
+namespace incdev {
+
+enum : int { kPhaseIdle = 0, kPhaseCascade = 1, kPhaseEvap = 2, kPhaseDone = 3 };
+
+// Cascade state of one event (registers).  The LIFO of pending products
+// lives in a private (scratch) array owned by the kernel.
+struct Cascade {
+  V3 pos, dir;
+  float eps;     // T - E_F(local): invariant under refraction
+  int sp;        // 0 n, 1 p
+  int shell;     // 0..14
+  float tau;     // remaining optical depth
+  float sh0, sh1;  // majorant cross-sections (fm^2) against n, p
+  float Ex;      // accumulated excitation energy
+  V3 pesc;       // sum of escaped momenta
+  int nesc0, nesc1, avail0, avail1;
+  int ncoll, nretry, nseg, flags, top;
+  int started;
+};
+
+// Residual nucleus entering / leaving the evaporation.
+struct Nucleus {
+  int A, Z;
+  float E;   // excitation energy
+  V3 P;      // momentum
+};
+
+struct StackEntry {
+  float v[8];  // pos xyz, dir xyz, eps, (sp | shell << 1) as bits
+};
+
+__device__ __forceinline__ void push(StackEntry* stk, Cascade& c, V3 pos, V3 dir, float eps, int sp) {
+  StackEntry& e = stk[c.top++];
+  e.v[0] = pos.x; e.v[1] = pos.y; e.v[2] = pos.z;
+  e.v[3] = dir.x; e.v[4] = dir.y; e.v[5] = dir.z;
+  e.v[6] = eps;
+  e.v[7] = __int_as_float(sp | (c.shell << 1));
+}
+__device__ __forceinline__ void pop(StackEntry* stk, Cascade& c) {
+  const StackEntry& e = stk[--c.top];
+  c.pos = {e.v[0], e.v[1], e.v[2]};
+  c.dir = {e.v[3], e.v[4], e.v[5]};
+  c.eps = e.v[6];
+  const int k = __float_as_int(e.v[7]);
+  c.sp = k & 1;
+  c.shell = k >> 1;
+}
+
+__device__ __forceinline__ void cascade_init(Cascade& c, const NucTab& nt) {
+  c.Ex = 0.0f;
+  c.pesc = {0.0f, 0.0f, 0.0f};
+  c.nesc0 = c.nesc1 = 0;
+  c.avail0 = nt.A - nt.Z;  // the projectile proton is out of the sea
+  c.avail1 = nt.Z;
+  c.ncoll = c.nretry = c.nseg = c.flags = c.top = 0;
+  c.started = 0;
+}
+
+// Entry (reading): impact parameter uniform over the disc of radius R,
+// incidence along +z, inward refraction at R; then the first optical depth.
+__device__ __forceinline__ void cascade_entry(Cascade& c, Rng& rng, const NucTab& nt, const XsTab& xs,
+                                              const Opts& o, float T0) {
+  const float ub = rng.next();
+  const float uphi = rng.next();
+  float b, z;
+  if (o.fixed_b >= 0.0f) {
+    b = o.fixed_b;
+    z = -sqrtf(fmaxf(0.0f, nt.R * nt.R - b * b));
+  } else {
+    b = nt.R * sqrtf(ub);
+    z = -nt.R * sqrtf(1.0f - ub);
+  }
+  float sp, cp;
+  sincospif(2.0f * uphi, &sp, &cp);
+  c.pos = {b * cp, b * sp, z};
+  c.dir = {0.0f, 0.0f, 1.0f};
+  c.eps = T0 + nt.EB;
+  c.sp = 1;
+  c.shell = kShells - 1;
+  const float r = sqrtf(dot3(c.pos, c.pos));
+  const V3 n = r > 0.0f ? scale(1.0f / r, c.pos) : V3{0.0f, 0.0f, -1.0f};
+  refract(c.dir, n, T0, c.eps + nt.EF[1][kShells - 1], kMassP);
+  majorant(nt, xs, o, c.sp, c.eps, c.sh0, c.sh1);
+  c.tau = -logf(rng.next());
+  c.started = 1;
+}
+
+// Capture (cutoff, Sec. 2.3): the particle stays, its excess energy heats the
+// nucleus and it rejoins the Fermi sea.
+__device__ __forceinline__ void capture(Cascade& c, float eps, int sp) {
+  c.Ex += eps;
+  if (sp) ++c.avail1; else ++c.avail0;
+}
+
+// Take the next particle from the stack or end the cascade.  Returns false
+// when the cascade is over.
+__device__ __forceinline__ bool next_particle(Cascade& c, StackEntry* stk, Rng& rng, const NucTab& nt,
+                                              const XsTab& xs, const Opts& o) {
+  if (c.top == 0) return false;
+  pop(stk, c);
+  majorant(nt, xs, o, c.sp, c.eps, c.sh0, c.sh1);
+  c.tau = -logf(rng.next());
+  return true;
+}
+
+struct Emit {
+  bool on;
+  uint32_t kind;
+  float T;
+  V3 u;
+};
+
+// One cascade step: entry if needed, then one flight segment ending at a
+// tentative collision or at a shell boundary.  Returns true when the cascade
+// of this event is complete.
+__device__ __forceinline__ bool cascade_step(Cascade& c, StackEntry* stk, Rng& rng, const NucTab& nt,
+                                             const XsTab& xs, const Opts& o, float T0, Emit& em) {
+  em.on = false;
+  if (!c.started) cascade_entry(c, rng, nt, xs, o, T0);
+  if (c.nseg >= kMaxSegments) {
+    // segment guard: capture everything still moving
+    c.flags |= kFlagSegments;
+    capture(c, c.eps, c.sp);
+    while (c.top > 0) {
+      pop(stk, c);
+      capture(c, c.eps, c.sp);
+    }
+    return true;
+  }
+  ++c.nseg;
+  const int s = c.shell;
+  const float w0 = c.avail0 > 0 ? nt.rho[0][s] * c.sh0 : 0.0f;
+  const float w1 = c.avail1 > 0 ? nt.rho[1][s] * c.sh1 : 0.0f;
+  const float lam = w0 + w1;
+  const float xd = dot3(c.pos, c.dir);
+  const V3 cx = {c.pos.y * c.dir.z - c.pos.z * c.dir.y, c.pos.z * c.dir.x - c.pos.x * c.dir.z,
+                 c.pos.x * c.dir.y - c.pos.y * c.dir.x};
+  const float b2 = dot3(cx, cx);
+  const float rin2 = nt.r2[s], rout2 = nt.r2[s + 1];
+  float t;
+  int dest;
+  if (s > 0 && xd < 0.0f && b2 < rin2) {
+    t = fmaxf(0.0f, -xd - sqrtf(rin2 - b2));
+    dest = s - 1;
+  } else {
+    t = fmaxf(0.0f, -xd + sqrtf(fmaxf(0.0f, rout2 - b2)));
+    dest = s + 1;
+  }
+
+  if (c.tau < lam * t) {
+    // ---- tentative collision (null-collision flight)
+    c.pos = axpy(c.tau / lam, c.dir, c.pos);
+    const int y = (w0 > rng.next() * (w0 + w1)) ? 0 : 1;
+    const float mx = nucleon_mass(c.sp), my = nucleon_mass(y);
+    // target momentum uniform in the local Fermi sphere (Sec. 2.2)
+    const float ptm = nt.pF[y][s] * cbrtf(rng.next());
+    const float ct = 2.0f * rng.next() - 1.0f;
+    const float st = sqrtf(fmaxf(0.0f, 1.0f - ct * ct));
+    float sph, cph;
+    sincospif(2.0f * rng.next(), &sph, &cph);
+    const V3 pt = {ptm * st * cph, ptm * st * sph, ptm * ct};
+    const float EFx = nt.EF[c.sp][s], EFy = nt.EF[y][s];
+    const float Tx = c.eps + EFx;
+    const V3 px = scale(sqrtf(Tx * Tx + 2.0f * Tx * mx), c.dir);
+    const int like = (c.sp == y);
+    const float Tt = kinetic_of(ptm, my);
+    const float Q = 2.0f * (Tx * Tt + Tx * my + Tt * mx - dot3(px, pt));
+    const float ss = (mx + my) * (mx + my) + Q;
+    const float rs = sqrtf(ss);
+    const float pstar = sqrtf(Q * (Q + 4.0f * mx * my) / (4.0f * ss));
+    const float plab = pstar * rs / my;
+    int k;
+    float f;
+    xs_coord(plab * 1e-3f, k, f);
+    const float sig = (o.const_sigma_mb > 0.0f ? o.const_sigma_mb : xs_lerp(xs.sig[like], k, f)) * kMbToFm2;
+    const float shy = y ? c.sh1 : c.sh0;
+    if (!(rng.next() < sig / shy)) {
+      c.tau = -logf(rng.next());
+      return false;
+    }
+    // ---- elastic scattering in the CM frame (Sec. 2.3), dsigma/dt ~ exp(b t)
+    const float u_th = rng.next();
+    const float u_ph = rng.next();
+    const float b = xs_lerp(xs.slope[like], k, f);
+    const V3 P = {px.x + pt.x, px.y + pt.y, px.z + pt.z};
+    const V3 u = scale(1.0f / rs, P);
+    const float g = (Tx + Tt + mx + my) / rs;
+    const V3 qcm = axpy(dot3(u, px) / (g + 1.0f) - (Tx + mx), u, px);
+    const V3 a = unit(qcm);
+    const float kk = 2.0f * b * (pstar * 1e-3f) * (pstar * 1e-3f);
+    float yy = (kk < 1e-6f) ? 2.0f * u_th : -log1pf(u_th * expm1f(-2.0f * kk)) / kk;
+    yy = fminf(fmaxf(yy, 0.0f), 2.0f);
+    const float cth = 1.0f - yy;
+    const float sth = sqrtf(fmaxf(0.0f, yy * (2.0f - yy)));
+    const V3 nn = rotate(a, cth, sth, u_ph);
+    V3 qx, qt;
+    float Txn, Ttn;
+    boost_out(scale(pstar, nn), mx, u, g, qx, Txn);
+    boost_out(scale(-pstar, nn), my, u, g, qt, Ttn);
+    if (like && rng.next() < 0.5f) {
+      const V3 tq = qx;
+      qx = qt;
+      qt = tq;
+      const float tT = Txn;
+      Txn = Ttn;
+      Ttn = tT;
+    }
+    // ---- Pauli (Sec. 2.3): both products above their local Fermi energy.
+    // The struck product's excess energy follows from energy conservation.
+    const float h = fmaxf(0.0f, EFy - Tt);
+    const float ex = Txn - EFx;
+    const float ey = c.eps - ex - h;
+    if (!o.no_pauli && !(ex > 0.0f && ey > 0.0f)) {
+      c.tau = -logf(rng.next());
+      return false;
+    }
+    ++c.ncoll;
+    if (y) --c.avail1; else --c.avail0;
+    c.Ex += h;
+    const V3 dx = unit(qx), dy = unit(qt);
+    const int spx = c.sp;
+    if (o.stop_after_first) {
+      capture(c, ex, spx);
+      capture(c, ey, y);
+      while (c.top > 0) {
+        pop(stk, c);
+        capture(c, c.eps, c.sp);
+      }
+      return true;
+    }
+    const bool tx = ex >= nt.EB + (spx ? nt.EC : 0.0f);
+    const bool ty = ey >= nt.EB + (y ? nt.EC : 0.0f);
+    if (!tx) capture(c, ex, spx);
+    if (!ty) capture(c, ey, y);
+    if (tx && ty) {
+      if (c.top >= kStackDepth) {
+        c.flags |= kFlagStack;
+        capture(c, ey, y);
+      } else {
+        push(stk, c, c.pos, dy, ey, y);
+      }
+      c.dir = dx;
+      c.eps = ex;
+    } else if (tx) {
+      c.dir = dx;
+      c.eps = ex;
+    } else if (ty) {
+      c.dir = dy;
+      c.eps = ey;
+      c.sp = y;
+    } else {
+      return !next_particle(c, stk, rng, nt, xs, o);
+    }
+    majorant(nt, xs, o, c.sp, c.eps, c.sh0, c.sh1);
+    c.tau = -logf(rng.next());
+    return false;
+  }
+
+  // ---- boundary crossing (Sec. 2.3 refraction / reflection)
+  c.tau -= lam * t;
+  c.pos = axpy(t, c.dir, c.pos);
+  const V3 n = scale(1.0f / sqrtf(dot3(c.pos, c.pos)), c.pos);
+  const float m = nucleon_mass(c.sp);
+  const float T_from = c.eps + nt.EF[c.sp][s];
+  if (dest == kShells) {
+    const float T_out = c.eps - nt.EB;
+    if (refract(c.dir, n, T_from, T_out, m)) {
+      if (c.ncoll == 0) {
+        // transparent pass: not a non-elastic event, try again (Sec. 2.1)
+        ++c.nretry;
+        c.started = 0;
+        return false;
+      }
+      const float p = sqrtf(T_out * T_out + 2.0f * T_out * m);
+      c.pesc = axpy(p, c.dir, c.pesc);
+      if (c.sp) ++c.nesc1; else ++c.nesc0;
+      em.on = true;
+      em.kind = (uint32_t)c.sp;  // stage 0
+      em.T = T_out;
+      em.u = c.dir;
+      return !next_particle(c, stk, rng, nt, xs, o);
+    }
+  } else if (refract(c.dir, n, T_from, c.eps + nt.EF[c.sp][dest], m)) {
+    c.shell = dest;
+  }
+  return false;
+}
+
+// Residual after the cascade (Sec. 2.3, excitation by energy conservation).
+__device__ __forceinline__ Nucleus cascade_residual(const Cascade& c, const NucTab& nt, float T0) {
+  Nucleus r;
+  r.A = nt.A + 1 - c.nesc0 - c.nesc1;
+  r.Z = nt.Z + 1 - c.nesc1;
+  r.E = c.Ex;
+  const float p0 = sqrtf(T0 * T0 + 2.0f * T0 * kMassP);
+  r.P = {-c.pesc.x, -c.pesc.y, p0 - c.pesc.z};
+  return r;
+}
+
+__device__ __forceinline__ double binding_of(const BindTab& bt, int A, int Z) { return bt.B[A * bt.zstride + Z]; }
+
+// One evaporation step (Sec. 2.4, Weisskopf-Ewing reading).  Returns true when
+// no channel is open (the nucleus is final).
+__device__ __forceinline__ bool evap_step(Nucleus& nu, Rng& rng, const BindTab& bt, const EvapTab& et, Emit& em) {
+  em.on = false;
+  constexpr int fa[6] = {1, 1, 2, 3, 3, 4};
+  constexpr int fz[6] = {0, 1, 1, 1, 2, 2};
+  constexpr float fg[6] = {2.0f, 2.0f, 3.0f, 2.0f, 2.0f, 1.0f};
+  const double BAZ = binding_of(bt, nu.A, nu.Z);
+  float lw[6], U[6], V[6], Y[6];
+  float lmax = -INFINITY;
+#pragma unroll
+  for (int j = 0; j < 6; ++j) {
+    lw[j] = -INFINITY;
+    U[j] = 0.0f;
+    V[j] = 0.0f;
+    Y[j] = 0.0f;
+    const int Ad = nu.A - fa[j], Zd = nu.Z - fz[j];
+    if (Ad >= 1 && Zd >= 0 && Zd <= Ad) {
+      const float S = (float)(BAZ - binding_of(bt, Ad, Zd) - et.B[j]);
+      const float ad13 = cbrtf((float)Ad);
+      V[j] = fz[j] ? kE2 * (float)(fz[j] * Zd) / (1.5f * (ad13 + et.a13[j])) : 0.0f;
+      U[j] = nu.E - S - V[j];
+      if (U[j] > 0.0f) {
+        const float a = (float)Ad * 0.125f;
+        const float Rj = j <= 1 ? 1.5f * ad13 : 1.5f * (ad13 + et.a13[j]);
+        Y[j] = 2.0f * sqrtf(a * U[j]);
+        lw[j] = logf(fg[j] * et.m[j] * Rj * Rj) + log_width_integral(a, U[j]);
+        lmax = fmaxf(lmax, lw[j]);
+      }
+    }
+  }
+  if (lmax == -INFINITY) return true;
+  float w[6], total = 0.0f;
+#pragma unroll
+  for (int j = 0; j < 6; ++j) {
+    w[j] = lw[j] == -INFINITY ? 0.0f : expf(lw[j] - lmax);
+    total += w[j];
+  }
+  const float uc = rng.next() * total;
+  int j = -1;
+  float cum = 0.0f;
+#pragma unroll
+  for (int i = 0; i < 6; ++i) {
+    cum += w[i];
+    if (j < 0 && w[i] > 0.0f && cum > uc) j = i;
+  }
+  if (j < 0) {
+#pragma unroll
+    for (int i = 0; i < 6; ++i)
+      if (w[i] > 0.0f) j = i;
+  }
+  float Uj = 0.0f, Vj = 0.0f, Yj = 0.0f, mj = 0.0f;
+  int aj = 0, zj = 0;
+#pragma unroll
+  for (int i = 0; i < 6; ++i)
+    if (i == j) {
+      Uj = U[i];
+      Vj = V[i];
+      Yj = Y[i];
+      mj = et.m[i];
+      aj = fa[i];
+      zj = fz[i];
+    }
+  const float s = spectrum_sample_s(Yj, rng.next());
+  const float x = Uj * s * (2.0f - s);
+  const float Ed = Uj * (1.0f - s) * (1.0f - s);
+  const float eps = Vj + x;
+  const int Ad = nu.A - aj, Zd = nu.Z - zj;
+  const float Mp = (float)((double)nu.Z * kMassP + (double)(nu.A - nu.Z) * kMassN - BAZ) + nu.E;
+  const float Mb = (float)((double)Zd * kMassP + (double)(Ad - Zd) * kMassN - binding_of(bt, Ad, Zd)) + Ed;
+  const float inv2a = 0.5f / Mp;
+  const float p2 = eps * (eps + 2.0f * mj) * ((eps + 2.0f * Mb) * inv2a) * ((eps + 2.0f * Mb + 2.0f * mj) * inv2a);
+  const float ps = sqrtf(fmaxf(p2, 0.0f));
+  const float ct = 2.0f * rng.next() - 1.0f;
+  const float st = sqrtf(fmaxf(0.0f, 1.0f - ct * ct));
+  float sph, cph;
+  sincospif(2.0f * rng.next(), &sph, &cph);
+  const V3 q = {ps * st * cph, ps * st * sph, ps * ct};
+  const V3 u = scale(1.0f / Mp, nu.P);
+  const float g = sqrtf(1.0f + dot3(u, u));
+  V3 pf;
+  float Tf;
+  boost_out(q, mj, u, g, pf, Tf);
+  em.on = true;
+  em.kind = (uint32_t)j | (1u << 8);
+  em.T = Tf;
+  em.u = unit(pf);
+  nu.P = {nu.P.x - pf.x, nu.P.y - pf.y, nu.P.z - pf.z};
+  nu.A = Ad;
+  nu.Z = Zd;
+  nu.E = Ed;
+  return false;
+}
+
+}  // namespace incdev

@@ -1,0 +1,55 @@
+// kernels.h — host-visible launch interface between the C ABI (api.hip) and
+// the kernels (kernels.hip).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "../../include/inc.h"
+#include "device.h"
+
+namespace incdev {
+
+// State handed from the plain cascade kernel to the plain evaporation kernel
+// (32 bytes per event).
+struct MidState {
+  int16_t A, Z;
+  uint16_t flags, ncoll, nretry, nsec;
+  float E;
+  float P[3];
+  uint32_t drawn;   // uniforms consumed by the cascade
+};
+static_assert(sizeof(MidState) == 32, "MidState layout");
+
+struct LaunchDesc {
+  int mode;
+  int block;
+  int persistent_blocks;
+  int evap_threshold;
+  const NucTab* nuc;
+  int n_targets;
+  const XsTab* xs;
+  const double* bind;
+  int amax, zmax;
+  EvapTab evap;
+  inc_options opt;
+  bool fixed_b_set;
+  size_t n;
+  const uint8_t* tidx;
+  const float* T0;
+  uint64_t seed, first_id;
+  inc_residual* res;
+  uint32_t* sec_event;
+  uint8_t* sec_species;
+  uint8_t* sec_stage;
+  float *sec_T, *sec_ux, *sec_uy, *sec_uz;
+  size_t sec_capacity;
+  unsigned long long* counters;
+  MidState* mid;
+};
+
+}  // namespace incdev
+
+size_t inc_lds_bytes(int n_targets, int block, bool with_xs);
+hipError_t inc_launch_setup(const int* d_AZ, int n_targets, incdev::NucTab* d_nuc, incdev::XsTab* d_xs, double* d_B,
+                            int amax, int zmax, incdev::EvapTab* d_evap, const inc_options& o, hipStream_t s);
+hipError_t inc_launch_events(const incdev::LaunchDesc& L, hipStream_t s);

@@ -1,0 +1,213 @@
+"""GPU path (HIP library through its C ABI) against the CPU oracle.
+
+* every GPU event satisfies the per-event conservation checks (exact integers,
+  energy ledgers within 1e-3 MeV, momentum within 1e-3 MeV/c);
+* replay: with the same seed both sides consume the same random stream, so
+  almost every event has the same integer outcome (FP32 vs FP64 comparisons
+  flip rarely);
+* distributions: two-sample chi-square (independent seeds) on 100-bin n/p
+  energy and angle histograms and the residual (A, Z) table, p > 0.01.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import ledger
+import oracle
+import stats
+from gpu_util import events_from_gpu, outcome_keys, run_gpu
+
+pytestmark = pytest.mark.gpu
+
+O16, CA40 = (16, 8), (40, 20)
+TISSUE = [(12, 6), (14, 7), (16, 8), (31, 15), (40, 20)]
+TISSUE_W = [0.18, 0.03, 0.65, 0.01, 0.13]
+IMPLANT = [(48, 22), (56, 26)]
+
+
+def _oracle_events(targets, T0, seed, tidx=None, **hooks):
+    out = oracle.run(targets, np.asarray(T0, dtype=np.float64), seed=seed, tidx=tidx, n_threads=16, **hooks)
+    return ledger.from_oracle(out, targets, T0, tidx), out
+
+
+def _mixture(n, targets, weights, lo, hi, seed):
+    rng = np.random.default_rng(seed)
+    tidx = rng.choice(len(targets), size=n, p=weights).astype(np.uint8)
+    T0 = rng.uniform(lo, hi, n).astype(np.float32)
+    return tidx, T0
+
+
+def test_nucleus_tables_match_oracle():
+    import paper_1309_7963_amd as inc
+
+    targets = TISSUE + IMPLANT
+    ctx = inc.Context(targets)
+    tab = ctx.tables()
+    for t, (A, Z) in enumerate(targets):
+        nu = oracle.nucleus(A, Z)
+        g = tab[t, :105].reshape(15, 7)
+        np.testing.assert_allclose(g[:, 0], nu.r[1:16], rtol=2e-6)
+        for col, sp in ((1, 0), (2, 1)):
+            np.testing.assert_allclose(g[:, col], nu.rho[sp][:], rtol=2e-5)
+        for col, sp in ((3, 0), (4, 1)):
+            np.testing.assert_allclose(g[:, col], nu.pF[sp][:], rtol=2e-5)
+        for col, sp in ((5, 0), (6, 1)):
+            np.testing.assert_allclose(g[:, col], nu.EF[sp][:], rtol=5e-5)
+        assert tab[t, 105] == pytest.approx(nu.EB, rel=1e-6)
+        assert tab[t, 106] == pytest.approx(nu.EC, rel=1e-6)
+        assert tab[t, 107] == pytest.approx(nu.R, rel=1e-6)
+
+
+@pytest.mark.parametrize("mode", ["plain", "persistent"])
+@pytest.mark.parametrize("target,T", [(O16, 200.0), (CA40, 200.0), ((12, 6), 20.0), ((56, 26), 250.0)])
+def test_ledgers_every_event(mode, target, T):
+    n = 20000
+    T0 = np.full(n, T, dtype=np.float32)
+    h = run_gpu([target], T0, seed=1, mode=mode)
+    ev = events_from_gpu(h, [target], T0)
+    s = ledger.check(ev)
+    ledger.assert_clean(s)
+    assert h["n_sec_total"] == int(h["res"]["n_sec"].sum())
+    assert np.all(h["res"]["n_coll"] >= 1)
+    assert s["max_E1"] < 1e-3 and s["max_E2"] < 1e-3 and s["max_P"] < 1e-3
+
+
+def test_ledgers_mixed_targets():
+    tidx, T0 = _mixture(50000, TISSUE, TISSUE_W, 20, 250, seed=3)
+    for mode in ("plain", "persistent"):
+        h = run_gpu(TISSUE, T0, seed=5, tidx=tidx, mode=mode)
+        ledger.assert_clean(ledger.check(events_from_gpu(h, TISSUE, T0, tidx)))
+
+
+@pytest.mark.parametrize("target", [O16, CA40])
+def test_replay_same_stream(target):
+    # C1-sized: 10^4 events, same seed on both sides
+    n = 10000
+    T0 = np.full(n, 200.0, dtype=np.float32)
+    g = events_from_gpu(run_gpu([target], T0, seed=1), [target], T0)
+    o, _ = _oracle_events([target], T0, seed=1)
+    kg, ko = outcome_keys(g), outcome_keys(o)
+    agree = np.mean([a == b for a, b in zip(kg, ko)])
+    print("replay agreement", target, agree)
+    assert agree > 0.97
+    # on agreeing events the excitation energies match to FP32 accuracy
+    same = np.array([a == b for a, b in zip(kg, ko)])
+    d = np.abs(g.Ex_casc[same] - o.Ex_casc[same])
+    assert np.median(d) < 1e-3
+
+
+def _chi2_gate(g, o, T_max, label):
+    res = stats.compare_samples(g, o, T_max)
+    print(label, {k: (round(v[0], 1), v[1], round(v[2], 4)) for k, v in res.items()})
+    for k, (chi2, dof, p) in res.items():
+        assert p > 0.01, (label, k, chi2, dof, p)
+
+
+@pytest.mark.parametrize("target", [O16, CA40])
+def test_chi2_paper_scale(target):
+    # C2: 10^6 events at 200 MeV, GPU seed 1 vs oracle seed 2
+    n = 1_000_000
+    T0 = np.full(n, 200.0, dtype=np.float32)
+    g = events_from_gpu(run_gpu([target], T0, seed=1, mode="plain"), [target], T0)
+    o, _ = _oracle_events([target], T0, seed=2)
+    _chi2_gate(g, o, 200.0, "C2 %s" % (target,))
+
+
+def test_chi2_mixed_persistent():
+    # C3-shaped mixture, persistent kernel
+    n = 1_000_000
+    tidx, T0 = _mixture(n, TISSUE, TISSUE_W, 20, 250, seed=11)
+    g = events_from_gpu(run_gpu(TISSUE, T0, seed=1, tidx=tidx, mode="persistent"), TISSUE, T0, tidx)
+    o, _ = _oracle_events(TISSUE, T0, seed=2, tidx=tidx)
+    _chi2_gate(g, o, 250.0, "C3")
+
+
+def test_plain_and_persistent_agree_per_event():
+    n = 30000
+    tidx, T0 = _mixture(n, TISSUE, TISSUE_W, 20, 250, seed=13)
+    a = events_from_gpu(run_gpu(TISSUE, T0, seed=7, tidx=tidx, mode="plain"), TISSUE, T0, tidx)
+    b = events_from_gpu(run_gpu(TISSUE, T0, seed=7, tidx=tidx, mode="persistent"), TISSUE, T0, tidx)
+    ka, kb = outcome_keys(a), outcome_keys(b)
+    agree = np.mean([x == y for x, y in zip(ka, kb)])
+    assert agree > 0.999, agree
+
+
+def test_same_seed_is_bitwise_reproducible():
+    n = 20000
+    tidx, T0 = _mixture(n, TISSUE, TISSUE_W, 20, 250, seed=17)
+    h1 = run_gpu(TISSUE, T0, seed=9, tidx=tidx)
+    h2 = run_gpu(TISSUE, T0, seed=9, tidx=tidx)
+    assert h1["res"].tobytes() == h2["res"].tobytes()
+    k1 = np.lexsort((h1["sec_T"], h1["sec_event"]))
+    k2 = np.lexsort((h2["sec_T"], h2["sec_event"]))
+    for f in ("sec_event", "sec_species", "sec_stage", "sec_T", "sec_u"):
+        assert np.array_equal(h1[f][k1], h2[f][k2]), f
+
+
+def test_event_identity_independent_of_batching():
+    n = 8000
+    T0 = np.full(n, 150.0, dtype=np.float32)
+    whole = run_gpu([O16], T0, seed=3)
+    part = run_gpu([O16], T0[3000:5000], seed=3, first_id=3000)
+    assert whole["res"][3000:5000].tobytes() == part["res"].tobytes()
+
+
+def test_transparency_closed_form_on_gpu():
+    sig = 40.0
+    n = 200000
+    h = run_gpu([O16], np.full(n, 150.0, dtype=np.float32), seed=21, const_sigma_mb=sig, uniform_density=1,
+                zero_fermi=1, zero_binding=1, no_pauli=1, no_evaporation=1, stop_after_first=1)
+    nu = oracle.nucleus(16, 8, uniform_density=1)
+    rho = 16 / (4 / 3 * math.pi * nu.R ** 3)
+    x = 2 * rho * sig * 0.1 * nu.R
+    P = 2 * (1 - (1 + x) * math.exp(-x)) / x ** 2
+    retries = int(h["res"]["n_retry"].astype(np.int64).sum())
+    passes = n + retries
+    z = (retries - P * passes) / math.sqrt(passes * P * (1 - P))
+    assert abs(z) < 4.0, (retries / passes, P)
+
+
+def test_capacity_overflow_reports_required_size():
+    n = 5000
+    T0 = np.full(n, 200.0, dtype=np.float32)
+    full = run_gpu([O16], T0, seed=4)
+    small = run_gpu([O16], T0, seed=4, capacity=1000)
+    assert small["n_sec_total"] == full["n_sec_total"] > 1000
+    assert small["res"].tobytes() == full["res"].tobytes()
+    assert small["sec_T"].shape[0] == 1000
+
+
+def test_out_of_range_energies_are_flagged():
+    import paper_1309_7963_amd as inc
+
+    T0 = np.array([200.0, 19.0, 251.0, np.nan, 100.0], dtype=np.float32)
+    h = run_gpu([O16], T0, seed=2)
+    flags = h["res"]["flags"]
+    assert list(flags & inc.FLAG_RANGE) == [0, inc.FLAG_RANGE, inc.FLAG_RANGE, inc.FLAG_RANGE, 0]
+    assert np.all(h["sec_event"] != 1) and np.all(h["sec_event"] != 3)
+    r = inc.simulate_host(16, 8, T0, seed=2)
+    assert r["rc"] == inc.INC_ERR_RANGE
+
+
+def test_host_call_matches_device_call():
+    import paper_1309_7963_amd as inc
+
+    T0 = np.full(4000, 200.0, dtype=np.float32)
+    r = inc.simulate_host(16, 8, T0, seed=6)
+    d = run_gpu([O16], T0, seed=6)
+    assert r["rc"] == 0
+    assert r["res"].tobytes() == d["res"].tobytes()
+    assert r["n_sec_total"] == d["n_sec_total"]
+
+
+def test_invalid_arguments():
+    import paper_1309_7963_amd as inc
+
+    with pytest.raises(inc.IncError) as e:
+        inc.Context([(16, 16)])
+    assert e.value.code == inc.INC_ERR_ARG
+    with pytest.raises(inc.IncError):
+        inc.Context([(300, 100)])
+    with pytest.raises(inc.IncError):
+        inc.Context([(16, 8)], block_size=100)

@@ -1,0 +1,84 @@
+"""CPU checks of the C ABI library: it builds, loads, and exports every
+function include/inc.h declares; without a GPU it reports INC_ERR_NO_DEVICE
+instead of falling back to anything."""
+import ctypes as C
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared_functions():
+    src = open(os.path.join(ROOT, "include", "inc.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(inc_[a-z_]+)\s*\(", src)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    from paper_1309_7963_amd import build
+
+    build.build(force=False)
+    return C.CDLL(build.LIB)
+
+
+def test_header_declares_the_entry_points():
+    names = declared_functions()
+    for want in ("inc_simulate", "inc_simulate_dev", "inc_ctx_create", "inc_ctx_destroy", "inc_strerror"):
+        assert want in names
+
+
+def test_every_declared_symbol_is_exported(lib):
+    for name in declared_functions():
+        assert hasattr(lib, name), name
+
+
+def test_binding_knows_every_symbol():
+    from paper_1309_7963_amd import _lib
+
+    assert sorted(_lib.SYMBOLS) == declared_functions()
+
+
+def test_error_strings(lib):
+    lib.inc_strerror.restype = C.c_char_p
+    for code in range(0, -7, -1):
+        assert lib.inc_strerror(code)
+    lib.inc_contract_version.restype = C.c_int
+    assert lib.inc_contract_version() >= 1
+
+
+def _has_gpu():
+    try:
+        import torch
+
+        return torch.cuda.device_count() > 0
+    except Exception:
+        return False
+
+
+@pytest.mark.skipif(_has_gpu(), reason="a GPU is present")
+def test_no_device_is_an_error_not_a_fallback():
+    import paper_1309_7963_amd as inc
+
+    with pytest.raises(inc.IncError) as e:
+        inc.Context([(16, 8)])
+    assert e.value.code == inc.INC_ERR_NO_DEVICE
+
+
+def test_argument_errors_before_device(lib):
+    import paper_1309_7963_amd as inc
+    from paper_1309_7963_amd import _lib
+
+    L = _lib.load()
+    h = C.c_void_p()
+    arr = (_lib.Nucleus * 1)(_lib.Nucleus(16, 16))
+    assert L.inc_ctx_create(arr, 1, None, C.byref(h)) == inc.INC_ERR_ARG
+    arr = (_lib.Nucleus * 1)(_lib.Nucleus(16, 8))
+    assert L.inc_ctx_create(arr, 0, None, C.byref(h)) == inc.INC_ERR_ARG
+    assert L.inc_simulate_dev(None, None, None, None, 0) == inc.INC_ERR_ARG
+    nsec = C.c_size_t()
+    e = (C.c_float * 1)(10.0)
+    rc = L.inc_simulate(16, 8, e, 1, 1, None, None, None, None, None, None, None, None, 0, C.byref(nsec))
+    assert rc == inc.INC_ERR_ARG
