@@ -64,8 +64,9 @@ typedef struct {
   float fixed_b;         /* fm, 0 <= fixed_b < R                             */
   /* launch policy (0 = library default) */
   int block_size;        /* threads per block: 64..256, multiple of 64       */
-  int evap_threshold;    /* persistent kernel: lanes in evaporation that make
-                            a wave run an evaporation step (1..64)           */
+  int evap_threshold;    /* persistent kernel: lanes waiting in a state that */
+  int tent_threshold;    /* make a wave run that state's step next (1..64): */
+  int kin_threshold;     /* evaporation, tentative collision, kinematics     */
   int waves_per_cu;      /* persistent kernel: resident waves per CU         */
 } inc_options;
 

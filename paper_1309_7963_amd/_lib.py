@@ -35,7 +35,8 @@ class Options(C.Structure):
         ("uniform_density", C.c_int), ("zero_fermi", C.c_int), ("zero_binding", C.c_int),
         ("no_pauli", C.c_int), ("no_evaporation", C.c_int), ("stop_after_first", C.c_int),
         ("const_sigma_mb", C.c_float), ("fixed_b_on", C.c_int), ("fixed_b", C.c_float),
-        ("block_size", C.c_int), ("evap_threshold", C.c_int), ("waves_per_cu", C.c_int),
+        ("block_size", C.c_int), ("evap_threshold", C.c_int), ("tent_threshold", C.c_int),
+        ("kin_threshold", C.c_int), ("waves_per_cu", C.c_int),
     ]
 
 
@@ -76,6 +77,12 @@ def load():
     """Load the HIP library; raises if it has not been built."""
     global _lib
     if _lib is None:
+        # One HIP runtime per process: torch ships its own libamdhip64.so.7 and
+        # the dynamic linker binds libinc.so to whichever copy is loaded
+        # first, so torch (which owns the device memory and streams) goes
+        # first.
+        import torch  # noqa: F401
+
         if not os.path.exists(LIB_PATH):
             raise RuntimeError(
                 "libinc.so is not built: run `python -m paper_1309_7963_amd.build` "

@@ -23,7 +23,7 @@ struct inc_ctx {
   MidState* d_mid;
   size_t mid_cap;
   int n_cu;
-  int block, evap_threshold, waves_per_cu;
+  int block, evap_threshold, tent_threshold, kin_threshold, waves_per_cu;
 };
 
 namespace {
@@ -86,7 +86,9 @@ int inc_ctx_create(const inc_nucleus* targets, int n_targets, const inc_options*
   memset(&o, 0, sizeof(o));
   if (opt) o = *opt;
   if (o.block_size && (o.block_size < 64 || o.block_size > 256 || o.block_size % 64)) return INC_ERR_ARG;
-  if (o.evap_threshold < 0 || o.evap_threshold > 64 || o.waves_per_cu < 0 || o.waves_per_cu > 32) return INC_ERR_ARG;
+  if (o.evap_threshold < 0 || o.evap_threshold > 64 || o.tent_threshold < 0 || o.tent_threshold > 64 ||
+      o.kin_threshold < 0 || o.kin_threshold > 64 || o.waves_per_cu < 0 || o.waves_per_cu > 32)
+    return INC_ERR_ARG;
   if (!(o.const_sigma_mb >= 0.0f) || o.const_sigma_mb > 1e5f) return INC_ERR_ARG;
   if (o.fixed_b_on && !(o.fixed_b >= 0.0f && o.fixed_b < 20.0f)) return INC_ERR_ARG;
   int dev = 0, n_cu = 0;
@@ -102,8 +104,12 @@ int inc_ctx_create(const inc_nucleus* targets, int n_targets, const inc_options*
   c->opt = o;
   c->fixed_b_set = o.fixed_b_on != 0;
   c->block = o.block_size ? o.block_size : 256;
-  c->evap_threshold = o.evap_threshold ? o.evap_threshold : 32;
-  c->waves_per_cu = o.waves_per_cu ? o.waves_per_cu : 8;
+  // defaults from a sweep on MI355X (16O/40Ca at 200 MeV): a deep state runs
+  // once 8-16 lanes wait in it; 12 resident waves per CU (3 per SIMD)
+  c->evap_threshold = o.evap_threshold ? o.evap_threshold : 16;
+  c->tent_threshold = o.tent_threshold ? o.tent_threshold : 8;
+  c->kin_threshold = o.kin_threshold ? o.kin_threshold : 16;
+  c->waves_per_cu = o.waves_per_cu ? o.waves_per_cu : 12;
   int amax = 0, zmax = 0;
   for (int t = 0; t < n_targets; ++t) {
     c->AZ[2 * t] = targets[t].A;
@@ -193,6 +199,8 @@ int inc_simulate_dev(inc_ctx* ctx, const inc_batch* b, const inc_output* out, vo
   L.persistent_blocks = ctx->n_cu * ctx->waves_per_cu / (ctx->block / 64);
   if (L.persistent_blocks < 1) L.persistent_blocks = 1;
   L.evap_threshold = ctx->evap_threshold;
+  L.tent_threshold = ctx->tent_threshold;
+  L.kin_threshold = ctx->kin_threshold;
   L.nuc = ctx->d_nuc;
   L.n_targets = ctx->n_targets;
   L.xs = ctx->d_xs;

@@ -63,7 +63,7 @@ struct Opts {
   int no_pauli, no_evaporation, stop_after_first;
   float const_sigma_mb;  // > 0 overrides every NN cross-section
   float fixed_b;         // >= 0 fixes the impact parameter
-  int evap_threshold;
+  int evap_threshold, tent_threshold, kin_threshold;
 };
 
 // Binding energies B(A, Z) in double for A <= amax, Z <= zmax.
@@ -101,11 +101,18 @@ __device__ __forceinline__ void philox4x32_10(uint32_t c0, uint32_t c1, uint32_t
 // Per-event stream: key = seed, counter = (block, id lo, id hi, 0); the four
 // words of a block are used in order; u = ((w >> 9) + 1/2) 2^-23, exact in
 // FP32 and strictly inside (0, 1).
+//
+// Two blocks are buffered (a: current, b: next).  Every step calls ensure(k)
+// once at its start with the most words it can draw, so the Philox rounds run
+// with all lanes of that step together instead of at scattered draw sites;
+// next() generates only the rare word the two blocks could not hold.  The
+// order of the words is the stream order whatever the buffering.
 struct Rng {
   uint32_t k0, k1, id0, id1;
   uint32_t blk;    // next block to generate
-  uint32_t w[4];
-  uint32_t pos;    // next word (4 = buffer empty)
+  uint32_t a[4], b[4];
+  uint32_t pos;    // next word of a (4 = a used up)
+  uint32_t nb;     // words valid in b (0 or 4)
 
   __device__ __forceinline__ void init(uint64_t seed, uint64_t id) {
     k0 = (uint32_t)seed;
@@ -114,26 +121,59 @@ struct Rng {
     id1 = (uint32_t)(id >> 32);
     blk = 0;
     pos = 4;
+    nb = 0;
+  }
+  __device__ __forceinline__ void gen(uint32_t out[4]) {
+    philox4x32_10(blk, id0, id1, 0u, k0, k1, out);
+    ++blk;
+  }
+  __device__ __forceinline__ uint32_t avail() const { return 4u - pos + nb; }
+  __device__ __forceinline__ void shift() {
+    a[0] = b[0];
+    a[1] = b[1];
+    a[2] = b[2];
+    a[3] = b[3];
+    pos = 0;
+    nb = 0;
+  }
+  // Prefetch so that at least k words are buffered when the two blocks can
+  // hold them (always for k <= 5); next() generates any word still missing.
+  __device__ __forceinline__ void ensure(uint32_t k) {
+    if (pos == 4 && nb == 4) shift();
+    if (avail() < k) {
+      if (pos == 4) {
+        gen(a);
+        pos = 0;
+      } else if (nb == 0) {
+        gen(b);
+        nb = 4;
+      }
+    }
+    if (avail() < k && nb == 0) {
+      gen(b);
+      nb = 4;
+    }
   }
   // Resume after `drawn` uniforms.
   __device__ __forceinline__ void seek(uint32_t drawn) {
     blk = drawn >> 2;
     pos = drawn & 3u;
-    if (pos) {
-      philox4x32_10(blk, id0, id1, 0u, k0, k1, w);
-      ++blk;
-    } else {
-      pos = 4;
-    }
+    nb = 0;
+    if (pos) gen(a);
+    else pos = 4;
   }
-  __device__ __forceinline__ uint32_t drawn() const { return pos == 4 ? blk * 4u : (blk - 1u) * 4u + pos; }
+  __device__ __forceinline__ uint32_t drawn() const { return blk * 4u - avail(); }
+  // Next uniform of the stream.
   __device__ __forceinline__ float next() {
     if (pos >= 4) {
-      philox4x32_10(blk, id0, id1, 0u, k0, k1, w);
-      ++blk;
-      pos = 0;
+      if (nb) {
+        shift();
+      } else {
+        gen(a);
+        pos = 0;
+      }
     }
-    const uint32_t v = pos == 0 ? w[0] : pos == 1 ? w[1] : pos == 2 ? w[2] : w[3];
+    const uint32_t v = pos == 0 ? a[0] : pos == 1 ? a[1] : pos == 2 ? a[2] : a[3];
     ++pos;
     return (float)(v >> 9) * 0x1p-23f + 0x1p-24f;
   }

@@ -1,29 +1,45 @@
 // event.h — per-lane state machines of one non-elastic event: the
-// intranuclear cascade (Sec. 2.3) and the evaporation (Sec. 2.4).  A lane
-// advances by one bounded step per call so that the calling kernels keep the
-// whole wave converged at the writer after every step.
+// intranuclear cascade (Sec. 2.3) and the evaporation (Sec. 2.4).
+//
+// A lane is always in one of a few states and advances by one bounded step per
+// call: FLIGHT (one flight segment, ending at a shell boundary or at a
+// tentative collision point), TENT (the tentative collision: target species
+// and momentum, p_lab, accept test), KIN (the accepted collision: CM angle,
+// boosts, Pauli test, cutoff, stack), EVAP (one evaporation emission).  The
+// kernels keep the whole wave converged at the writer after every step, and
+// the persistent kernel picks per iteration which state the wave advances, so
+// that each step runs with many lanes together.
 #pragma once
 
 #include "device.h"
 
 namespace incdev {
 
-enum : int { kPhaseIdle = 0, kPhaseCascade = 1, kPhaseEvap = 2, kPhaseDone = 3 };
+enum : int {
+  kStIdle = 0,    // no event (queue exhausted)
+  kStFlight = 1,
+  kStTent = 2,
+  kStKin = 3,
+  kStEvap = 4,
+  kStDone = 5,    // event finished, lane needs a new one
+};
 
 // Cascade state of one event (registers).  The LIFO of pending products
 // lives in a private (scratch) array owned by the kernel.
 struct Cascade {
   V3 pos, dir;
-  float eps;     // T - E_F(local): invariant under refraction
-  int sp;        // 0 n, 1 p
-  int shell;     // 0..14
-  float tau;     // remaining optical depth
+  float eps;       // T - E_F(local): invariant under refraction
+  int sp;          // 0 n, 1 p
+  int shell;       // 0..14
+  float tau;       // remaining optical depth
   float sh0, sh1;  // majorant cross-sections (fm^2) against n, p
-  float Ex;      // accumulated excitation energy
-  V3 pesc;       // sum of escaped momenta
+  float Ex;        // accumulated excitation energy
+  V3 pesc;         // sum of escaped momenta
   int nesc0, nesc1, avail0, avail1;
   int ncoll, nretry, nseg, flags, top;
   int started;
+  V3 pt;           // target momentum of the pending collision (TENT -> KIN)
+  int ytgt;        // target species of the pending collision
 };
 
 // Residual nucleus entering / leaving the evaporation.
@@ -118,12 +134,19 @@ struct Emit {
   V3 u;
 };
 
-// One cascade step: entry if needed, then one flight segment ending at a
-// tentative collision or at a shell boundary.  Returns true when the cascade
-// of this event is complete.
-__device__ __forceinline__ bool cascade_step(Cascade& c, StackEntry* stk, Rng& rng, const NucTab& nt,
-                                             const XsTab& xs, const Opts& o, float T0, Emit& em) {
+__device__ __forceinline__ float flight_weight(const Cascade& c, const NucTab& nt, int y, int s) {
+  return y ? (c.avail1 > 0 ? nt.rho[1][s] * c.sh1 : 0.0f) : (c.avail0 > 0 ? nt.rho[0][s] * c.sh0 : 0.0f);
+}
+
+// FLIGHT: entry if needed, then one flight segment (null-collision flight,
+// reading of the mean free path): the segment ends at a tentative collision
+// point (-> TENT) or at a shell boundary, where the particle is refracted,
+// reflected or escapes (Sec. 2.3).  Returns the next state; kStDone means the
+// cascade of this event is over.  Draws at most 3 uniforms.
+__device__ __forceinline__ int flight_step(Cascade& c, StackEntry* stk, Rng& rng, const NucTab& nt, const XsTab& xs,
+                                           const Opts& o, float T0, Emit& em) {
   em.on = false;
+  rng.ensure(3);
   if (!c.started) cascade_entry(c, rng, nt, xs, o, T0);
   if (c.nseg >= kMaxSegments) {
     // segment guard: capture everything still moving
@@ -133,13 +156,11 @@ __device__ __forceinline__ bool cascade_step(Cascade& c, StackEntry* stk, Rng& r
       pop(stk, c);
       capture(c, c.eps, c.sp);
     }
-    return true;
+    return kStDone;
   }
   ++c.nseg;
   const int s = c.shell;
-  const float w0 = c.avail0 > 0 ? nt.rho[0][s] * c.sh0 : 0.0f;
-  const float w1 = c.avail1 > 0 ? nt.rho[1][s] * c.sh1 : 0.0f;
-  const float lam = w0 + w1;
+  const float lam = flight_weight(c, nt, 0, s) + flight_weight(c, nt, 1, s);
   const float xd = dot3(c.pos, c.dir);
   const V3 cx = {c.pos.y * c.dir.z - c.pos.z * c.dir.y, c.pos.z * c.dir.x - c.pos.x * c.dir.z,
                  c.pos.x * c.dir.y - c.pos.y * c.dir.x};
@@ -154,116 +175,10 @@ __device__ __forceinline__ bool cascade_step(Cascade& c, StackEntry* stk, Rng& r
     t = fmaxf(0.0f, -xd + sqrtf(fmaxf(0.0f, rout2 - b2)));
     dest = s + 1;
   }
-
   if (c.tau < lam * t) {
-    // ---- tentative collision (null-collision flight)
     c.pos = axpy(c.tau / lam, c.dir, c.pos);
-    const int y = (w0 > rng.next() * (w0 + w1)) ? 0 : 1;
-    const float mx = nucleon_mass(c.sp), my = nucleon_mass(y);
-    // target momentum uniform in the local Fermi sphere (Sec. 2.2)
-    const float ptm = nt.pF[y][s] * cbrtf(rng.next());
-    const float ct = 2.0f * rng.next() - 1.0f;
-    const float st = sqrtf(fmaxf(0.0f, 1.0f - ct * ct));
-    float sph, cph;
-    sincospif(2.0f * rng.next(), &sph, &cph);
-    const V3 pt = {ptm * st * cph, ptm * st * sph, ptm * ct};
-    const float EFx = nt.EF[c.sp][s], EFy = nt.EF[y][s];
-    const float Tx = c.eps + EFx;
-    const V3 px = scale(sqrtf(Tx * Tx + 2.0f * Tx * mx), c.dir);
-    const int like = (c.sp == y);
-    const float Tt = kinetic_of(ptm, my);
-    const float Q = 2.0f * (Tx * Tt + Tx * my + Tt * mx - dot3(px, pt));
-    const float ss = (mx + my) * (mx + my) + Q;
-    const float rs = sqrtf(ss);
-    const float pstar = sqrtf(Q * (Q + 4.0f * mx * my) / (4.0f * ss));
-    const float plab = pstar * rs / my;
-    int k;
-    float f;
-    xs_coord(plab * 1e-3f, k, f);
-    const float sig = (o.const_sigma_mb > 0.0f ? o.const_sigma_mb : xs_lerp(xs.sig[like], k, f)) * kMbToFm2;
-    const float shy = y ? c.sh1 : c.sh0;
-    if (!(rng.next() < sig / shy)) {
-      c.tau = -logf(rng.next());
-      return false;
-    }
-    // ---- elastic scattering in the CM frame (Sec. 2.3), dsigma/dt ~ exp(b t)
-    const float u_th = rng.next();
-    const float u_ph = rng.next();
-    const float b = xs_lerp(xs.slope[like], k, f);
-    const V3 P = {px.x + pt.x, px.y + pt.y, px.z + pt.z};
-    const V3 u = scale(1.0f / rs, P);
-    const float g = (Tx + Tt + mx + my) / rs;
-    const V3 qcm = axpy(dot3(u, px) / (g + 1.0f) - (Tx + mx), u, px);
-    const V3 a = unit(qcm);
-    const float kk = 2.0f * b * (pstar * 1e-3f) * (pstar * 1e-3f);
-    float yy = (kk < 1e-6f) ? 2.0f * u_th : -log1pf(u_th * expm1f(-2.0f * kk)) / kk;
-    yy = fminf(fmaxf(yy, 0.0f), 2.0f);
-    const float cth = 1.0f - yy;
-    const float sth = sqrtf(fmaxf(0.0f, yy * (2.0f - yy)));
-    const V3 nn = rotate(a, cth, sth, u_ph);
-    V3 qx, qt;
-    float Txn, Ttn;
-    boost_out(scale(pstar, nn), mx, u, g, qx, Txn);
-    boost_out(scale(-pstar, nn), my, u, g, qt, Ttn);
-    if (like && rng.next() < 0.5f) {
-      const V3 tq = qx;
-      qx = qt;
-      qt = tq;
-      const float tT = Txn;
-      Txn = Ttn;
-      Ttn = tT;
-    }
-    // ---- Pauli (Sec. 2.3): both products above their local Fermi energy.
-    // The struck product's excess energy follows from energy conservation.
-    const float h = fmaxf(0.0f, EFy - Tt);
-    const float ex = Txn - EFx;
-    const float ey = c.eps - ex - h;
-    if (!o.no_pauli && !(ex > 0.0f && ey > 0.0f)) {
-      c.tau = -logf(rng.next());
-      return false;
-    }
-    ++c.ncoll;
-    if (y) --c.avail1; else --c.avail0;
-    c.Ex += h;
-    const V3 dx = unit(qx), dy = unit(qt);
-    const int spx = c.sp;
-    if (o.stop_after_first) {
-      capture(c, ex, spx);
-      capture(c, ey, y);
-      while (c.top > 0) {
-        pop(stk, c);
-        capture(c, c.eps, c.sp);
-      }
-      return true;
-    }
-    const bool tx = ex >= nt.EB + (spx ? nt.EC : 0.0f);
-    const bool ty = ey >= nt.EB + (y ? nt.EC : 0.0f);
-    if (!tx) capture(c, ex, spx);
-    if (!ty) capture(c, ey, y);
-    if (tx && ty) {
-      if (c.top >= kStackDepth) {
-        c.flags |= kFlagStack;
-        capture(c, ey, y);
-      } else {
-        push(stk, c, c.pos, dy, ey, y);
-      }
-      c.dir = dx;
-      c.eps = ex;
-    } else if (tx) {
-      c.dir = dx;
-      c.eps = ex;
-    } else if (ty) {
-      c.dir = dy;
-      c.eps = ey;
-      c.sp = y;
-    } else {
-      return !next_particle(c, stk, rng, nt, xs, o);
-    }
-    majorant(nt, xs, o, c.sp, c.eps, c.sh0, c.sh1);
-    c.tau = -logf(rng.next());
-    return false;
+    return kStTent;
   }
-
   // ---- boundary crossing (Sec. 2.3 refraction / reflection)
   c.tau -= lam * t;
   c.pos = axpy(t, c.dir, c.pos);
@@ -277,7 +192,7 @@ __device__ __forceinline__ bool cascade_step(Cascade& c, StackEntry* stk, Rng& r
         // transparent pass: not a non-elastic event, try again (Sec. 2.1)
         ++c.nretry;
         c.started = 0;
-        return false;
+        return kStFlight;
       }
       const float p = sqrtf(T_out * T_out + 2.0f * T_out * m);
       c.pesc = axpy(p, c.dir, c.pesc);
@@ -286,12 +201,155 @@ __device__ __forceinline__ bool cascade_step(Cascade& c, StackEntry* stk, Rng& r
       em.kind = (uint32_t)c.sp;  // stage 0
       em.T = T_out;
       em.u = c.dir;
-      return !next_particle(c, stk, rng, nt, xs, o);
+      return next_particle(c, stk, rng, nt, xs, o) ? kStFlight : kStDone;
     }
   } else if (refract(c.dir, n, T_from, c.eps + nt.EF[c.sp][dest], m)) {
     c.shell = dest;
   }
-  return false;
+  return kStFlight;
+}
+
+// Invariants of the pair (x, y) used by TENT and KIN.
+struct Pair {
+  float mx, my, Tx, Tt, rs, pstar, plab;
+  V3 px;
+};
+__device__ __forceinline__ Pair pair_of(const Cascade& c, const NucTab& nt, int y) {
+  Pair q;
+  const int s = c.shell;
+  q.mx = nucleon_mass(c.sp);
+  q.my = nucleon_mass(y);
+  q.Tx = c.eps + nt.EF[c.sp][s];
+  q.px = scale(sqrtf(q.Tx * q.Tx + 2.0f * q.Tx * q.mx), c.dir);
+  const float ptm = sqrtf(dot3(c.pt, c.pt));
+  q.Tt = kinetic_of(ptm, q.my);
+  const float Q = 2.0f * (q.Tx * q.Tt + q.Tx * q.my + q.Tt * q.mx - dot3(q.px, c.pt));
+  const float ss = (q.mx + q.my) * (q.mx + q.my) + Q;
+  q.rs = sqrtf(ss);
+  q.pstar = sqrtf(Q * (Q + 4.0f * q.mx * q.my) / (4.0f * ss));
+  q.plab = q.pstar * q.rs / q.my;
+  return q;
+}
+
+// TENT: the tentative collision.  Target species in proportion to
+// rho_y sigma_hat_xy, target momentum uniform in the local Fermi sphere
+// (Sec. 2.2), accept with sigma(p_lab) / sigma_hat.  A rejected (null)
+// collision draws a fresh optical depth and the flight goes on (-> FLIGHT);
+// an accepted one goes to KIN.  Draws at most 6 uniforms.
+__device__ __forceinline__ int tent_step(Cascade& c, Rng& rng, const NucTab& nt, const XsTab& xs, const Opts& o) {
+  rng.ensure(6);
+  const int s = c.shell;
+  const float w0 = flight_weight(c, nt, 0, s), w1 = flight_weight(c, nt, 1, s);
+  const int y = (w0 > rng.next() * (w0 + w1)) ? 0 : 1;
+  const float ptm = nt.pF[y][s] * cbrtf(rng.next());
+  const float ct = 2.0f * rng.next() - 1.0f;
+  const float st = sqrtf(fmaxf(0.0f, 1.0f - ct * ct));
+  float sph, cph;
+  sincospif(2.0f * rng.next(), &sph, &cph);
+  c.pt = {ptm * st * cph, ptm * st * sph, ptm * ct};
+  c.ytgt = y;
+  const Pair q = pair_of(c, nt, y);
+  int k;
+  float f;
+  xs_coord(q.plab * 1e-3f, k, f);
+  const int like = (c.sp == y);
+  const float sig = (o.const_sigma_mb > 0.0f ? o.const_sigma_mb : xs_lerp(xs.sig[like], k, f)) * kMbToFm2;
+  const float shy = y ? c.sh1 : c.sh0;
+  if (!(rng.next() < sig / shy)) {
+    c.tau = -logf(rng.next());
+    return kStFlight;
+  }
+  return kStKin;
+}
+
+// KIN: elastic scattering in the CM frame (Sec. 2.3), dsigma/dt ~ exp(b t),
+// boosts to the lab, Pauli test on both products, hole energy, cutoff
+// capture, LIFO push of the struck nucleon.  Returns the next state (kStDone
+// when the cascade is over).  Draws at most 4 uniforms.
+__device__ __forceinline__ int kin_step(Cascade& c, StackEntry* stk, Rng& rng, const NucTab& nt, const XsTab& xs,
+                                        const Opts& o) {
+  rng.ensure(4);
+  const int s = c.shell;
+  const int y = c.ytgt;
+  const Pair q = pair_of(c, nt, y);
+  const int like = (c.sp == y);
+  int k;
+  float f;
+  xs_coord(q.plab * 1e-3f, k, f);
+  const float u_th = rng.next();
+  const float u_ph = rng.next();
+  const float b = xs_lerp(xs.slope[like], k, f);
+  const V3 P = {q.px.x + c.pt.x, q.px.y + c.pt.y, q.px.z + c.pt.z};
+  const V3 u = scale(1.0f / q.rs, P);
+  const float g = (q.Tx + q.Tt + q.mx + q.my) / q.rs;
+  const V3 qcm = axpy(dot3(u, q.px) / (g + 1.0f) - (q.Tx + q.mx), u, q.px);
+  const V3 a = unit(qcm);
+  const float kk = 2.0f * b * (q.pstar * 1e-3f) * (q.pstar * 1e-3f);
+  float yy = (kk < 1e-6f) ? 2.0f * u_th : -log1pf(u_th * expm1f(-2.0f * kk)) / kk;
+  yy = fminf(fmaxf(yy, 0.0f), 2.0f);
+  const float cth = 1.0f - yy;
+  const float sth = sqrtf(fmaxf(0.0f, yy * (2.0f - yy)));
+  const V3 nn = rotate(a, cth, sth, u_ph);
+  V3 qx, qt;
+  float Txn, Ttn;
+  boost_out(scale(q.pstar, nn), q.mx, u, g, qx, Txn);
+  boost_out(scale(-q.pstar, nn), q.my, u, g, qt, Ttn);
+  if (like && rng.next() < 0.5f) {
+    const V3 tq = qx;
+    qx = qt;
+    qt = tq;
+    Txn = Ttn;
+  }
+  // Pauli (Sec. 2.3): both products above their local Fermi energy.  The
+  // struck product's excess energy follows from energy conservation.
+  const float EFx = nt.EF[c.sp][s], EFy = nt.EF[y][s];
+  const float h = fmaxf(0.0f, EFy - q.Tt);
+  const float ex = Txn - EFx;
+  const float ey = c.eps - ex - h;
+  if (!o.no_pauli && !(ex > 0.0f && ey > 0.0f)) {
+    c.tau = -logf(rng.next());
+    return kStFlight;
+  }
+  ++c.ncoll;
+  if (y) --c.avail1; else --c.avail0;
+  c.Ex += h;
+  const V3 dx = unit(qx), dy = unit(qt);
+  const int spx = c.sp;
+  if (o.stop_after_first) {
+    capture(c, ex, spx);
+    capture(c, ey, y);
+    while (c.top > 0) {
+      pop(stk, c);
+      capture(c, c.eps, c.sp);
+    }
+    return kStDone;
+  }
+  const bool tx = ex >= nt.EB + (spx ? nt.EC : 0.0f);
+  const bool ty = ey >= nt.EB + (y ? nt.EC : 0.0f);
+  if (!tx) capture(c, ex, spx);
+  if (!ty) capture(c, ey, y);
+  if (tx && ty) {
+    if (c.top >= kStackDepth) {
+      c.flags |= kFlagStack;
+      capture(c, ey, y);
+    } else {
+      push(stk, c, c.pos, dy, ey, y);
+    }
+    c.dir = dx;
+    c.eps = ex;
+  } else if (tx) {
+    c.dir = dx;
+    c.eps = ex;
+  } else if (ty) {
+    c.dir = dy;
+    c.eps = ey;
+    c.sp = y;
+  } else {
+    return next_particle(c, stk, rng, nt, xs, o) ? kStFlight : kStDone;
+  }
+  majorant(nt, xs, o, c.sp, c.eps, c.sh0, c.sh1);
+  c.tau = -logf(rng.next());
+  return kStFlight;
 }
 
 // Residual after the cascade (Sec. 2.3, excitation by energy conservation).
@@ -307,10 +365,11 @@ __device__ __forceinline__ Nucleus cascade_residual(const Cascade& c, const NucT
 
 __device__ __forceinline__ double binding_of(const BindTab& bt, int A, int Z) { return bt.B[A * bt.zstride + Z]; }
 
-// One evaporation step (Sec. 2.4, Weisskopf-Ewing reading).  Returns true when
-// no channel is open (the nucleus is final).
+// EVAP: one evaporation step (Sec. 2.4, Weisskopf-Ewing reading).  Returns true
+// when no channel is open (the nucleus is final).  Draws at most 4 uniforms.
 __device__ __forceinline__ bool evap_step(Nucleus& nu, Rng& rng, const BindTab& bt, const EvapTab& et, Emit& em) {
   em.on = false;
+  rng.ensure(4);
   constexpr int fa[6] = {1, 1, 2, 3, 3, 4};
   constexpr int fz[6] = {0, 1, 1, 1, 2, 2};
   constexpr float fg[6] = {2.0f, 2.0f, 3.0f, 2.0f, 2.0f, 1.0f};
@@ -384,12 +443,12 @@ __device__ __forceinline__ bool evap_step(Nucleus& nu, Rng& rng, const BindTab& 
   const float st = sqrtf(fmaxf(0.0f, 1.0f - ct * ct));
   float sph, cph;
   sincospif(2.0f * rng.next(), &sph, &cph);
-  const V3 q = {ps * st * cph, ps * st * sph, ps * ct};
+  const V3 qv = {ps * st * cph, ps * st * sph, ps * ct};
   const V3 u = scale(1.0f / Mp, nu.P);
   const float g = sqrtf(1.0f + dot3(u, u));
   V3 pf;
   float Tf;
-  boost_out(q, mj, u, g, pf, Tf);
+  boost_out(qv, mj, u, g, pf, Tf);
   em.on = true;
   em.kind = (uint32_t)j | (1u << 8);
   em.T = Tf;
@@ -399,6 +458,15 @@ __device__ __forceinline__ bool evap_step(Nucleus& nu, Rng& rng, const BindTab& 
   nu.Z = Zd;
   nu.E = Ed;
   return false;
+}
+
+// One cascade step of whatever state the lane is in (plain kernels).
+__device__ __forceinline__ int cascade_advance(int st, Cascade& c, StackEntry* stk, Rng& rng, const NucTab& nt,
+                                               const XsTab& xs, const Opts& o, float T0, Emit& em) {
+  em.on = false;
+  if (st == kStFlight) return flight_step(c, stk, rng, nt, xs, o, T0, em);
+  if (st == kStTent) return tent_step(c, rng, nt, xs, o);
+  return kin_step(c, stk, rng, nt, xs, o);
 }
 
 }  // namespace incdev

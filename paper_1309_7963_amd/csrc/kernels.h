@@ -24,7 +24,7 @@ struct LaunchDesc {
   int mode;
   int block;
   int persistent_blocks;
-  int evap_threshold;
+  int evap_threshold, tent_threshold, kin_threshold;
   const NucTab* nuc;
   int n_targets;
   const XsTab* xs;

@@ -228,8 +228,9 @@ __device__ __forceinline__ void write_residual(inc_residual* r, const Nucleus& n
 }
 
 // Plain cascade kernel: one event per thread (Sec. 3.2).  Each iteration of
-// the wave loop advances every live lane by one flight segment, then the wave
-// writes the escaping particles through the compacted writer.
+// the wave loop advances every live lane by one flight segment together with
+// the tentative collision and kinematics it may end in, then the wave writes
+// the escaping particles through the compacted writer.
 __global__ void __launch_bounds__(256) k_cascade_plain(KernelArgs a) {
   extern __shared__ __align__(16) char lds[];
   stage_tables(lds, a, true);
@@ -266,7 +267,10 @@ __global__ void __launch_bounds__(256) k_cascade_plain(KernelArgs a) {
     Emit em;
     em.on = false;
     if (live) {
-      if (cascade_step(c, stk, rng, nt, sxs, a.opt, T0, em)) {
+      int st = flight_step(c, stk, rng, nt, sxs, a.opt, T0, em);
+      if (st == kStTent) st = tent_step(c, rng, nt, sxs, a.opt);
+      if (st == kStKin) st = kin_step(c, stk, rng, nt, sxs, a.opt);
+      if (st == kStDone) {
         const Nucleus r = cascade_residual(c, nt, T0);
         MidState m;
         m.A = (int16_t)r.A;
@@ -339,12 +343,14 @@ __global__ void __launch_bounds__(256) k_evap_plain(KernelArgs a) {
   writer_flush(wbuf, fill, a.out);
 }
 
-// Persistent fused kernel: every wave keeps 64 events in flight.  Finished
-// lanes refill from a global work queue (one atomic per 64 events per wave);
-// each iteration the wave runs either a cascade step for its cascade lanes or
-// an evaporation step for its evaporation lanes (stage selection by ballot:
-// evaporation runs once at least `evap_threshold` lanes wait for it, or when
-// no lane is in the cascade).
+// Persistent fused kernel.  Every wave keeps 64 events in flight; finished
+// lanes refill from a global work queue (one atomic per 64 events per wave).
+// Each iteration the wave advances the lanes of ONE state (FLIGHT, TENT, KIN
+// or EVAP), chosen by ballot: a deeper state runs once enough lanes wait in it
+// (kin / tent / evap thresholds), else FLIGHT, else whatever state has lanes.
+// Lanes in other states wait, so every step runs with many lanes together;
+// each lane still consumes its own random stream in order, so results do not
+// depend on the schedule.
 constexpr int kChunk = 64;
 
 __global__ void __launch_bounds__(256) k_persistent(KernelArgs a) {
@@ -358,7 +364,7 @@ __global__ void __launch_bounds__(256) k_persistent(KernelArgs a) {
 
   unsigned long long chunk_next = 0, chunk_end = 0;
   bool exhausted = false;
-  int phase = kPhaseDone;
+  int st = kStDone;
   size_t ev = 0;
   float T0 = 0.0f;
   int tgt = 0, nsec = 0;
@@ -370,7 +376,7 @@ __global__ void __launch_bounds__(256) k_persistent(KernelArgs a) {
 
   for (;;) {
     // ---- refill finished lanes from the work queue
-    const uint64_t need = __ballot(phase == kPhaseDone);
+    const uint64_t need = __ballot(st == kStDone);
     if (need && !exhausted) {
       if (chunk_next == chunk_end) {
         unsigned long long base = 0;
@@ -385,7 +391,7 @@ __global__ void __launch_bounds__(256) k_persistent(KernelArgs a) {
       }
       const unsigned long long avail = chunk_end - chunk_next;
       const uint32_t r = rank_in(need);
-      if (phase == kPhaseDone && r < avail) {
+      if (st == kStDone && r < avail) {
         ev = (size_t)(chunk_next + r);
         T0 = a.T0[ev];
         tgt = a.tidx ? (int)a.tidx[ev] : 0;
@@ -398,49 +404,64 @@ __global__ void __launch_bounds__(256) k_persistent(KernelArgs a) {
           rng.init(a.seed, a.first_id + ev);
           cascade_init(c, snt[tgt]);
           nsec = 0;
-          phase = kPhaseCascade;
+          st = kStFlight;
         }
       }
       const unsigned long long cnt = (unsigned long long)__popcll(need);
       chunk_next += cnt < avail ? cnt : avail;
     }
-    if (exhausted && phase == kPhaseDone) phase = kPhaseIdle;
-    const uint64_t casc = __ballot(phase == kPhaseCascade);
-    const uint64_t evap = __ballot(phase == kPhaseEvap);
-    if (!casc && !evap) {
+    if (exhausted && st == kStDone) st = kStIdle;
+    const int nF = __popcll(__ballot(st == kStFlight));
+    const int nT = __popcll(__ballot(st == kStTent));
+    const int nK = __popcll(__ballot(st == kStKin));
+    const int nE = __popcll(__ballot(st == kStEvap));
+    if (nF + nT + nK + nE == 0) {
       if (exhausted) break;
       continue;
     }
-    // ---- stage selection
-    const int ne = __popcll(evap);
-    const bool run_evap = evap && (!casc || ne >= a.opt.evap_threshold);
+    // ---- state selection (wave-uniform)
+    int run;
+    if (nK >= a.opt.kin_threshold) run = kStKin;
+    else if (nT >= a.opt.tent_threshold) run = kStTent;
+    else if (nE >= a.opt.evap_threshold) run = kStEvap;
+    else if (nF) run = kStFlight;
+    else if (nK) run = kStKin;
+    else if (nT) run = kStTent;
+    else run = kStEvap;
+
     Emit em;
     em.on = false;
-    if (run_evap) {
-      if (phase == kPhaseEvap) {
+    if (run == kStEvap) {
+      if (st == kStEvap) {
         if (evap_step(nu, rng, a.bind, a.evap, em)) {
           write_residual(&a.res[ev], nu, Ex_casc, nsec, c.flags, c.ncoll, c.nretry);
           if (c.flags) atomicAdd(&a.counters[1], 1ull);
-          phase = kPhaseDone;
+          st = kStDone;
         } else {
           ++nsec;
         }
       }
-    } else if (phase == kPhaseCascade) {
+    } else if (st == run) {
       const NucTab& nt = snt[tgt];
-      if (cascade_step(c, stk, rng, nt, sxs, a.opt, T0, em)) {
+      int ns;
+      if (run == kStFlight) ns = flight_step(c, stk, rng, nt, sxs, a.opt, T0, em);
+      else if (run == kStTent) ns = tent_step(c, rng, nt, sxs, a.opt);
+      else ns = kin_step(c, stk, rng, nt, sxs, a.opt);
+      if (em.on) ++nsec;
+      if (ns == kStDone) {
         nu = cascade_residual(c, nt, T0);
         Ex_casc = nu.E;
         if (nu.A <= 0) c.flags |= kFlagEmpty;
         if (nu.A <= 0 || a.opt.no_evaporation) {
-          write_residual(&a.res[ev], nu, Ex_casc, nsec + (em.on ? 1 : 0), c.flags, c.ncoll, c.nretry);
+          write_residual(&a.res[ev], nu, Ex_casc, nsec, c.flags, c.ncoll, c.nretry);
           if (c.flags) atomicAdd(&a.counters[1], 1ull);
-          phase = kPhaseDone;
+          st = kStDone;
         } else {
-          phase = kPhaseEvap;
+          st = kStEvap;
         }
+      } else {
+        st = ns;
       }
-      if (em.on) ++nsec;
     }
     writer_append(wbuf, fill, a.out, em.on, (uint32_t)ev, em.kind, em.T, em.u);
   }
@@ -480,6 +501,8 @@ hipError_t inc_launch_events(const LaunchDesc& L, hipStream_t s) {
   a.opt.const_sigma_mb = L.opt.const_sigma_mb;
   a.opt.fixed_b = L.fixed_b_set ? L.opt.fixed_b : -1.0f;
   a.opt.evap_threshold = L.evap_threshold;
+  a.opt.tent_threshold = L.tent_threshold;
+  a.opt.kin_threshold = L.kin_threshold;
   a.n = L.n;
   a.tidx = L.tidx;
   a.T0 = L.T0;

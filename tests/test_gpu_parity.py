@@ -186,8 +186,9 @@ def test_out_of_range_energies_are_flagged():
     flags = h["res"]["flags"]
     assert list(flags & inc.FLAG_RANGE) == [0, inc.FLAG_RANGE, inc.FLAG_RANGE, inc.FLAG_RANGE, 0]
     assert np.all(h["sec_event"] != 1) and np.all(h["sec_event"] != 3)
-    r = inc.simulate_host(16, 8, T0, seed=2)
-    assert r["rc"] == inc.INC_ERR_RANGE
+    with pytest.raises(inc.IncError) as e:
+        inc.simulate_host(16, 8, T0, seed=2)
+    assert e.value.code == inc.INC_ERR_RANGE
 
 
 def test_host_call_matches_device_call():
