@@ -41,6 +41,7 @@ extern "C" {
 #define INC_ERR_NO_DEVICE -4  /* no usable gfx950 device                      */
 #define INC_ERR_OOM -5        /* device allocation failed                     */
 #define INC_ERR_DEVICE -6     /* a HIP call or kernel launch failed           */
+#define INC_ERR_BUSY -7       /* serving: no free slot or HBM budget now      */
 
 const char* inc_strerror(int code);
 
@@ -150,6 +151,65 @@ int inc_simulate(int target_A, int target_Z, const float* energies_MeV, size_t n
                  uint64_t seed, inc_residual* res, uint32_t* sec_event, uint8_t* sec_species,
                  uint8_t* sec_stage, float* sec_T, float* sec_ux, float* sec_uy, float* sec_uz,
                  size_t sec_capacity, size_t* n_sec);
+
+/* ------------------------------------------------------------- serving
+ * Continuous batching of event batches arriving from a transport stepper.
+ * A request is admitted when one of max_slots slots (HIP streams of the
+ * server) is free and its buffers (inputs, residuals, secondaries) fit in the
+ * HBM budget; it runs as its own persistent-kernel launch, overlapping with
+ * the requests already on the device.  Tables stay resident in the context;
+ * a request's results depend only on (seed, first_event_id + i, target, T0),
+ * so they are the same alone and in the mix.  Not thread-safe. */
+typedef struct inc_server inc_server;
+
+typedef struct {            /* one request; all pointers are host memory     */
+  size_t n;                 /* events, 1 <= n < 2^32                         */
+  const uint8_t* target_idx;/* n target indices or NULL                      */
+  const float* T0;          /* n energies in [20, 250] MeV (else flagged)    */
+  uint64_t seed;
+  uint64_t first_event_id;
+  size_t sec_capacity;      /* 0 = 12 n + 4096                               */
+} inc_request;
+
+typedef struct {            /* host buffers receiving a request's results   */
+  inc_residual* res;        /* n entries, or NULL                            */
+  uint32_t* sec_event;      /* sec_capacity entries each, or NULL            */
+  uint8_t* sec_species;
+  uint8_t* sec_stage;
+  float *sec_T, *sec_ux, *sec_uy, *sec_uz;
+  size_t sec_capacity;
+  unsigned long long* n_sec;/* out: secondaries produced, or NULL            */
+  double* latency_s;        /* out: submit -> results on host, or NULL       */
+} inc_host_output;
+
+typedef struct {
+  unsigned long long submitted, completed, rejected_busy, events, secondaries;
+  unsigned long long in_flight;
+  size_t pool_free_largest;
+} inc_server_stats;
+
+/* hbm_budget: bytes of device memory for requests in flight (>= 1 MiB; the
+ * server also pins the same amount of host memory); max_slots 1..16. */
+int inc_server_create(inc_ctx* ctx, size_t hbm_budget, int max_slots, inc_server** out);
+int inc_server_destroy(inc_server* server);
+/* Admit a request or return INC_ERR_BUSY (retry later); INC_ERR_ARG if it can
+ * never fit the budget.  On success *ticket identifies it. */
+int inc_server_submit(inc_server* server, const inc_request* req, uint64_t* ticket);
+/* 1 = results ready on the host, 0 = still running, < 0 error. */
+int inc_server_poll(inc_server* server, uint64_t ticket);
+int inc_server_wait(inc_server* server, uint64_t ticket);
+/* Copy a ready request's results (out may be NULL to discard) and release
+ * its memory; returns the request's status (INC_ERR_CAPACITY when its
+ * secondary buffer overflowed, INC_ERR_BUSY if it is not ready yet). */
+int inc_server_fetch(inc_server* server, uint64_t ticket, const inc_host_output* out);
+int inc_server_stats_get(inc_server* server, inc_server_stats* out);
+/* Native request loop: request k arrives arrival_s[k] seconds (ascending)
+ * after the call starts; requests are admitted first come first served as
+ * slots and memory free up, polled, fetched and discarded.  latency_s[k]
+ * receives arrival -> results on host; *span_s the time from the first
+ * arrival to the last completion. */
+int inc_server_replay(inc_server* server, int n_req, const double* arrival_s, const inc_request* reqs,
+                      double* latency_s, double* span_s);
 
 /* Library version of the frozen physics readings (changes when any reading
  * that affects results changes). */

@@ -20,7 +20,7 @@ import numpy as np
 
 from . import _lib
 from ._lib import (  # noqa: F401
-    INC_ERR_ARG, INC_ERR_CAPACITY, INC_ERR_DEVICE, INC_ERR_NO_DEVICE, INC_ERR_OOM, INC_ERR_RANGE,
+    INC_ERR_ARG, INC_ERR_BUSY, INC_ERR_CAPACITY, INC_ERR_DEVICE, INC_ERR_NO_DEVICE, INC_ERR_OOM, INC_ERR_RANGE,
     MODE_PERSISTENT, MODE_PLAIN, RESIDUAL_DTYPE, IncError,
 )
 
@@ -200,6 +200,107 @@ def simulate_host(A: int, Z: int, energies: np.ndarray, seed: int, capacity: Opt
         _lib.check(rc, "inc_simulate")
     out["rc"] = rc
     return out
+
+
+class Server:
+    """Continuous-batching serving loop over a Context (inc_server_*).
+
+    submit() admits a host-side event batch when a slot and HBM budget are
+    free (else returns None: retry later); poll()/wait() follow it; fetch()
+    returns its results as host arrays and releases its memory."""
+
+    def __init__(self, ctx: Context, hbm_budget: int = 2 << 30, max_slots: int = 4):
+        self.ctx = ctx
+        h = C.c_void_p()
+        _lib.check(_lib.load().inc_server_create(ctx._h, int(hbm_budget), int(max_slots), C.byref(h)),
+                   "inc_server_create")
+        self._h = h
+        self._keep = {}
+
+    def close(self):
+        if getattr(self, "_h", None) and self._h.value:
+            _lib.load().inc_server_destroy(self._h)
+            self._h = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    @staticmethod
+    def _request(T0, tidx, seed, first_event_id, capacity):
+        T0 = np.ascontiguousarray(T0, dtype=np.float32)
+        ti = None if tidx is None else np.ascontiguousarray(tidx, dtype=np.uint8)
+        r = _lib.Request()
+        r.n = T0.shape[0]
+        r.T0 = T0.ctypes.data
+        r.target_idx = ti.ctypes.data if ti is not None else None
+        r.seed = int(seed)
+        r.first_event_id = int(first_event_id)
+        r.sec_capacity = int(capacity or 0)
+        return r, (T0, ti)
+
+    def submit(self, T0, seed: int, target_idx=None, first_event_id: int = 0, capacity: int = 0):
+        r, keep = self._request(T0, target_idx, seed, first_event_id, capacity)
+        t = C.c_uint64()
+        rc = _lib.load().inc_server_submit(self._h, C.byref(r), C.byref(t))
+        if rc == _lib.INC_ERR_BUSY:
+            return None
+        _lib.check(rc, "inc_server_submit")
+        self._keep[t.value] = (int(r.n), int(capacity or (r.n * 12 + 4096)))
+        return t.value
+
+    def poll(self, ticket: int) -> bool:
+        rc = _lib.load().inc_server_poll(self._h, ticket)
+        if rc < 0:
+            _lib.check(rc, "inc_server_poll")
+        return rc == 1
+
+    def wait(self, ticket: int):
+        rc = _lib.load().inc_server_wait(self._h, ticket)
+        if rc < 0:
+            _lib.check(rc, "inc_server_wait")
+
+    def fetch(self, ticket: int) -> dict:
+        n, cap = self._keep.pop(ticket)
+        res = np.zeros(n, dtype=RESIDUAL_DTYPE)
+        ev = np.zeros(cap, np.uint32)
+        sp = np.zeros(cap, np.uint8)
+        st = np.zeros(cap, np.uint8)
+        T, ux, uy, uz = (np.zeros(cap, np.float32) for _ in range(4))
+        nsec = C.c_ulonglong()
+        lat = C.c_double()
+        o = _lib.HostOutput(res.ctypes.data, ev.ctypes.data, sp.ctypes.data, st.ctypes.data, T.ctypes.data,
+                            ux.ctypes.data, uy.ctypes.data, uz.ctypes.data, cap, C.pointer(nsec), C.pointer(lat))
+        rc = _lib.load().inc_server_fetch(self._h, ticket, C.byref(o))
+        if rc not in (_lib.INC_OK, _lib.INC_ERR_CAPACITY):
+            _lib.check(rc, "inc_server_fetch")
+        k = min(nsec.value, cap)
+        return dict(rc=rc, res=res, n_sec_total=nsec.value, latency_s=lat.value, sec_event=ev[:k],
+                    sec_species=sp[:k], sec_stage=st[:k], sec_T=T[:k], sec_u=np.stack([ux[:k], uy[:k], uz[:k]], 1))
+
+    def stats(self) -> dict:
+        s = _lib.ServerStats()
+        _lib.check(_lib.load().inc_server_stats_get(self._h, C.byref(s)), "inc_server_stats_get")
+        return {f: getattr(s, f) for f, _ in s._fields_}
+
+    def replay(self, arrivals_s, requests):
+        """Native request loop.  requests: list of dicts with T0, target_idx,
+        seed, first_event_id.  Returns (latency per request in s, span s)."""
+        arr = np.ascontiguousarray(arrivals_s, dtype=np.float64)
+        reqs = (_lib.Request * len(requests))()
+        keep = []
+        for i, q in enumerate(requests):
+            r, k = self._request(q["T0"], q.get("target_idx"), q["seed"], q.get("first_event_id", 0),
+                                 q.get("capacity", 0))
+            reqs[i] = r
+            keep.append(k)
+        lat = np.zeros(len(requests), dtype=np.float64)
+        span = C.c_double()
+        _lib.check(_lib.load().inc_server_replay(self._h, len(requests), arr.ctypes.data, C.addressof(reqs),
+                                                 lat.ctypes.data, C.byref(span)), "inc_server_replay")
+        return lat, span.value
 
 
 def contract_version() -> int:

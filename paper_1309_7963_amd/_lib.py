@@ -16,13 +16,16 @@ INC_ERR_CAPACITY = -3
 INC_ERR_NO_DEVICE = -4
 INC_ERR_OOM = -5
 INC_ERR_DEVICE = -6
+INC_ERR_BUSY = -7
 MODE_PLAIN = 0
 MODE_PERSISTENT = 1
 
 # exported symbols, in the order include/inc.h declares them
 SYMBOLS = (
     "inc_strerror", "inc_ctx_create", "inc_ctx_destroy", "inc_ctx_tables",
-    "inc_simulate_dev", "inc_simulate", "inc_contract_version",
+    "inc_simulate_dev", "inc_simulate", "inc_server_create", "inc_server_destroy",
+    "inc_server_submit", "inc_server_poll", "inc_server_wait", "inc_server_fetch",
+    "inc_server_stats_get", "inc_server_replay", "inc_contract_version",
 )
 
 
@@ -53,6 +56,30 @@ class Batch(C.Structure):
     _fields_ = [
         ("n", C.c_size_t), ("target_idx", C.c_void_p), ("T0", C.c_void_p),
         ("seed", C.c_uint64), ("first_event_id", C.c_uint64),
+    ]
+
+
+class Request(C.Structure):
+    _fields_ = [
+        ("n", C.c_size_t), ("target_idx", C.c_void_p), ("T0", C.c_void_p),
+        ("seed", C.c_uint64), ("first_event_id", C.c_uint64), ("sec_capacity", C.c_size_t),
+    ]
+
+
+class HostOutput(C.Structure):
+    _fields_ = [
+        ("res", C.c_void_p), ("sec_event", C.c_void_p), ("sec_species", C.c_void_p),
+        ("sec_stage", C.c_void_p), ("sec_T", C.c_void_p), ("sec_ux", C.c_void_p),
+        ("sec_uy", C.c_void_p), ("sec_uz", C.c_void_p), ("sec_capacity", C.c_size_t),
+        ("n_sec", C.POINTER(C.c_ulonglong)), ("latency_s", C.POINTER(C.c_double)),
+    ]
+
+
+class ServerStats(C.Structure):
+    _fields_ = [
+        ("submitted", C.c_ulonglong), ("completed", C.c_ulonglong), ("rejected_busy", C.c_ulonglong),
+        ("events", C.c_ulonglong), ("secondaries", C.c_ulonglong), ("in_flight", C.c_ulonglong),
+        ("pool_free_largest", C.c_size_t),
     ]
 
 
@@ -105,6 +132,23 @@ def load():
             C.c_size_t, C.POINTER(C.c_size_t),
         ]
         L.inc_simulate.restype = C.c_int
+        vp = C.c_void_p
+        L.inc_server_create.argtypes = [vp, C.c_size_t, C.c_int, C.POINTER(vp)]
+        L.inc_server_create.restype = C.c_int
+        L.inc_server_destroy.argtypes = [vp]
+        L.inc_server_destroy.restype = C.c_int
+        L.inc_server_submit.argtypes = [vp, C.POINTER(Request), C.POINTER(C.c_uint64)]
+        L.inc_server_submit.restype = C.c_int
+        L.inc_server_poll.argtypes = [vp, C.c_uint64]
+        L.inc_server_poll.restype = C.c_int
+        L.inc_server_wait.argtypes = [vp, C.c_uint64]
+        L.inc_server_wait.restype = C.c_int
+        L.inc_server_fetch.argtypes = [vp, C.c_uint64, C.POINTER(HostOutput)]
+        L.inc_server_fetch.restype = C.c_int
+        L.inc_server_stats_get.argtypes = [vp, C.POINTER(ServerStats)]
+        L.inc_server_stats_get.restype = C.c_int
+        L.inc_server_replay.argtypes = [vp, C.c_int, C.c_void_p, C.c_void_p, C.c_void_p, C.POINTER(C.c_double)]
+        L.inc_server_replay.restype = C.c_int
         L.inc_contract_version.argtypes = []
         L.inc_contract_version.restype = C.c_int
         _lib = L

@@ -12,8 +12,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libinc.so")
-SOURCES = ["api.hip", "kernels.hip"]
-HEADERS = ["device.h", "event.h", "kernels.h"]
+SOURCES = ["api.hip", "kernels.hip", "server.hip"]
+HEADERS = ["device.h", "event.h", "kernels.h", "ctx.h"]
 
 HIPCC_FLAGS = [
     "--offload-arch=gfx950",

@@ -5,26 +5,9 @@
 
 #include <new>
 
-#include "kernels.h"
+#include "ctx.h"
 
 using namespace incdev;
-
-struct inc_ctx {
-  int device;
-  int n_targets;
-  int AZ[2 * kMaxTargets];
-  inc_options opt;
-  bool fixed_b_set;
-  NucTab* d_nuc;
-  XsTab* d_xs;
-  double* d_B;
-  int amax, zmax;
-  EvapTab evap;
-  MidState* d_mid;
-  size_t mid_cap;
-  int n_cu;
-  int block, evap_threshold, tent_threshold, kin_threshold, waves_per_cu;
-};
 
 namespace {
 
@@ -52,12 +35,70 @@ void release(inc_ctx* c) {
   if (!c) return;
   if (c->d_nuc) (void)hipFree(c->d_nuc);
   if (c->d_xs) (void)hipFree(c->d_xs);
+  if (c->d_mass) (void)hipFree(c->d_mass);
   if (c->d_B) (void)hipFree(c->d_B);
   if (c->d_mid) (void)hipFree(c->d_mid);
   delete c;
 }
 
 }  // namespace
+
+int inc_launch_batch(inc_ctx* ctx, const inc_batch* b, const inc_output* out, hipStream_t s, int mode, int max_blocks) {
+  if (!ctx || !b || !out) return INC_ERR_ARG;
+  if (mode != INC_MODE_PLAIN && mode != INC_MODE_PERSISTENT) return INC_ERR_ARG;
+  if (b->n < 1 || b->n >= (1ull << 32) || !b->T0) return INC_ERR_ARG;
+  if (!out->res || !out->counters) return INC_ERR_ARG;
+  if (out->sec_capacity && (!out->sec_event || !out->sec_species || !out->sec_stage || !out->sec_T ||
+                            !out->sec_ux || !out->sec_uy || !out->sec_uz))
+    return INC_ERR_ARG;
+  if (mode == INC_MODE_PLAIN && ctx->mid_cap < b->n) {
+    if (ctx->d_mid) (void)hipFree(ctx->d_mid);
+    ctx->d_mid = nullptr;
+    ctx->mid_cap = 0;
+    hipError_t e = hipMalloc(&ctx->d_mid, sizeof(MidState) * b->n);
+    if (e != hipSuccess) return map_err(e);
+    ctx->mid_cap = b->n;
+  }
+  LaunchDesc L;
+  memset(&L, 0, sizeof(L));
+  L.mode = mode;
+  L.block = ctx->block;
+  L.persistent_blocks = ctx->n_cu * ctx->waves_per_cu / (ctx->block / 64);
+  if (max_blocks > 0 && max_blocks < L.persistent_blocks) L.persistent_blocks = max_blocks;
+  if (L.persistent_blocks < 1) L.persistent_blocks = 1;
+  L.evap_threshold = ctx->evap_threshold;
+  L.tent_threshold = ctx->tent_threshold;
+  L.kin_threshold = ctx->kin_threshold;
+  L.nuc = ctx->d_nuc;
+  L.n_targets = ctx->n_targets;
+  L.xs = ctx->d_xs;
+  L.mass = ctx->d_mass;
+  L.bind = ctx->d_B;
+  L.amax = ctx->amax;
+  L.zmax = ctx->zmax;
+  L.evap = ctx->evap;
+  L.opt = ctx->opt;
+  L.fixed_b_set = ctx->fixed_b_set;
+  L.n = b->n;
+  L.tidx = b->target_idx;
+  L.T0 = b->T0;
+  L.seed = b->seed;
+  L.first_id = b->first_event_id;
+  L.res = out->res;
+  L.sec_event = out->sec_event;
+  L.sec_species = out->sec_species;
+  L.sec_stage = out->sec_stage;
+  L.sec_T = out->sec_T;
+  L.sec_ux = out->sec_ux;
+  L.sec_uy = out->sec_uy;
+  L.sec_uz = out->sec_uz;
+  L.sec_capacity = out->sec_capacity;
+  L.counters = out->counters;
+  L.mid = ctx->d_mid;
+  return map_err(inc_launch_events(L, s));
+}
+
+int inc_map_hip_error(hipError_t e) { return map_err(e); }
 
 extern "C" {
 
@@ -70,6 +111,7 @@ const char* inc_strerror(int code) {
     case INC_ERR_NO_DEVICE: return "no gfx950 device";
     case INC_ERR_OOM: return "device out of memory";
     case INC_ERR_DEVICE: return "HIP error";
+    case INC_ERR_BUSY: return "no free slot or memory now";
     default: return "unknown error";
   }
 }
@@ -126,11 +168,12 @@ int inc_ctx_create(const inc_nucleus* targets, int n_targets, const inc_options*
   do {
     if ((e = hipMalloc(&c->d_nuc, sizeof(NucTab) * n_targets)) != hipSuccess) break;
     if ((e = hipMalloc(&c->d_xs, sizeof(XsTab))) != hipSuccess) break;
+    if ((e = hipMalloc(&c->d_mass, sizeof(MassTab))) != hipSuccess) break;
     if ((e = hipMalloc(&c->d_B, sizeof(double) * (amax + 1) * (zmax + 1))) != hipSuccess) break;
     if ((e = hipMalloc(&d_AZ, sizeof(int) * 2 * n_targets)) != hipSuccess) break;
     if ((e = hipMalloc(&d_evap, sizeof(EvapTab))) != hipSuccess) break;
     if ((e = hipMemcpy(d_AZ, c->AZ, sizeof(int) * 2 * n_targets, hipMemcpyHostToDevice)) != hipSuccess) break;
-    if ((e = inc_launch_setup(d_AZ, n_targets, c->d_nuc, c->d_xs, c->d_B, amax, zmax, d_evap, o, nullptr)) !=
+    if ((e = inc_launch_setup(d_AZ, n_targets, c->d_nuc, c->d_xs, c->d_B, amax, zmax, d_evap, c->d_mass, o, nullptr)) !=
         hipSuccess)
       break;
     if ((e = hipDeviceSynchronize()) != hipSuccess) break;
@@ -176,57 +219,7 @@ int inc_ctx_tables(const inc_ctx* ctx, float* host_out) {
 }
 
 int inc_simulate_dev(inc_ctx* ctx, const inc_batch* b, const inc_output* out, void* stream, int mode) {
-  if (!ctx || !b || !out) return INC_ERR_ARG;
-  if (mode != INC_MODE_PLAIN && mode != INC_MODE_PERSISTENT) return INC_ERR_ARG;
-  if (b->n < 1 || b->n >= (1ull << 32) || !b->T0) return INC_ERR_ARG;
-  if (!out->res || !out->counters) return INC_ERR_ARG;
-  if (out->sec_capacity && (!out->sec_event || !out->sec_species || !out->sec_stage || !out->sec_T ||
-                            !out->sec_ux || !out->sec_uy || !out->sec_uz))
-    return INC_ERR_ARG;
-  hipStream_t s = (hipStream_t)stream;
-  if (mode == INC_MODE_PLAIN && ctx->mid_cap < b->n) {
-    if (ctx->d_mid) (void)hipFree(ctx->d_mid);
-    ctx->d_mid = nullptr;
-    ctx->mid_cap = 0;
-    hipError_t e = hipMalloc(&ctx->d_mid, sizeof(MidState) * b->n);
-    if (e != hipSuccess) return map_err(e);
-    ctx->mid_cap = b->n;
-  }
-  LaunchDesc L;
-  memset(&L, 0, sizeof(L));
-  L.mode = mode;
-  L.block = ctx->block;
-  L.persistent_blocks = ctx->n_cu * ctx->waves_per_cu / (ctx->block / 64);
-  if (L.persistent_blocks < 1) L.persistent_blocks = 1;
-  L.evap_threshold = ctx->evap_threshold;
-  L.tent_threshold = ctx->tent_threshold;
-  L.kin_threshold = ctx->kin_threshold;
-  L.nuc = ctx->d_nuc;
-  L.n_targets = ctx->n_targets;
-  L.xs = ctx->d_xs;
-  L.bind = ctx->d_B;
-  L.amax = ctx->amax;
-  L.zmax = ctx->zmax;
-  L.evap = ctx->evap;
-  L.opt = ctx->opt;
-  L.fixed_b_set = ctx->fixed_b_set;
-  L.n = b->n;
-  L.tidx = b->target_idx;
-  L.T0 = b->T0;
-  L.seed = b->seed;
-  L.first_id = b->first_event_id;
-  L.res = out->res;
-  L.sec_event = out->sec_event;
-  L.sec_species = out->sec_species;
-  L.sec_stage = out->sec_stage;
-  L.sec_T = out->sec_T;
-  L.sec_ux = out->sec_ux;
-  L.sec_uy = out->sec_uy;
-  L.sec_uz = out->sec_uz;
-  L.sec_capacity = out->sec_capacity;
-  L.counters = out->counters;
-  L.mid = ctx->d_mid;
-  return map_err(inc_launch_events(L, s));
+  return inc_launch_batch(ctx, b, out, (hipStream_t)stream, mode, 0);
 }
 
 int inc_simulate(int target_A, int target_Z, const float* energies, size_t n, uint64_t seed, inc_residual* res,

@@ -1,0 +1,31 @@
+// ctx.h — the context object shared by the C ABI (api.hip) and the serving
+// loop (server.hip): resident tables and launch policy.
+#pragma once
+
+#include "kernels.h"
+
+struct inc_ctx {
+  int device;
+  int n_targets;
+  int AZ[2 * incdev::kMaxTargets];
+  inc_options opt;
+  bool fixed_b_set;
+  incdev::NucTab* d_nuc;
+  incdev::XsTab* d_xs;
+  incdev::MassTab* d_mass;
+  double* d_B;
+  int amax, zmax;
+  incdev::EvapTab evap;
+  incdev::MidState* d_mid;
+  size_t mid_cap;
+  int n_cu;
+  int block, evap_threshold, tent_threshold, kin_threshold, waves_per_cu;
+};
+
+
+// Launch one batch (validated like inc_simulate_dev); max_blocks > 0 caps the
+// persistent grid (small batches use fewer blocks).  Internal to the library.
+__attribute__((visibility("hidden"))) int inc_launch_batch(inc_ctx* ctx, const inc_batch* b,
+                                                           const inc_output* out, hipStream_t s, int mode,
+                                                           int max_blocks);
+__attribute__((visibility("hidden"))) int inc_map_hip_error(hipError_t e);

@@ -55,7 +55,15 @@ struct XsTab {
 struct EvapTab {
   float m[6];
   float a13[6];
+  float lngm[6];   // ln(g_j m_j)
   double B[6];
+};
+
+// Per mass number A = 0..kMaxA: A^(1/3) and ln A (evaporation geometry).
+constexpr int kMaxA = 255;
+struct MassTab {
+  float a13[kMaxA + 1];
+  float lnA[kMaxA + 1];
 };
 
 // Per-call constants shared by the kernels.
@@ -83,8 +91,11 @@ __device__ __forceinline__ void philox4x32_10(uint32_t c0, uint32_t c1, uint32_t
       k0 += 0x9E3779B9u;
       k1 += 0xBB67AE85u;
     }
-    const uint32_t hi0 = __umulhi(0xD2511F53u, c0), lo0 = 0xD2511F53u * c0;
-    const uint32_t hi1 = __umulhi(0xCD9E8D57u, c2), lo1 = 0xCD9E8D57u * c2;
+    // one 32 x 32 -> 64-bit multiply gives both halves of each product
+    const uint64_t p0 = (uint64_t)0xD2511F53u * (uint64_t)c0;
+    const uint64_t p1 = (uint64_t)0xCD9E8D57u * (uint64_t)c2;
+    const uint32_t hi0 = (uint32_t)(p0 >> 32), lo0 = (uint32_t)p0;
+    const uint32_t hi1 = (uint32_t)(p1 >> 32), lo1 = (uint32_t)p1;
     const uint32_t n0 = hi1 ^ c1 ^ k0;
     const uint32_t n2 = hi0 ^ c3 ^ k1;
     c0 = n0;
@@ -189,10 +200,7 @@ struct V3 {
 __device__ __forceinline__ float dot3(V3 a, V3 b) { return a.x * b.x + a.y * b.y + a.z * b.z; }
 __device__ __forceinline__ V3 axpy(float s, V3 a, V3 b) { return {s * a.x + b.x, s * a.y + b.y, s * a.z + b.z}; }
 __device__ __forceinline__ V3 scale(float s, V3 a) { return {s * a.x, s * a.y, s * a.z}; }
-__device__ __forceinline__ V3 unit(V3 a) {
-  const float r = 1.0f / sqrtf(dot3(a, a));
-  return scale(r, a);
-}
+__device__ __forceinline__ V3 unit(V3 a) { return scale(rsqrtf(dot3(a, a)), a); }
 
 // Unit vector at polar angle (cos c, sin s) and azimuth 2 pi u_phi from a.
 __device__ __forceinline__ V3 rotate(V3 a, float c, float s, float u_phi) {
@@ -219,10 +227,12 @@ __device__ __forceinline__ void boost_out(V3 q, float m, V3 u, float g, V3& p, f
 }
 
 // -------------------------------------------------------- cross-sections
+// Table coordinate of p_lab: nodes are equally spaced in log p between kPlo and
+// kPhi; the hardware log2 (about 1 ulp) places p between two nodes.
 __device__ __forceinline__ void xs_coord(float p_GeV, int& k, float& f) {
   const float pc = fminf(fmaxf(p_GeV, kPlo), kPhi);
-  const float scale = (float)(kXsNodes - 1) / logf(kPhi / kPlo);
-  float x = logf(pc * (1.0f / kPlo)) * scale;
+  const float scale = (float)(kXsNodes - 1) / 3.4485086f;  // log2(kPhi / kPlo)
+  float x = __builtin_amdgcn_logf(pc * (1.0f / kPlo)) * scale;
   x = fminf(fmaxf(x, 0.0f), (float)(kXsNodes - 1));
   k = min((int)x, kXsNodes - 2);
   f = x - (float)k;
@@ -288,8 +298,8 @@ __device__ __forceinline__ bool refract(V3& d, V3 n, float T_from, float T_to, f
 // ln I(a, U), I = int_0^U x exp(2 sqrt(a (U - x))) dx
 //   = [e^Y (2Y^2 - 6Y + 6) + Y^2 - 6] / (8 a^2),  Y = 2 sqrt(a U),
 // with the all-positive series (1/4a^2) sum_{n>=4} (n-1)(n-3) Y^n/n! below Y = 2.
-__device__ __forceinline__ float log_width_integral(float a, float U) {
-  const float Y = 2.0f * sqrtf(a * U);
+// a = A_d / 8, so ln(8 a^2) = 2 ln A_d - ln 8 and ln(4 a^2) = 2 ln A_d - ln 16.
+__device__ __forceinline__ float log_width_integral(float Y, float lnAd) {
   if (Y < 2.0f) {
     float term = Y * Y * Y * Y * (1.0f / 24.0f);
     float sum = 0.0f;
@@ -298,10 +308,10 @@ __device__ __forceinline__ float log_width_integral(float a, float U) {
       sum += (float)((n - 1) * (n - 3)) * term;
       term *= Y / (float)(n + 1);
     }
-    return logf(sum) - logf(4.0f * a * a);
+    return logf(sum) - (2.0f * lnAd - 2.7725887f);
   }
   const float k = (2.0f * Y - 6.0f) * Y + 6.0f + expf(-Y) * (Y * Y - 6.0f);
-  return Y + logf(k) - logf(8.0f * a * a);
+  return Y + logf(k) - (2.0f * lnAd - 2.0794415f);
 }
 
 // Kinetic-energy excess x in [0, U] with density ~ x exp(2 sqrt(a (U - x))).

@@ -367,12 +367,12 @@ __device__ __forceinline__ double binding_of(const BindTab& bt, int A, int Z) { 
 
 // EVAP: one evaporation step (Sec. 2.4, Weisskopf-Ewing reading).  Returns true
 // when no channel is open (the nucleus is final).  Draws at most 4 uniforms.
-__device__ __forceinline__ bool evap_step(Nucleus& nu, Rng& rng, const BindTab& bt, const EvapTab& et, Emit& em) {
+__device__ __forceinline__ bool evap_step(Nucleus& nu, Rng& rng, const BindTab& bt, const EvapTab& et,
+                                          const MassTab& mt, Emit& em) {
   em.on = false;
   rng.ensure(4);
   constexpr int fa[6] = {1, 1, 2, 3, 3, 4};
   constexpr int fz[6] = {0, 1, 1, 1, 2, 2};
-  constexpr float fg[6] = {2.0f, 2.0f, 3.0f, 2.0f, 2.0f, 1.0f};
   const double BAZ = binding_of(bt, nu.A, nu.Z);
   float lw[6], U[6], V[6], Y[6];
   float lmax = -INFINITY;
@@ -385,14 +385,16 @@ __device__ __forceinline__ bool evap_step(Nucleus& nu, Rng& rng, const BindTab& 
     const int Ad = nu.A - fa[j], Zd = nu.Z - fz[j];
     if (Ad >= 1 && Zd >= 0 && Zd <= Ad) {
       const float S = (float)(BAZ - binding_of(bt, Ad, Zd) - et.B[j]);
-      const float ad13 = cbrtf((float)Ad);
+      const float ad13 = mt.a13[Ad];
       V[j] = fz[j] ? kE2 * (float)(fz[j] * Zd) / (1.5f * (ad13 + et.a13[j])) : 0.0f;
       U[j] = nu.E - S - V[j];
       if (U[j] > 0.0f) {
         const float a = (float)Ad * 0.125f;
-        const float Rj = j <= 1 ? 1.5f * ad13 : 1.5f * (ad13 + et.a13[j]);
+        const float lnAd = mt.lnA[Ad];
+        // ln R_j^2: R_j = 1.5 A_d^1/3 (n, p) or 1.5 (A_d^1/3 + a_j^1/3)
+        const float lnR2 = j <= 1 ? 0.8109302f + (2.0f / 3.0f) * lnAd : 2.0f * logf(1.5f * (ad13 + et.a13[j]));
         Y[j] = 2.0f * sqrtf(a * U[j]);
-        lw[j] = logf(fg[j] * et.m[j] * Rj * Rj) + log_width_integral(a, U[j]);
+        lw[j] = et.lngm[j] + lnR2 + log_width_integral(Y[j], lnAd);
         lmax = fmaxf(lmax, lw[j]);
       }
     }

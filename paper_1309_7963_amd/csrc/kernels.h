@@ -28,6 +28,7 @@ struct LaunchDesc {
   const NucTab* nuc;
   int n_targets;
   const XsTab* xs;
+  const MassTab* mass;
   const double* bind;
   int amax, zmax;
   EvapTab evap;
@@ -51,5 +52,6 @@ struct LaunchDesc {
 
 size_t inc_lds_bytes(int n_targets, int block, bool with_xs);
 hipError_t inc_launch_setup(const int* d_AZ, int n_targets, incdev::NucTab* d_nuc, incdev::XsTab* d_xs, double* d_B,
-                            int amax, int zmax, incdev::EvapTab* d_evap, const inc_options& o, hipStream_t s);
+                            int amax, int zmax, incdev::EvapTab* d_evap, incdev::MassTab* d_mass, const inc_options& o,
+                            hipStream_t s);
 hipError_t inc_launch_events(const incdev::LaunchDesc& L, hipStream_t s);

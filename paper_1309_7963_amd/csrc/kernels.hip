@@ -29,17 +29,27 @@ __device__ double semf_binding(int A, int Z) {
   return B > 0.0 ? B : 0.0;
 }
 
-__global__ void k_bind_table(double* B, int amax, int zmax, EvapTab* et) {
+// Binding energies B(A, Z) for the evaporation chain, the six fragments'
+// constants (mass, A^1/3, ln(g m) with spin factors g = 2, 2, 3, 2, 2, 1) and
+// the per-A table of A^1/3 and ln A.
+__global__ void k_bind_table(double* B, int amax, int zmax, EvapTab* et, MassTab* mt) {
   const int idx = blockIdx.x * blockDim.x + threadIdx.x;
   const int zs = zmax + 1;
   if (idx < (amax + 1) * zs) B[idx] = semf_binding(idx / zs, idx % zs);
+  if (idx <= kMaxA) {
+    mt->a13[idx] = (float)cbrt((double)idx);
+    mt->lnA[idx] = idx > 0 ? (float)log((double)idx) : 0.0f;
+  }
   if (idx == 0) {
     const int fa[6] = {1, 1, 2, 3, 3, 4}, fz[6] = {0, 1, 1, 1, 2, 2};
+    const double g[6] = {2.0, 2.0, 3.0, 2.0, 2.0, 1.0};
     for (int j = 0; j < 6; ++j) {
       const double b = semf_binding(fa[j], fz[j]);
+      const double m = (double)fz[j] * kMassP + (double)(fa[j] - fz[j]) * kMassN - b;
       et->B[j] = b;
-      et->m[j] = (float)((double)fz[j] * kMassP + (double)(fa[j] - fz[j]) * kMassN - b);
+      et->m[j] = (float)m;
       et->a13[j] = (float)cbrt((double)fa[j]);
+      et->lngm[j] = (float)log(g[j] * m);
     }
   }
 }
@@ -182,6 +192,7 @@ struct KernelArgs {
   const NucTab* nuc;
   int n_targets;
   const XsTab* xs;
+  const MassTab* mass;
   BindTab bind;
   EvapTab evap;
   Opts opt;
@@ -197,16 +208,24 @@ struct KernelArgs {
 
 __device__ __forceinline__ bool energy_ok(float T0) { return T0 >= 20.0f && T0 <= 250.0f; }
 
-__device__ __forceinline__ void stage_tables(char* lds, const KernelArgs& a, bool with_xs) {
-  const int nw = a.n_targets * (int)(sizeof(NucTab) / 4);
+// LDS layout of the event kernels: [n_targets NucTab][XsTab][MassTab][writer
+// buffers of the block's waves].  The plain evaporation kernel stages only the
+// MassTab (n_targets = 0, no XsTab).
+__device__ __forceinline__ size_t lds_mass_offset(int n_targets, bool with_xs) {
+  return (size_t)n_targets * sizeof(NucTab) + (with_xs ? sizeof(XsTab) : 0);
+}
+__device__ __forceinline__ void stage_tables(char* lds, const KernelArgs& a, int n_targets, bool with_xs) {
   uint32_t* dst = (uint32_t*)lds;
   const uint32_t* src = (const uint32_t*)a.nuc;
-  for (int i = threadIdx.x; i < nw; i += blockDim.x) dst[i] = src[i];
+  for (int i = threadIdx.x; i < n_targets * (int)(sizeof(NucTab) / 4); i += blockDim.x) dst[i] = src[i];
   if (with_xs) {
-    uint32_t* dx = (uint32_t*)(lds + a.n_targets * sizeof(NucTab));
+    uint32_t* dx = (uint32_t*)(lds + n_targets * sizeof(NucTab));
     const uint32_t* sx = (const uint32_t*)a.xs;
     for (int i = threadIdx.x; i < (int)(sizeof(XsTab) / 4); i += blockDim.x) dx[i] = sx[i];
   }
+  uint32_t* dm = (uint32_t*)(lds + lds_mass_offset(n_targets, with_xs));
+  const uint32_t* sm = (const uint32_t*)a.mass;
+  for (int i = threadIdx.x; i < (int)(sizeof(MassTab) / 4); i += blockDim.x) dm[i] = sm[i];
   __syncthreads();
 }
 
@@ -233,10 +252,11 @@ __device__ __forceinline__ void write_residual(inc_residual* r, const Nucleus& n
 // the escaping particles through the compacted writer.
 __global__ void __launch_bounds__(256) k_cascade_plain(KernelArgs a) {
   extern __shared__ __align__(16) char lds[];
-  stage_tables(lds, a, true);
+  stage_tables(lds, a, a.n_targets, true);
   const NucTab* snt = (const NucTab*)lds;
   const XsTab& sxs = *(const XsTab*)(lds + a.n_targets * sizeof(NucTab));
-  uint32_t* wbuf = (uint32_t*)(lds + a.n_targets * sizeof(NucTab) + sizeof(XsTab)) +
+  const MassTab& smt = *(const MassTab*)(lds + lds_mass_offset(a.n_targets, true));
+  uint32_t* wbuf = (uint32_t*)(lds + lds_mass_offset(a.n_targets, true) + sizeof(MassTab)) +
                    (threadIdx.x / 64) * (kWriterCap * kRecWords);
   int fill = 0;
 
@@ -297,7 +317,9 @@ __global__ void __launch_bounds__(256) k_cascade_plain(KernelArgs a) {
 // random stream continued after the cascade's draws.
 __global__ void __launch_bounds__(256) k_evap_plain(KernelArgs a) {
   extern __shared__ __align__(16) char lds[];
-  uint32_t* wbuf = (uint32_t*)lds + (threadIdx.x / 64) * (kWriterCap * kRecWords);
+  stage_tables(lds, a, 0, false);
+  const MassTab& smt = *(const MassTab*)lds;
+  uint32_t* wbuf = (uint32_t*)(lds + sizeof(MassTab)) + (threadIdx.x / 64) * (kWriterCap * kRecWords);
   int fill = 0;
   const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
   bool live = i < a.n;
@@ -331,7 +353,7 @@ __global__ void __launch_bounds__(256) k_evap_plain(KernelArgs a) {
     Emit em;
     em.on = false;
     if (live) {
-      if (evap_step(nu, rng, a.bind, a.evap, em)) {
+      if (evap_step(nu, rng, a.bind, a.evap, smt, em)) {
         write_residual(&a.res[i], nu, m.E, nsec, flags, m.ncoll, m.nretry);
         live = false;
       } else {
@@ -355,10 +377,11 @@ constexpr int kChunk = 64;
 
 __global__ void __launch_bounds__(256) k_persistent(KernelArgs a) {
   extern __shared__ __align__(16) char lds[];
-  stage_tables(lds, a, true);
+  stage_tables(lds, a, a.n_targets, true);
   const NucTab* snt = (const NucTab*)lds;
   const XsTab& sxs = *(const XsTab*)(lds + a.n_targets * sizeof(NucTab));
-  uint32_t* wbuf = (uint32_t*)(lds + a.n_targets * sizeof(NucTab) + sizeof(XsTab)) +
+  const MassTab& smt = *(const MassTab*)(lds + lds_mass_offset(a.n_targets, true));
+  uint32_t* wbuf = (uint32_t*)(lds + lds_mass_offset(a.n_targets, true) + sizeof(MassTab)) +
                    (threadIdx.x / 64) * (kWriterCap * kRecWords);
   int fill = 0;
 
@@ -433,7 +456,7 @@ __global__ void __launch_bounds__(256) k_persistent(KernelArgs a) {
     em.on = false;
     if (run == kStEvap) {
       if (st == kStEvap) {
-        if (evap_step(nu, rng, a.bind, a.evap, em)) {
+        if (evap_step(nu, rng, a.bind, a.evap, smt, em)) {
           write_residual(&a.res[ev], nu, Ex_casc, nsec, c.flags, c.ncoll, c.nretry);
           if (c.flags) atomicAdd(&a.counters[1], 1ull);
           st = kStDone;
@@ -474,17 +497,17 @@ __global__ void __launch_bounds__(256) k_persistent(KernelArgs a) {
 using namespace incdev;
 
 size_t inc_lds_bytes(int n_targets, int block, bool with_xs) {
-  return (size_t)n_targets * sizeof(NucTab) + (with_xs ? sizeof(XsTab) : 0) +
+  return (size_t)n_targets * sizeof(NucTab) + (with_xs ? sizeof(XsTab) : 0) + sizeof(MassTab) +
          (size_t)(block / 64) * kWriterCap * kRecWords * sizeof(uint32_t);
 }
 
 hipError_t inc_launch_setup(const int* d_AZ, int n_targets, NucTab* d_nuc, XsTab* d_xs, double* d_B, int amax,
-                            int zmax, EvapTab* d_evap, const inc_options& o, hipStream_t s) {
+                            int zmax, EvapTab* d_evap, MassTab* d_mass, const inc_options& o, hipStream_t s) {
   hipLaunchKernelGGL(k_nucleus_setup, dim3(n_targets), dim3(64), 0, s, d_AZ, d_nuc, o.uniform_density, o.zero_fermi,
                      o.zero_binding);
   hipLaunchKernelGGL(k_xs_table, dim3(1), dim3(kXsNodes), 0, s, d_xs, o.const_sigma_mb);
-  const int cells = (amax + 1) * (zmax + 1);
-  hipLaunchKernelGGL(k_bind_table, dim3((cells + 255) / 256), dim3(256), 0, s, d_B, amax, zmax, d_evap);
+  const int cells = (amax + 1) * (zmax + 1) > kMaxA + 1 ? (amax + 1) * (zmax + 1) : kMaxA + 1;
+  hipLaunchKernelGGL(k_bind_table, dim3((cells + 255) / 256), dim3(256), 0, s, d_B, amax, zmax, d_evap, d_mass);
   return hipGetLastError();
 }
 
@@ -493,6 +516,7 @@ hipError_t inc_launch_events(const LaunchDesc& L, hipStream_t s) {
   a.nuc = L.nuc;
   a.n_targets = L.n_targets;
   a.xs = L.xs;
+  a.mass = L.mass;
   a.bind = {L.bind, L.zmax + 1, L.amax, L.zmax};
   a.evap = L.evap;
   a.opt.no_pauli = L.opt.no_pauli;

@@ -212,3 +212,93 @@ def test_invalid_arguments():
         inc.Context([(300, 100)])
     with pytest.raises(inc.IncError):
         inc.Context([(16, 8)], block_size=100)
+
+
+# ------------------------------------------------------------------- serving
+def _serving_requests(k, seed=31):
+    rng = np.random.default_rng(seed)
+    out = []
+    for r in range(k):
+        n = int(10 ** rng.uniform(3, 4.3))
+        tidx = rng.choice(5, size=n, p=TISSUE_W).astype(np.uint8)
+        hi = rng.random(n) < 0.85
+        T0 = np.where(hi, rng.uniform(150, 250, n), rng.uniform(20, 150, n)).astype(np.float32)
+        out.append(dict(T0=T0, target_idx=tidx, seed=5, first_event_id=r << 32))
+    return out
+
+
+def test_serving_result_same_alone_and_in_the_mix():
+    import paper_1309_7963_amd as inc
+
+    ctx = inc.Context(TISSUE)
+    srv = inc.Server(ctx, hbm_budget=256 << 20, max_slots=4)
+    reqs = _serving_requests(12)
+    tickets = []
+    pending = list(range(len(reqs)))
+    results = {}
+    while pending or tickets:
+        while pending:
+            q = reqs[pending[0]]
+            t = srv.submit(q["T0"], seed=q["seed"], target_idx=q["target_idx"], first_event_id=q["first_event_id"])
+            if t is None:
+                break
+            tickets.append((pending.pop(0), t))
+        for k, t in list(tickets):
+            if srv.poll(t):
+                results[k] = srv.fetch(t)
+                tickets.remove((k, t))
+    st = srv.stats()
+    assert st["completed"] == len(reqs) and st["in_flight"] == 0
+    for k, q in enumerate(reqs):
+        alone = run_gpu(TISSUE, q["T0"], seed=q["seed"], tidx=q["target_idx"], first_id=q["first_event_id"], ctx=ctx)
+        mix = results[k]
+        assert mix["rc"] == 0
+        assert mix["res"].tobytes() == alone["res"].tobytes(), k
+        assert mix["n_sec_total"] == alone["n_sec_total"]
+        ka = np.lexsort((alone["sec_T"], alone["sec_event"]))
+        km = np.lexsort((mix["sec_T"], mix["sec_event"]))
+        for f in ("sec_event", "sec_species", "sec_stage", "sec_T", "sec_u"):
+            assert np.array_equal(alone[f][ka], mix[f][km]), (k, f)
+    srv.close()
+
+
+def test_serving_admission_by_budget():
+    import paper_1309_7963_amd as inc
+
+    ctx = inc.Context(TISSUE)
+    srv = inc.Server(ctx, hbm_budget=4 << 20, max_slots=8)
+    big = np.full(200000, 200.0, np.float32)
+    with pytest.raises(inc.IncError) as e:
+        srv.submit(big, seed=1)
+    assert e.value.code == inc.INC_ERR_ARG
+    small = np.full(6000, 200.0, np.float32)
+    t1 = srv.submit(small, seed=1)
+    assert t1 is not None
+    admitted = [t1]
+    while True:
+        t = srv.submit(small, seed=1, first_event_id=len(admitted) << 32)
+        if t is None:
+            break
+        admitted.append(t)
+    assert 1 <= len(admitted) < 8
+    assert srv.stats()["rejected_busy"] >= 1
+    for t in admitted:
+        srv.wait(t)
+        r = srv.fetch(t)
+        assert r["rc"] == 0
+    assert srv.submit(small, seed=1) is not None
+    srv.close()
+
+
+def test_serving_replay_latencies():
+    import paper_1309_7963_amd as inc
+
+    ctx = inc.Context(TISSUE)
+    srv = inc.Server(ctx, hbm_budget=512 << 20, max_slots=4)
+    reqs = _serving_requests(40, seed=8)
+    arrivals = np.cumsum(np.random.default_rng(2).exponential(0.002, len(reqs)))
+    lat, span = srv.replay(arrivals, reqs)
+    assert np.all(lat > 0) and np.isfinite(lat).all()
+    assert span > 0
+    assert srv.stats()["completed"] == len(reqs)
+    srv.close()
