@@ -154,12 +154,16 @@ int inc_simulate(int target_A, int target_Z, const float* energies_MeV, size_t n
 
 /* ------------------------------------------------------------- serving
  * Continuous batching of event batches arriving from a transport stepper.
- * A request is admitted when one of max_slots slots (HIP streams of the
- * server) is free and its buffers (inputs, residuals, secondaries) fit in the
- * HBM budget; it runs as its own persistent-kernel launch, overlapping with
- * the requests already on the device.  Tables stay resident in the context;
- * a request's results depend only on (seed, first_event_id + i, target, T0),
- * so they are the same alone and in the mix.  Not thread-safe. */
+ * A request is admitted when its buffers (inputs, residuals, secondaries) fit
+ * in the HBM budget not yet promised to admitted requests, and queues.
+ * Whenever one of max_slots slots (HIP streams of the server) is free, the
+ * queued requests sharing the head's seed are launched together as one
+ * persistent-kernel launch in which every request keeps its own event ids and
+ * output buffers; launches on different slots overlap on the device.  Tables
+ * stay resident in the context; a request's results depend only on (seed,
+ * first_event_id + i, target, T0), so they are the same alone and in the mix.
+ * Progress is made inside the server calls (submit, poll, wait, fetch,
+ * replay).  Not thread-safe. */
 typedef struct inc_server inc_server;
 
 typedef struct {            /* one request; all pointers are host memory     */
@@ -192,8 +196,9 @@ typedef struct {
  * server also pins the same amount of host memory); max_slots 1..16. */
 int inc_server_create(inc_ctx* ctx, size_t hbm_budget, int max_slots, inc_server** out);
 int inc_server_destroy(inc_server* server);
-/* Admit a request or return INC_ERR_BUSY (retry later); INC_ERR_ARG if it can
- * never fit the budget.  On success *ticket identifies it. */
+/* Admit a request (its arrays are copied) or return INC_ERR_BUSY (retry
+ * after fetching finished requests); INC_ERR_ARG if it can never fit the
+ * budget.  On success *ticket identifies it. */
 int inc_server_submit(inc_server* server, const inc_request* req, uint64_t* ticket);
 /* 1 = results ready on the host, 0 = still running, < 0 error. */
 int inc_server_poll(inc_server* server, uint64_t ticket);
@@ -205,9 +210,9 @@ int inc_server_fetch(inc_server* server, uint64_t ticket, const inc_host_output*
 int inc_server_stats_get(inc_server* server, inc_server_stats* out);
 /* Native request loop: request k arrives arrival_s[k] seconds (ascending)
  * after the call starts; requests are admitted first come first served as
- * slots and memory free up, polled, fetched and discarded.  latency_s[k]
- * receives arrival -> results on host; *span_s the time from the first
- * arrival to the last completion. */
+ * memory frees up, batched into launches as slots free up, polled, fetched
+ * and discarded.  latency_s[k] receives arrival -> results on host; *span_s
+ * the time from the first arrival to the last completion. */
 int inc_server_replay(inc_server* server, int n_req, const double* arrival_s, const inc_request* reqs,
                       double* latency_s, double* span_s);
 

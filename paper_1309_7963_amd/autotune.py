@@ -1,0 +1,113 @@
+"""Autotuner for the persistent kernel's launch policy.
+
+Sweeps the launch options that set how a wave keeps its lanes busy:
+block size (waves per workgroup), resident waves per CU (events in flight)
+and the per-state lane thresholds of the wave scheduler (how many lanes must
+wait in the tentative-collision, kinematics or evaporation state before the
+wave runs that state).  Each candidate is timed on the caller's workload with
+HIP events (a warm-up launch, then the median of `repeats` launches); the
+best is cached in a JSON file keyed by GPU architecture and workload
+signature (targets, energy range), so later contexts can reuse it.
+
+    from paper_1309_7963_amd import autotune
+    best = autotune.tune([(16, 8), (40, 20)], T0, tidx)
+    ctx = paper_1309_7963_amd.Context(targets, **best["options"])
+"""
+from __future__ import annotations
+
+import json
+import os
+import time
+from typing import Optional
+
+import numpy as np
+
+DEFAULT_GRID = {
+    "block_size": (128, 256),
+    "waves_per_cu": (8, 12),
+    "thresholds": ((16, 8, 16), (12, 8, 12), (16, 4, 16), (24, 8, 16), (16, 8, 24), (8, 8, 8), (16, 12, 16)),
+}
+
+
+def cache_path() -> str:
+    base = os.environ.get("XDG_CACHE_HOME") or os.path.join(os.path.expanduser("~"), ".cache")
+    return os.path.join(base, "paper_1309_7963_amd", "autotune.json")
+
+
+def signature(targets, T0) -> str:
+    t = ",".join("%d-%d" % (a, z) for a, z in sorted(set(map(tuple, targets))))
+    lo, hi = float(np.min(T0)), float(np.max(T0))
+    return "%s|%d-%d" % (t, int(lo // 10) * 10, int(np.ceil(hi / 10)) * 10)
+
+
+def _arch() -> str:
+    import torch
+
+    return torch.cuda.get_device_properties(0).gcnArchName.split(":")[0]
+
+
+def _time(targets, T0_d, tidx_d, opts, repeats):
+    import torch
+
+    import paper_1309_7963_amd as inc
+
+    ctx = inc.Context(targets, **opts)
+    n = int(T0_d.shape[0])
+    out = inc.DeviceOutput.allocate(n, ctx.default_capacity(n))
+    stream = torch.cuda.current_stream()
+    ctx.simulate(T0_d, seed=1, target_idx=tidx_d, out=out)
+    times = []
+    for k in range(repeats):
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record(stream)
+        ctx.simulate(T0_d, seed=1, target_idx=tidx_d, out=out, first_event_id=(k + 1) * n)
+        b.record(stream)
+        torch.cuda.synchronize()
+        times.append(a.elapsed_time(b))
+    ctx.close()
+    return float(np.median(times))
+
+
+def tune(targets, T0, tidx=None, grid: Optional[dict] = None, repeats: int = 3, use_cache: bool = True,
+         verbose: bool = False) -> dict:
+    """Return {"options": {...}, "ms": best, "table": [...]} for the workload
+    (T0: host float32 array, tidx: host uint8 array or None)."""
+    import torch
+
+    grid = grid or DEFAULT_GRID
+    key = "%s|%s|%d" % (_arch(), signature(targets, T0), len(T0))
+    path = cache_path()
+    cache = {}
+    if use_cache and os.path.exists(path):
+        try:
+            with open(path) as f:
+                cache = json.load(f)
+        except (OSError, ValueError):
+            cache = {}
+        if key in cache:
+            return cache[key]
+    T0_d = torch.as_tensor(np.asarray(T0, dtype=np.float32), device="cuda")
+    tidx_d = None if tidx is None else torch.as_tensor(np.asarray(tidx, dtype=np.uint8), device="cuda")
+    table = []
+    t0 = time.perf_counter()
+    for bs in grid["block_size"]:
+        for w in grid["waves_per_cu"]:
+            for kin, tent, evap in grid["thresholds"]:
+                opts = dict(block_size=bs, waves_per_cu=w, kin_threshold=kin, tent_threshold=tent,
+                            evap_threshold=evap)
+                ms = _time(targets, T0_d, tidx_d, opts, repeats)
+                table.append(dict(options=opts, ms=ms))
+                if verbose:
+                    print("autotune", opts, "%.3f ms" % ms, flush=True)
+    best = min(table, key=lambda r: r["ms"])
+    result = {"options": best["options"], "ms": best["ms"], "events": int(len(T0)),
+              "sweep_s": time.perf_counter() - t0, "table": table}
+    if use_cache:
+        cache[key] = result
+        try:
+            os.makedirs(os.path.dirname(path), exist_ok=True)
+            with open(path, "w") as f:
+                json.dump(cache, f, indent=1)
+        except OSError:
+            pass
+    return result

@@ -38,26 +38,21 @@ void release(inc_ctx* c) {
   if (c->d_mass) (void)hipFree(c->d_mass);
   if (c->d_B) (void)hipFree(c->d_B);
   if (c->d_mid) (void)hipFree(c->d_mid);
+  if (c->d_segs) (void)hipFree(c->d_segs);
   delete c;
 }
 
 }  // namespace
 
-int inc_launch_batch(inc_ctx* ctx, const inc_batch* b, const inc_output* out, hipStream_t s, int mode, int max_blocks) {
-  if (!ctx || !b || !out) return INC_ERR_ARG;
-  if (mode != INC_MODE_PLAIN && mode != INC_MODE_PERSISTENT) return INC_ERR_ARG;
-  if (b->n < 1 || b->n >= (1ull << 32) || !b->T0) return INC_ERR_ARG;
-  if (!out->res || !out->counters) return INC_ERR_ARG;
-  if (out->sec_capacity && (!out->sec_event || !out->sec_species || !out->sec_stage || !out->sec_T ||
-                            !out->sec_ux || !out->sec_uy || !out->sec_uz))
-    return INC_ERR_ARG;
-  if (mode == INC_MODE_PLAIN && ctx->mid_cap < b->n) {
+int inc_launch_segments(inc_ctx* ctx, size_t n, const uint8_t* tidx, const float* T0, const Segment* d_segs,
+                        int n_seg, unsigned long long* queue, hipStream_t s, int mode, int max_blocks) {
+  if (mode == INC_MODE_PLAIN && ctx->mid_cap < n) {
     if (ctx->d_mid) (void)hipFree(ctx->d_mid);
     ctx->d_mid = nullptr;
     ctx->mid_cap = 0;
-    hipError_t e = hipMalloc(&ctx->d_mid, sizeof(MidState) * b->n);
+    hipError_t e = hipMalloc(&ctx->d_mid, sizeof(MidState) * n);
     if (e != hipSuccess) return map_err(e);
-    ctx->mid_cap = b->n;
+    ctx->mid_cap = n;
   }
   LaunchDesc L;
   memset(&L, 0, sizeof(L));
@@ -79,23 +74,43 @@ int inc_launch_batch(inc_ctx* ctx, const inc_batch* b, const inc_output* out, hi
   L.evap = ctx->evap;
   L.opt = ctx->opt;
   L.fixed_b_set = ctx->fixed_b_set;
-  L.n = b->n;
-  L.tidx = b->target_idx;
-  L.T0 = b->T0;
-  L.seed = b->seed;
-  L.first_id = b->first_event_id;
-  L.res = out->res;
-  L.sec_event = out->sec_event;
-  L.sec_species = out->sec_species;
-  L.sec_stage = out->sec_stage;
-  L.sec_T = out->sec_T;
-  L.sec_ux = out->sec_ux;
-  L.sec_uy = out->sec_uy;
-  L.sec_uz = out->sec_uz;
-  L.sec_capacity = out->sec_capacity;
-  L.counters = out->counters;
+  L.n = n;
+  L.tidx = tidx;
+  L.T0 = T0;
+  L.segs = d_segs;
+  L.n_seg = n_seg;
+  L.queue = queue;
   L.mid = ctx->d_mid;
   return map_err(inc_launch_events(L, s));
+}
+
+int inc_launch_batch(inc_ctx* ctx, const inc_batch* b, const inc_output* out, hipStream_t s, int mode, int max_blocks) {
+  if (!ctx || !b || !out) return INC_ERR_ARG;
+  if (mode != INC_MODE_PLAIN && mode != INC_MODE_PERSISTENT) return INC_ERR_ARG;
+  if (b->n < 1 || b->n >= (1ull << 32) || !b->T0) return INC_ERR_ARG;
+  if (!out->res || !out->counters) return INC_ERR_ARG;
+  if (out->sec_capacity && (!out->sec_event || !out->sec_species || !out->sec_stage || !out->sec_T ||
+                            !out->sec_ux || !out->sec_uy || !out->sec_uz))
+    return INC_ERR_ARG;
+  Segment seg;
+  seg.start = 0;
+  seg.n = (uint32_t)b->n;
+  seg.seed = b->seed;
+  seg.first_id = b->first_event_id;
+  seg.res = out->res;
+  seg.ev = out->sec_event;
+  seg.species = out->sec_species;
+  seg.stage = out->sec_stage;
+  seg.T = out->sec_T;
+  seg.ux = out->sec_ux;
+  seg.uy = out->sec_uy;
+  seg.uz = out->sec_uz;
+  seg.cap = out->sec_capacity;
+  seg.counters = out->counters;
+  Segment* slot = ctx->d_segs + (ctx->seg_next++ % kSegSlots);
+  const int rc = map_err(inc_upload_segment(seg, slot, s));
+  if (rc) return rc;
+  return inc_launch_segments(ctx, b->n, b->target_idx, b->T0, slot, 1, out->counters + 2, s, mode, max_blocks);
 }
 
 int inc_map_hip_error(hipError_t e) { return map_err(e); }
@@ -169,6 +184,7 @@ int inc_ctx_create(const inc_nucleus* targets, int n_targets, const inc_options*
     if ((e = hipMalloc(&c->d_nuc, sizeof(NucTab) * n_targets)) != hipSuccess) break;
     if ((e = hipMalloc(&c->d_xs, sizeof(XsTab))) != hipSuccess) break;
     if ((e = hipMalloc(&c->d_mass, sizeof(MassTab))) != hipSuccess) break;
+    if ((e = hipMalloc(&c->d_segs, sizeof(Segment) * kSegSlots)) != hipSuccess) break;
     if ((e = hipMalloc(&c->d_B, sizeof(double) * (amax + 1) * (zmax + 1))) != hipSuccess) break;
     if ((e = hipMalloc(&d_AZ, sizeof(int) * 2 * n_targets)) != hipSuccess) break;
     if ((e = hipMalloc(&d_evap, sizeof(EvapTab))) != hipSuccess) break;

@@ -18,10 +18,21 @@ struct inc_ctx {
   incdev::EvapTab evap;
   incdev::MidState* d_mid;
   size_t mid_cap;
+  incdev::Segment* d_segs;  // kSegSlots single-segment descriptors, used in turn
+  unsigned seg_next;
   int n_cu;
   int block, evap_threshold, tent_threshold, kin_threshold, waves_per_cu;
 };
 
+
+constexpr int kSegSlots = 64;  // inc_simulate_dev calls that may be in flight per context
+
+// Launch n events described by n_seg device segments (sorted by start, each
+// with its own key, ids and outputs); queue: device work-queue counter.
+__attribute__((visibility("hidden"))) int inc_launch_segments(inc_ctx* ctx, size_t n, const uint8_t* tidx,
+                                                              const float* T0, const incdev::Segment* d_segs,
+                                                              int n_seg, unsigned long long* queue, hipStream_t s,
+                                                              int mode, int max_blocks);
 
 // Launch one batch (validated like inc_simulate_dev); max_blocks > 0 caps the
 // persistent grid (small batches use fewer blocks).  Internal to the library.

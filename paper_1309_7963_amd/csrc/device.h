@@ -8,6 +8,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include "../../include/inc.h"
+
 namespace incdev {
 
 constexpr int kShells = 15;
@@ -368,9 +370,17 @@ __device__ __forceinline__ float spectrum_sample_s(float Y, float u) {
 // wave reserves space with one global atomic and all 64 lanes copy the
 // buffer out contiguously into the SoA arrays.
 constexpr int kWriterCap = 128;  // records per wave buffer
-constexpr int kRecWords = 6;     // event, species | stage << 8, T, ux, uy, uz
+constexpr int kRecWords = 6;     // event, species | stage << 8 | segment << 16, T, ux, uy, uz
 
-struct OutPtrs {
+// One segment of a launch: a request with its own random-stream key, event
+// ids and output buffers.  Event i of the launch with start <= i < start + n
+// belongs to the segment, has id first_id + (i - start) and writes its
+// residual to res[i - start] and its secondaries to the segment's arrays
+// (records hold i - start).  counters: [0] secondaries produced, [1] flagged.
+struct Segment {
+  uint32_t start, n;
+  uint64_t seed, first_id;
+  inc_residual* res;
   uint32_t* ev;
   uint8_t* species;
   uint8_t* stage;
@@ -378,8 +388,8 @@ struct OutPtrs {
   float* ux;
   float* uy;
   float* uz;
-  unsigned long long* counter;
   unsigned long long cap;
+  unsigned long long* counters;
 };
 
 __device__ __forceinline__ int lane_id() { return __lane_id(); }
@@ -388,37 +398,63 @@ __device__ __forceinline__ uint32_t rank_in(uint64_t mask) {
   return __builtin_amdgcn_mbcnt_hi((uint32_t)(mask >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)mask, 0u));
 }
 
-// Must be called by all lanes of the wave.
-__device__ __forceinline__ void writer_flush(uint32_t* buf, int& fill, const OutPtrs& o) {
+// Segment holding launch event i (segments are sorted by start).
+__device__ __forceinline__ int segment_of(const Segment* segs, int n_seg, uint32_t i) {
+  int lo = 0, hi = n_seg - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (segs[mid].start <= i) lo = mid; else hi = mid - 1;
+  }
+  return lo;
+}
+
+// Must be called by all lanes of the wave.  The wave's records are copied out
+// 64 at a time; within a group of 64 the lanes of each distinct segment
+// reserve their slots with one atomic and store contiguously.
+__device__ __forceinline__ void writer_flush(uint32_t* buf, int& fill, const Segment* segs) {
   if (fill == 0) return;
   __builtin_amdgcn_wave_barrier();
-  unsigned long long base = 0;
-  if (lane_id() == 0) base = atomicAdd(o.counter, (unsigned long long)fill);
-  base = __shfl(base, 0);
-  for (int i = lane_id(); i < fill; i += 64) {
-    const unsigned long long k = base + (unsigned long long)i;
-    if (k < o.cap) {
-      const uint32_t* r = buf + i * kRecWords;
-      o.ev[k] = r[0];
-      o.species[k] = (uint8_t)(r[1] & 0xFFu);
-      o.stage[k] = (uint8_t)(r[1] >> 8);
-      o.T[k] = __uint_as_float(r[2]);
-      o.ux[k] = __uint_as_float(r[3]);
-      o.uy[k] = __uint_as_float(r[4]);
-      o.uz[k] = __uint_as_float(r[5]);
+  for (int g = 0; g < fill; g += 64) {
+    const int i = g + lane_id();
+    const bool have = i < fill;
+    const uint32_t* r = buf + (have ? i : 0) * kRecWords;
+    const int seg = have ? (int)(r[1] >> 16) : -1;
+    uint64_t todo = __ballot(have);
+    while (todo) {
+      const int lead = __ffsll((unsigned long long)todo) - 1;
+      const int s0 = __shfl(seg, lead);
+      const uint64_t m = __ballot(have && seg == s0);
+      unsigned long long base = 0;
+      if (lane_id() == lead) base = atomicAdd(&segs[s0].counters[0], (unsigned long long)__popcll(m));
+      base = __shfl(base, lead);
+      if (have && seg == s0) {
+        const Segment& S = segs[s0];
+        const unsigned long long k = base + rank_in(m);
+        if (k < S.cap) {
+          S.ev[k] = r[0];
+          S.species[k] = (uint8_t)(r[1] & 0xFFu);
+          S.stage[k] = (uint8_t)((r[1] >> 8) & 0xFFu);
+          S.T[k] = __uint_as_float(r[2]);
+          S.ux[k] = __uint_as_float(r[3]);
+          S.uy[k] = __uint_as_float(r[4]);
+          S.uz[k] = __uint_as_float(r[5]);
+        }
+      }
+      todo &= ~m;
     }
   }
   __builtin_amdgcn_wave_barrier();
   fill = 0;
 }
 
-// Must be called by all lanes of the wave.
-__device__ __forceinline__ void writer_append(uint32_t* buf, int& fill, const OutPtrs& o, bool emit, uint32_t ev,
+// Must be called by all lanes of the wave.  ev: index of the event in its
+// segment; kind: species | stage << 8 | segment << 16.
+__device__ __forceinline__ void writer_append(uint32_t* buf, int& fill, const Segment* segs, bool emit, uint32_t ev,
                                               uint32_t kind, float T, V3 u) {
   const uint64_t m = __ballot(emit);
   if (m == 0) return;
   const int cnt = __popcll(m);
-  if (fill + cnt > kWriterCap) writer_flush(buf, fill, o);
+  if (fill + cnt > kWriterCap) writer_flush(buf, fill, segs);
   if (emit) {
     uint32_t* r = buf + (fill + (int)rank_in(m)) * kRecWords;
     r[0] = ev;

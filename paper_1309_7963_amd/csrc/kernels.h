@@ -37,14 +37,9 @@ struct LaunchDesc {
   size_t n;
   const uint8_t* tidx;
   const float* T0;
-  uint64_t seed, first_id;
-  inc_residual* res;
-  uint32_t* sec_event;
-  uint8_t* sec_species;
-  uint8_t* sec_stage;
-  float *sec_T, *sec_ux, *sec_uy, *sec_uz;
-  size_t sec_capacity;
-  unsigned long long* counters;
+  const Segment* segs;   // device
+  int n_seg;
+  unsigned long long* queue;
   MidState* mid;
 };
 
@@ -55,3 +50,4 @@ hipError_t inc_launch_setup(const int* d_AZ, int n_targets, incdev::NucTab* d_nu
                             int amax, int zmax, incdev::EvapTab* d_evap, incdev::MassTab* d_mass, const inc_options& o,
                             hipStream_t s);
 hipError_t inc_launch_events(const incdev::LaunchDesc& L, hipStream_t s);
+hipError_t inc_upload_segment(const incdev::Segment& seg, incdev::Segment* d_slot, hipStream_t s);

@@ -196,14 +196,13 @@ struct KernelArgs {
   BindTab bind;
   EvapTab evap;
   Opts opt;
-  size_t n;
-  const uint8_t* tidx;
+  size_t n;                  // events in the launch
+  const uint8_t* tidx;       // launch inputs (NULL: target 0)
   const float* T0;
-  uint64_t seed, first_id;
-  inc_residual* res;
-  OutPtrs out;
-  unsigned long long* counters;
-  MidState* mid;
+  const Segment* segs;       // requests of the launch, sorted by start
+  int n_seg;
+  unsigned long long* queue; // work-queue head (persistent kernel)
+  MidState* mid;             // plain kernels: cascade -> evaporation hand-over
 };
 
 __device__ __forceinline__ bool energy_ok(float T0) { return T0 >= 20.0f && T0 <= 250.0f; }
@@ -246,6 +245,22 @@ __device__ __forceinline__ void write_residual(inc_residual* r, const Nucleus& n
   *r = v;
 }
 
+// Where event i of the launch belongs: its segment, index in the segment.
+struct EventRef {
+  int seg;
+  uint32_t local;
+};
+__device__ __forceinline__ EventRef event_ref(const KernelArgs& a, size_t i) {
+  EventRef e;
+  e.seg = a.n_seg == 1 ? 0 : segment_of(a.segs, a.n_seg, (uint32_t)i);
+  e.local = (uint32_t)i - a.segs[e.seg].start;
+  return e;
+}
+__device__ __forceinline__ void init_stream(Rng& rng, const KernelArgs& a, EventRef e) {
+  rng.init(a.segs[e.seg].seed, a.segs[e.seg].first_id + e.local);
+}
+__device__ __forceinline__ uint32_t kind_of(uint32_t k, EventRef e) { return k | ((uint32_t)e.seg << 16); }
+
 // Plain cascade kernel: one event per thread (Sec. 3.2).  Each iteration of
 // the wave loop advances every live lane by one flight segment together with
 // the tentative collision and kinematics it may end in, then the wave writes
@@ -255,7 +270,6 @@ __global__ void __launch_bounds__(256) k_cascade_plain(KernelArgs a) {
   stage_tables(lds, a, a.n_targets, true);
   const NucTab* snt = (const NucTab*)lds;
   const XsTab& sxs = *(const XsTab*)(lds + a.n_targets * sizeof(NucTab));
-  const MassTab& smt = *(const MassTab*)(lds + lds_mass_offset(a.n_targets, true));
   uint32_t* wbuf = (uint32_t*)(lds + lds_mass_offset(a.n_targets, true) + sizeof(MassTab)) +
                    (threadIdx.x / 64) * (kWriterCap * kRecWords);
   int fill = 0;
@@ -264,21 +278,23 @@ __global__ void __launch_bounds__(256) k_cascade_plain(KernelArgs a) {
   bool live = i < a.n;
   float T0 = 0.0f;
   int tgt = 0;
+  EventRef er = {0, 0};
+  Rng rng;
   if (live) {
+    er = event_ref(a, i);
     T0 = a.T0[i];
     tgt = a.tidx ? (int)a.tidx[i] : 0;
     if (!energy_ok(T0) || tgt >= a.n_targets) {
       MidState m = {};
       m.flags = kFlagRange;
       a.mid[i] = m;
-      atomicAdd(&a.counters[1], 1ull);
+      atomicAdd(&a.segs[er.seg].counters[1], 1ull);
       live = false;
       tgt = 0;
     }
+    init_stream(rng, a, er);
   }
   const NucTab& nt = snt[tgt];
-  Rng rng;
-  rng.init(a.seed, a.first_id + i);
   Cascade c;
   cascade_init(c, nt);
   StackEntry stk[kStackDepth];
@@ -308,9 +324,9 @@ __global__ void __launch_bounds__(256) k_cascade_plain(KernelArgs a) {
         live = false;
       }
     }
-    writer_append(wbuf, fill, a.out, em.on, (uint32_t)i, em.kind, em.T, em.u);
+    writer_append(wbuf, fill, a.segs, em.on, er.local, kind_of(em.kind, er), em.T, em.u);
   }
-  writer_flush(wbuf, fill, a.out);
+  writer_flush(wbuf, fill, a.segs);
 }
 
 // Plain evaporation kernel: one de-excitation per thread (Sec. 3.3), same
@@ -326,12 +342,15 @@ __global__ void __launch_bounds__(256) k_evap_plain(KernelArgs a) {
   MidState m = {};
   Nucleus nu = {0, 0, 0.0f, {0.0f, 0.0f, 0.0f}};
   Rng rng;
+  EventRef er = {0, 0};
   int nsec = 0, flags = 0;
   if (live) {
+    er = event_ref(a, i);
+    inc_residual* res = a.segs[er.seg].res + er.local;
     m = a.mid[i];
     flags = m.flags;
     if (flags & kFlagRange) {
-      write_residual(&a.res[i], nu, 0.0f, 0, flags, 0, 0);
+      write_residual(res, nu, 0.0f, 0, flags, 0, 0);
       live = false;
     } else {
       nu.A = m.A;
@@ -339,12 +358,12 @@ __global__ void __launch_bounds__(256) k_evap_plain(KernelArgs a) {
       nu.E = m.E;
       nu.P = {m.P[0], m.P[1], m.P[2]};
       nsec = m.nsec;
-      rng.init(a.seed, a.first_id + i);
+      init_stream(rng, a, er);
       rng.seek(m.drawn);
       if (nu.A <= 0) flags |= kFlagEmpty;
-      if (flags) atomicAdd(&a.counters[1], 1ull);
+      if (flags) atomicAdd(&a.segs[er.seg].counters[1], 1ull);
       if (nu.A <= 0 || a.opt.no_evaporation) {
-        write_residual(&a.res[i], nu, m.E, nsec, flags, m.ncoll, m.nretry);
+        write_residual(res, nu, m.E, nsec, flags, m.ncoll, m.nretry);
         live = false;
       }
     }
@@ -354,15 +373,15 @@ __global__ void __launch_bounds__(256) k_evap_plain(KernelArgs a) {
     em.on = false;
     if (live) {
       if (evap_step(nu, rng, a.bind, a.evap, smt, em)) {
-        write_residual(&a.res[i], nu, m.E, nsec, flags, m.ncoll, m.nretry);
+        write_residual(a.segs[er.seg].res + er.local, nu, m.E, nsec, flags, m.ncoll, m.nretry);
         live = false;
       } else {
         ++nsec;
       }
     }
-    writer_append(wbuf, fill, a.out, em.on, (uint32_t)i, em.kind, em.T, em.u);
+    writer_append(wbuf, fill, a.segs, em.on, er.local, kind_of(em.kind, er), em.T, em.u);
   }
-  writer_flush(wbuf, fill, a.out);
+  writer_flush(wbuf, fill, a.segs);
 }
 
 // Persistent fused kernel.  Every wave keeps 64 events in flight; finished
@@ -388,7 +407,7 @@ __global__ void __launch_bounds__(256) k_persistent(KernelArgs a) {
   unsigned long long chunk_next = 0, chunk_end = 0;
   bool exhausted = false;
   int st = kStDone;
-  size_t ev = 0;
+  EventRef er = {0, 0};
   float T0 = 0.0f;
   int tgt = 0, nsec = 0;
   float Ex_casc = 0.0f;
@@ -403,7 +422,7 @@ __global__ void __launch_bounds__(256) k_persistent(KernelArgs a) {
     if (need && !exhausted) {
       if (chunk_next == chunk_end) {
         unsigned long long base = 0;
-        if (lane_id() == 0) base = atomicAdd(&a.counters[2], (unsigned long long)kChunk);
+        if (lane_id() == 0) base = atomicAdd(a.queue, (unsigned long long)kChunk);
         base = __shfl(base, 0);
         chunk_next = base;
         chunk_end = base + kChunk < a.n ? base + kChunk : a.n;
@@ -415,16 +434,17 @@ __global__ void __launch_bounds__(256) k_persistent(KernelArgs a) {
       const unsigned long long avail = chunk_end - chunk_next;
       const uint32_t r = rank_in(need);
       if (st == kStDone && r < avail) {
-        ev = (size_t)(chunk_next + r);
+        const size_t ev = (size_t)(chunk_next + r);
+        er = event_ref(a, ev);
         T0 = a.T0[ev];
         tgt = a.tidx ? (int)a.tidx[ev] : 0;
         if (!energy_ok(T0) || tgt >= a.n_targets) {
           tgt = 0;
           const Nucleus z = {0, 0, 0.0f, {0.0f, 0.0f, 0.0f}};
-          write_residual(&a.res[ev], z, 0.0f, 0, kFlagRange, 0, 0);
-          atomicAdd(&a.counters[1], 1ull);
+          write_residual(a.segs[er.seg].res + er.local, z, 0.0f, 0, kFlagRange, 0, 0);
+          atomicAdd(&a.segs[er.seg].counters[1], 1ull);
         } else {
-          rng.init(a.seed, a.first_id + ev);
+          init_stream(rng, a, er);
           cascade_init(c, snt[tgt]);
           nsec = 0;
           st = kStFlight;
@@ -457,8 +477,8 @@ __global__ void __launch_bounds__(256) k_persistent(KernelArgs a) {
     if (run == kStEvap) {
       if (st == kStEvap) {
         if (evap_step(nu, rng, a.bind, a.evap, smt, em)) {
-          write_residual(&a.res[ev], nu, Ex_casc, nsec, c.flags, c.ncoll, c.nretry);
-          if (c.flags) atomicAdd(&a.counters[1], 1ull);
+          write_residual(a.segs[er.seg].res + er.local, nu, Ex_casc, nsec, c.flags, c.ncoll, c.nretry);
+          if (c.flags) atomicAdd(&a.segs[er.seg].counters[1], 1ull);
           st = kStDone;
         } else {
           ++nsec;
@@ -476,8 +496,8 @@ __global__ void __launch_bounds__(256) k_persistent(KernelArgs a) {
         Ex_casc = nu.E;
         if (nu.A <= 0) c.flags |= kFlagEmpty;
         if (nu.A <= 0 || a.opt.no_evaporation) {
-          write_residual(&a.res[ev], nu, Ex_casc, nsec, c.flags, c.ncoll, c.nretry);
-          if (c.flags) atomicAdd(&a.counters[1], 1ull);
+          write_residual(a.segs[er.seg].res + er.local, nu, Ex_casc, nsec, c.flags, c.ncoll, c.nretry);
+          if (c.flags) atomicAdd(&a.segs[er.seg].counters[1], 1ull);
           st = kStDone;
         } else {
           st = kStEvap;
@@ -486,9 +506,25 @@ __global__ void __launch_bounds__(256) k_persistent(KernelArgs a) {
         st = ns;
       }
     }
-    writer_append(wbuf, fill, a.out, em.on, (uint32_t)ev, em.kind, em.T, em.u);
+    writer_append(wbuf, fill, a.segs, em.on, er.local, kind_of(em.kind, er), em.T, em.u);
   }
-  writer_flush(wbuf, fill, a.out);
+  writer_flush(wbuf, fill, a.segs);
+}
+
+// Zero the segments' counters and the work-queue head (a fill kernel rather
+// than a memset, so the launch sequence stays capturable in a graph).
+__global__ void k_zero_counters(const Segment* segs, int n_seg, unsigned long long* queue) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n_seg) {
+    segs[i].counters[0] = 0ull;
+    segs[i].counters[1] = 0ull;
+  }
+  if (i == 0) *queue = 0ull;
+}
+
+// Copy one segment description (a kernel argument) into device memory.
+__global__ void k_set_segment(Segment s, Segment* dst) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) *dst = s;
 }
 
 }  // namespace incdev
@@ -511,6 +547,11 @@ hipError_t inc_launch_setup(const int* d_AZ, int n_targets, NucTab* d_nuc, XsTab
   return hipGetLastError();
 }
 
+hipError_t inc_upload_segment(const Segment& seg, Segment* d_slot, hipStream_t s) {
+  hipLaunchKernelGGL(k_set_segment, dim3(1), dim3(64), 0, s, seg, d_slot);
+  return hipGetLastError();
+}
+
 hipError_t inc_launch_events(const LaunchDesc& L, hipStream_t s) {
   KernelArgs a;
   a.nuc = L.nuc;
@@ -530,14 +571,11 @@ hipError_t inc_launch_events(const LaunchDesc& L, hipStream_t s) {
   a.n = L.n;
   a.tidx = L.tidx;
   a.T0 = L.T0;
-  a.seed = L.seed;
-  a.first_id = L.first_id;
-  a.res = L.res;
-  a.out = {L.sec_event, L.sec_species, L.sec_stage, L.sec_T, L.sec_ux, L.sec_uy, L.sec_uz, L.counters,
-           (unsigned long long)L.sec_capacity};
-  a.counters = L.counters;
+  a.segs = L.segs;
+  a.n_seg = L.n_seg;
+  a.queue = L.queue;
   a.mid = L.mid;
-  hipLaunchKernelGGL(k_fill_u64, dim3(1), dim3(64), 0, s, L.counters, 4);
+  hipLaunchKernelGGL(k_zero_counters, dim3((L.n_seg + 63) / 64), dim3(64), 0, s, L.segs, L.n_seg, L.queue);
   const int block = L.block;
   if (L.mode == INC_MODE_PLAIN) {
     const unsigned grid = (unsigned)((L.n + block - 1) / block);

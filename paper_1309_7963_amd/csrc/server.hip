@@ -2,17 +2,20 @@
 // inc_server_* of include/inc.h).
 //
 // Event batches (requests) come from a proton-transport stepper as they
-// arrive.  A request is admitted when a slot (a HIP stream) is free and its
-// buffers fit in the HBM budget; it then runs as its own persistent-kernel
-// launch sized to its event count, so requests admitted while others run
-// overlap on the device.  The nucleus, cross-section and binding tables stay
-// resident in the context; each request keeps its own event ids, so its
-// results are the same alone and in the mix.  Results come back through a
-// pinned host mirror of the device pool.
+// arrive.  A request is admitted when its buffers fit in the HBM budget and
+// joins the queue.  Whenever one of the server's slots (HIP streams) is free,
+// every queued request with the same random-stream key is launched together
+// as ONE persistent-kernel launch: each request is a segment of that launch
+// with its own event ids and output buffers, so a request's results do not
+// depend on what it was batched with.  Launches on different slots overlap
+// on the device, so the tail of one launch runs beside the bulk of the next.
+// Nucleus, cross-section and binding tables stay resident in the context.
+// Results come back through a pinned host mirror of the device pool.
 #include <string.h>
 
 #include <algorithm>
 #include <chrono>
+#include <deque>
 #include <map>
 #include <new>
 #include <thread>
@@ -20,6 +23,8 @@
 #include <vector>
 
 #include "ctx.h"
+
+using incdev::Segment;
 
 namespace {
 
@@ -76,39 +81,45 @@ class Pool {
   std::map<size_t, size_t> free_;
 };
 
-// Offsets of one request's buffers inside its pool region.
-struct Layout {
-  size_t T0, tidx, res, cnt, sec_T, sec_ux, sec_uy, sec_uz, sec_event, sec_species, sec_stage, total;
-  static Layout of(size_t n, size_t cap) {
-    Layout L;
-    size_t o = 0;
-    L.T0 = o;          o += align_up(4 * n);
-    L.tidx = o;        o += align_up(n);
-    L.res = o;         o += align_up(sizeof(inc_residual) * n);
-    L.cnt = o;         o += align_up(4 * sizeof(unsigned long long));
-    L.sec_T = o;       o += align_up(4 * cap);
-    L.sec_ux = o;      o += align_up(4 * cap);
-    L.sec_uy = o;      o += align_up(4 * cap);
-    L.sec_uz = o;      o += align_up(4 * cap);
-    L.sec_event = o;   o += align_up(4 * cap);
-    L.sec_species = o; o += align_up(cap);
-    L.sec_stage = o;   o += align_up(cap);
-    L.total = o;
-    return L;
-  }
+// Device bytes a request needs inside a launch.
+size_t request_bytes(size_t n, size_t cap) {
+  return align_up(4 * n) + align_up(n) + align_up(sizeof(inc_residual) * n) + 5 * align_up(4 * cap) +
+         2 * align_up(cap) + align_up(4 * sizeof(unsigned long long)) + align_up(sizeof(Segment));
+}
+
+enum RState { kQueued = 0, kLaunched = 1, kReady = 2 };
+enum LPhase { kRunning = 0, kCopying = 1, kDone = 2 };
+
+// Offsets of one request's buffers inside its launch region.
+struct ROffsets {
+  size_t res, cnt, T, ux, uy, uz, ev, sp, st;
 };
 
-enum Phase { kRunning = 0, kCopying = 1, kReady = 2 };
-
 struct Request {
-  size_t n, cap, off;
-  Layout L;
-  int slot;
-  int phase;
-  hipEvent_t ev_kernel, ev_copy;
+  size_t n, cap;
+  uint64_t seed, first_id;
+  std::vector<float> T0;
+  std::vector<uint8_t> tidx;
+  bool has_tidx;
+  size_t bytes;       // admission charge
+  int state;
+  int launch;
+  size_t start;       // first event of the request in its launch
+  ROffsets o;
   unsigned long long n_sec;
   int rc;
   double t_submit, t_done;
+};
+
+struct Launch {
+  int slot;
+  size_t off, bytes;
+  size_t n;
+  std::vector<uint64_t> tickets;
+  size_t seg_off, queue_off;
+  int phase;
+  hipEvent_t ev_kernel, ev_copy;
+  int pending_fetch;
 };
 
 }  // namespace
@@ -118,73 +129,213 @@ struct inc_server {
   char* d_pool;
   char* h_pool;
   size_t budget;
+  size_t charged;     // bytes promised to admitted, not yet fetched requests
   Pool pool;
   std::vector<hipStream_t> streams;
   std::vector<int> slot_busy;
   std::unordered_map<uint64_t, Request> reqs;
+  std::deque<uint64_t> queue;
+  std::map<int, Launch> launches;
+  int next_launch;
   uint64_t next_ticket;
   inc_server_stats st;
 };
 
 namespace {
 
-void finish_copy_phase(inc_server* s, Request& r) {
-  // results are in the pinned mirror; the slot (stream) is free again
-  r.phase = kReady;
-  r.t_done = now_s();
-  s->slot_busy[r.slot] = 0;
-  s->st.completed += 1;
-  s->st.events += r.n;
-  s->st.secondaries += r.n_sec;
+void complete_launch(inc_server* s, Launch& L, int rc) {
+  const double t = now_s();
+  for (uint64_t tk : L.tickets) {
+    Request& r = s->reqs[tk];
+    if (rc != INC_OK && r.rc == INC_OK) r.rc = rc;
+    r.state = kReady;
+    r.t_done = t;
+    s->st.completed += 1;
+    s->st.events += r.n;
+    s->st.secondaries += r.n_sec;
+  }
+  L.phase = kDone;
+  s->slot_busy[L.slot] = 0;
 }
 
-// Advance one request's phase without blocking; returns 1 when ready.
-int advance(inc_server* s, Request& r) {
-  if (r.phase == kRunning) {
-    const hipError_t q = hipEventQuery(r.ev_kernel);
-    if (q == hipErrorNotReady) return 0;
+// Advance a launch without blocking.
+void advance_launch(inc_server* s, Launch& L) {
+  if (L.phase == kRunning) {
+    const hipError_t q = hipEventQuery(L.ev_kernel);
+    if (q == hipErrorNotReady) return;
     if (q != hipSuccess) {
-      r.rc = inc_map_hip_error(q);
-      finish_copy_phase(s, r);
-      return 1;
+      complete_launch(s, L, inc_map_hip_error(q));
+      return;
     }
-    const unsigned long long* cnt = (const unsigned long long*)(s->h_pool + r.off + r.L.cnt);
-    r.n_sec = cnt[0];
-    if (r.n_sec > r.cap) r.rc = INC_ERR_CAPACITY;
-    const size_t k = (size_t)std::min<unsigned long long>(r.n_sec, r.cap);
-    hipStream_t st = s->streams[r.slot];
+    hipStream_t st = s->streams[L.slot];
     hipError_t e = hipSuccess;
-    const size_t offs[7] = {r.L.sec_T, r.L.sec_ux, r.L.sec_uy, r.L.sec_uz, r.L.sec_event, r.L.sec_species,
-                            r.L.sec_stage};
-    const size_t width[7] = {4, 4, 4, 4, 4, 1, 1};
-    for (int f = 0; f < 7 && e == hipSuccess && k; ++f)
-      e = hipMemcpyAsync(s->h_pool + r.off + offs[f], s->d_pool + r.off + offs[f], width[f] * k,
-                         hipMemcpyDeviceToHost, st);
-    if (e == hipSuccess) e = hipEventRecord(r.ev_copy, st);
-    if (e != hipSuccess) {
-      r.rc = inc_map_hip_error(e);
-      finish_copy_phase(s, r);
-      return 1;
+    for (uint64_t tk : L.tickets) {
+      Request& r = s->reqs[tk];
+      const unsigned long long* cnt = (const unsigned long long*)(s->h_pool + L.off + r.o.cnt);
+      r.n_sec = cnt[0];
+      if (r.n_sec > r.cap) r.rc = INC_ERR_CAPACITY;
+      const size_t k = (size_t)std::min<unsigned long long>(r.n_sec, r.cap);
+      const size_t offs[7] = {r.o.T, r.o.ux, r.o.uy, r.o.uz, r.o.ev, r.o.sp, r.o.st};
+      const size_t width[7] = {4, 4, 4, 4, 4, 1, 1};
+      for (int f = 0; f < 7 && e == hipSuccess && k; ++f)
+        e = hipMemcpyAsync(s->h_pool + L.off + offs[f], s->d_pool + L.off + offs[f], width[f] * k,
+                           hipMemcpyDeviceToHost, st);
     }
-    r.phase = kCopying;
+    if (e == hipSuccess) e = hipEventRecord(L.ev_copy, st);
+    if (e != hipSuccess) {
+      complete_launch(s, L, inc_map_hip_error(e));
+      return;
+    }
+    L.phase = kCopying;
   }
-  if (r.phase == kCopying) {
-    const hipError_t q = hipEventQuery(r.ev_copy);
-    if (q == hipErrorNotReady) return 0;
-    if (q != hipSuccess && r.rc == INC_OK) r.rc = inc_map_hip_error(q);
-    finish_copy_phase(s, r);
+  if (L.phase == kCopying) {
+    const hipError_t q = hipEventQuery(L.ev_copy);
+    if (q == hipErrorNotReady) return;
+    complete_launch(s, L, q == hipSuccess ? INC_OK : inc_map_hip_error(q));
   }
-  return 1;
 }
 
-void drop(inc_server* s, uint64_t ticket) {
+// Launch the queued requests that share the head's key on a free slot.
+int start_launch(inc_server* s) {
+  if (s->queue.empty()) return INC_OK;
+  int slot = -1;
+  for (size_t i = 0; i < s->streams.size(); ++i)
+    if (!s->slot_busy[i]) {
+      slot = (int)i;
+      break;
+    }
+  if (slot < 0) return INC_OK;
+  // the longest prefix of the queue with the head's key that fits the
+  // largest free block of the pool
+  const uint64_t key = s->reqs[s->queue.front()].seed;
+  const size_t room = s->pool.largest();
+  const size_t fixed = align_up(sizeof(unsigned long long)) + 2 * kAlign;
+  std::vector<uint64_t> take;
+  size_t n = 0, bytes = fixed;
+  for (uint64_t tk : s->queue) {
+    const Request& r = s->reqs[tk];
+    if (r.seed != key || n + r.n >= (1ull << 31) || bytes + r.bytes > room) break;
+    take.push_back(tk);
+    n += r.n;
+    bytes += r.bytes;
+  }
+  if (take.empty()) return INC_OK;  // wait for memory
+  Launch L;
+  if (!s->pool.alloc(bytes, &L.off)) return INC_OK;  // wait for memory
+  for (size_t k = 0; k < take.size(); ++k) s->queue.pop_front();
+  L.slot = slot;
+  L.bytes = bytes;
+  L.n = n;
+  L.tickets = take;
+  L.phase = kRunning;
+  L.pending_fetch = (int)take.size();
+  const int id = s->next_launch++;
+  // layout: [T0][tidx][segments][queue][per request: counters res T ux uy uz ev sp st]
+  size_t o = 0;
+  const size_t T0_off = o;   o += align_up(4 * n);
+  const size_t tidx_off = o; o += align_up(n);
+  L.seg_off = o;             o += align_up(sizeof(Segment) * take.size());
+  L.queue_off = o;           o += align_up(sizeof(unsigned long long));
+  char* h = s->h_pool + L.off;
+  char* d = s->d_pool + L.off;
+  bool any_tidx = false;
+  size_t start = 0;
+  std::vector<Segment> segs(take.size());
+  for (size_t k = 0; k < take.size(); ++k) {
+    Request& r = s->reqs[take[k]];
+    r.state = kLaunched;
+    r.launch = id;
+    r.start = start;
+    r.o.cnt = o; o += align_up(4 * sizeof(unsigned long long));
+    r.o.res = o; o += align_up(sizeof(inc_residual) * r.n);
+    r.o.T = o;   o += align_up(4 * r.cap);
+    r.o.ux = o;  o += align_up(4 * r.cap);
+    r.o.uy = o;  o += align_up(4 * r.cap);
+    r.o.uz = o;  o += align_up(4 * r.cap);
+    r.o.ev = o;  o += align_up(4 * r.cap);
+    r.o.sp = o;  o += align_up(r.cap);
+    r.o.st = o;  o += align_up(r.cap);
+    memcpy(h + T0_off + 4 * start, r.T0.data(), 4 * r.n);
+    if (r.has_tidx) {
+      memcpy(h + tidx_off + start, r.tidx.data(), r.n);
+      any_tidx = true;
+    } else {
+      memset(h + tidx_off + start, 0, r.n);
+    }
+    Segment& g = segs[k];
+    g.start = (uint32_t)start;
+    g.n = (uint32_t)r.n;
+    g.seed = r.seed;
+    g.first_id = r.first_id;
+    g.res = (inc_residual*)(d + r.o.res);
+    g.ev = (uint32_t*)(d + r.o.ev);
+    g.species = (uint8_t*)(d + r.o.sp);
+    g.stage = (uint8_t*)(d + r.o.st);
+    g.T = (float*)(d + r.o.T);
+    g.ux = (float*)(d + r.o.ux);
+    g.uy = (float*)(d + r.o.uy);
+    g.uz = (float*)(d + r.o.uz);
+    g.cap = r.cap;
+    g.counters = (unsigned long long*)(d + r.o.cnt);
+    start += r.n;
+  }
+  memcpy(h + L.seg_off, segs.data(), sizeof(Segment) * segs.size());
+  hipStream_t st = s->streams[slot];
+  const size_t in_bytes = L.queue_off;  // T0, tidx and segment table are contiguous at the front
+  hipError_t e = hipEventCreateWithFlags(&L.ev_kernel, hipEventDisableTiming);
+  if (e == hipSuccess) e = hipEventCreateWithFlags(&L.ev_copy, hipEventDisableTiming);
+  if (e == hipSuccess) e = hipMemcpyAsync(d, h, in_bytes, hipMemcpyHostToDevice, st);
+  int rc = inc_map_hip_error(e);
+  if (rc == INC_OK) {
+    // one lane per event at most: small launches take fewer blocks
+    const int blocks = (int)((n + s->ctx->block - 1) / s->ctx->block);
+    rc = inc_launch_segments(s->ctx, n, any_tidx ? (const uint8_t*)(d + tidx_off) : nullptr, (const float*)(d + T0_off),
+                             (const Segment*)(d + L.seg_off), (int)segs.size(),
+                             (unsigned long long*)(d + L.queue_off), st, INC_MODE_PERSISTENT, blocks);
+  }
+  for (size_t k = 0; k < take.size() && rc == INC_OK; ++k) {
+    const Request& r = s->reqs[take[k]];
+    e = hipMemcpyAsync(h + r.o.cnt, d + r.o.cnt, 4 * sizeof(unsigned long long), hipMemcpyDeviceToHost, st);
+    if (e == hipSuccess) e = hipMemcpyAsync(h + r.o.res, d + r.o.res, sizeof(inc_residual) * r.n, hipMemcpyDeviceToHost, st);
+    rc = inc_map_hip_error(e);
+  }
+  if (rc == INC_OK) rc = inc_map_hip_error(hipEventRecord(L.ev_kernel, st));
+  s->slot_busy[slot] = 1;
+  s->launches.emplace(id, L);
+  if (rc != INC_OK) {
+    (void)hipStreamSynchronize(st);
+    complete_launch(s, s->launches[id], rc);
+  }
+  return INC_OK;
+}
+
+// Make progress: finish launches, start new ones on free slots.
+void pump(inc_server* s) {
+  for (auto& kv : s->launches) advance_launch(s, kv.second);
+  while (!s->queue.empty()) {
+    const size_t before = s->queue.size();
+    start_launch(s);
+    if (s->queue.size() == before) break;
+  }
+}
+
+void release_request(inc_server* s, uint64_t ticket) {
   auto it = s->reqs.find(ticket);
   if (it == s->reqs.end()) return;
   Request& r = it->second;
-  (void)hipEventDestroy(r.ev_kernel);
-  (void)hipEventDestroy(r.ev_copy);
-  if (r.phase != kReady) s->slot_busy[r.slot] = 0;
-  s->pool.release(r.off, r.L.total);
+  s->charged -= r.bytes;
+  if (r.state != kQueued) {
+    auto lt = s->launches.find(r.launch);
+    if (lt != s->launches.end() && --lt->second.pending_fetch == 0) {
+      Launch& L = lt->second;
+      (void)hipEventDestroy(L.ev_kernel);
+      (void)hipEventDestroy(L.ev_copy);
+      s->pool.release(L.off, L.bytes);
+      s->launches.erase(lt);
+    }
+  } else {
+    s->queue.erase(std::remove(s->queue.begin(), s->queue.end(), ticket), s->queue.end());
+  }
   s->reqs.erase(it);
 }
 
@@ -200,9 +351,11 @@ int inc_server_create(inc_ctx* ctx, size_t hbm_budget, int max_slots, inc_server
   if (!s) return INC_ERR_OOM;
   s->ctx = ctx;
   s->budget = hbm_budget;
+  s->charged = 0;
   s->d_pool = nullptr;
   s->h_pool = nullptr;
   s->next_ticket = 1;
+  s->next_launch = 1;
   memset(&s->st, 0, sizeof(s->st));
   hipError_t e = hipMalloc(&s->d_pool, hbm_budget);
   if (e == hipSuccess) e = hipHostMalloc(&s->h_pool, hbm_budget, hipHostMallocDefault);
@@ -226,9 +379,10 @@ int inc_server_create(inc_ctx* ctx, size_t hbm_budget, int max_slots, inc_server
 int inc_server_destroy(inc_server* s) {
   if (!s) return INC_ERR_ARG;
   for (hipStream_t st : s->streams) (void)hipStreamSynchronize(st);
-  std::vector<uint64_t> tickets;
-  for (auto& kv : s->reqs) tickets.push_back(kv.first);
-  for (uint64_t t : tickets) drop(s, t);
+  for (auto& kv : s->launches) {
+    (void)hipEventDestroy(kv.second.ev_kernel);
+    (void)hipEventDestroy(kv.second.ev_copy);
+  }
   for (hipStream_t st : s->streams) (void)hipStreamDestroy(st);
   if (s->d_pool) (void)hipFree(s->d_pool);
   if (s->h_pool) (void)hipHostFree(s->h_pool);
@@ -237,78 +391,40 @@ int inc_server_destroy(inc_server* s) {
 }
 
 int inc_server_submit(inc_server* s, const inc_request* q, uint64_t* ticket) {
-  if (!s || !q || !ticket || !q->T0 || q->n < 1 || q->n >= (1ull << 32)) return INC_ERR_ARG;
+  if (!s || !q || !ticket || !q->T0 || q->n < 1 || q->n >= (1ull << 31)) return INC_ERR_ARG;
   const size_t cap = q->sec_capacity ? q->sec_capacity : q->n * 12 + 4096;
-  const Layout L = Layout::of(q->n, cap);
-  if (L.total > s->budget) return INC_ERR_ARG;  // never admissible
-  int slot = -1;
-  for (size_t i = 0; i < s->streams.size(); ++i)
-    if (!s->slot_busy[i]) {
-      slot = (int)i;
-      break;
-    }
-  size_t off = 0;
-  if (slot < 0 || !s->pool.alloc(L.total, &off)) {
+  const size_t bytes = request_bytes(q->n, cap);
+  // a launch of this request alone must fit the pool
+  if (bytes + 4 * kAlign > s->budget) return INC_ERR_ARG;
+  pump(s);
+  if (s->charged + bytes + 4 * kAlign > s->budget) {
     s->st.rejected_busy += 1;
     return INC_ERR_BUSY;
   }
   Request r;
   r.n = q->n;
   r.cap = cap;
-  r.off = off;
-  r.L = L;
-  r.slot = slot;
-  r.phase = kRunning;
+  r.seed = q->seed;
+  r.first_id = q->first_event_id;
+  r.T0.assign(q->T0, q->T0 + q->n);
+  r.has_tidx = q->target_idx != nullptr;
+  if (r.has_tidx) r.tidx.assign(q->target_idx, q->target_idx + q->n);
+  r.bytes = bytes;
+  r.state = kQueued;
+  r.launch = 0;
+  r.start = 0;
+  memset(&r.o, 0, sizeof(r.o));
   r.n_sec = 0;
   r.rc = INC_OK;
   r.t_submit = now_s();
   r.t_done = 0.0;
-  hipStream_t st = s->streams[slot];
-  char* h = s->h_pool + off;
-  char* d = s->d_pool + off;
-  memcpy(h + L.T0, q->T0, 4 * q->n);
-  if (q->target_idx) memcpy(h + L.tidx, q->target_idx, q->n);
-  hipError_t e = hipEventCreateWithFlags(&r.ev_kernel, hipEventDisableTiming);
-  if (e == hipSuccess) e = hipEventCreateWithFlags(&r.ev_copy, hipEventDisableTiming);
-  if (e == hipSuccess) e = hipMemcpyAsync(d + L.T0, h + L.T0, 4 * q->n, hipMemcpyHostToDevice, st);
-  if (e == hipSuccess && q->target_idx) e = hipMemcpyAsync(d + L.tidx, h + L.tidx, q->n, hipMemcpyHostToDevice, st);
-  if (e != hipSuccess) {
-    s->pool.release(off, L.total);
-    return inc_map_hip_error(e);
-  }
-  inc_batch b = {q->n, q->target_idx ? (const uint8_t*)(d + L.tidx) : nullptr, (const float*)(d + L.T0), q->seed,
-                 q->first_event_id};
-  inc_output o;
-  o.res = (inc_residual*)(d + L.res);
-  o.sec_T = (float*)(d + L.sec_T);
-  o.sec_ux = (float*)(d + L.sec_ux);
-  o.sec_uy = (float*)(d + L.sec_uy);
-  o.sec_uz = (float*)(d + L.sec_uz);
-  o.sec_event = (uint32_t*)(d + L.sec_event);
-  o.sec_species = (uint8_t*)(d + L.sec_species);
-  o.sec_stage = (uint8_t*)(d + L.sec_stage);
-  o.sec_capacity = cap;
-  o.counters = (unsigned long long*)(d + L.cnt);
-  // one lane per event at most: small requests take fewer blocks
-  const int blocks = (int)((q->n + s->ctx->block - 1) / s->ctx->block);
-  int rc = inc_launch_batch(s->ctx, &b, &o, st, INC_MODE_PERSISTENT, blocks);
-  if (rc == INC_OK) {
-    e = hipMemcpyAsync(h + L.cnt, d + L.cnt, 4 * sizeof(unsigned long long), hipMemcpyDeviceToHost, st);
-    if (e == hipSuccess) e = hipMemcpyAsync(h + L.res, d + L.res, sizeof(inc_residual) * q->n, hipMemcpyDeviceToHost, st);
-    if (e == hipSuccess) e = hipEventRecord(r.ev_kernel, st);
-    rc = inc_map_hip_error(e);
-  }
-  if (rc != INC_OK) {
-    (void)hipStreamSynchronize(st);
-    (void)hipEventDestroy(r.ev_kernel);
-    (void)hipEventDestroy(r.ev_copy);
-    s->pool.release(off, L.total);
-    return rc;
-  }
-  s->slot_busy[slot] = 1;
-  *ticket = s->next_ticket++;
-  s->reqs.emplace(*ticket, r);
+  const uint64_t t = s->next_ticket++;
+  s->reqs.emplace(t, std::move(r));
+  s->queue.push_back(t);
+  s->charged += bytes;
   s->st.submitted += 1;
+  *ticket = t;
+  pump(s);
   return INC_OK;
 }
 
@@ -316,18 +432,19 @@ int inc_server_poll(inc_server* s, uint64_t ticket) {
   if (!s) return INC_ERR_ARG;
   auto it = s->reqs.find(ticket);
   if (it == s->reqs.end()) return INC_ERR_ARG;
-  return advance(s, it->second);
+  pump(s);
+  return it->second.state == kReady ? 1 : 0;
 }
 
 int inc_server_wait(inc_server* s, uint64_t ticket) {
   if (!s) return INC_ERR_ARG;
   auto it = s->reqs.find(ticket);
   if (it == s->reqs.end()) return INC_ERR_ARG;
-  Request& r = it->second;
-  while (advance(s, r) == 0) {
-    (void)hipEventSynchronize(r.phase == kRunning ? r.ev_kernel : r.ev_copy);
+  while (true) {
+    pump(s);
+    if (it->second.state == kReady) return 1;
+    std::this_thread::sleep_for(std::chrono::microseconds(20));
   }
-  return 1;
 }
 
 int inc_server_fetch(inc_server* s, uint64_t ticket, const inc_host_output* out) {
@@ -335,25 +452,26 @@ int inc_server_fetch(inc_server* s, uint64_t ticket, const inc_host_output* out)
   auto it = s->reqs.find(ticket);
   if (it == s->reqs.end()) return INC_ERR_ARG;
   Request& r = it->second;
-  if (r.phase != kReady) return INC_ERR_BUSY;
+  if (r.state != kReady) return INC_ERR_BUSY;
   const int rc = r.rc;
   if (out) {
-    const char* h = s->h_pool + r.off;
+    const char* h = s->h_pool + s->launches[r.launch].off;
     const size_t k = (size_t)std::min<unsigned long long>(r.n_sec, std::min(r.cap, out->sec_capacity));
-    if (out->res) memcpy(out->res, h + r.L.res, sizeof(inc_residual) * r.n);
+    if (out->res) memcpy(out->res, h + r.o.res, sizeof(inc_residual) * r.n);
     if (k) {
-      if (out->sec_T) memcpy(out->sec_T, h + r.L.sec_T, 4 * k);
-      if (out->sec_ux) memcpy(out->sec_ux, h + r.L.sec_ux, 4 * k);
-      if (out->sec_uy) memcpy(out->sec_uy, h + r.L.sec_uy, 4 * k);
-      if (out->sec_uz) memcpy(out->sec_uz, h + r.L.sec_uz, 4 * k);
-      if (out->sec_event) memcpy(out->sec_event, h + r.L.sec_event, 4 * k);
-      if (out->sec_species) memcpy(out->sec_species, h + r.L.sec_species, k);
-      if (out->sec_stage) memcpy(out->sec_stage, h + r.L.sec_stage, k);
+      if (out->sec_T) memcpy(out->sec_T, h + r.o.T, 4 * k);
+      if (out->sec_ux) memcpy(out->sec_ux, h + r.o.ux, 4 * k);
+      if (out->sec_uy) memcpy(out->sec_uy, h + r.o.uy, 4 * k);
+      if (out->sec_uz) memcpy(out->sec_uz, h + r.o.uz, 4 * k);
+      if (out->sec_event) memcpy(out->sec_event, h + r.o.ev, 4 * k);
+      if (out->sec_species) memcpy(out->sec_species, h + r.o.sp, k);
+      if (out->sec_stage) memcpy(out->sec_stage, h + r.o.st, k);
     }
     if (out->n_sec) *out->n_sec = r.n_sec;
     if (out->latency_s) *out->latency_s = r.t_done - r.t_submit;
   }
-  drop(s, ticket);
+  release_request(s, ticket);
+  pump(s);
   return rc;
 }
 
@@ -371,10 +489,11 @@ int inc_server_replay(inc_server* s, int n_req, const double* arrival_s, const i
   for (int i = 0; i < n_req; ++i) {
     if (i && arrival_s[i] < arrival_s[i - 1]) return INC_ERR_ARG;
     const size_t cap = reqs[i].sec_capacity ? reqs[i].sec_capacity : reqs[i].n * 12 + 4096;
-    if (Layout::of(reqs[i].n, cap).total > s->budget) return INC_ERR_ARG;
+    if (request_bytes(reqs[i].n, cap) + 4 * kAlign > s->budget) return INC_ERR_ARG;
   }
   std::vector<uint64_t> ticket(n_req, 0);
-  std::vector<int> state(n_req, 0);  // 0 waiting, 1 in flight, 2 done
+  std::vector<int> state(n_req, 0);  // 0 waiting, 1 admitted, 2 done
+  std::vector<int> admitted;
   int next_arrival = 0, head = 0, done = 0, rc_all = INC_OK;
   std::vector<int> fifo;
   const double t0 = now_s();
@@ -390,26 +509,29 @@ int inc_server_replay(inc_server* s, int n_req, const double* arrival_s, const i
       if (rc == INC_ERR_BUSY) break;
       if (rc != INC_OK) return rc;
       state[k] = 1;
+      admitted.push_back(k);
       ++head;
       progressed = true;
     }
-    for (int k = 0; k < n_req; ++k) {
-      if (state[k] != 1) continue;
-      auto it = s->reqs.find(ticket[k]);
-      if (advance(s, it->second)) {
-        latency_s[k] = it->second.t_done - t0 - arrival_s[k];
-        t_last = it->second.t_done;
+    pump(s);
+    for (size_t a = 0; a < admitted.size();) {
+      const int k = admitted[a];
+      Request& r = s->reqs[ticket[k]];
+      if (r.state == kReady) {
+        latency_s[k] = r.t_done - t0 - arrival_s[k];
+        t_last = std::max(t_last, r.t_done);
         const int rc = inc_server_fetch(s, ticket[k], nullptr);
         if (rc != INC_OK && rc_all == INC_OK) rc_all = rc;
         state[k] = 2;
         ++done;
         progressed = true;
+        admitted[a] = admitted.back();
+        admitted.pop_back();
+      } else {
+        ++a;
       }
     }
-    if (!progressed) {
-      // nothing to do: the next arrival or a completion
-      std::this_thread::sleep_for(std::chrono::microseconds(20));
-    }
+    if (!progressed) std::this_thread::sleep_for(std::chrono::microseconds(20));
   }
   if (span_s) *span_s = t_last - t0 - arrival_s[0];
   return rc_all;
