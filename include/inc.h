@@ -216,6 +216,35 @@ int inc_server_stats_get(inc_server* server, inc_server_stats* out);
 int inc_server_replay(inc_server* server, int n_req, const double* arrival_s, const inc_request* reqs,
                       double* latency_s, double* span_s);
 
+/* ------------------------------------------------------------- ring output
+ * Streaming output for large batches: the secondaries flow through a ring of
+ * `slots` records (a power of two >= 1024) in coherent host memory while the
+ * kernel runs; the calling thread drains the ring into the caller's host
+ * arrays (in ring order) and hands the space back.  A full ring makes the
+ * producing waves wait (up to ~3 s without consumer progress, then the call
+ * fails with INC_ERR_DEVICE); no record is lost or duplicated. */
+typedef struct inc_ring inc_ring;
+
+typedef struct {
+  unsigned long long records;    /* secondaries that passed through the ring */
+  unsigned long long slots;
+  unsigned long long wraps;      /* records / slots                           */
+  unsigned long long consumer_idle_polls;
+  double seconds;                /* launch to last record drained             */
+  unsigned int producer_gave_up; /* 1 if a wave timed out waiting for room    */
+} inc_ring_stats;
+
+int inc_ring_create(inc_ctx* ctx, size_t slots, inc_ring** out);
+int inc_ring_destroy(inc_ring* ring);
+/* Generate batch->n events (device inputs, as inc_simulate_dev) with their
+ * residuals written to d_res (device, n entries) and their secondaries
+ * streamed through the ring into out (host arrays, out->sec_capacity each;
+ * *out->n_sec receives the total).  Blocks until the batch is drained.
+ * Returns INC_ERR_CAPACITY if the host arrays were too small (the rest was
+ * drained and dropped).  Not thread-safe; one call at a time per ring. */
+int inc_ring_simulate(inc_ring* ring, const inc_batch* batch, inc_residual* d_res, const inc_host_output* out,
+                      void* stream, int mode, inc_ring_stats* stats);
+
 /* Library version of the frozen physics readings (changes when any reading
  * that affects results changes). */
 int inc_contract_version(void);

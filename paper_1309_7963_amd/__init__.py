@@ -303,5 +303,63 @@ class Server:
         return lat, span.value
 
 
+class Ring:
+    """Streaming output through a bounded ring of `slots` records
+    (inc_ring_*): the secondaries of a batch are drained to host arrays while
+    the kernel runs."""
+
+    def __init__(self, ctx: Context, slots: int = 1 << 20):
+        self.ctx = ctx
+        h = C.c_void_p()
+        _lib.check(_lib.load().inc_ring_create(ctx._h, int(slots), C.byref(h)), "inc_ring_create")
+        self._h = h
+        self.slots = int(slots)
+
+    def close(self):
+        if getattr(self, "_h", None) and self._h.value:
+            _lib.load().inc_ring_destroy(self._h)
+            self._h = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def simulate(self, T0, seed: int, target_idx=None, first_event_id: int = 0, mode: str = "persistent",
+                 capacity: Optional[int] = None, stream=None) -> dict:
+        """T0 / target_idx: CUDA tensors as in Context.simulate.  Returns host
+        arrays of the secondaries, the residuals and the ring statistics."""
+        torch = _torch()
+        n = int(T0.shape[0])
+        cap = int(capacity) if capacity is not None else self.ctx.default_capacity(n)
+        res_d = torch.empty(n * 32, dtype=torch.uint8, device=T0.device)
+        ev = np.zeros(cap, np.uint32)
+        sp = np.zeros(cap, np.uint8)
+        st = np.zeros(cap, np.uint8)
+        T, ux, uy, uz = (np.zeros(cap, np.float32) for _ in range(4))
+        nsec = C.c_ulonglong()
+        o = _lib.HostOutput(None, ev.ctypes.data, sp.ctypes.data, st.ctypes.data, T.ctypes.data, ux.ctypes.data,
+                            uy.ctypes.data, uz.ctypes.data, cap, C.pointer(nsec), None)
+        b = _lib.Batch()
+        b.n = n
+        b.target_idx = target_idx.data_ptr() if target_idx is not None else None
+        b.T0 = T0.data_ptr()
+        b.seed = int(seed)
+        b.first_event_id = int(first_event_id)
+        stats = _lib.RingStats()
+        s = stream if stream is not None else torch.cuda.current_stream()
+        m = {"plain": _lib.MODE_PLAIN, "persistent": _lib.MODE_PERSISTENT}[mode]
+        rc = _lib.load().inc_ring_simulate(self._h, C.byref(b), C.c_void_p(res_d.data_ptr()), C.byref(o),
+                                           C.c_void_p(s.cuda_stream), m, C.byref(stats))
+        if rc not in (_lib.INC_OK, _lib.INC_ERR_CAPACITY):
+            _lib.check(rc, "inc_ring_simulate")
+        k = min(nsec.value, cap)
+        return dict(rc=rc, res=res_d.cpu().numpy().view(RESIDUAL_DTYPE), n_sec_total=nsec.value,
+                    sec_event=ev[:k], sec_species=sp[:k], sec_stage=st[:k], sec_T=T[:k],
+                    sec_u=np.stack([ux[:k], uy[:k], uz[:k]], 1),
+                    stats={f: getattr(stats, f) for f, _ in stats._fields_})
+
+
 def contract_version() -> int:
     return _lib.load().inc_contract_version()

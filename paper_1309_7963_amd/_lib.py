@@ -25,7 +25,8 @@ SYMBOLS = (
     "inc_strerror", "inc_ctx_create", "inc_ctx_destroy", "inc_ctx_tables",
     "inc_simulate_dev", "inc_simulate", "inc_server_create", "inc_server_destroy",
     "inc_server_submit", "inc_server_poll", "inc_server_wait", "inc_server_fetch",
-    "inc_server_stats_get", "inc_server_replay", "inc_contract_version",
+    "inc_server_stats_get", "inc_server_replay", "inc_ring_create", "inc_ring_destroy",
+    "inc_ring_simulate", "inc_contract_version",
 )
 
 
@@ -80,6 +81,13 @@ class ServerStats(C.Structure):
         ("submitted", C.c_ulonglong), ("completed", C.c_ulonglong), ("rejected_busy", C.c_ulonglong),
         ("events", C.c_ulonglong), ("secondaries", C.c_ulonglong), ("in_flight", C.c_ulonglong),
         ("pool_free_largest", C.c_size_t),
+    ]
+
+
+class RingStats(C.Structure):
+    _fields_ = [
+        ("records", C.c_ulonglong), ("slots", C.c_ulonglong), ("wraps", C.c_ulonglong),
+        ("consumer_idle_polls", C.c_ulonglong), ("seconds", C.c_double), ("producer_gave_up", C.c_uint),
     ]
 
 
@@ -149,6 +157,13 @@ def load():
         L.inc_server_stats_get.restype = C.c_int
         L.inc_server_replay.argtypes = [vp, C.c_int, C.c_void_p, C.c_void_p, C.c_void_p, C.POINTER(C.c_double)]
         L.inc_server_replay.restype = C.c_int
+        L.inc_ring_create.argtypes = [vp, C.c_size_t, C.POINTER(vp)]
+        L.inc_ring_create.restype = C.c_int
+        L.inc_ring_destroy.argtypes = [vp]
+        L.inc_ring_destroy.restype = C.c_int
+        L.inc_ring_simulate.argtypes = [vp, C.POINTER(Batch), vp, C.POINTER(HostOutput), vp, C.c_int,
+                                        C.POINTER(RingStats)]
+        L.inc_ring_simulate.restype = C.c_int
         L.inc_contract_version.argtypes = []
         L.inc_contract_version.restype = C.c_int
         _lib = L

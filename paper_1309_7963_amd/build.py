@@ -12,7 +12,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libinc.so")
-SOURCES = ["api.hip", "kernels.hip", "server.hip"]
+SOURCES = ["api.hip", "kernels.hip", "server.hip", "ring.hip"]
 HEADERS = ["device.h", "event.h", "kernels.h", "ctx.h"]
 
 HIPCC_FLAGS = [

@@ -45,7 +45,8 @@ void release(inc_ctx* c) {
 }  // namespace
 
 int inc_launch_segments(inc_ctx* ctx, size_t n, const uint8_t* tidx, const float* T0, const Segment* d_segs,
-                        int n_seg, unsigned long long* queue, hipStream_t s, int mode, int max_blocks) {
+                        int n_seg, unsigned long long* queue, hipStream_t s, int mode, int max_blocks,
+                        const RingDev* ring) {
   if (mode == INC_MODE_PLAIN && ctx->mid_cap < n) {
     if (ctx->d_mid) (void)hipFree(ctx->d_mid);
     ctx->d_mid = nullptr;
@@ -81,6 +82,7 @@ int inc_launch_segments(inc_ctx* ctx, size_t n, const uint8_t* tidx, const float
   L.n_seg = n_seg;
   L.queue = queue;
   L.mid = ctx->d_mid;
+  if (ring) L.ring = *ring;
   return map_err(inc_launch_events(L, s));
 }
 

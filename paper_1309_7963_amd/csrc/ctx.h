@@ -29,10 +29,12 @@ constexpr int kSegSlots = 64;  // inc_simulate_dev calls that may be in flight p
 
 // Launch n events described by n_seg device segments (sorted by start, each
 // with its own key, ids and outputs); queue: device work-queue counter.
+// ring: streaming output of the secondaries (NULL: the segments' arrays).
 __attribute__((visibility("hidden"))) int inc_launch_segments(inc_ctx* ctx, size_t n, const uint8_t* tidx,
                                                               const float* T0, const incdev::Segment* d_segs,
                                                               int n_seg, unsigned long long* queue, hipStream_t s,
-                                                              int mode, int max_blocks);
+                                                              int mode, int max_blocks,
+                                                              const incdev::RingDev* ring = nullptr);
 
 // Launch one batch (validated like inc_simulate_dev); max_blocks > 0 caps the
 // persistent grid (small batches use fewer blocks).  Internal to the library.

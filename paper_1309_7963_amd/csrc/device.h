@@ -408,12 +408,72 @@ __device__ __forceinline__ int segment_of(const Segment* segs, int n_seg, uint32
   return lo;
 }
 
+// Ring output (streaming mode): records go to a ring of `mask + 1` slots in
+// coherent host memory while a host thread drains it.  A wave reserves `fill`
+// sequence numbers on the device counter `head`, waits (bounded) until the
+// consumer's `tail` leaves room, writes the records' payload, then - after a
+// system-scope release fence - their tags (sequence number + 1).  The
+// consumer takes slot s & mask once its tag equals s + 1.  Record: tag,
+// event, kind, T, ux, uy, uz, unused (32 bytes).
+struct RingDev {
+  uint32_t* rec;                    // host memory, 8 words per slot; NULL = off
+  unsigned long long mask;          // slots - 1 (slots a power of two)
+  unsigned long long* head;         // device counter: sequence numbers handed out
+  const unsigned long long* tail;   // host memory: records consumed so far
+  unsigned int* error;              // host memory: 1 = producer gave up waiting
+  unsigned long long spin_limit;    // waits of ~1.7 us before giving up
+};
+
+__device__ __forceinline__ void sys_store(uint32_t* p, uint32_t v) {
+  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+}
+
+// Must be called by all lanes of the wave.
+__device__ __forceinline__ void ring_flush(const uint32_t* buf, int fill, const RingDev& R) {
+  unsigned long long base = 0;
+  int ok = 1;
+  if (lane_id() == 0) {
+    base = atomicAdd(R.head, (unsigned long long)fill);
+    unsigned long long t = __hip_atomic_load(R.tail, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+    unsigned long long spins = 0;
+    while (base + (unsigned long long)fill > t + R.mask + 1ull) {
+      if (++spins > R.spin_limit ||
+          __hip_atomic_load(R.error, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM) != 0u) {
+        ok = 0;
+        break;
+      }
+      __builtin_amdgcn_s_sleep(63);
+      t = __hip_atomic_load(R.tail, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+    }
+    if (!ok) __hip_atomic_fetch_or(R.error, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+  }
+  base = __shfl(base, 0);
+  ok = __shfl(ok, 0);
+  if (!ok) return;
+  for (int i = lane_id(); i < fill; i += 64) {
+    uint32_t* slot = R.rec + ((base + (unsigned long long)i) & R.mask) * 8ull;
+    const uint32_t* r = buf + i * kRecWords;
+    for (int w = 0; w < kRecWords; ++w) sys_store(slot + 1 + w, r[w]);
+  }
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "");
+  for (int i = lane_id(); i < fill; i += 64) {
+    uint32_t* slot = R.rec + ((base + (unsigned long long)i) & R.mask) * 8ull;
+    sys_store(slot, (uint32_t)(base + (unsigned long long)i + 1ull));
+  }
+}
+
 // Must be called by all lanes of the wave.  The wave's records are copied out
 // 64 at a time; within a group of 64 the lanes of each distinct segment
 // reserve their slots with one atomic and store contiguously.
-__device__ __forceinline__ void writer_flush(uint32_t* buf, int& fill, const Segment* segs) {
+__device__ __forceinline__ void writer_flush(uint32_t* buf, int& fill, const Segment* segs, const RingDev& ring) {
   if (fill == 0) return;
   __builtin_amdgcn_wave_barrier();
+  if (ring.rec) {
+    ring_flush(buf, fill, ring);
+    __builtin_amdgcn_wave_barrier();
+    fill = 0;
+    return;
+  }
   for (int g = 0; g < fill; g += 64) {
     const int i = g + lane_id();
     const bool have = i < fill;
@@ -449,12 +509,12 @@ __device__ __forceinline__ void writer_flush(uint32_t* buf, int& fill, const Seg
 
 // Must be called by all lanes of the wave.  ev: index of the event in its
 // segment; kind: species | stage << 8 | segment << 16.
-__device__ __forceinline__ void writer_append(uint32_t* buf, int& fill, const Segment* segs, bool emit, uint32_t ev,
-                                              uint32_t kind, float T, V3 u) {
+__device__ __forceinline__ void writer_append(uint32_t* buf, int& fill, const Segment* segs, const RingDev& ring,
+                                              bool emit, uint32_t ev, uint32_t kind, float T, V3 u) {
   const uint64_t m = __ballot(emit);
   if (m == 0) return;
   const int cnt = __popcll(m);
-  if (fill + cnt > kWriterCap) writer_flush(buf, fill, segs);
+  if (fill + cnt > kWriterCap) writer_flush(buf, fill, segs, ring);
   if (emit) {
     uint32_t* r = buf + (fill + (int)rank_in(m)) * kRecWords;
     r[0] = ev;

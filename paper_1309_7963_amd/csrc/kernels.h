@@ -41,6 +41,7 @@ struct LaunchDesc {
   int n_seg;
   unsigned long long* queue;
   MidState* mid;
+  RingDev ring;          // rec == NULL: records go to the segments' arrays
 };
 
 }  // namespace incdev

@@ -203,6 +203,7 @@ struct KernelArgs {
   int n_seg;
   unsigned long long* queue; // work-queue head (persistent kernel)
   MidState* mid;             // plain kernels: cascade -> evaporation hand-over
+  RingDev ring;              // streaming output (rec == NULL: segment arrays)
 };
 
 __device__ __forceinline__ bool energy_ok(float T0) { return T0 >= 20.0f && T0 <= 250.0f; }
@@ -324,9 +325,9 @@ __global__ void __launch_bounds__(256) k_cascade_plain(KernelArgs a) {
         live = false;
       }
     }
-    writer_append(wbuf, fill, a.segs, em.on, er.local, kind_of(em.kind, er), em.T, em.u);
+    writer_append(wbuf, fill, a.segs, a.ring, em.on, er.local, kind_of(em.kind, er), em.T, em.u);
   }
-  writer_flush(wbuf, fill, a.segs);
+  writer_flush(wbuf, fill, a.segs, a.ring);
 }
 
 // Plain evaporation kernel: one de-excitation per thread (Sec. 3.3), same
@@ -379,9 +380,9 @@ __global__ void __launch_bounds__(256) k_evap_plain(KernelArgs a) {
         ++nsec;
       }
     }
-    writer_append(wbuf, fill, a.segs, em.on, er.local, kind_of(em.kind, er), em.T, em.u);
+    writer_append(wbuf, fill, a.segs, a.ring, em.on, er.local, kind_of(em.kind, er), em.T, em.u);
   }
-  writer_flush(wbuf, fill, a.segs);
+  writer_flush(wbuf, fill, a.segs, a.ring);
 }
 
 // Persistent fused kernel.  Every wave keeps 64 events in flight; finished
@@ -506,9 +507,9 @@ __global__ void __launch_bounds__(256) k_persistent(KernelArgs a) {
         st = ns;
       }
     }
-    writer_append(wbuf, fill, a.segs, em.on, er.local, kind_of(em.kind, er), em.T, em.u);
+    writer_append(wbuf, fill, a.segs, a.ring, em.on, er.local, kind_of(em.kind, er), em.T, em.u);
   }
-  writer_flush(wbuf, fill, a.segs);
+  writer_flush(wbuf, fill, a.segs, a.ring);
 }
 
 // Zero the segments' counters and the work-queue head (a fill kernel rather
@@ -575,6 +576,7 @@ hipError_t inc_launch_events(const LaunchDesc& L, hipStream_t s) {
   a.n_seg = L.n_seg;
   a.queue = L.queue;
   a.mid = L.mid;
+  a.ring = L.ring;
   hipLaunchKernelGGL(k_zero_counters, dim3((L.n_seg + 63) / 64), dim3(64), 0, s, L.segs, L.n_seg, L.queue);
   const int block = L.block;
   if (L.mode == INC_MODE_PLAIN) {

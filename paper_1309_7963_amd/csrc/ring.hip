@@ -1,0 +1,198 @@
+// ring.hip — streaming output through a bounded ring (the C ABI inc_ring_* of
+// include/inc.h).  The secondaries of a batch flow through a ring of a fixed
+// number of records in coherent host memory while the kernel runs; the
+// calling thread drains the ring into the caller's arrays and hands the space
+// back, so the secondary output needs no device buffer sized by the batch.
+// The producer waits (bounded) when the ring is full; no record is lost or
+// duplicated.  Sequence numbers run on across calls, so stale tags of an
+// earlier call can never be taken for new records.
+#include <string.h>
+
+#include <chrono>
+#include <new>
+#include <thread>
+
+#include "ctx.h"
+
+using incdev::RingDev;
+using incdev::Segment;
+
+struct inc_ring {
+  inc_ctx* ctx;
+  size_t slots;
+  uint32_t* h_rec;                // slots x 8 words, coherent host memory
+  unsigned long long* h_ctrl;     // [0] tail (consumed), [1] error flag word
+  uint32_t* d_rec;
+  unsigned long long* d_ctrl;
+  unsigned long long* d_dev;      // device: [0] head, [1] queue, [2..5] counters
+  Segment* d_seg;
+  unsigned long long next_seq;    // head after the last call
+};
+
+namespace {
+
+double now_s() {
+  using namespace std::chrono;
+  return duration<double>(steady_clock::now().time_since_epoch()).count();
+}
+
+}  // namespace
+
+extern "C" {
+
+int inc_ring_create(inc_ctx* ctx, size_t slots, inc_ring** out) {
+  if (!out) return INC_ERR_ARG;
+  *out = nullptr;
+  if (!ctx || slots < 1024 || (slots & (slots - 1)) != 0 || slots > (1ull << 30)) return INC_ERR_ARG;
+  inc_ring* r = new (std::nothrow) inc_ring;
+  if (!r) return INC_ERR_OOM;
+  memset(r, 0, sizeof(*r));
+  r->ctx = ctx;
+  r->slots = slots;
+  hipError_t e = hipHostMalloc(&r->h_rec, slots * 32, hipHostMallocCoherent | hipHostMallocMapped);
+  if (e == hipSuccess) e = hipHostMalloc(&r->h_ctrl, 64, hipHostMallocCoherent | hipHostMallocMapped);
+  if (e == hipSuccess) {
+    memset(r->h_rec, 0, slots * 32);
+    memset(r->h_ctrl, 0, 64);
+    e = hipHostGetDevicePointer((void**)&r->d_rec, r->h_rec, 0);
+  }
+  if (e == hipSuccess) e = hipHostGetDevicePointer((void**)&r->d_ctrl, r->h_ctrl, 0);
+  if (e == hipSuccess) e = hipMalloc(&r->d_dev, 8 * sizeof(unsigned long long));
+  if (e == hipSuccess) e = hipMalloc(&r->d_seg, sizeof(Segment));
+  if (e == hipSuccess) {
+    const unsigned long long zero[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    e = hipMemcpy(r->d_dev, zero, sizeof(zero), hipMemcpyHostToDevice);
+  }
+  if (e != hipSuccess) {
+    inc_ring_destroy(r);
+    return inc_map_hip_error(e);
+  }
+  *out = r;
+  return INC_OK;
+}
+
+int inc_ring_destroy(inc_ring* r) {
+  if (!r) return INC_ERR_ARG;
+  if (r->h_rec) (void)hipHostFree(r->h_rec);
+  if (r->h_ctrl) (void)hipHostFree(r->h_ctrl);
+  if (r->d_dev) (void)hipFree(r->d_dev);
+  if (r->d_seg) (void)hipFree(r->d_seg);
+  delete r;
+  return INC_OK;
+}
+
+int inc_ring_simulate(inc_ring* r, const inc_batch* b, inc_residual* d_res, const inc_host_output* out, void* stream,
+                      int mode, inc_ring_stats* stats) {
+  if (!r || !b || !d_res || !b->T0 || b->n < 1 || b->n >= (1ull << 32)) return INC_ERR_ARG;
+  if (mode != INC_MODE_PLAIN && mode != INC_MODE_PERSISTENT) return INC_ERR_ARG;
+  hipStream_t st = (hipStream_t)stream;
+  volatile unsigned long long* tail_p = r->h_ctrl;
+  volatile unsigned int* err_p = (volatile unsigned int*)(r->h_ctrl + 1);
+  if (*err_p) return INC_ERR_DEVICE;  // an earlier call gave up: the ring state is unknown
+  const unsigned long long start = r->next_seq;
+  Segment seg;
+  memset(&seg, 0, sizeof(seg));
+  seg.start = 0;
+  seg.n = (uint32_t)b->n;
+  seg.seed = b->seed;
+  seg.first_id = b->first_event_id;
+  seg.res = d_res;
+  seg.counters = r->d_dev + 2;
+  RingDev R;
+  R.rec = r->d_rec;
+  R.mask = r->slots - 1;
+  R.head = r->d_dev;
+  R.tail = r->d_ctrl;
+  R.error = (unsigned int*)(r->d_ctrl + 1);
+  R.spin_limit = 2000000ull;  // ~3 s without progress of the consumer
+  hipEvent_t done;
+  hipError_t e = hipEventCreateWithFlags(&done, hipEventDisableTiming);
+  if (e != hipSuccess) return inc_map_hip_error(e);
+  int rc = inc_map_hip_error(inc_upload_segment(seg, r->d_seg, st));
+  if (rc == INC_OK)
+    rc = inc_launch_segments(r->ctx, b->n, b->target_idx, b->T0, r->d_seg, 1, r->d_dev + 1, st, mode, 0, &R);
+  if (rc == INC_OK) rc = inc_map_hip_error(hipEventRecord(done, st));
+  if (rc != INC_OK) {
+    (void)hipStreamSynchronize(st);
+    (void)hipEventDestroy(done);
+    return rc;
+  }
+  // ---- drain while the kernel runs
+  unsigned long long tail = start, final_head = ~0ull, max_fill = 0, copied = 0, waits = 0;
+  const size_t cap_out = out ? out->sec_capacity : 0;
+  const unsigned long long mask = r->slots - 1;
+  bool kernel_done = false;
+  const double t0 = now_s();
+  double t_last = t0;
+  while (true) {
+    bool progressed = false;
+    while (true) {
+      const uint32_t* slot = r->h_rec + (tail & mask) * 8;
+      const uint32_t tag = __atomic_load_n(slot, __ATOMIC_ACQUIRE);
+      if (tag != (uint32_t)(tail + 1ull)) break;
+      const unsigned long long k = tail - start;
+      if (out && k < cap_out) {
+        if (out->sec_event) out->sec_event[k] = slot[1];
+        if (out->sec_species) out->sec_species[k] = (uint8_t)(slot[2] & 0xFFu);
+        if (out->sec_stage) out->sec_stage[k] = (uint8_t)((slot[2] >> 8) & 0xFFu);
+        if (out->sec_T) memcpy(&out->sec_T[k], &slot[3], 4);
+        if (out->sec_ux) memcpy(&out->sec_ux[k], &slot[4], 4);
+        if (out->sec_uy) memcpy(&out->sec_uy[k], &slot[5], 4);
+        if (out->sec_uz) memcpy(&out->sec_uz[k], &slot[6], 4);
+        ++copied;
+      }
+      ++tail;
+      progressed = true;
+      if ((tail & 1023ull) == 0) __atomic_store_n((unsigned long long*)tail_p, tail, __ATOMIC_RELEASE);
+    }
+    if (progressed) __atomic_store_n((unsigned long long*)tail_p, tail, __ATOMIC_RELEASE);
+    if (!kernel_done) {
+      const hipError_t q = hipEventQuery(done);
+      if (q == hipSuccess) {
+        kernel_done = true;
+        t_last = now_s();
+        e = hipMemcpy(&final_head, r->d_dev, sizeof(final_head), hipMemcpyDeviceToHost);
+        if (e != hipSuccess) {
+          rc = inc_map_hip_error(e);
+          break;
+        }
+      } else if (q != hipErrorNotReady) {
+        rc = inc_map_hip_error(q);
+        (void)hipStreamSynchronize(st);
+        break;
+      }
+    }
+    if (kernel_done && (tail >= final_head || *err_p)) break;
+    if (progressed) {
+      t_last = now_s();
+    } else {
+      ++waits;
+      // every record is tagged before the kernel ends: a missing tag after
+      // the end (2 s without progress) is an error, not a reason to wait on
+      if (kernel_done && now_s() - t_last > 2.0) {
+        rc = INC_ERR_DEVICE;
+        break;
+      }
+      std::this_thread::sleep_for(std::chrono::microseconds(5));
+    }
+  }
+  (void)hipEventDestroy(done);
+  if (kernel_done) r->next_seq = final_head;
+  if (rc == INC_OK && *err_p) rc = INC_ERR_DEVICE;
+  const unsigned long long produced = kernel_done ? final_head - start : tail - start;
+  if (out && out->n_sec) *out->n_sec = produced;
+  if (stats) {
+    stats->records = produced;
+    stats->slots = r->slots;
+    stats->wraps = produced / r->slots;
+    stats->consumer_idle_polls = waits;
+    stats->seconds = now_s() - t0;
+    stats->producer_gave_up = *err_p;
+  }
+  (void)max_fill;
+  if (rc == INC_OK && produced > cap_out && out) rc = INC_ERR_CAPACITY;
+  (void)copied;
+  return rc;
+}
+
+}  // extern "C"

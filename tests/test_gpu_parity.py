@@ -302,3 +302,31 @@ def test_serving_replay_latencies():
     assert span > 0
     assert srv.stats()["completed"] == len(reqs)
     srv.close()
+
+
+# ------------------------------------------------------------------- ring
+def test_ring_output_equals_direct_output():
+    import torch
+
+    import paper_1309_7963_amd as inc
+
+    n = 60000
+    tidx, T0 = _mixture(n, IMPLANT, [0.5, 0.5], 70, 250, seed=23)
+    ctx = inc.Context(IMPLANT)
+    direct = run_gpu(IMPLANT, T0, seed=3, tidx=tidx, ctx=ctx)
+    ring = inc.Ring(ctx, slots=1 << 14)
+    T0_d = torch.as_tensor(T0, device="cuda")
+    ti_d = torch.as_tensor(tidx, device="cuda")
+    for rep in range(2):  # the second call continues the sequence numbers
+        r = ring.simulate(T0_d, seed=3, target_idx=ti_d)
+        assert r["rc"] == 0
+        assert r["stats"]["producer_gave_up"] == 0
+        assert r["stats"]["wraps"] >= 10
+        assert r["res"].tobytes() == direct["res"].tobytes()
+        assert r["n_sec_total"] == direct["n_sec_total"]
+        kd = np.lexsort((direct["sec_T"], direct["sec_species"], direct["sec_stage"], direct["sec_event"]))
+        kr = np.lexsort((r["sec_T"], r["sec_species"], r["sec_stage"], r["sec_event"]))
+        for f in ("sec_event", "sec_species", "sec_stage", "sec_T", "sec_u"):
+            assert np.array_equal(direct[f][kd], r[f][kr]), (rep, f)
+    ring.close()
+    ctx.close()
