@@ -413,10 +413,17 @@ __device__ __forceinline__ int segment_of(const Segment* segs, int n_seg, uint32
 // sequence numbers on the device counter `head`, waits (bounded) until the
 // consumer's `tail` leaves room, writes the records' payload, then - after a
 // system-scope release fence - their tags (sequence number + 1).  The
-// consumer takes slot s & mask once its tag equals s + 1.  Record: tag,
-// event, kind, T, ux, uy, uz, unused (32 bytes).
+// consumer takes slot s & mask once its tag equals s + 1.  The ring is a
+// structure of arrays so that a wave's stores are contiguous (256 bytes per
+// array and store instruction).
 struct RingDev {
-  uint32_t* rec;                    // host memory, 8 words per slot; NULL = off
+  uint32_t* tag;                    // host memory, one array per field; NULL = off
+  uint32_t* ev;
+  uint32_t* kind;
+  uint32_t* T;                      // float bits
+  uint32_t* ux;
+  uint32_t* uy;
+  uint32_t* uz;
   unsigned long long mask;          // slots - 1 (slots a power of two)
   unsigned long long* head;         // device counter: sequence numbers handed out
   const unsigned long long* tail;   // host memory: records consumed so far
@@ -451,14 +458,19 @@ __device__ __forceinline__ void ring_flush(const uint32_t* buf, int fill, const 
   ok = __shfl(ok, 0);
   if (!ok) return;
   for (int i = lane_id(); i < fill; i += 64) {
-    uint32_t* slot = R.rec + ((base + (unsigned long long)i) & R.mask) * 8ull;
+    const unsigned long long k = (base + (unsigned long long)i) & R.mask;
     const uint32_t* r = buf + i * kRecWords;
-    for (int w = 0; w < kRecWords; ++w) sys_store(slot + 1 + w, r[w]);
+    sys_store(R.ev + k, r[0]);
+    sys_store(R.kind + k, r[1]);
+    sys_store(R.T + k, r[2]);
+    sys_store(R.ux + k, r[3]);
+    sys_store(R.uy + k, r[4]);
+    sys_store(R.uz + k, r[5]);
   }
   __builtin_amdgcn_fence(__ATOMIC_RELEASE, "");
   for (int i = lane_id(); i < fill; i += 64) {
-    uint32_t* slot = R.rec + ((base + (unsigned long long)i) & R.mask) * 8ull;
-    sys_store(slot, (uint32_t)(base + (unsigned long long)i + 1ull));
+    const unsigned long long k = (base + (unsigned long long)i) & R.mask;
+    sys_store(R.tag + k, (uint32_t)(base + (unsigned long long)i + 1ull));
   }
 }
 
@@ -468,7 +480,7 @@ __device__ __forceinline__ void ring_flush(const uint32_t* buf, int fill, const 
 __device__ __forceinline__ void writer_flush(uint32_t* buf, int& fill, const Segment* segs, const RingDev& ring) {
   if (fill == 0) return;
   __builtin_amdgcn_wave_barrier();
-  if (ring.rec) {
+  if (ring.tag) {
     ring_flush(buf, fill, ring);
     __builtin_amdgcn_wave_barrier();
     fill = 0;

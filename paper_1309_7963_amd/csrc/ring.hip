@@ -8,6 +8,7 @@
 // earlier call can never be taken for new records.
 #include <string.h>
 
+#include <algorithm>
 #include <chrono>
 #include <new>
 #include <thread>
@@ -20,7 +21,7 @@ using incdev::Segment;
 struct inc_ring {
   inc_ctx* ctx;
   size_t slots;
-  uint32_t* h_rec;                // slots x 8 words, coherent host memory
+  uint32_t* h_rec;                // 7 arrays of `slots` words (tag, ev, kind, T, ux, uy, uz), coherent host memory
   unsigned long long* h_ctrl;     // [0] tail (consumed), [1] error flag word
   uint32_t* d_rec;
   unsigned long long* d_ctrl;
@@ -49,10 +50,10 @@ int inc_ring_create(inc_ctx* ctx, size_t slots, inc_ring** out) {
   memset(r, 0, sizeof(*r));
   r->ctx = ctx;
   r->slots = slots;
-  hipError_t e = hipHostMalloc(&r->h_rec, slots * 32, hipHostMallocCoherent | hipHostMallocMapped);
+  hipError_t e = hipHostMalloc(&r->h_rec, slots * 28, hipHostMallocCoherent | hipHostMallocMapped);
   if (e == hipSuccess) e = hipHostMalloc(&r->h_ctrl, 64, hipHostMallocCoherent | hipHostMallocMapped);
   if (e == hipSuccess) {
-    memset(r->h_rec, 0, slots * 32);
+    memset(r->h_rec, 0, slots * 28);
     memset(r->h_ctrl, 0, 64);
     e = hipHostGetDevicePointer((void**)&r->d_rec, r->h_rec, 0);
   }
@@ -99,7 +100,13 @@ int inc_ring_simulate(inc_ring* r, const inc_batch* b, inc_residual* d_res, cons
   seg.res = d_res;
   seg.counters = r->d_dev + 2;
   RingDev R;
-  R.rec = r->d_rec;
+  R.tag = r->d_rec;
+  R.ev = r->d_rec + r->slots;
+  R.kind = r->d_rec + 2 * r->slots;
+  R.T = r->d_rec + 3 * r->slots;
+  R.ux = r->d_rec + 4 * r->slots;
+  R.uy = r->d_rec + 5 * r->slots;
+  R.uz = r->d_rec + 6 * r->slots;
   R.mask = r->slots - 1;
   R.head = r->d_dev;
   R.tail = r->d_ctrl;
@@ -126,24 +133,35 @@ int inc_ring_simulate(inc_ring* r, const inc_batch* b, inc_residual* d_res, cons
   double t_last = t0;
   while (true) {
     bool progressed = false;
+    const uint32_t* h_tag = r->h_rec;
+    const size_t S = r->slots;
     while (true) {
-      const uint32_t* slot = r->h_rec + (tail & mask) * 8;
-      const uint32_t tag = __atomic_load_n(slot, __ATOMIC_ACQUIRE);
-      if (tag != (uint32_t)(tail + 1ull)) break;
+      // the run of ready records starting at tail, within the ring's linear range
+      const size_t j = (size_t)(tail & mask);
+      size_t run = 0;
+      while (run < S - j && run < 65536 &&
+             __atomic_load_n(h_tag + j + run, __ATOMIC_RELAXED) == (uint32_t)(tail + run + 1ull))
+        ++run;
+      if (run == 0) break;
+      __atomic_thread_fence(__ATOMIC_ACQUIRE);
       const unsigned long long k = tail - start;
       if (out && k < cap_out) {
-        if (out->sec_event) out->sec_event[k] = slot[1];
-        if (out->sec_species) out->sec_species[k] = (uint8_t)(slot[2] & 0xFFu);
-        if (out->sec_stage) out->sec_stage[k] = (uint8_t)((slot[2] >> 8) & 0xFFu);
-        if (out->sec_T) memcpy(&out->sec_T[k], &slot[3], 4);
-        if (out->sec_ux) memcpy(&out->sec_ux[k], &slot[4], 4);
-        if (out->sec_uy) memcpy(&out->sec_uy[k], &slot[5], 4);
-        if (out->sec_uz) memcpy(&out->sec_uz[k], &slot[6], 4);
-        ++copied;
+        const size_t m = (size_t)std::min<unsigned long long>(run, cap_out - k);
+        const uint32_t* kind = r->h_rec + 2 * S + j;
+        if (out->sec_event) memcpy(out->sec_event + k, r->h_rec + S + j, 4 * m);
+        if (out->sec_T) memcpy(out->sec_T + k, r->h_rec + 3 * S + j, 4 * m);
+        if (out->sec_ux) memcpy(out->sec_ux + k, r->h_rec + 4 * S + j, 4 * m);
+        if (out->sec_uy) memcpy(out->sec_uy + k, r->h_rec + 5 * S + j, 4 * m);
+        if (out->sec_uz) memcpy(out->sec_uz + k, r->h_rec + 6 * S + j, 4 * m);
+        if (out->sec_species)
+          for (size_t q = 0; q < m; ++q) out->sec_species[k + q] = (uint8_t)(kind[q] & 0xFFu);
+        if (out->sec_stage)
+          for (size_t q = 0; q < m; ++q) out->sec_stage[k + q] = (uint8_t)((kind[q] >> 8) & 0xFFu);
+        copied += m;
       }
-      ++tail;
+      tail += run;
       progressed = true;
-      if ((tail & 1023ull) == 0) __atomic_store_n((unsigned long long*)tail_p, tail, __ATOMIC_RELEASE);
+      __atomic_store_n((unsigned long long*)tail_p, tail, __ATOMIC_RELEASE);
     }
     if (progressed) __atomic_store_n((unsigned long long*)tail_p, tail, __ATOMIC_RELEASE);
     if (!kernel_done) {
