@@ -69,6 +69,11 @@ typedef struct {
   int tent_threshold;    /* make a wave run that state's step next (1..64): */
   int kin_threshold;     /* evaporation, tentative collision, kinematics     */
   int waves_per_cu;      /* persistent kernel: resident waves per CU         */
+  int stack_levels;      /* entries of each lane's LIFO kept in LDS (deeper  */
+                         /* ones in private memory): 0 = as many as fit     */
+                         /* beside the tables at the launch's occupancy, up */
+                         /* to 4; -1 = none; 1..4 = at most that many.      */
+                         /* Results do not depend on it.                    */
 } inc_options;
 
 /* One residual nucleus per event, 32 bytes. */

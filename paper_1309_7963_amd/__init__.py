@@ -112,7 +112,10 @@ class Context:
         self.targets = [(int(a), int(z)) for a, z in targets]
         arr = (_lib.Nucleus * len(self.targets))(*[_lib.Nucleus(a, z) for a, z in self.targets])
         opt = _lib.Options()
+        known = {f[0] for f in _lib.Options._fields_} | {"fixed_b"}
         for k, v in options.items():
+            if k not in known:
+                raise TypeError("unknown Context option %r" % k)
             if k == "fixed_b" and v is not None:
                 opt.fixed_b_on = 1
                 opt.fixed_b = float(v)

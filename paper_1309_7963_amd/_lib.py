@@ -40,7 +40,7 @@ class Options(C.Structure):
         ("no_pauli", C.c_int), ("no_evaporation", C.c_int), ("stop_after_first", C.c_int),
         ("const_sigma_mb", C.c_float), ("fixed_b_on", C.c_int), ("fixed_b", C.c_float),
         ("block_size", C.c_int), ("evap_threshold", C.c_int), ("tent_threshold", C.c_int),
-        ("kin_threshold", C.c_int), ("waves_per_cu", C.c_int),
+        ("kin_threshold", C.c_int), ("waves_per_cu", C.c_int), ("stack_levels", C.c_int),
     ]
 
 

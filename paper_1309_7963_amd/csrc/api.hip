@@ -65,6 +65,7 @@ int inc_launch_segments(inc_ctx* ctx, size_t n, const uint8_t* tidx, const float
   L.evap_threshold = ctx->evap_threshold;
   L.tent_threshold = ctx->tent_threshold;
   L.kin_threshold = ctx->kin_threshold;
+  L.stack_lds = ctx->stack_lds[mode == INC_MODE_PLAIN ? 0 : 1];
   L.nuc = ctx->d_nuc;
   L.n_targets = ctx->n_targets;
   L.xs = ctx->d_xs;
@@ -146,7 +147,8 @@ int inc_ctx_create(const inc_nucleus* targets, int n_targets, const inc_options*
   if (opt) o = *opt;
   if (o.block_size && (o.block_size < 64 || o.block_size > 256 || o.block_size % 64)) return INC_ERR_ARG;
   if (o.evap_threshold < 0 || o.evap_threshold > 64 || o.tent_threshold < 0 || o.tent_threshold > 64 ||
-      o.kin_threshold < 0 || o.kin_threshold > 64 || o.waves_per_cu < 0 || o.waves_per_cu > 32)
+      o.kin_threshold < 0 || o.kin_threshold > 64 || o.waves_per_cu < 0 || o.waves_per_cu > 32 ||
+      o.stack_levels < -1 || o.stack_levels > incdev::kStackLdsMax)
     return INC_ERR_ARG;
   if (!(o.const_sigma_mb >= 0.0f) || o.const_sigma_mb > 1e5f) return INC_ERR_ARG;
   if (o.fixed_b_on && !(o.fixed_b >= 0.0f && o.fixed_b < 20.0f)) return INC_ERR_ARG;
@@ -196,6 +198,12 @@ int inc_ctx_create(const inc_nucleus* targets, int n_targets, const inc_options*
       break;
     if ((e = hipDeviceSynchronize()) != hipSuccess) break;
     e = hipMemcpy(&c->evap, d_evap, sizeof(EvapTab), hipMemcpyDeviceToHost);
+    for (int m = 0; m < 2; ++m) {
+      int lv = inc_stack_levels(m == 0 ? INC_MODE_PLAIN : INC_MODE_PERSISTENT, n_targets, c->block, c->waves_per_cu);
+      if (o.stack_levels < 0) lv = 0;
+      else if (o.stack_levels > 0 && o.stack_levels < lv) lv = o.stack_levels;
+      c->stack_lds[m] = lv;
+    }
   } while (false);
   if (d_AZ) (void)hipFree(d_AZ);
   if (d_evap) (void)hipFree(d_evap);

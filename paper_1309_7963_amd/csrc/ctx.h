@@ -22,6 +22,7 @@ struct inc_ctx {
   unsigned seg_next;
   int n_cu;
   int block, evap_threshold, tent_threshold, kin_threshold, waves_per_cu;
+  int stack_lds[2];  // LIFO entries per lane in LDS: [plain, persistent]
 };
 
 

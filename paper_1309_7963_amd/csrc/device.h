@@ -15,6 +15,7 @@ namespace incdev {
 constexpr int kShells = 15;
 constexpr int kMaxTargets = 16;
 constexpr int kStackDepth = 64;      // LIFO guard (depth 64)
+constexpr int kStackLdsMax = 4;      // stack entries per lane that may sit in LDS
 constexpr int kMaxSegments = 10000;  // flight-segment guard per event
 constexpr int kXsNodes = 512;        // log-spaced p_lab nodes
 constexpr float kPi = 3.14159265358979323846f;

@@ -25,7 +25,7 @@ enum : int {
 };
 
 // Cascade state of one event (registers).  The LIFO of pending products
-// lives in a private (scratch) array owned by the kernel.
+// is split between LDS and a private array owned by the kernel.
 struct Cascade {
   V3 pos, dir;
   float eps;       // T - E_F(local): invariant under refraction
@@ -40,6 +40,7 @@ struct Cascade {
   int started;
   V3 pt;           // target momentum of the pending collision (TENT -> KIN)
   int ytgt;        // target species of the pending collision
+  int stk_base, stk_levels;  // LDS part of the LIFO (set by the kernel)
 };
 
 // Residual nucleus entering / leaving the evaporation.
@@ -49,23 +50,46 @@ struct Nucleus {
   V3 P;      // momentum
 };
 
+// LIFO of pending products (depth kStackDepth).  The lowest `stk_levels`
+// entries of each lane sit in LDS, interleaved over the 64 lanes of the wave
+// (entry t, half h of the lane at float4 index stk_base + (2 t + h) * 64 of the
+// dynamic LDS), so a wave's pushes and pops are bank-conflict-free and never
+// leave the CU; deeper entries go to the kernel's private array.  An entry is
+// (pos, dir.x) and (dir.y, dir.z, eps, sp | shell << 1).
+extern __shared__ __align__(16) float4 lds_f4[];
+
 struct StackEntry {
-  float v[8];  // pos xyz, dir xyz, eps, (sp | shell << 1) as bits
+  float v[8];
 };
 
 __device__ __forceinline__ void push(StackEntry* stk, Cascade& c, V3 pos, V3 dir, float eps, int sp) {
-  StackEntry& e = stk[c.top++];
-  e.v[0] = pos.x; e.v[1] = pos.y; e.v[2] = pos.z;
-  e.v[3] = dir.x; e.v[4] = dir.y; e.v[5] = dir.z;
-  e.v[6] = eps;
-  e.v[7] = __int_as_float(sp | (c.shell << 1));
+  const int t = c.top++;
+  const float4 lo = make_float4(pos.x, pos.y, pos.z, dir.x);
+  const float4 hi = make_float4(dir.y, dir.z, eps, __int_as_float(sp | (c.shell << 1)));
+  if (t < c.stk_levels) {
+    lds_f4[c.stk_base + 2 * t * 64] = lo;
+    lds_f4[c.stk_base + (2 * t + 1) * 64] = hi;
+  } else {
+    float* v = stk[t].v;
+    v[0] = lo.x; v[1] = lo.y; v[2] = lo.z; v[3] = lo.w;
+    v[4] = hi.x; v[5] = hi.y; v[6] = hi.z; v[7] = hi.w;
+  }
 }
 __device__ __forceinline__ void pop(StackEntry* stk, Cascade& c) {
-  const StackEntry& e = stk[--c.top];
-  c.pos = {e.v[0], e.v[1], e.v[2]};
-  c.dir = {e.v[3], e.v[4], e.v[5]};
-  c.eps = e.v[6];
-  const int k = __float_as_int(e.v[7]);
+  const int t = --c.top;
+  float4 lo, hi;
+  if (t < c.stk_levels) {
+    lo = lds_f4[c.stk_base + 2 * t * 64];
+    hi = lds_f4[c.stk_base + (2 * t + 1) * 64];
+  } else {
+    const float* v = stk[t].v;
+    lo = make_float4(v[0], v[1], v[2], v[3]);
+    hi = make_float4(v[4], v[5], v[6], v[7]);
+  }
+  c.pos = {lo.x, lo.y, lo.z};
+  c.dir = {lo.w, hi.x, hi.y};
+  c.eps = hi.z;
+  const int k = __float_as_int(hi.w);
   c.sp = k & 1;
   c.shell = k >> 1;
 }

@@ -25,6 +25,7 @@ struct LaunchDesc {
   int block;
   int persistent_blocks;
   int evap_threshold, tent_threshold, kin_threshold;
+  int stack_lds;         // stack entries per lane held in LDS (inc_stack_levels)
   const NucTab* nuc;
   int n_targets;
   const XsTab* xs;
@@ -46,7 +47,11 @@ struct LaunchDesc {
 
 }  // namespace incdev
 
-size_t inc_lds_bytes(int n_targets, int block, bool with_xs);
+size_t inc_lds_bytes(int n_targets, int block, bool with_xs, int stack_levels);
+// Stack entries per lane that fit in LDS for the event kernel of `mode` at the
+// given block size when `waves_per_cu` waves are meant to share a CU (the
+// kernel's own occupancy limit applies too); 0 when none fit.
+int inc_stack_levels(int mode, int n_targets, int block, int waves_per_cu);
 hipError_t inc_launch_setup(const int* d_AZ, int n_targets, incdev::NucTab* d_nuc, incdev::XsTab* d_xs, double* d_B,
                             int amax, int zmax, incdev::EvapTab* d_evap, incdev::MassTab* d_mass, const inc_options& o,
                             hipStream_t s);

@@ -204,15 +204,25 @@ struct KernelArgs {
   unsigned long long* queue; // work-queue head (persistent kernel)
   MidState* mid;             // plain kernels: cascade -> evaporation hand-over
   RingDev ring;              // streaming output (rec == NULL: segment arrays)
+  int stack_lds;             // stack entries per lane held in LDS
 };
 
 __device__ __forceinline__ bool energy_ok(float T0) { return T0 >= 20.0f && T0 <= 250.0f; }
 
 // LDS layout of the event kernels: [n_targets NucTab][XsTab][MassTab][writer
-// buffers of the block's waves].  The plain evaporation kernel stages only the
-// MassTab (n_targets = 0, no XsTab).
+// buffers of the block's waves][LIFO levels: per wave stack_lds x 2 x 64
+// float4].  The plain evaporation kernel stages only the MassTab (n_targets =
+// 0, no XsTab) and has no stack.
 __device__ __forceinline__ size_t lds_mass_offset(int n_targets, bool with_xs) {
   return (size_t)n_targets * sizeof(NucTab) + (with_xs ? sizeof(XsTab) : 0);
+}
+// First float4 of this lane's column in the LDS stack area (each wave owns
+// levels x 2 x 64 consecutive float4).
+__device__ __forceinline__ int lds_stack_base(int n_targets, int levels) {
+  return (int)((lds_mass_offset(n_targets, true) + sizeof(MassTab) +
+                (blockDim.x / 64) * (kWriterCap * kRecWords * sizeof(uint32_t))) /
+               sizeof(float4)) +
+         (int)(threadIdx.x / 64) * levels * 128 + (int)(threadIdx.x % 64);
 }
 __device__ __forceinline__ void stage_tables(char* lds, const KernelArgs& a, int n_targets, bool with_xs) {
   uint32_t* dst = (uint32_t*)lds;
@@ -299,6 +309,8 @@ __global__ void __launch_bounds__(256) k_cascade_plain(KernelArgs a) {
   Cascade c;
   cascade_init(c, nt);
   StackEntry stk[kStackDepth];
+  c.stk_base = lds_stack_base(a.n_targets, a.stack_lds);
+  c.stk_levels = a.stack_lds;
 
   while (__any(live)) {
     Emit em;
@@ -395,7 +407,9 @@ __global__ void __launch_bounds__(256) k_evap_plain(KernelArgs a) {
 // depend on the schedule.
 constexpr int kChunk = 64;
 
-__global__ void __launch_bounds__(256) k_persistent(KernelArgs a) {
+// 3 waves per SIMD (<= 168 VGPRs): the lane scheduler needs many events in
+// flight per CU more than it needs extra registers.
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) k_persistent(KernelArgs a) {
   extern __shared__ __align__(16) char lds[];
   stage_tables(lds, a, a.n_targets, true);
   const NucTab* snt = (const NucTab*)lds;
@@ -416,6 +430,8 @@ __global__ void __launch_bounds__(256) k_persistent(KernelArgs a) {
   Cascade c;
   Nucleus nu = {0, 0, 0.0f, {0.0f, 0.0f, 0.0f}};
   StackEntry stk[kStackDepth];
+  c.stk_base = lds_stack_base(a.n_targets, a.stack_lds);
+  c.stk_levels = a.stack_lds;
 
   for (;;) {
     // ---- refill finished lanes from the work queue
@@ -533,9 +549,32 @@ __global__ void k_set_segment(Segment s, Segment* dst) {
 // ================================================================ launchers
 using namespace incdev;
 
-size_t inc_lds_bytes(int n_targets, int block, bool with_xs) {
+size_t inc_lds_bytes(int n_targets, int block, bool with_xs, int stack_levels) {
   return (size_t)n_targets * sizeof(NucTab) + (with_xs ? sizeof(XsTab) : 0) + sizeof(MassTab) +
-         (size_t)(block / 64) * kWriterCap * kRecWords * sizeof(uint32_t);
+         (size_t)(block / 64) * kWriterCap * kRecWords * sizeof(uint32_t) +
+         (size_t)stack_levels * 2 * block * sizeof(float4);
+}
+
+int inc_stack_levels(int mode, int n_targets, int block, int waves_per_cu) {
+  int dev = 0, lds_cu = 0;
+  if (hipGetDevice(&dev) != hipSuccess ||
+      hipDeviceGetAttribute(&lds_cu, hipDeviceAttributeMaxSharedMemoryPerMultiprocessor, dev) != hipSuccess ||
+      lds_cu <= 0)
+    return 0;
+  const size_t base = inc_lds_bytes(n_targets, block, true, 0);
+  int occ = 0;
+  const void* fn = mode == INC_MODE_PLAIN ? (const void*)k_cascade_plain : (const void*)k_persistent;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, fn, block, base) != hipSuccess || occ < 1) return 0;
+  int blocks = occ;
+  if (mode != INC_MODE_PLAIN) {
+    const int want = (waves_per_cu * 64 + block - 1) / block;
+    if (want < blocks) blocks = want < 1 ? 1 : want;
+  }
+  // keep a 1 KiB allocation margin per workgroup
+  const size_t budget = (size_t)lds_cu / blocks;
+  if (budget < base + 1024) return 0;
+  const size_t levels = (budget - base - 1024) / (2 * (size_t)block * sizeof(float4));
+  return levels > (size_t)kStackLdsMax ? kStackLdsMax : (int)levels;
 }
 
 hipError_t inc_launch_setup(const int* d_AZ, int n_targets, NucTab* d_nuc, XsTab* d_xs, double* d_B, int amax,
@@ -577,15 +616,17 @@ hipError_t inc_launch_events(const LaunchDesc& L, hipStream_t s) {
   a.queue = L.queue;
   a.mid = L.mid;
   a.ring = L.ring;
+  a.stack_lds = L.stack_lds;
   hipLaunchKernelGGL(k_zero_counters, dim3((L.n_seg + 63) / 64), dim3(64), 0, s, L.segs, L.n_seg, L.queue);
   const int block = L.block;
   if (L.mode == INC_MODE_PLAIN) {
     const unsigned grid = (unsigned)((L.n + block - 1) / block);
-    hipLaunchKernelGGL(k_cascade_plain, dim3(grid), dim3(block), inc_lds_bytes(L.n_targets, block, true), s, a);
-    hipLaunchKernelGGL(k_evap_plain, dim3(grid), dim3(block), inc_lds_bytes(0, block, false), s, a);
+    hipLaunchKernelGGL(k_cascade_plain, dim3(grid), dim3(block), inc_lds_bytes(L.n_targets, block, true, L.stack_lds),
+                       s, a);
+    hipLaunchKernelGGL(k_evap_plain, dim3(grid), dim3(block), inc_lds_bytes(0, block, false, 0), s, a);
   } else {
-    hipLaunchKernelGGL(k_persistent, dim3(L.persistent_blocks), dim3(block), inc_lds_bytes(L.n_targets, block, true), s,
-                       a);
+    hipLaunchKernelGGL(k_persistent, dim3(L.persistent_blocks), dim3(block),
+                       inc_lds_bytes(L.n_targets, block, true, L.stack_lds), s, a);
   }
   return hipGetLastError();
 }
