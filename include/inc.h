@@ -74,6 +74,10 @@ typedef struct {
                          /* beside the tables at the launch's occupancy, up */
                          /* to 4; -1 = none; 1..4 = at most that many.      */
                          /* Results do not depend on it.                    */
+  /* diagnostics */
+  int same_stream;       /* every event of a launch draws from the random    */
+                         /* stream of its request's first event id, so all   */
+                         /* lanes follow one history (divergence-free rate)  */
 } inc_options;
 
 /* One residual nucleus per event, 32 bytes. */

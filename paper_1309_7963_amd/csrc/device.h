@@ -75,6 +75,7 @@ struct Opts {
   float const_sigma_mb;  // > 0 overrides every NN cross-section
   float fixed_b;         // >= 0 fixes the impact parameter
   int evap_threshold, tent_threshold, kin_threshold;
+  int same_stream;       // every event uses its segment's first id
 };
 
 // Binding energies B(A, Z) in double for A <= amax, Z <= zmax.

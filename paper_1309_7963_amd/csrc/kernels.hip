@@ -268,7 +268,7 @@ __device__ __forceinline__ EventRef event_ref(const KernelArgs& a, size_t i) {
   return e;
 }
 __device__ __forceinline__ void init_stream(Rng& rng, const KernelArgs& a, EventRef e) {
-  rng.init(a.segs[e.seg].seed, a.segs[e.seg].first_id + e.local);
+  rng.init(a.segs[e.seg].seed, a.segs[e.seg].first_id + (a.opt.same_stream ? 0 : e.local));
 }
 __device__ __forceinline__ uint32_t kind_of(uint32_t k, EventRef e) { return k | ((uint32_t)e.seg << 16); }
 
@@ -608,6 +608,7 @@ hipError_t inc_launch_events(const LaunchDesc& L, hipStream_t s) {
   a.opt.evap_threshold = L.evap_threshold;
   a.opt.tent_threshold = L.tent_threshold;
   a.opt.kin_threshold = L.kin_threshold;
+  a.opt.same_stream = L.opt.same_stream;
   a.n = L.n;
   a.tidx = L.tidx;
   a.T0 = L.T0;

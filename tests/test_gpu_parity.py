@@ -164,6 +164,26 @@ def test_stack_placement_does_not_change_results(mode):
             assert np.array_equal(runs[0][f][k0], h[f][k1]), f
 
 
+@pytest.mark.parametrize("mode", ["plain", "persistent"])
+def test_same_stream_hook_repeats_one_history(mode):
+    """Diagnostic hook: every event of the launch replays the first event's
+    stream, so all residuals and per-event secondary lists are identical."""
+    n = 3000
+    T0 = np.full(n, 200.0, dtype=np.float32)
+    h = run_gpu([CA40], T0, seed=12, first_id=77, mode=mode, same_stream=1)
+    ref = run_gpu([CA40], T0[:1], seed=12, first_id=77, mode=mode)
+    assert (h["res"] == h["res"][0]).all()
+    assert h["res"][:1].tobytes() == ref["res"].tobytes()
+    m = int(ref["res"]["n_sec"][0])
+    assert len(h["sec_event"]) == n * m
+    counts = np.bincount(h["sec_event"].astype(np.int64), minlength=n)
+    assert (counts == m).all()
+    k = np.lexsort((h["sec_T"], h["sec_event"]))
+    kr = np.argsort(ref["sec_T"], kind="stable")
+    for f in ("sec_species", "sec_stage", "sec_T"):
+        assert np.array_equal(h[f][k].reshape(n, m), np.broadcast_to(ref[f][kr], (n, m))), f
+
+
 def test_event_identity_independent_of_batching():
     n = 8000
     T0 = np.full(n, 150.0, dtype=np.float32)
