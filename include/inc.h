@@ -78,6 +78,13 @@ typedef struct {
   int same_stream;       /* every event of a launch draws from the random    */
                          /* stream of its request's first event id, so all   */
                          /* lanes follow one history (divergence-free rate)  */
+  /* arithmetic (Sec. 4.2) */
+  int fast_math;         /* 1: event kernels built with approximate          */
+                         /* transcendentals (hardware log2, exp2, sqrt),     */
+                         /* reciprocal division and flushed FP32 denormals;  */
+                         /* results differ from the default in the last bits */
+                         /* of each step, so event histories diverge, and    */
+                         /* agree with it in distribution                    */
 } inc_options;
 
 /* One residual nucleus per event, 32 bytes. */

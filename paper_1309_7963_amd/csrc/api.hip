@@ -84,7 +84,7 @@ int inc_launch_segments(inc_ctx* ctx, size_t n, const uint8_t* tidx, const float
   L.queue = queue;
   L.mid = ctx->d_mid;
   if (ring) L.ring = *ring;
-  return map_err(inc_launch_events(L, s));
+  return map_err(ctx->opt.fast_math ? fast::launch_events(L, s) : precise::launch_events(L, s));
 }
 
 int inc_launch_batch(inc_ctx* ctx, const inc_batch* b, const inc_output* out, hipStream_t s, int mode, int max_blocks) {
@@ -148,7 +148,8 @@ int inc_ctx_create(const inc_nucleus* targets, int n_targets, const inc_options*
   if (o.block_size && (o.block_size < 64 || o.block_size > 256 || o.block_size % 64)) return INC_ERR_ARG;
   if (o.evap_threshold < 0 || o.evap_threshold > 64 || o.tent_threshold < 0 || o.tent_threshold > 64 ||
       o.kin_threshold < 0 || o.kin_threshold > 64 || o.waves_per_cu < 0 || o.waves_per_cu > 32 ||
-      o.stack_levels < -1 || o.stack_levels > incdev::kStackLdsMax)
+      o.stack_levels < -1 || o.stack_levels > incdev::kStackLdsMax || o.fast_math < 0 || o.fast_math > 1 ||
+      o.same_stream < 0 || o.same_stream > 1)
     return INC_ERR_ARG;
   if (!(o.const_sigma_mb >= 0.0f) || o.const_sigma_mb > 1e5f) return INC_ERR_ARG;
   if (o.fixed_b_on && !(o.fixed_b >= 0.0f && o.fixed_b < 20.0f)) return INC_ERR_ARG;
@@ -199,7 +200,9 @@ int inc_ctx_create(const inc_nucleus* targets, int n_targets, const inc_options*
     if ((e = hipDeviceSynchronize()) != hipSuccess) break;
     e = hipMemcpy(&c->evap, d_evap, sizeof(EvapTab), hipMemcpyDeviceToHost);
     for (int m = 0; m < 2; ++m) {
-      int lv = inc_stack_levels(m == 0 ? INC_MODE_PLAIN : INC_MODE_PERSISTENT, n_targets, c->block, c->waves_per_cu);
+      const int mode = m == 0 ? INC_MODE_PLAIN : INC_MODE_PERSISTENT;
+      int lv = o.fast_math ? fast::stack_levels(mode, n_targets, c->block, c->waves_per_cu)
+                           : precise::stack_levels(mode, n_targets, c->block, c->waves_per_cu);
       if (o.stack_levels < 0) lv = 0;
       else if (o.stack_levels > 0 && o.stack_levels < lv) lv = o.stack_levels;
       c->stack_lds[m] = lv;

@@ -25,7 +25,7 @@ struct LaunchDesc {
   int block;
   int persistent_blocks;
   int evap_threshold, tent_threshold, kin_threshold;
-  int stack_lds;         // stack entries per lane held in LDS (inc_stack_levels)
+  int stack_lds;         // stack entries per lane held in LDS (stack_levels)
   const NucTab* nuc;
   int n_targets;
   const XsTab* xs;
@@ -45,15 +45,29 @@ struct LaunchDesc {
   RingDev ring;          // rec == NULL: records go to the segments' arrays
 };
 
+// The event kernels exist in two builds of one source (kernels.hip): IEEE
+// arithmetic and precise transcendentals (precise, the default) and the
+// fast-math build (fast, Sec. 4.2).  Each namespace provides:
+//   lds_bytes     dynamic LDS of an event kernel launch;
+//   stack_levels  LIFO entries per lane that fit in LDS for the event kernel of
+//                 `mode` at this block size when `waves_per_cu` waves are meant
+//                 to share a CU (the kernel's own occupancy limit applies too);
+//                 0 when none fit;
+//   launch_events zero the counters, then launch the event kernel(s) of L.mode.
+namespace precise {
+size_t lds_bytes(int n_targets, int block, bool with_xs, int stack_levels);
+int stack_levels(int mode, int n_targets, int block, int waves_per_cu);
+hipError_t launch_events(const LaunchDesc& L, hipStream_t s);
+}  // namespace precise
+namespace fast {
+size_t lds_bytes(int n_targets, int block, bool with_xs, int stack_levels);
+int stack_levels(int mode, int n_targets, int block, int waves_per_cu);
+hipError_t launch_events(const LaunchDesc& L, hipStream_t s);
+}  // namespace fast
+
 }  // namespace incdev
 
-size_t inc_lds_bytes(int n_targets, int block, bool with_xs, int stack_levels);
-// Stack entries per lane that fit in LDS for the event kernel of `mode` at the
-// given block size when `waves_per_cu` waves are meant to share a CU (the
-// kernel's own occupancy limit applies too); 0 when none fit.
-int inc_stack_levels(int mode, int n_targets, int block, int waves_per_cu);
 hipError_t inc_launch_setup(const int* d_AZ, int n_targets, incdev::NucTab* d_nuc, incdev::XsTab* d_xs, double* d_B,
                             int amax, int zmax, incdev::EvapTab* d_evap, incdev::MassTab* d_mass, const inc_options& o,
                             hipStream_t s);
-hipError_t inc_launch_events(const incdev::LaunchDesc& L, hipStream_t s);
 hipError_t inc_upload_segment(const incdev::Segment& seg, incdev::Segment* d_slot, hipStream_t s);

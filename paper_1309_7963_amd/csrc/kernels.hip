@@ -1,193 +1,22 @@
-// kernels.hip — setup kernels (Sec. 2.2, 2.3, 2.4 tables), the plain
-// cascade / evaporation kernel pair (the paper's Sec. 3 organisation: one
-// cascade per thread, then one de-excitation per thread) and the fused
-// persistent work-queue kernel.
+// kernels.hip — the event kernels: the plain cascade / evaporation pair (the
+// paper's Sec. 3 organisation: one cascade per thread, then one de-excitation
+// per thread) and the fused persistent work-queue kernel.
+//
+// This file is compiled twice into one library: as is (namespace
+// incdev::precise: IEEE division and square root, precise transcendentals)
+// and from kernels_fast.hip (namespace incdev::fast: approximate
+// transcendentals, reciprocal division, flushed denormals, Sec. 4.2).
 #include "kernels.h"
 
 #include "event.h"
 
+#ifndef INC_KERNEL_NS
+#define INC_KERNEL_NS precise
+#endif
+
 namespace incdev {
+namespace INC_KERNEL_NS {
 
-// ---------------------------------------------------------------- setup
-// Semi-empirical binding energy (Sec. 2.2) in double precision: textbook
-// coefficient set, measured values for d, t, 3He, alpha, zero for other A <= 4.
-__device__ double semf_binding(int A, int Z) {
-  if (A <= 0 || Z < 0 || Z > A) return 0.0;
-  if (A <= 4) {
-    if (A == 2 && Z == 1) return 2.224566;
-    if (A == 3 && Z == 1) return 8.481798;
-    if (A == 3 && Z == 2) return 7.718043;
-    if (A == 4 && Z == 2) return 28.29566;
-    return 0.0;
-  }
-  const int N = A - Z;
-  const double a = (double)A, a13 = cbrt(a);
-  double B = 15.75 * a - 17.8 * a13 * a13 - 0.711 * (double)(Z * (Z - 1)) / a13 - 23.7 * (double)((N - Z) * (N - Z)) / a;
-  const double pair = 11.18 / sqrt(a);
-  if (((Z | N) & 1) == 0) B += pair;
-  if ((Z & 1) && (N & 1)) B -= pair;
-  return B > 0.0 ? B : 0.0;
-}
-
-// Binding energies B(A, Z) for the evaporation chain, the six fragments'
-// constants (mass, A^1/3, ln(g m) with spin factors g = 2, 2, 3, 2, 2, 1) and
-// the per-A table of A^1/3 and ln A.
-__global__ void k_bind_table(double* B, int amax, int zmax, EvapTab* et, MassTab* mt) {
-  const int idx = blockIdx.x * blockDim.x + threadIdx.x;
-  const int zs = zmax + 1;
-  if (idx < (amax + 1) * zs) B[idx] = semf_binding(idx / zs, idx % zs);
-  if (idx <= kMaxA) {
-    mt->a13[idx] = (float)cbrt((double)idx);
-    mt->lnA[idx] = idx > 0 ? (float)log((double)idx) : 0.0f;
-  }
-  if (idx == 0) {
-    const int fa[6] = {1, 1, 2, 3, 3, 4}, fz[6] = {0, 1, 1, 1, 2, 2};
-    const double g[6] = {2.0, 2.0, 3.0, 2.0, 2.0, 1.0};
-    for (int j = 0; j < 6; ++j) {
-      const double b = semf_binding(fa[j], fz[j]);
-      const double m = (double)fz[j] * kMassP + (double)(fa[j] - fz[j]) * kMassN - b;
-      et->B[j] = b;
-      et->m[j] = (float)m;
-      et->a13[j] = (float)cbrt((double)fa[j]);
-      et->lngm[j] = (float)log(g[j] * m);
-    }
-  }
-}
-
-// Fermi density of Eq. (1), c = 1.07 A^1/3, delta = 0.545, R = c + 2.5 fm,
-// 15 equal shells; each shell's density is its share of the A nucleons over
-// its volume (integrals by 64-panel 5-point Gauss-Legendre, double).
-// Two-component Fermi gas: p_F = hbar c (3 pi^2 rho_x)^1/3, relativistic E_F.
-__global__ void k_nucleus_setup(const int* AZ, NucTab* out, int uniform_density, int zero_fermi, int zero_binding) {
-  __shared__ double integ[kShells];
-  const int t = blockIdx.x;
-  const int A = AZ[2 * t], Z = AZ[2 * t + 1];
-  const double c = 1.07 * cbrt((double)A), delta = 0.545, R = c + 2.5;
-  const int i = threadIdx.x;
-  if (i < kShells) {
-    const double gx[5] = {-0.9061798459386640, -0.5384693101056831, 0.0, 0.5384693101056831, 0.9061798459386640};
-    const double gw[5] = {0.2369268850561891, 0.4786286704993665, 0.5688888888888889, 0.4786286704993665,
-                          0.2369268850561891};
-    const double r0 = R * i / kShells, r1 = R * (i + 1) / kShells;
-    const int panels = 64;
-    const double h = (r1 - r0) / panels;
-    double sum = 0.0;
-    for (int p = 0; p < panels; ++p) {
-      const double mid = r0 + (p + 0.5) * h;
-      for (int q = 0; q < 5; ++q) {
-        const double r = mid + 0.5 * h * gx[q];
-        sum += gw[q] * r * r / (1.0 + exp((r - c) / delta));
-      }
-    }
-    integ[i] = 0.5 * h * sum;
-  }
-  __syncthreads();
-  if (i < kShells) {
-    double total = 0.0;
-    for (int k = 0; k < kShells; ++k) total += integ[k];
-    const double r0 = R * i / kShells, r1 = R * (i + 1) / kShells;
-    const double pi = 3.14159265358979323846;
-    double rho = (double)A * (integ[i] / total) / (4.0 / 3.0 * pi * (r1 * r1 * r1 - r0 * r0 * r0));
-    if (uniform_density) rho = (double)A / (4.0 / 3.0 * pi * R * R * R);
-    const double frac[2] = {(double)(A - Z) / A, (double)Z / A};
-    const double mass[2] = {(double)kMassN, (double)kMassP};
-    for (int sp = 0; sp < 2; ++sp) {
-      const double r = rho * frac[sp];
-      double pF = 197.3269804 * cbrt(3.0 * pi * pi * r);
-      if (zero_fermi) pF = 0.0;
-      out[t].rho[sp][i] = (float)r;
-      out[t].pF[sp][i] = (float)pF;
-      out[t].EF[sp][i] = (float)(pF * pF / (sqrt(pF * pF + mass[sp] * mass[sp]) + mass[sp]));
-    }
-    out[t].r2[i + 1] = (float)(r1 * r1);
-    if (i == 0) {
-      out[t].r2[0] = 0.0f;
-      out[t].R = (float)R;
-      double EB = semf_binding(A, Z) / A, EC = 1.44 * Z / R;
-      if (zero_binding) EB = EC = 0.0;
-      out[t].EB = (float)EB;
-      out[t].EC = (float)EC;
-      out[t].A = A;
-      out[t].Z = Z;
-      for (int sp = 0; sp < 2; ++sp) {
-        out[t].rho[sp][15] = 0.0f;
-        out[t].pF[sp][15] = 0.0f;
-        out[t].EF[sp][15] = 0.0f;
-      }
-      for (int k = 0; k < 7; ++k) out[t].pad[k] = 0.0f;
-    }
-  }
-  __syncthreads();
-  if (i == 0) {
-    // densities fall outwards: the smallest E_F is the outermost shell's, the
-    // largest p_F the innermost's; scan anyway
-    for (int sp = 0; sp < 2; ++sp) {
-      float efmin = out[t].EF[sp][0], pfmax = out[t].pF[sp][0];
-      for (int k = 1; k < kShells; ++k) {
-        efmin = fminf(efmin, out[t].EF[sp][k]);
-        pfmax = fmaxf(pfmax, out[t].pF[sp][k]);
-      }
-      out[t].EFmin[sp] = efmin;
-      out[t].pFmax[sp] = pfmax;
-    }
-  }
-}
-
-// Free NN elastic cross-sections (Sec. 2.3, reading of the Cugnon et al.
-// parameterisation): p = p_lab in GeV/c, sigma in mb; below 0.8 GeV/c the
-// larger of the first two branches.
-__device__ double sigma_like(double p) {
-  if (p < 0.8) return fmax(34.0 * pow(p / 0.4, -2.104), 23.5 + 1000.0 * pow(p - 0.7, 4.0));
-  return 1250.0 / (p + 50.0) - 4.0 * (p - 1.3) * (p - 1.3);
-}
-__device__ double sigma_unlike(double p) {
-  if (p < 0.8) {
-    const double l = log(p);
-    return fmax(6.3555 * pow(p, -3.2481) * exp(-0.377 * l * l), 33.0 + 196.0 * pow(fabs(p - 0.95), 2.5));
-  }
-  return 31.0 / sqrt(p);
-}
-__device__ double slope_like(double p) {
-  const double p8 = p * p * p * p * p * p * p * p;
-  return 5.5 * p8 / (7.7 + p8);
-}
-__device__ double slope_unlike(double p) {
-  if (p < 0.225) return 0.0;
-  if (p < 0.6) return 16.53 * (p - 0.225);
-  return -1.63 * p + 7.16;
-}
-
-__global__ void k_xs_table(XsTab* xs, float const_sigma) {
-  __shared__ float sig[2][kXsNodes];
-  const int k = threadIdx.x;
-  const double lo = kPlo, hi = kPhi;
-  if (k < kXsNodes) {
-    const double p = lo * exp(log(hi / lo) * (double)k / (double)(kXsNodes - 1));
-    sig[0][k] = (float)sigma_unlike(p);
-    sig[1][k] = (float)sigma_like(p);
-    if (const_sigma > 0.0f) sig[0][k] = sig[1][k] = const_sigma;
-    xs->sig[0][k] = sig[0][k];
-    xs->sig[1][k] = sig[1][k];
-    xs->slope[0][k] = (float)slope_unlike(p);
-    xs->slope[1][k] = (float)slope_like(p);
-  }
-  __syncthreads();
-  if (k < 2) {
-    // suffix maximum: a majorant of the interpolated sigma above each node
-    float m = sig[k][kXsNodes - 1];
-    for (int j = kXsNodes - 1; j >= 0; --j) {
-      m = fmaxf(m, sig[k][j]);
-      xs->hat[k][j] = m;
-    }
-  }
-}
-
-__global__ void k_fill_u64(unsigned long long* p, int n) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < n) p[i] = 0ull;
-}
-
-// ----------------------------------------------------------- event kernels
 struct KernelArgs {
   const NucTab* nuc;
   int n_targets;
@@ -539,29 +368,20 @@ __global__ void k_zero_counters(const Segment* segs, int n_seg, unsigned long lo
   if (i == 0) *queue = 0ull;
 }
 
-// Copy one segment description (a kernel argument) into device memory.
-__global__ void k_set_segment(Segment s, Segment* dst) {
-  if (threadIdx.x == 0 && blockIdx.x == 0) *dst = s;
-}
-
-}  // namespace incdev
-
 // ================================================================ launchers
-using namespace incdev;
-
-size_t inc_lds_bytes(int n_targets, int block, bool with_xs, int stack_levels) {
+size_t lds_bytes(int n_targets, int block, bool with_xs, int stack_levels) {
   return (size_t)n_targets * sizeof(NucTab) + (with_xs ? sizeof(XsTab) : 0) + sizeof(MassTab) +
          (size_t)(block / 64) * kWriterCap * kRecWords * sizeof(uint32_t) +
          (size_t)stack_levels * 2 * block * sizeof(float4);
 }
 
-int inc_stack_levels(int mode, int n_targets, int block, int waves_per_cu) {
+int stack_levels(int mode, int n_targets, int block, int waves_per_cu) {
   int dev = 0, lds_cu = 0;
   if (hipGetDevice(&dev) != hipSuccess ||
       hipDeviceGetAttribute(&lds_cu, hipDeviceAttributeMaxSharedMemoryPerMultiprocessor, dev) != hipSuccess ||
       lds_cu <= 0)
     return 0;
-  const size_t base = inc_lds_bytes(n_targets, block, true, 0);
+  const size_t base = lds_bytes(n_targets, block, true, 0);
   int occ = 0;
   const void* fn = mode == INC_MODE_PLAIN ? (const void*)k_cascade_plain : (const void*)k_persistent;
   if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, fn, block, base) != hipSuccess || occ < 1) return 0;
@@ -577,22 +397,7 @@ int inc_stack_levels(int mode, int n_targets, int block, int waves_per_cu) {
   return levels > (size_t)kStackLdsMax ? kStackLdsMax : (int)levels;
 }
 
-hipError_t inc_launch_setup(const int* d_AZ, int n_targets, NucTab* d_nuc, XsTab* d_xs, double* d_B, int amax,
-                            int zmax, EvapTab* d_evap, MassTab* d_mass, const inc_options& o, hipStream_t s) {
-  hipLaunchKernelGGL(k_nucleus_setup, dim3(n_targets), dim3(64), 0, s, d_AZ, d_nuc, o.uniform_density, o.zero_fermi,
-                     o.zero_binding);
-  hipLaunchKernelGGL(k_xs_table, dim3(1), dim3(kXsNodes), 0, s, d_xs, o.const_sigma_mb);
-  const int cells = (amax + 1) * (zmax + 1) > kMaxA + 1 ? (amax + 1) * (zmax + 1) : kMaxA + 1;
-  hipLaunchKernelGGL(k_bind_table, dim3((cells + 255) / 256), dim3(256), 0, s, d_B, amax, zmax, d_evap, d_mass);
-  return hipGetLastError();
-}
-
-hipError_t inc_upload_segment(const Segment& seg, Segment* d_slot, hipStream_t s) {
-  hipLaunchKernelGGL(k_set_segment, dim3(1), dim3(64), 0, s, seg, d_slot);
-  return hipGetLastError();
-}
-
-hipError_t inc_launch_events(const LaunchDesc& L, hipStream_t s) {
+hipError_t launch_events(const LaunchDesc& L, hipStream_t s) {
   KernelArgs a;
   a.nuc = L.nuc;
   a.n_targets = L.n_targets;
@@ -622,12 +427,15 @@ hipError_t inc_launch_events(const LaunchDesc& L, hipStream_t s) {
   const int block = L.block;
   if (L.mode == INC_MODE_PLAIN) {
     const unsigned grid = (unsigned)((L.n + block - 1) / block);
-    hipLaunchKernelGGL(k_cascade_plain, dim3(grid), dim3(block), inc_lds_bytes(L.n_targets, block, true, L.stack_lds),
+    hipLaunchKernelGGL(k_cascade_plain, dim3(grid), dim3(block), lds_bytes(L.n_targets, block, true, L.stack_lds),
                        s, a);
-    hipLaunchKernelGGL(k_evap_plain, dim3(grid), dim3(block), inc_lds_bytes(0, block, false, 0), s, a);
+    hipLaunchKernelGGL(k_evap_plain, dim3(grid), dim3(block), lds_bytes(0, block, false, 0), s, a);
   } else {
     hipLaunchKernelGGL(k_persistent, dim3(L.persistent_blocks), dim3(block),
-                       inc_lds_bytes(L.n_targets, block, true, L.stack_lds), s, a);
+                       lds_bytes(L.n_targets, block, true, L.stack_lds), s, a);
   }
   return hipGetLastError();
 }
+
+}  // namespace INC_KERNEL_NS
+}  // namespace incdev

@@ -78,6 +78,12 @@ def test_argument_errors_before_device(lib):
     arr = (_lib.Nucleus * 1)(_lib.Nucleus(16, 8))
     assert L.inc_ctx_create(arr, 0, None, C.byref(h)) == inc.INC_ERR_ARG
     assert L.inc_simulate_dev(None, None, None, None, 0) == inc.INC_ERR_ARG
+    # option ranges are checked before the device is looked for
+    for field, bad in (("fast_math", 2), ("same_stream", -1), ("stack_levels", 5), ("block_size", 96),
+                       ("waves_per_cu", 33), ("kin_threshold", 65)):
+        o = _lib.Options()
+        setattr(o, field, bad)
+        assert L.inc_ctx_create(arr, 1, C.byref(o), C.byref(h)) == inc.INC_ERR_ARG, field
     nsec = C.c_size_t()
     e = (C.c_float * 1)(10.0)
     rc = L.inc_simulate(16, 8, e, 1, 1, None, None, None, None, None, None, None, None, 0, C.byref(nsec))
