@@ -261,6 +261,30 @@ int inc_ring_destroy(inc_ring* ring);
 int inc_ring_simulate(inc_ring* ring, const inc_batch* batch, inc_residual* d_res, const inc_host_output* out,
                       void* stream, int mode, inc_ring_stats* stats);
 
+/* ------------------------------------------------------ nuclide tally
+ * Residual-nuclide counts, the reduction behind positron-emitter yields
+ * (11C, 13N, 15O, 30P, 38K ... for range verification: the application the
+ * paper's Sec. 4.2 looks ahead to). */
+
+/* Shape of the context's tally table: n_targets, and the largest residual
+ * mass number and charge a context can produce (amax = max A + 1, zmax =
+ * max Z + 1 over its targets).  Host out-params. */
+int inc_ctx_tally_shape(const inc_ctx* ctx, int* n_targets, int* amax, int* zmax);
+
+/* Add one count per event of a generated batch to
+ *   table[((t * n_ebins + e) * (zmax + 1) + Z_f) * (amax + 1) + A_f]
+ * with t the event's target index (batch->target_idx, NULL = 0) and e the bin
+ * of its incident energy among n_ebins (1..1024) equal bins over [20, 250] MeV
+ * (e = (int)((T0 - 20) * n_ebins / 230) in FP32, clamped to the last bin).
+ * Events whose residual is flagged out of range (0x8000) or empty (A_f = 0)
+ * are not counted.  batch: as given to inc_simulate_dev (seed and ids are not
+ * used); res: device, batch->n residuals; table: device, n_targets * n_ebins *
+ * (zmax + 1) * (amax + 1) counters owned by the caller, accumulated (zero it
+ * before the first batch).  Asynchronous on `stream`.  Returns INC_ERR_ARG
+ * for bad pointers or sizes, INC_ERR_DEVICE if the launch fails. */
+int inc_tally_residuals(inc_ctx* ctx, const inc_batch* batch, const inc_residual* res, int n_ebins,
+                        unsigned long long* table, void* stream);
+
 /* Library version of the frozen physics readings (changes when any reading
  * that affects results changes). */
 int inc_contract_version(void);

@@ -179,6 +179,60 @@ class Context:
         return out
 
 
+    def tally_shape(self):
+        """(n_targets, amax, zmax) of the residual-nuclide table (inc_ctx_tally_shape)."""
+        t, a, z = C.c_int(), C.c_int(), C.c_int()
+        _lib.check(_lib.load().inc_ctx_tally_shape(self._h, C.byref(t), C.byref(a), C.byref(z)), "inc_ctx_tally_shape")
+        return t.value, a.value, z.value
+
+    def tally(self, T0, out: DeviceOutput, target_idx=None, n_ebins: int = 1, table=None, stream=None):
+        """Residual-nuclide counts of a generated batch (inc_tally_residuals):
+        an int64 CUDA tensor (n_targets, n_ebins, zmax + 1, amax + 1) indexed
+        [target, energy bin over 20-250 MeV, Z_f, A_f]; `table` accumulates."""
+        torch = _torch()
+        nt, amax, zmax = self.tally_shape()
+        shape = (nt, int(n_ebins), zmax + 1, amax + 1)
+        if table is None:
+            table = torch.zeros(shape, dtype=torch.int64, device=T0.device)
+        elif tuple(table.shape) != shape or table.dtype != torch.int64 or not table.is_contiguous():
+            raise ValueError("table must be a contiguous int64 tensor of shape %s" % (shape,))
+        b = _lib.Batch()
+        b.n = int(T0.shape[0])
+        b.target_idx = target_idx.data_ptr() if target_idx is not None else None
+        b.T0 = T0.data_ptr()
+        s = stream if stream is not None else torch.cuda.current_stream()
+        _lib.check(_lib.load().inc_tally_residuals(self._h, C.byref(b), C.c_void_p(out.res.data_ptr()), int(n_ebins),
+                                                   C.c_void_p(table.data_ptr()), C.c_void_p(s.cuda_stream)),
+                   "inc_tally_residuals")
+        return table
+
+
+# Positron emitters reachable from tissue nuclei (C, N, O, P, Ca) by
+# nucleon and light-fragment removal: (A, Z) -> (name, half-life in s).
+POSITRON_EMITTERS = {
+    (10, 6): ("10C", 19.29), (11, 6): ("11C", 1221.8), (13, 7): ("13N", 597.9), (14, 8): ("14O", 70.62),
+    (15, 8): ("15O", 122.24), (29, 15): ("29P", 4.142), (30, 15): ("30P", 149.9), (34, 17): ("34Cl", 1.527),
+    (37, 19): ("37K", 1.226), (38, 19): ("38K", 458.2), (39, 20): ("39Ca", 0.8603),
+}
+
+
+def positron_yields(table, targets) -> dict:
+    """Counts of each positron emitter per target and energy bin from a
+    residual-nuclide table (numpy or torch, shape (n_targets, n_ebins, zmax+1,
+    amax+1)): {(A_t, Z_t): {name: counts per energy bin}}."""
+    t = table.cpu().numpy() if hasattr(table, "cpu") else np.asarray(table)
+    out = {}
+    for i, (a_t, z_t) in enumerate(targets):
+        row = {}
+        for (a, z), (name, _) in POSITRON_EMITTERS.items():
+            if z < t.shape[2] and a < t.shape[3]:
+                c = t[i, :, z, a]
+                if c.sum() > 0:
+                    row[name] = c.copy()
+        out[(a_t, z_t)] = row
+    return out
+
+
 def simulate_host(A: int, Z: int, energies: np.ndarray, seed: int, capacity: Optional[int] = None) -> dict:
     """The synchronous host-array call inc_simulate(target_A, target_Z,
     energies, n_events, seed, out...).  Raises IncError on failure."""

@@ -26,7 +26,7 @@ SYMBOLS = (
     "inc_simulate_dev", "inc_simulate", "inc_server_create", "inc_server_destroy",
     "inc_server_submit", "inc_server_poll", "inc_server_wait", "inc_server_fetch",
     "inc_server_stats_get", "inc_server_replay", "inc_ring_create", "inc_ring_destroy",
-    "inc_ring_simulate", "inc_contract_version",
+    "inc_ring_simulate", "inc_ctx_tally_shape", "inc_tally_residuals", "inc_contract_version",
 )
 
 
@@ -165,6 +165,10 @@ def load():
         L.inc_ring_simulate.argtypes = [vp, C.POINTER(Batch), vp, C.POINTER(HostOutput), vp, C.c_int,
                                         C.POINTER(RingStats)]
         L.inc_ring_simulate.restype = C.c_int
+        L.inc_ctx_tally_shape.argtypes = [vp, C.POINTER(C.c_int), C.POINTER(C.c_int), C.POINTER(C.c_int)]
+        L.inc_ctx_tally_shape.restype = C.c_int
+        L.inc_tally_residuals.argtypes = [vp, C.POINTER(Batch), vp, C.c_int, vp, vp]
+        L.inc_tally_residuals.restype = C.c_int
         L.inc_contract_version.argtypes = []
         L.inc_contract_version.restype = C.c_int
         _lib = L

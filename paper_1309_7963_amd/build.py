@@ -19,7 +19,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libinc.so")
-SOURCES = ["api.hip", "setup.hip", "kernels.hip", "kernels_fast.hip", "server.hip", "ring.hip"]
+SOURCES = ["api.hip", "setup.hip", "kernels.hip", "kernels_fast.hip", "server.hip", "ring.hip", "tally.hip"]
 HEADERS = ["device.h", "event.h", "kernels.h", "ctx.h"]
 
 HIPCC_FLAGS = [

@@ -65,6 +65,14 @@ def chi2_table(keys1, keys2, min_expected: float = 5.0):
         c2 = np.bincount(idx2, minlength=cats.size).astype(np.float64)
     else:
         c2 = np.array([np.sum(k2 == c) for c in cats], dtype=np.float64)
+    return chi2_counts(c1, c2, min_expected)
+
+
+def chi2_counts(c1, c2, min_expected: float = 5.0):
+    """Two-sample chi-square of two count vectors over the same categories;
+    cells with an expected count below min_expected are merged into one."""
+    c1 = np.asarray(c1, dtype=np.float64)
+    c2 = np.asarray(c2, dtype=np.float64)
     N1, N2 = c1.sum(), c2.sum()
     tot = c1 + c2
     e1 = tot * N1 / (N1 + N2)
