@@ -113,8 +113,8 @@ typedef struct {
   unsigned long long* counters; /* device, >= 4 entries, caller-owned:
                             [0] secondaries produced (may exceed capacity:
                                 only the first sec_capacity are stored),
-                            [1] flagged events, [2] work-queue head,
-                            [3] reserved.  Reset by the call.               */
+                            [1] flagged events, [2] and [3] work-queue
+                            heads.  Reset by the call.                      */
 } inc_output;
 
 /* A batch of incident protons, in device memory. */
@@ -147,6 +147,11 @@ int inc_ctx_tables(const inc_ctx* ctx, float* host_out);
                                  evaporation kernel (the paper's Sec. 3 shape) */
 #define INC_MODE_PERSISTENT 1 /* one fused persistent kernel: lanes refill
                                  from a global work queue                     */
+#define INC_MODE_STAGED 2     /* persistent cascade kernel, then persistent
+                                 evaporation kernel; the post-cascade nucleus
+                                 and stream position are handed over in device
+                                 memory (32 B per event).  Same results as
+                                 INC_MODE_PERSISTENT                          */
 
 /* Generate batch->n non-elastic events asynchronously on `stream` (a
  * hipStream_t; NULL = the default stream).  All batch and output pointers

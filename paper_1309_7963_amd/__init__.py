@@ -21,7 +21,7 @@ import numpy as np
 from . import _lib
 from ._lib import (  # noqa: F401
     INC_ERR_ARG, INC_ERR_BUSY, INC_ERR_CAPACITY, INC_ERR_DEVICE, INC_ERR_NO_DEVICE, INC_ERR_OOM, INC_ERR_RANGE,
-    MODE_PERSISTENT, MODE_PLAIN, RESIDUAL_DTYPE, IncError,
+    MODE_PERSISTENT, MODE_PLAIN, MODE_STAGED, RESIDUAL_DTYPE, IncError,
 )
 
 FLAG_STACK, FLAG_SEGMENTS, FLAG_EMPTY, FLAG_RANGE = 1, 2, 4, 0x8000
@@ -173,7 +173,7 @@ class Context:
         b.first_event_id = int(first_event_id)
         o = out.c_struct(capacity)
         s = stream if stream is not None else torch.cuda.current_stream()
-        m = {"plain": _lib.MODE_PLAIN, "persistent": _lib.MODE_PERSISTENT}[mode]
+        m = MODES[mode]
         _lib.check(_lib.load().inc_simulate_dev(self._h, C.byref(b), C.byref(o), C.c_void_p(s.cuda_stream), m),
                    "inc_simulate_dev")
         return out
@@ -205,6 +205,9 @@ class Context:
                                                    C.c_void_p(table.data_ptr()), C.c_void_p(s.cuda_stream)),
                    "inc_tally_residuals")
         return table
+
+
+MODES = {"plain": MODE_PLAIN, "persistent": MODE_PERSISTENT, "staged": MODE_STAGED}
 
 
 # Positron emitters reachable from tissue nuclei (C, N, O, P, Ca) by
@@ -406,7 +409,7 @@ class Ring:
         b.first_event_id = int(first_event_id)
         stats = _lib.RingStats()
         s = stream if stream is not None else torch.cuda.current_stream()
-        m = {"plain": _lib.MODE_PLAIN, "persistent": _lib.MODE_PERSISTENT}[mode]
+        m = MODES[mode]
         rc = _lib.load().inc_ring_simulate(self._h, C.byref(b), C.c_void_p(res_d.data_ptr()), C.byref(o),
                                            C.c_void_p(s.cuda_stream), m, C.byref(stats))
         if rc not in (_lib.INC_OK, _lib.INC_ERR_CAPACITY):

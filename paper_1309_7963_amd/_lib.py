@@ -19,6 +19,7 @@ INC_ERR_DEVICE = -6
 INC_ERR_BUSY = -7
 MODE_PLAIN = 0
 MODE_PERSISTENT = 1
+MODE_STAGED = 2
 
 # exported symbols, in the order include/inc.h declares them
 SYMBOLS = (

@@ -47,7 +47,7 @@ void release(inc_ctx* c) {
 int inc_launch_segments(inc_ctx* ctx, size_t n, const uint8_t* tidx, const float* T0, const Segment* d_segs,
                         int n_seg, unsigned long long* queue, hipStream_t s, int mode, int max_blocks,
                         const RingDev* ring) {
-  if (mode == INC_MODE_PLAIN && ctx->mid_cap < n) {
+  if ((mode == INC_MODE_PLAIN || mode == INC_MODE_STAGED) && ctx->mid_cap < n) {
     if (ctx->d_mid) (void)hipFree(ctx->d_mid);
     ctx->d_mid = nullptr;
     ctx->mid_cap = 0;
@@ -89,7 +89,7 @@ int inc_launch_segments(inc_ctx* ctx, size_t n, const uint8_t* tidx, const float
 
 int inc_launch_batch(inc_ctx* ctx, const inc_batch* b, const inc_output* out, hipStream_t s, int mode, int max_blocks) {
   if (!ctx || !b || !out) return INC_ERR_ARG;
-  if (mode != INC_MODE_PLAIN && mode != INC_MODE_PERSISTENT) return INC_ERR_ARG;
+  if (mode != INC_MODE_PLAIN && mode != INC_MODE_PERSISTENT && mode != INC_MODE_STAGED) return INC_ERR_ARG;
   if (b->n < 1 || b->n >= (1ull << 32) || !b->T0) return INC_ERR_ARG;
   if (!out->res || !out->counters) return INC_ERR_ARG;
   if (out->sec_capacity && (!out->sec_event || !out->sec_species || !out->sec_stage || !out->sec_T ||

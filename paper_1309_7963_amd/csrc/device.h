@@ -27,6 +27,8 @@ constexpr float kPlo = 0.1374f;      // GeV/c; NN argument floor (T_lab ~ 10 MeV
 constexpr float kPhi = 1.5f;         // GeV/c; NN argument ceiling
 
 constexpr uint16_t kFlagStack = 1, kFlagSegments = 2, kFlagEmpty = 4, kFlagRange = 0x8000;
+// hand-over only (never in a residual): the residual is already written
+constexpr uint16_t kMidFinal = 0x4000;
 
 // --------------------------------------------------------------- tables
 // One target nucleus: 15 shells (Sec. 2.2).  Index [species][shell], species

@@ -30,10 +30,11 @@ struct KernelArgs {
   const float* T0;
   const Segment* segs;       // requests of the launch, sorted by start
   int n_seg;
-  unsigned long long* queue; // work-queue head (persistent kernel)
+  unsigned long long* queue; // work-queue heads: [0] events, [1] staged evaporation
   MidState* mid;             // plain kernels: cascade -> evaporation hand-over
   RingDev ring;              // streaming output (rec == NULL: segment arrays)
   int stack_lds;             // stack entries per lane held in LDS
+  int defer_evap;            // persistent kernel: hand the evaporation over (mid)
 };
 
 __device__ __forceinline__ bool energy_ok(float T0) { return T0 >= 20.0f && T0 <= 250.0f; }
@@ -254,6 +255,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) k
   EventRef er = {0, 0};
   float T0 = 0.0f;
   int tgt = 0, nsec = 0;
+  uint32_t ev_idx = 0;
   float Ex_casc = 0.0f;
   Rng rng;
   Cascade c;
@@ -281,6 +283,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) k
       const uint32_t r = rank_in(need);
       if (st == kStDone && r < avail) {
         const size_t ev = (size_t)(chunk_next + r);
+        ev_idx = (uint32_t)ev;
         er = event_ref(a, ev);
         T0 = a.T0[ev];
         tgt = a.tidx ? (int)a.tidx[ev] : 0;
@@ -289,6 +292,11 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) k
           const Nucleus z = {0, 0, 0.0f, {0.0f, 0.0f, 0.0f}};
           write_residual(a.segs[er.seg].res + er.local, z, 0.0f, 0, kFlagRange, 0, 0);
           atomicAdd(&a.segs[er.seg].counters[1], 1ull);
+          if (a.defer_evap) {
+            MidState m = {};
+            m.flags = kFlagRange | kMidFinal;
+            a.mid[ev] = m;
+          }
         } else {
           init_stream(rng, a, er);
           cascade_init(c, snt[tgt]);
@@ -341,12 +349,29 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) k
         nu = cascade_residual(c, nt, T0);
         Ex_casc = nu.E;
         if (nu.A <= 0) c.flags |= kFlagEmpty;
-        if (nu.A <= 0 || a.opt.no_evaporation) {
+        const bool final = nu.A <= 0 || a.opt.no_evaporation;
+        if (final) {
           write_residual(a.segs[er.seg].res + er.local, nu, Ex_casc, nsec, c.flags, c.ncoll, c.nretry);
           if (c.flags) atomicAdd(&a.segs[er.seg].counters[1], 1ull);
+        }
+        if (a.defer_evap) {
+          // staged mode: the evaporation kernel continues this event
+          MidState m;
+          m.A = (int16_t)nu.A;
+          m.Z = (int16_t)nu.Z;
+          m.flags = (uint16_t)(c.flags | (final ? kMidFinal : 0));
+          m.ncoll = (uint16_t)min(c.ncoll, 65535);
+          m.nretry = (uint16_t)min(c.nretry, 65535);
+          m.nsec = (uint16_t)nsec;
+          m.E = nu.E;
+          m.P[0] = nu.P.x;
+          m.P[1] = nu.P.y;
+          m.P[2] = nu.P.z;
+          m.drawn = rng.drawn();
+          a.mid[ev_idx] = m;
           st = kStDone;
         } else {
-          st = kStEvap;
+          st = final ? kStDone : kStEvap;
         }
       } else {
         st = ns;
@@ -357,15 +382,96 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) k
   writer_flush(wbuf, fill, a.segs, a.ring);
 }
 
-// Zero the segments' counters and the work-queue head (a fill kernel rather
-// than a memset, so the launch sequence stays capturable in a graph).
+// Staged mode, second kernel: the evaporation of every event whose cascade
+// the persistent kernel handed over (MidState), as a persistent work-queue
+// kernel of its own.  Every lane is in the evaporation state, so a wave step
+// runs with all lanes that still have work; a lane whose nucleus has
+// de-excited takes the next event.  The random stream resumes after the
+// cascade's draws, so the results equal the fused kernel's.
+__global__ void __launch_bounds__(256) k_evap_persistent(KernelArgs a) {
+  extern __shared__ __align__(16) char lds[];
+  stage_tables(lds, a, 0, false);
+  const MassTab& smt = *(const MassTab*)lds;
+  uint32_t* wbuf = (uint32_t*)(lds + sizeof(MassTab)) + (threadIdx.x / 64) * (kWriterCap * kRecWords);
+  int fill = 0;
+
+  unsigned long long chunk_next = 0, chunk_end = 0;
+  bool exhausted = false, busy = false;
+  EventRef er = {0, 0};
+  Rng rng;
+  Nucleus nu = {0, 0, 0.0f, {0.0f, 0.0f, 0.0f}};
+  int nsec = 0, flags = 0, ncoll = 0, nretry = 0;
+  float Ex_casc = 0.0f;
+  for (;;) {
+    const uint64_t need = __ballot(!busy);
+    if (need && !exhausted) {
+      if (chunk_next == chunk_end) {
+        unsigned long long base = 0;
+        if (lane_id() == 0) base = atomicAdd(a.queue + 1, (unsigned long long)kChunk);
+        base = __shfl(base, 0);
+        chunk_next = base;
+        chunk_end = base + kChunk < a.n ? base + kChunk : a.n;
+        if (base >= a.n) {
+          exhausted = true;
+          chunk_next = chunk_end = a.n;
+        }
+      }
+      const unsigned long long avail = chunk_end - chunk_next;
+      const uint32_t r = rank_in(need);
+      if (!busy && r < avail) {
+        const size_t ev = (size_t)(chunk_next + r);
+        const MidState m = a.mid[ev];
+        if (!(m.flags & kMidFinal)) {
+          er = event_ref(a, ev);
+          nu.A = m.A;
+          nu.Z = m.Z;
+          nu.E = m.E;
+          nu.P = {m.P[0], m.P[1], m.P[2]};
+          Ex_casc = m.E;
+          nsec = m.nsec;
+          flags = m.flags;
+          ncoll = m.ncoll;
+          nretry = m.nretry;
+          init_stream(rng, a, er);
+          rng.seek(m.drawn);
+          busy = true;
+        }
+      }
+      const unsigned long long cnt = (unsigned long long)__popcll(need);
+      chunk_next += cnt < avail ? cnt : avail;
+    }
+    if (!__any(busy)) {
+      if (exhausted) break;
+      continue;
+    }
+    Emit em;
+    em.on = false;
+    if (busy) {
+      if (evap_step(nu, rng, a.bind, a.evap, smt, em)) {
+        write_residual(a.segs[er.seg].res + er.local, nu, Ex_casc, nsec, flags, ncoll, nretry);
+        if (flags) atomicAdd(&a.segs[er.seg].counters[1], 1ull);
+        busy = false;
+      } else {
+        ++nsec;
+      }
+    }
+    writer_append(wbuf, fill, a.segs, a.ring, em.on, er.local, kind_of(em.kind, er), em.T, em.u);
+  }
+  writer_flush(wbuf, fill, a.segs, a.ring);
+}
+
+// Zero the segments' counters and the two work-queue heads (a fill kernel
+// rather than a memset, so the launch sequence stays capturable in a graph).
 __global__ void k_zero_counters(const Segment* segs, int n_seg, unsigned long long* queue) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n_seg) {
     segs[i].counters[0] = 0ull;
     segs[i].counters[1] = 0ull;
   }
-  if (i == 0) *queue = 0ull;
+  if (i == 0) {
+    queue[0] = 0ull;
+    queue[1] = 0ull;
+  }
 }
 
 // ================================================================ launchers
@@ -423,6 +529,7 @@ hipError_t launch_events(const LaunchDesc& L, hipStream_t s) {
   a.mid = L.mid;
   a.ring = L.ring;
   a.stack_lds = L.stack_lds;
+  a.defer_evap = L.mode == INC_MODE_STAGED;
   hipLaunchKernelGGL(k_zero_counters, dim3((L.n_seg + 63) / 64), dim3(64), 0, s, L.segs, L.n_seg, L.queue);
   const int block = L.block;
   if (L.mode == INC_MODE_PLAIN) {
@@ -433,6 +540,9 @@ hipError_t launch_events(const LaunchDesc& L, hipStream_t s) {
   } else {
     hipLaunchKernelGGL(k_persistent, dim3(L.persistent_blocks), dim3(block),
                        lds_bytes(L.n_targets, block, true, L.stack_lds), s, a);
+    if (L.mode == INC_MODE_STAGED)
+      hipLaunchKernelGGL(k_evap_persistent, dim3(L.persistent_blocks), dim3(block), lds_bytes(0, block, false, 0), s,
+                         a);
   }
   return hipGetLastError();
 }

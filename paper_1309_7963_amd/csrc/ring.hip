@@ -25,7 +25,7 @@ struct inc_ring {
   unsigned long long* h_ctrl;     // [0] tail (consumed), [1] error flag word
   uint32_t* d_rec;
   unsigned long long* d_ctrl;
-  unsigned long long* d_dev;      // device: [0] head, [1] queue, [2..5] counters
+  unsigned long long* d_dev;      // device: [0] head, [1..2] work queues, [4..5] counters
   Segment* d_seg;
   unsigned long long next_seq;    // head after the last call
 };
@@ -85,7 +85,7 @@ int inc_ring_destroy(inc_ring* r) {
 int inc_ring_simulate(inc_ring* r, const inc_batch* b, inc_residual* d_res, const inc_host_output* out, void* stream,
                       int mode, inc_ring_stats* stats) {
   if (!r || !b || !d_res || !b->T0 || b->n < 1 || b->n >= (1ull << 32)) return INC_ERR_ARG;
-  if (mode != INC_MODE_PLAIN && mode != INC_MODE_PERSISTENT) return INC_ERR_ARG;
+  if (mode != INC_MODE_PLAIN && mode != INC_MODE_PERSISTENT && mode != INC_MODE_STAGED) return INC_ERR_ARG;
   hipStream_t st = (hipStream_t)stream;
   volatile unsigned long long* tail_p = r->h_ctrl;
   volatile unsigned int* err_p = (volatile unsigned int*)(r->h_ctrl + 1);
@@ -98,7 +98,7 @@ int inc_ring_simulate(inc_ring* r, const inc_batch* b, inc_residual* d_res, cons
   seg.seed = b->seed;
   seg.first_id = b->first_event_id;
   seg.res = d_res;
-  seg.counters = r->d_dev + 2;
+  seg.counters = r->d_dev + 4;
   RingDev R;
   R.tag = r->d_rec;
   R.ev = r->d_rec + r->slots;

@@ -209,7 +209,7 @@ int start_launch(inc_server* s) {
   // largest free block of the pool
   const uint64_t key = s->reqs[s->queue.front()].seed;
   const size_t room = s->pool.largest();
-  const size_t fixed = align_up(sizeof(unsigned long long)) + 2 * kAlign;
+  const size_t fixed = align_up(2 * sizeof(unsigned long long)) + 2 * kAlign;
   std::vector<uint64_t> take;
   size_t n = 0, bytes = fixed;
   for (uint64_t tk : s->queue) {
@@ -235,7 +235,7 @@ int start_launch(inc_server* s) {
   const size_t T0_off = o;   o += align_up(4 * n);
   const size_t tidx_off = o; o += align_up(n);
   L.seg_off = o;             o += align_up(sizeof(Segment) * take.size());
-  L.queue_off = o;           o += align_up(sizeof(unsigned long long));
+  L.queue_off = o;           o += align_up(2 * sizeof(unsigned long long));
   char* h = s->h_pool + L.off;
   char* d = s->d_pool + L.off;
   bool any_tidx = false;

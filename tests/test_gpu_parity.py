@@ -59,7 +59,7 @@ def test_nucleus_tables_match_oracle():
         assert tab[t, 107] == pytest.approx(nu.R, rel=1e-6)
 
 
-@pytest.mark.parametrize("mode", ["plain", "persistent"])
+@pytest.mark.parametrize("mode", ["plain", "persistent", "staged"])
 @pytest.mark.parametrize("target,T", [(O16, 200.0), (CA40, 200.0), ((12, 6), 20.0), ((56, 26), 250.0)])
 def test_ledgers_every_event(mode, target, T):
     n = 20000
@@ -130,6 +130,26 @@ def test_plain_and_persistent_agree_per_event():
     b = events_from_gpu(run_gpu(TISSUE, T0, seed=7, tidx=tidx, mode="persistent"), TISSUE, T0, tidx)
     ka, kb = outcome_keys(a), outcome_keys(b)
     agree = np.mean([x == y for x, y in zip(ka, kb)])
+    assert agree > 0.999, agree
+
+
+def test_staged_equals_fused_persistent():
+    """Staged mode (cascade kernel, hand-over, evaporation kernel) resumes the
+    same random stream: per event it gives the fused kernel's results."""
+    n = 30000
+    tidx, T0 = _mixture(n, TISSUE, TISSUE_W, 20, 250, seed=23)
+    T0[:10] = 300.0  # out of range: flagged in both
+    hf = run_gpu(TISSUE, T0, seed=8, tidx=tidx, mode="persistent")
+    hs = run_gpu(TISSUE, T0, seed=8, tidx=tidx, mode="staged")
+    same = hf["res"].view(np.uint8).reshape(n, -1) == hs["res"].view(np.uint8).reshape(n, -1)
+    frac = float(np.mean(same.all(axis=1)))
+    print("staged vs fused: identical residual records", frac)
+    assert frac > 0.999
+    assert (hs["res"]["flags"][:10] == 0x8000).all()
+    a = events_from_gpu(hf, TISSUE, T0, tidx)
+    b = events_from_gpu(hs, TISSUE, T0, tidx)
+    ledger.assert_clean(ledger.check(b))
+    agree = np.mean([x == y for x, y in zip(outcome_keys(a), outcome_keys(b))])
     assert agree > 0.999, agree
 
 
@@ -370,5 +390,28 @@ def test_ring_output_equals_direct_output():
         kr = np.lexsort((r["sec_T"], r["sec_species"], r["sec_stage"], r["sec_event"]))
         for f in ("sec_event", "sec_species", "sec_stage", "sec_T", "sec_u"):
             assert np.array_equal(direct[f][kd], r[f][kr]), (rep, f)
+    ring.close()
+    ctx.close()
+
+
+def test_ring_staged_mode_equals_direct_staged():
+    import torch
+
+    import paper_1309_7963_amd as inc
+
+    n = 40000
+    tidx, T0 = _mixture(n, IMPLANT, [0.5, 0.5], 70, 250, seed=29)
+    ctx = inc.Context(IMPLANT)
+    direct = run_gpu(IMPLANT, T0, seed=4, tidx=tidx, ctx=ctx, mode="staged")
+    ring = inc.Ring(ctx, slots=1 << 14)
+    r = ring.simulate(torch.as_tensor(T0, device="cuda"), seed=4, target_idx=torch.as_tensor(tidx, device="cuda"),
+                      mode="staged")
+    assert r["rc"] == 0 and r["stats"]["producer_gave_up"] == 0
+    assert r["res"].tobytes() == direct["res"].tobytes()
+    assert r["n_sec_total"] == direct["n_sec_total"]
+    kd = np.lexsort((direct["sec_T"], direct["sec_species"], direct["sec_stage"], direct["sec_event"]))
+    kr = np.lexsort((r["sec_T"], r["sec_species"], r["sec_stage"], r["sec_event"]))
+    for f in ("sec_event", "sec_species", "sec_stage", "sec_T", "sec_u"):
+        assert np.array_equal(direct[f][kd], r[f][kr]), f
     ring.close()
     ctx.close()
