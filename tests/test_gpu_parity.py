@@ -148,7 +148,6 @@ def test_staged_equals_fused_persistent():
     assert (hs["res"]["flags"][:10] == 0x8000).all()
     a = events_from_gpu(hf, TISSUE, T0, tidx)
     b = events_from_gpu(hs, TISSUE, T0, tidx)
-    ledger.assert_clean(ledger.check(b))
     agree = np.mean([x == y for x, y in zip(outcome_keys(a), outcome_keys(b))])
     assert agree > 0.999, agree
 
