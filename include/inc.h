@@ -85,6 +85,10 @@ typedef struct {
                          /* results differ from the default in the last bits */
                          /* of each step, so event histories diverge, and    */
                          /* agree with it in distribution                    */
+  /* launch policy, continued */
+  int start_threshold;   /* persistent kernel: lanes that must wait to begin */
+                         /* a flight (entry or stack pop) before the wave    */
+                         /* runs that step (1..64; 0 = default)              */
 } inc_options;
 
 /* One residual nucleus per event, 32 bytes. */

@@ -148,7 +148,7 @@ class Context:
         # at most A + 1 secondaries per event; the mean is far lower
         return int(n * min(self.max_A + 1, 12)) + 4096
 
-    def simulate(self, T0, seed: int, target_idx=None, first_event_id: int = 0, mode: str = "persistent",
+    def simulate(self, T0, seed: int, target_idx=None, first_event_id: int = 0, mode: str = "staged",
                  out: Optional[DeviceOutput] = None, capacity: Optional[int] = None, stream=None) -> DeviceOutput:
         """Generate len(T0) non-elastic events asynchronously on `stream`
         (default: torch's current stream).  T0: float32 cuda tensor (MeV);

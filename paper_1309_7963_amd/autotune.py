@@ -3,7 +3,7 @@
 Sweeps the launch options that set how a wave keeps its lanes busy:
 block size (waves per workgroup), resident waves per CU (events in flight)
 and the per-state lane thresholds of the wave scheduler (how many lanes must
-wait in the tentative-collision, kinematics or evaporation state before the
+wait in the kinematics, tentative-collision or flight-start state before the
 wave runs that state).  Each candidate is timed on the caller's workload with
 HIP events (a warm-up launch, then the median of `repeats` launches); the
 best is cached in a JSON file keyed by GPU architecture and workload
@@ -25,7 +25,8 @@ import numpy as np
 DEFAULT_GRID = {
     "block_size": (128, 256),
     "waves_per_cu": (8, 12),
-    "thresholds": ((16, 8, 16), (12, 8, 12), (16, 4, 16), (24, 8, 16), (16, 8, 24), (8, 8, 8), (16, 12, 16)),
+    # (kinematics, tentative collision, flight start) lane thresholds
+    "thresholds": ((16, 8, 8), (24, 12, 4), (24, 8, 8), (16, 12, 8), (16, 4, 4), (24, 4, 8)),
 }
 
 
@@ -46,7 +47,7 @@ def _arch() -> str:
     return torch.cuda.get_device_properties(0).gcnArchName.split(":")[0]
 
 
-def _time(targets, T0_d, tidx_d, opts, repeats):
+def _time(targets, T0_d, tidx_d, opts, repeats, mode):
     import torch
 
     import paper_1309_7963_amd as inc
@@ -55,12 +56,12 @@ def _time(targets, T0_d, tidx_d, opts, repeats):
     n = int(T0_d.shape[0])
     out = inc.DeviceOutput.allocate(n, ctx.default_capacity(n))
     stream = torch.cuda.current_stream()
-    ctx.simulate(T0_d, seed=1, target_idx=tidx_d, out=out)
+    ctx.simulate(T0_d, seed=1, target_idx=tidx_d, out=out, mode=mode)
     times = []
     for k in range(repeats):
         a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         a.record(stream)
-        ctx.simulate(T0_d, seed=1, target_idx=tidx_d, out=out, first_event_id=(k + 1) * n)
+        ctx.simulate(T0_d, seed=1, target_idx=tidx_d, out=out, first_event_id=(k + 1) * n, mode=mode)
         b.record(stream)
         torch.cuda.synchronize()
         times.append(a.elapsed_time(b))
@@ -69,13 +70,13 @@ def _time(targets, T0_d, tidx_d, opts, repeats):
 
 
 def tune(targets, T0, tidx=None, grid: Optional[dict] = None, repeats: int = 3, use_cache: bool = True,
-         verbose: bool = False) -> dict:
+         verbose: bool = False, mode: str = "staged") -> dict:
     """Return {"options": {...}, "ms": best, "table": [...]} for the workload
     (T0: host float32 array, tidx: host uint8 array or None)."""
     import torch
 
     grid = grid or DEFAULT_GRID
-    key = "%s|%s|%d" % (_arch(), signature(targets, T0), len(T0))
+    key = "%s|%s|%s|%d" % (_arch(), mode, signature(targets, T0), len(T0))
     path = cache_path()
     cache = {}
     if use_cache and os.path.exists(path):
@@ -92,10 +93,10 @@ def tune(targets, T0, tidx=None, grid: Optional[dict] = None, repeats: int = 3, 
     t0 = time.perf_counter()
     for bs in grid["block_size"]:
         for w in grid["waves_per_cu"]:
-            for kin, tent, evap in grid["thresholds"]:
+            for kin, tent, start in grid["thresholds"]:
                 opts = dict(block_size=bs, waves_per_cu=w, kin_threshold=kin, tent_threshold=tent,
-                            evap_threshold=evap)
-                ms = _time(targets, T0_d, tidx_d, opts, repeats)
+                            start_threshold=start)
+                ms = _time(targets, T0_d, tidx_d, opts, repeats, mode)
                 table.append(dict(options=opts, ms=ms))
                 if verbose:
                     print("autotune", opts, "%.3f ms" % ms, flush=True)

@@ -46,8 +46,8 @@ void release(inc_ctx* c) {
 
 int inc_launch_segments(inc_ctx* ctx, size_t n, const uint8_t* tidx, const float* T0, const Segment* d_segs,
                         int n_seg, unsigned long long* queue, hipStream_t s, int mode, int max_blocks,
-                        const RingDev* ring) {
-  if ((mode == INC_MODE_PLAIN || mode == INC_MODE_STAGED) && ctx->mid_cap < n) {
+                        const RingDev* ring, MidState* mid) {
+  if (!mid && (mode == INC_MODE_PLAIN || mode == INC_MODE_STAGED) && ctx->mid_cap < n) {
     if (ctx->d_mid) (void)hipFree(ctx->d_mid);
     ctx->d_mid = nullptr;
     ctx->mid_cap = 0;
@@ -62,9 +62,12 @@ int inc_launch_segments(inc_ctx* ctx, size_t n, const uint8_t* tidx, const float
   L.persistent_blocks = ctx->n_cu * ctx->waves_per_cu / (ctx->block / 64);
   if (max_blocks > 0 && max_blocks < L.persistent_blocks) L.persistent_blocks = max_blocks;
   if (L.persistent_blocks < 1) L.persistent_blocks = 1;
+  L.evap_blocks = ctx->evap_blocks;
+  if (max_blocks > 0 && max_blocks < L.evap_blocks) L.evap_blocks = max_blocks;
   L.evap_threshold = ctx->evap_threshold;
   L.tent_threshold = ctx->tent_threshold;
   L.kin_threshold = ctx->kin_threshold;
+  L.start_threshold = ctx->start_threshold;
   L.stack_lds = ctx->stack_lds[mode == INC_MODE_PLAIN ? 0 : 1];
   L.nuc = ctx->d_nuc;
   L.n_targets = ctx->n_targets;
@@ -82,7 +85,7 @@ int inc_launch_segments(inc_ctx* ctx, size_t n, const uint8_t* tidx, const float
   L.segs = d_segs;
   L.n_seg = n_seg;
   L.queue = queue;
-  L.mid = ctx->d_mid;
+  L.mid = mid ? mid : ctx->d_mid;
   if (ring) L.ring = *ring;
   return map_err(ctx->opt.fast_math ? fast::launch_events(L, s) : precise::launch_events(L, s));
 }
@@ -149,6 +152,7 @@ int inc_ctx_create(const inc_nucleus* targets, int n_targets, const inc_options*
   if (o.evap_threshold < 0 || o.evap_threshold > 64 || o.tent_threshold < 0 || o.tent_threshold > 64 ||
       o.kin_threshold < 0 || o.kin_threshold > 64 || o.waves_per_cu < 0 || o.waves_per_cu > 32 ||
       o.stack_levels < -1 || o.stack_levels > incdev::kStackLdsMax || o.fast_math < 0 || o.fast_math > 1 ||
+      o.start_threshold < 0 || o.start_threshold > 64 ||
       o.same_stream < 0 || o.same_stream > 1)
     return INC_ERR_ARG;
   if (!(o.const_sigma_mb >= 0.0f) || o.const_sigma_mb > 1e5f) return INC_ERR_ARG;
@@ -171,6 +175,7 @@ int inc_ctx_create(const inc_nucleus* targets, int n_targets, const inc_options*
   c->evap_threshold = o.evap_threshold ? o.evap_threshold : 16;
   c->tent_threshold = o.tent_threshold ? o.tent_threshold : 8;
   c->kin_threshold = o.kin_threshold ? o.kin_threshold : 16;
+  c->start_threshold = o.start_threshold ? o.start_threshold : 8;
   c->waves_per_cu = o.waves_per_cu ? o.waves_per_cu : 12;
   int amax = 0, zmax = 0;
   for (int t = 0; t < n_targets; ++t) {
@@ -207,6 +212,7 @@ int inc_ctx_create(const inc_nucleus* targets, int n_targets, const inc_options*
       else if (o.stack_levels > 0 && o.stack_levels < lv) lv = o.stack_levels;
       c->stack_lds[m] = lv;
     }
+    c->evap_blocks = n_cu * (o.fast_math ? fast::evap_blocks_per_cu(c->block) : precise::evap_blocks_per_cu(c->block));
   } while (false);
   if (d_AZ) (void)hipFree(d_AZ);
   if (d_evap) (void)hipFree(d_evap);
@@ -290,7 +296,7 @@ int inc_simulate(int target_A, int target_Z, const float* energies, size_t n, ui
     o.sec_capacity = cap;
     o.counters = d_cnt;
     inc_batch bt = {n, nullptr, d_T0, seed, 0};
-    rc = inc_simulate_dev(ctx, &bt, &o, nullptr, INC_MODE_PERSISTENT);
+    rc = inc_simulate_dev(ctx, &bt, &o, nullptr, INC_MODE_STAGED);
     if (rc) break;
     if ((e = hipDeviceSynchronize()) != hipSuccess) break;
     if ((e = hipMemcpy(cnt, d_cnt, sizeof(cnt), hipMemcpyDeviceToHost)) != hipSuccess) break;

@@ -21,21 +21,26 @@ struct inc_ctx {
   incdev::Segment* d_segs;  // kSegSlots single-segment descriptors, used in turn
   unsigned seg_next;
   int n_cu;
-  int block, evap_threshold, tent_threshold, kin_threshold, waves_per_cu;
+  int block, evap_threshold, tent_threshold, kin_threshold, start_threshold, waves_per_cu;
   int stack_lds[2];  // LIFO entries per lane in LDS: [plain, persistent]
+  int evap_blocks;   // staged mode: evaporation kernel grid (full occupancy)
 };
 
 
 constexpr int kSegSlots = 64;  // inc_simulate_dev calls that may be in flight per context
 
 // Launch n events described by n_seg device segments (sorted by start, each
-// with its own key, ids and outputs); queue: device work-queue counter.
+// with its own key, ids and outputs); queue: two device work-queue counters.
 // ring: streaming output of the secondaries (NULL: the segments' arrays).
+// mid: plain/staged hand-over buffer of n records (NULL: the context's own,
+// grown on demand; launches that overlap on different streams must each
+// bring their own).
 __attribute__((visibility("hidden"))) int inc_launch_segments(inc_ctx* ctx, size_t n, const uint8_t* tidx,
                                                               const float* T0, const incdev::Segment* d_segs,
                                                               int n_seg, unsigned long long* queue, hipStream_t s,
                                                               int mode, int max_blocks,
-                                                              const incdev::RingDev* ring = nullptr);
+                                                              const incdev::RingDev* ring = nullptr,
+                                                              incdev::MidState* mid = nullptr);
 
 // Launch one batch (validated like inc_simulate_dev); max_blocks > 0 caps the
 // persistent grid (small batches use fewer blocks).  Internal to the library.

@@ -76,7 +76,7 @@ struct Opts {
   int no_pauli, no_evaporation, stop_after_first;
   float const_sigma_mb;  // > 0 overrides every NN cross-section
   float fixed_b;         // >= 0 fixes the impact parameter
-  int evap_threshold, tent_threshold, kin_threshold;
+  int evap_threshold, tent_threshold, kin_threshold, start_threshold;
   int same_stream;       // every event uses its segment's first id
 };
 

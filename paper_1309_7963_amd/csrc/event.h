@@ -2,13 +2,16 @@
 // intranuclear cascade (Sec. 2.3) and the evaporation (Sec. 2.4).
 //
 // A lane is always in one of a few states and advances by one bounded step per
-// call: FLIGHT (one flight segment, ending at a shell boundary or at a
-// tentative collision point), TENT (the tentative collision: target species
-// and momentum, p_lab, accept test), KIN (the accepted collision: CM angle,
-// boosts, Pauli test, cutoff, stack), EVAP (one evaporation emission).  The
-// kernels keep the whole wave converged at the writer after every step, and
-// the persistent kernel picks per iteration which state the wave advances, so
-// that each step runs with many lanes together.
+// call: START (begin a flight: the entry of a pass, or the next particle from
+// the stack after an escape), FLIGHT (one flight segment, ending at a shell
+// boundary, at a tentative collision point or at an escape; no random draws),
+// TENT (the tentative collision: target species and momentum, p_lab, accept
+// test), KIN (the accepted collision: CM angle, boosts, Pauli test, cutoff,
+// stack), EVAP (one evaporation emission).  The kernels keep the whole wave
+// converged at the writer after every step, and the persistent kernel picks
+// per iteration which state the wave advances, so that each step runs with
+// many lanes together and the rare paths (entry, stack pop) do not ride along
+// with every flight segment.
 #pragma once
 
 #include "device.h"
@@ -22,6 +25,7 @@ enum : int {
   kStKin = 3,
   kStEvap = 4,
   kStDone = 5,    // event finished, lane needs a new one
+  kStStart = 6,   // begin a flight (entry of a pass, or pop after an escape)
 };
 
 // Cascade state of one event (registers).  The LIFO of pending products
@@ -162,16 +166,29 @@ __device__ __forceinline__ float flight_weight(const Cascade& c, const NucTab& n
   return y ? (c.avail1 > 0 ? nt.rho[1][s] * c.sh1 : 0.0f) : (c.avail0 > 0 ? nt.rho[0][s] * c.sh0 : 0.0f);
 }
 
-// FLIGHT: entry if needed, then one flight segment (null-collision flight,
-// reading of the mean free path): the segment ends at a tentative collision
-// point (-> TENT) or at a shell boundary, where the particle is refracted,
-// reflected or escapes (Sec. 2.3).  Returns the next state; kStDone means the
-// cascade of this event is over.  Draws at most 3 uniforms.
-__device__ __forceinline__ int flight_step(Cascade& c, StackEntry* stk, Rng& rng, const NucTab& nt, const XsTab& xs,
-                                           const Opts& o, float T0, Emit& em) {
-  em.on = false;
+// START: begin the next flight.  A pass that has not started enters the
+// nucleus (impact parameter, refraction, majorant, first optical depth);
+// otherwise the particle in hand has escaped and the next one comes from the
+// stack (kStDone when it is empty).  Draws at most 3 uniforms.
+__device__ __forceinline__ int start_step(Cascade& c, StackEntry* stk, Rng& rng, const NucTab& nt, const XsTab& xs,
+                                          const Opts& o, float T0) {
   rng.ensure(3);
-  if (!c.started) cascade_entry(c, rng, nt, xs, o, T0);
+  if (!c.started) {
+    cascade_entry(c, rng, nt, xs, o, T0);
+    return kStFlight;
+  }
+  return next_particle(c, stk, rng, nt, xs, o) ? kStFlight : kStDone;
+}
+
+// FLIGHT: one flight segment (null-collision flight, reading of the mean free
+// path): the segment ends at a tentative collision point (-> TENT) or at a
+// shell boundary, where the particle is refracted, reflected or escapes (Sec.
+// 2.3).  An escape emits the particle and returns kStStart (next particle); an
+// escape before any collision is a transparent pass, retried from the entry
+// (Sec. 2.1), also through kStStart.  kStDone: the segment guard ended the
+// cascade.  No random draws.
+__device__ __forceinline__ int flight_core(Cascade& c, StackEntry* stk, const NucTab& nt, Emit& em) {
+  em.on = false;
   if (c.nseg >= kMaxSegments) {
     // segment guard: capture everything still moving
     c.flags |= kFlagSegments;
@@ -216,7 +233,7 @@ __device__ __forceinline__ int flight_step(Cascade& c, StackEntry* stk, Rng& rng
         // transparent pass: not a non-elastic event, try again (Sec. 2.1)
         ++c.nretry;
         c.started = 0;
-        return kStFlight;
+        return kStStart;
       }
       const float p = sqrtf(T_out * T_out + 2.0f * T_out * m);
       c.pesc = axpy(p, c.dir, c.pesc);
@@ -225,12 +242,24 @@ __device__ __forceinline__ int flight_step(Cascade& c, StackEntry* stk, Rng& rng
       em.kind = (uint32_t)c.sp;  // stage 0
       em.T = T_out;
       em.u = c.dir;
-      return next_particle(c, stk, rng, nt, xs, o) ? kStFlight : kStDone;
+      return kStStart;
     }
   } else if (refract(c.dir, n, T_from, c.eps + nt.EF[c.sp][dest], m)) {
     c.shell = dest;
   }
   return kStFlight;
+}
+
+// START and FLIGHT as one call (the plain kernel): the entry when the pass has
+// not started, one segment, and after an escape the next particle.  Returns
+// kStFlight, kStTent or kStDone; a transparent pass returns kStFlight with the
+// entry left for the next call.
+__device__ __forceinline__ int flight_step(Cascade& c, StackEntry* stk, Rng& rng, const NucTab& nt, const XsTab& xs,
+                                           const Opts& o, float T0, Emit& em) {
+  if (!c.started) start_step(c, stk, rng, nt, xs, o, T0);
+  int st = flight_core(c, stk, nt, em);
+  if (st == kStStart) st = c.started ? start_step(c, stk, rng, nt, xs, o, T0) : kStFlight;
+  return st;
 }
 
 // Invariants of the pair (x, y) used by TENT and KIN.
@@ -484,15 +513,6 @@ __device__ __forceinline__ bool evap_step(Nucleus& nu, Rng& rng, const BindTab& 
   nu.Z = Zd;
   nu.E = Ed;
   return false;
-}
-
-// One cascade step of whatever state the lane is in (plain kernels).
-__device__ __forceinline__ int cascade_advance(int st, Cascade& c, StackEntry* stk, Rng& rng, const NucTab& nt,
-                                               const XsTab& xs, const Opts& o, float T0, Emit& em) {
-  em.on = false;
-  if (st == kStFlight) return flight_step(c, stk, rng, nt, xs, o, T0, em);
-  if (st == kStTent) return tent_step(c, rng, nt, xs, o);
-  return kin_step(c, stk, rng, nt, xs, o);
 }
 
 }  // namespace incdev

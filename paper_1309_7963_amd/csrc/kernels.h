@@ -24,7 +24,8 @@ struct LaunchDesc {
   int mode;
   int block;
   int persistent_blocks;
-  int evap_threshold, tent_threshold, kin_threshold;
+  int evap_blocks;       // staged mode: grid of the evaporation kernel
+  int evap_threshold, tent_threshold, kin_threshold, start_threshold;
   int stack_lds;         // stack entries per lane held in LDS (stack_levels)
   const NucTab* nuc;
   int n_targets;
@@ -53,15 +54,19 @@ struct LaunchDesc {
 //                 `mode` at this block size when `waves_per_cu` waves are meant
 //                 to share a CU (the kernel's own occupancy limit applies too);
 //                 0 when none fit;
+//   evap_blocks_per_cu  resident blocks per CU of the staged evaporation
+//                 kernel (its own occupancy: it needs fewer registers);
 //   launch_events zero the counters, then launch the event kernel(s) of L.mode.
 namespace precise {
 size_t lds_bytes(int n_targets, int block, bool with_xs, int stack_levels);
 int stack_levels(int mode, int n_targets, int block, int waves_per_cu);
+int evap_blocks_per_cu(int block);
 hipError_t launch_events(const LaunchDesc& L, hipStream_t s);
 }  // namespace precise
 namespace fast {
 size_t lds_bytes(int n_targets, int block, bool with_xs, int stack_levels);
 int stack_levels(int mode, int n_targets, int block, int waves_per_cu);
+int evap_blocks_per_cu(int block);
 hipError_t launch_events(const LaunchDesc& L, hipStream_t s);
 }  // namespace fast
 

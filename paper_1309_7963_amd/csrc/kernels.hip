@@ -301,7 +301,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) k
           init_stream(rng, a, er);
           cascade_init(c, snt[tgt]);
           nsec = 0;
-          st = kStFlight;
+          st = kStStart;
         }
       }
       const unsigned long long cnt = (unsigned long long)__popcll(need);
@@ -312,7 +312,8 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) k
     const int nT = __popcll(__ballot(st == kStTent));
     const int nK = __popcll(__ballot(st == kStKin));
     const int nE = __popcll(__ballot(st == kStEvap));
-    if (nF + nT + nK + nE == 0) {
+    const int nS = __popcll(__ballot(st == kStStart));
+    if (nF + nT + nK + nE + nS == 0) {
       if (exhausted) break;
       continue;
     }
@@ -320,10 +321,12 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) k
     int run;
     if (nK >= a.opt.kin_threshold) run = kStKin;
     else if (nT >= a.opt.tent_threshold) run = kStTent;
+    else if (nS >= a.opt.start_threshold) run = kStStart;
     else if (nE >= a.opt.evap_threshold) run = kStEvap;
     else if (nF) run = kStFlight;
     else if (nK) run = kStKin;
     else if (nT) run = kStTent;
+    else if (nS) run = kStStart;
     else run = kStEvap;
 
     Emit em;
@@ -341,7 +344,8 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) k
     } else if (st == run) {
       const NucTab& nt = snt[tgt];
       int ns;
-      if (run == kStFlight) ns = flight_step(c, stk, rng, nt, sxs, a.opt, T0, em);
+      if (run == kStFlight) ns = flight_core(c, stk, nt, em);
+      else if (run == kStStart) ns = start_step(c, stk, rng, nt, sxs, a.opt, T0);
       else if (run == kStTent) ns = tent_step(c, rng, nt, sxs, a.opt);
       else ns = kin_step(c, stk, rng, nt, sxs, a.opt);
       if (em.on) ++nsec;
@@ -503,6 +507,15 @@ int stack_levels(int mode, int n_targets, int block, int waves_per_cu) {
   return levels > (size_t)kStackLdsMax ? kStackLdsMax : (int)levels;
 }
 
+int evap_blocks_per_cu(int block) {
+  int occ = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, (const void*)k_evap_persistent, block,
+                                                   lds_bytes(0, block, false, 0)) != hipSuccess ||
+      occ < 1)
+    return 1;
+  return occ;
+}
+
 hipError_t launch_events(const LaunchDesc& L, hipStream_t s) {
   KernelArgs a;
   a.nuc = L.nuc;
@@ -519,6 +532,7 @@ hipError_t launch_events(const LaunchDesc& L, hipStream_t s) {
   a.opt.evap_threshold = L.evap_threshold;
   a.opt.tent_threshold = L.tent_threshold;
   a.opt.kin_threshold = L.kin_threshold;
+  a.opt.start_threshold = L.start_threshold;
   a.opt.same_stream = L.opt.same_stream;
   a.n = L.n;
   a.tidx = L.tidx;
@@ -541,8 +555,7 @@ hipError_t launch_events(const LaunchDesc& L, hipStream_t s) {
     hipLaunchKernelGGL(k_persistent, dim3(L.persistent_blocks), dim3(block),
                        lds_bytes(L.n_targets, block, true, L.stack_lds), s, a);
     if (L.mode == INC_MODE_STAGED)
-      hipLaunchKernelGGL(k_evap_persistent, dim3(L.persistent_blocks), dim3(block), lds_bytes(0, block, false, 0), s,
-                         a);
+      hipLaunchKernelGGL(k_evap_persistent, dim3(L.evap_blocks), dim3(block), lds_bytes(0, block, false, 0), s, a);
   }
   return hipGetLastError();
 }

@@ -24,6 +24,7 @@
 
 #include "ctx.h"
 
+using incdev::MidState;
 using incdev::Segment;
 
 namespace {
@@ -81,10 +82,12 @@ class Pool {
   std::map<size_t, size_t> free_;
 };
 
-// Device bytes a request needs inside a launch.
+// Device bytes a request needs inside a launch (inputs, its share of the
+// staged hand-over buffer, residuals, secondaries, counters, segment entry).
 size_t request_bytes(size_t n, size_t cap) {
-  return align_up(4 * n) + align_up(n) + align_up(sizeof(inc_residual) * n) + 5 * align_up(4 * cap) +
-         2 * align_up(cap) + align_up(4 * sizeof(unsigned long long)) + align_up(sizeof(Segment));
+  return align_up(4 * n) + align_up(n) + align_up(sizeof(MidState) * n) + align_up(sizeof(inc_residual) * n) +
+         5 * align_up(4 * cap) + 2 * align_up(cap) + align_up(4 * sizeof(unsigned long long)) +
+         align_up(sizeof(Segment));
 }
 
 enum RState { kQueued = 0, kLaunched = 1, kReady = 2 };
@@ -230,12 +233,13 @@ int start_launch(inc_server* s) {
   L.phase = kRunning;
   L.pending_fetch = (int)take.size();
   const int id = s->next_launch++;
-  // layout: [T0][tidx][segments][queue][per request: counters res T ux uy uz ev sp st]
+  // layout: [T0][tidx][segments][queues][hand-over][per request: counters res T ux uy uz ev sp st]
   size_t o = 0;
   const size_t T0_off = o;   o += align_up(4 * n);
   const size_t tidx_off = o; o += align_up(n);
   L.seg_off = o;             o += align_up(sizeof(Segment) * take.size());
   L.queue_off = o;           o += align_up(2 * sizeof(unsigned long long));
+  const size_t mid_off = o;  o += align_up(sizeof(MidState) * n);
   char* h = s->h_pool + L.off;
   char* d = s->d_pool + L.off;
   bool any_tidx = false;
@@ -291,7 +295,8 @@ int start_launch(inc_server* s) {
     const int blocks = (int)((n + s->ctx->block - 1) / s->ctx->block);
     rc = inc_launch_segments(s->ctx, n, any_tidx ? (const uint8_t*)(d + tidx_off) : nullptr, (const float*)(d + T0_off),
                              (const Segment*)(d + L.seg_off), (int)segs.size(),
-                             (unsigned long long*)(d + L.queue_off), st, INC_MODE_PERSISTENT, blocks);
+                             (unsigned long long*)(d + L.queue_off), st, INC_MODE_STAGED, blocks, nullptr,
+                             (MidState*)(d + mid_off));
   }
   for (size_t k = 0; k < take.size() && rc == INC_OK; ++k) {
     const Request& r = s->reqs[take[k]];
