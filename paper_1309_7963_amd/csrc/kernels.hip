@@ -34,7 +34,6 @@ struct KernelArgs {
   MidState* mid;             // plain kernels: cascade -> evaporation hand-over
   RingDev ring;              // streaming output (rec == NULL: segment arrays)
   int stack_lds;             // stack entries per lane held in LDS
-  int defer_evap;            // persistent kernel: hand the evaporation over (mid)
 };
 
 __device__ __forceinline__ bool energy_ok(float T0) { return T0 >= 20.0f && T0 <= 250.0f; }
@@ -239,6 +238,10 @@ constexpr int kChunk = 64;
 
 // 3 waves per SIMD (<= 168 VGPRs): the lane scheduler needs many events in
 // flight per CU more than it needs extra registers.
+// kFused: the evaporation runs in the same kernel as a fifth lane state;
+// otherwise (staged mode) the kernel hands each finished cascade over and has
+// no evaporation code at all, which leaves it fewer live registers.
+template <bool kFused>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) k_persistent(KernelArgs a) {
   extern __shared__ __align__(16) char lds[];
   stage_tables(lds, a, a.n_targets, true);
@@ -292,7 +295,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) k
           const Nucleus z = {0, 0, 0.0f, {0.0f, 0.0f, 0.0f}};
           write_residual(a.segs[er.seg].res + er.local, z, 0.0f, 0, kFlagRange, 0, 0);
           atomicAdd(&a.segs[er.seg].counters[1], 1ull);
-          if (a.defer_evap) {
+          if (!kFused) {
             MidState m = {};
             m.flags = kFlagRange | kMidFinal;
             a.mid[ev] = m;
@@ -311,7 +314,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) k
     const int nF = __popcll(__ballot(st == kStFlight));
     const int nT = __popcll(__ballot(st == kStTent));
     const int nK = __popcll(__ballot(st == kStKin));
-    const int nE = __popcll(__ballot(st == kStEvap));
+    const int nE = kFused ? __popcll(__ballot(st == kStEvap)) : 0;
     const int nS = __popcll(__ballot(st == kStStart));
     if (nF + nT + nK + nE + nS == 0) {
       if (exhausted) break;
@@ -331,7 +334,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) k
 
     Emit em;
     em.on = false;
-    if (run == kStEvap) {
+    if (kFused && run == kStEvap) {
       if (st == kStEvap) {
         if (evap_step(nu, rng, a.bind, a.evap, smt, em)) {
           write_residual(a.segs[er.seg].res + er.local, nu, Ex_casc, nsec, c.flags, c.ncoll, c.nretry);
@@ -358,7 +361,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) k
           write_residual(a.segs[er.seg].res + er.local, nu, Ex_casc, nsec, c.flags, c.ncoll, c.nretry);
           if (c.flags) atomicAdd(&a.segs[er.seg].counters[1], 1ull);
         }
-        if (a.defer_evap) {
+        if (!kFused) {
           // staged mode: the evaporation kernel continues this event
           MidState m;
           m.A = (int16_t)nu.A;
@@ -493,7 +496,9 @@ int stack_levels(int mode, int n_targets, int block, int waves_per_cu) {
     return 0;
   const size_t base = lds_bytes(n_targets, block, true, 0);
   int occ = 0;
-  const void* fn = mode == INC_MODE_PLAIN ? (const void*)k_cascade_plain : (const void*)k_persistent;
+  const void* fn = mode == INC_MODE_PLAIN        ? (const void*)k_cascade_plain
+                   : mode == INC_MODE_PERSISTENT ? (const void*)k_persistent<true>
+                                                 : (const void*)k_persistent<false>;
   if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, fn, block, base) != hipSuccess || occ < 1) return 0;
   int blocks = occ;
   if (mode != INC_MODE_PLAIN) {
@@ -543,7 +548,6 @@ hipError_t launch_events(const LaunchDesc& L, hipStream_t s) {
   a.mid = L.mid;
   a.ring = L.ring;
   a.stack_lds = L.stack_lds;
-  a.defer_evap = L.mode == INC_MODE_STAGED;
   hipLaunchKernelGGL(k_zero_counters, dim3((L.n_seg + 63) / 64), dim3(64), 0, s, L.segs, L.n_seg, L.queue);
   const int block = L.block;
   if (L.mode == INC_MODE_PLAIN) {
@@ -552,8 +556,12 @@ hipError_t launch_events(const LaunchDesc& L, hipStream_t s) {
                        s, a);
     hipLaunchKernelGGL(k_evap_plain, dim3(grid), dim3(block), lds_bytes(0, block, false, 0), s, a);
   } else {
-    hipLaunchKernelGGL(k_persistent, dim3(L.persistent_blocks), dim3(block),
-                       lds_bytes(L.n_targets, block, true, L.stack_lds), s, a);
+    if (L.mode == INC_MODE_STAGED)
+      hipLaunchKernelGGL(k_persistent<false>, dim3(L.persistent_blocks), dim3(block),
+                         lds_bytes(L.n_targets, block, true, L.stack_lds), s, a);
+    else
+      hipLaunchKernelGGL(k_persistent<true>, dim3(L.persistent_blocks), dim3(block),
+                         lds_bytes(L.n_targets, block, true, L.stack_lds), s, a);
     if (L.mode == INC_MODE_STAGED)
       hipLaunchKernelGGL(k_evap_persistent, dim3(L.evap_blocks), dim3(block), lds_bytes(0, block, false, 0), s, a);
   }
