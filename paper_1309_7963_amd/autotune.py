@@ -26,7 +26,7 @@ DEFAULT_GRID = {
     "block_size": (128, 256),
     "waves_per_cu": (8, 12),
     # (kinematics, tentative collision, flight start) lane thresholds
-    "thresholds": ((16, 8, 8), (24, 12, 4), (24, 8, 8), (16, 12, 8), (16, 4, 4), (24, 4, 8)),
+    "thresholds": ((24, 24, 8), (24, 32, 8), (16, 32, 8), (16, 16, 8), (24, 12, 4), (16, 8, 8)),
 }
 
 

@@ -170,11 +170,12 @@ int inc_ctx_create(const inc_nucleus* targets, int n_targets, const inc_options*
   c->opt = o;
   c->fixed_b_set = o.fixed_b_on != 0;
   c->block = o.block_size ? o.block_size : 256;
-  // defaults from a sweep on MI355X (16O/40Ca at 200 MeV): a deep state runs
-  // once 8-16 lanes wait in it; 12 resident waves per CU (3 per SIMD)
+  // defaults from sweeps on MI355X (16O/40Ca at 200 MeV, staged mode): the
+  // tentative-collision and kinematics steps run once 24 lanes wait in them,
+  // a flight start once 8 do; 12 resident waves per CU (3 per SIMD)
   c->evap_threshold = o.evap_threshold ? o.evap_threshold : 16;
-  c->tent_threshold = o.tent_threshold ? o.tent_threshold : 8;
-  c->kin_threshold = o.kin_threshold ? o.kin_threshold : 16;
+  c->tent_threshold = o.tent_threshold ? o.tent_threshold : 24;
+  c->kin_threshold = o.kin_threshold ? o.kin_threshold : 24;
   c->start_threshold = o.start_threshold ? o.start_threshold : 8;
   c->waves_per_cu = o.waves_per_cu ? o.waves_per_cu : 12;
   int amax = 0, zmax = 0;
