@@ -325,7 +325,10 @@ __device__ __forceinline__ float log_width_integral(float Y, float lnAd) {
 // x = U s (2 - s), U - x = U (1 - s)^2, and the CDF in s is K(s) / K(1) with
 // dK/ds ~ s (2 - s) (1 - s) e^{-Y s}.  K is integrated in closed form
 // (large Y) or by its series in s (small Y); the root of K(s) = u K(1) is found
-// by bracketed Newton iteration.  Returns s.
+// by bracketed Newton iteration, stopped once the CDF residual is below 1e-6
+// (a quantile error far below what any sample of this size resolves).  For
+// large Y the start is the quantile of the Gamma(2) limit, x = Y s with
+// 1 - u = (1 + x) e^{-x}, from one fixed-point step.  Returns s.
 __device__ __forceinline__ float spectrum_K(float Y, float s) {
   if (Y < 1.0f) {
     // sum_m (-Y)^m / m! [2 s^{m+2}/(m+2) - 3 s^{m+3}/(m+3) + s^{m+4}/(m+4)]
@@ -352,11 +355,17 @@ __device__ __forceinline__ float spectrum_dK(float Y, float s) {
 __device__ __forceinline__ float spectrum_sample_s(float Y, float u) {
   const float K1 = spectrum_K(Y, 1.0f);
   const float target = u * K1;
+  const float ftol = 1e-6f * K1;
   float lo = 0.0f, hi = 1.0f;
-  float s = Y > 4.0f ? fminf(0.5f, 2.0f / Y) : 0.5f;
+  float s = 0.5f;
+  if (Y > 4.0f) {
+    const float x0 = -log1pf(-u);
+    s = fminf(fmaxf((x0 + log1pf(x0)) / Y, 1e-4f), 0.95f);
+  }
   for (int it = 0; it < 40; ++it) {
     const float F = spectrum_K(Y, s) - target;
     if (F < 0.0f) lo = s; else hi = s;
+    if (fabsf(F) <= ftol) break;
     const float dF = spectrum_dK(Y, s);
     float sn = (dF > 0.0f) ? s - F / dF : 0.5f * (lo + hi);
     if (!(sn > lo && sn < hi)) sn = 0.5f * (lo + hi);
