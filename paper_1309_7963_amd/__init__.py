@@ -386,18 +386,35 @@ class Ring:
         except Exception:
             pass
 
-    def simulate(self, T0, seed: int, target_idx=None, first_event_id: int = 0, mode: str = "persistent",
-                 capacity: Optional[int] = None, stream=None) -> dict:
+    @staticmethod
+    def host_buffers(capacity: int) -> dict:
+        """Host arrays for `capacity` secondaries (written once, so that a
+        later drain into them takes no first-touch page faults); pass them to
+        simulate(out=...) to reuse them across batches."""
+        out = dict(ev=np.zeros(capacity, np.uint32), sp=np.zeros(capacity, np.uint8),
+                   st=np.zeros(capacity, np.uint8), T=np.zeros(capacity, np.float32),
+                   ux=np.zeros(capacity, np.float32), uy=np.zeros(capacity, np.float32),
+                   uz=np.zeros(capacity, np.float32))
+        for a in out.values():
+            a.fill(0)
+        return out
+
+    def simulate(self, T0, seed: int, target_idx=None, first_event_id: int = 0, mode: str = "staged",
+                 capacity: Optional[int] = None, stream=None, out: Optional[dict] = None) -> dict:
         """T0 / target_idx: CUDA tensors as in Context.simulate.  Returns host
-        arrays of the secondaries, the residuals and the ring statistics."""
+        arrays of the secondaries (views of `out` when given, see
+        host_buffers), the residuals and the ring statistics."""
         torch = _torch()
         n = int(T0.shape[0])
-        cap = int(capacity) if capacity is not None else self.ctx.default_capacity(n)
+        if out is not None:
+            cap = int(out["T"].shape[0])
+        else:
+            cap = int(capacity) if capacity is not None else self.ctx.default_capacity(n)
+            out = dict(ev=np.zeros(cap, np.uint32), sp=np.zeros(cap, np.uint8), st=np.zeros(cap, np.uint8),
+                       T=np.zeros(cap, np.float32), ux=np.zeros(cap, np.float32), uy=np.zeros(cap, np.float32),
+                       uz=np.zeros(cap, np.float32))
         res_d = torch.empty(n * 32, dtype=torch.uint8, device=T0.device)
-        ev = np.zeros(cap, np.uint32)
-        sp = np.zeros(cap, np.uint8)
-        st = np.zeros(cap, np.uint8)
-        T, ux, uy, uz = (np.zeros(cap, np.float32) for _ in range(4))
+        ev, sp, st, T, ux, uy, uz = (out[k] for k in ("ev", "sp", "st", "T", "ux", "uy", "uz"))
         nsec = C.c_ulonglong()
         o = _lib.HostOutput(None, ev.ctypes.data, sp.ctypes.data, st.ctypes.data, T.ctypes.data, ux.ctypes.data,
                             uy.ctypes.data, uz.ctypes.data, cap, C.pointer(nsec), None)
@@ -417,7 +434,7 @@ class Ring:
         k = min(nsec.value, cap)
         return dict(rc=rc, res=res_d.cpu().numpy().view(RESIDUAL_DTYPE), n_sec_total=nsec.value,
                     sec_event=ev[:k], sec_species=sp[:k], sec_stage=st[:k], sec_T=T[:k],
-                    sec_u=np.stack([ux[:k], uy[:k], uz[:k]], 1),
+                    sec_ux=ux[:k], sec_uy=uy[:k], sec_uz=uz[:k],
                     stats={f: getattr(stats, f) for f, _ in stats._fields_})
 
 

@@ -9,14 +9,94 @@
 #include <string.h>
 
 #include <algorithm>
+#include <atomic>
 #include <chrono>
+#include <condition_variable>
+#include <functional>
+#include <mutex>
 #include <new>
 #include <thread>
+#include <vector>
 
 #include "ctx.h"
 
 using incdev::RingDev;
 using incdev::Segment;
+
+namespace {
+
+// Host copy workers of a ring.  Copying the drained records into the
+// caller's arrays is memory-bound on one thread and bounds the drain, so a
+// large run of ready records is cut into chunks that the calling thread and
+// these workers copy together.
+class CopyPool {
+ public:
+  explicit CopyPool(int workers) {
+    for (int i = 0; i < workers; ++i) th_.emplace_back([this] { loop(); });
+  }
+  ~CopyPool() {
+    {
+      std::lock_guard<std::mutex> g(m_);
+      stop_ = true;
+    }
+    cv_.notify_all();
+    for (auto& t : th_) t.join();
+  }
+  // Run fn(c) for every chunk c in [0, n) on the workers and the caller;
+  // returns when all chunks are done.
+  void run(int n, const std::function<void(int)>& fn) {
+    {
+      std::lock_guard<std::mutex> g(m_);
+      fn_ = &fn;
+      n_ = n;
+      left_ = n;
+      next_.store(0);
+      ++gen_;
+    }
+    cv_.notify_all();
+    work();
+    std::unique_lock<std::mutex> l(m_);
+    done_cv_.wait(l, [this] { return left_ == 0; });
+  }
+
+ private:
+  void work() {
+    int done = 0;
+    for (int c; (c = next_.fetch_add(1)) < n_;) {
+      (*fn_)(c);
+      ++done;
+    }
+    if (done) {
+      std::lock_guard<std::mutex> g(m_);
+      left_ -= done;
+      if (left_ == 0) done_cv_.notify_all();
+    }
+  }
+  void loop() {
+    unsigned seen = 0;
+    std::unique_lock<std::mutex> l(m_);
+    for (;;) {
+      cv_.wait(l, [&] { return stop_ || gen_ != seen; });
+      if (stop_) return;
+      seen = gen_;
+      l.unlock();
+      work();
+      l.lock();
+    }
+  }
+  std::vector<std::thread> th_;
+  std::mutex m_;
+  std::condition_variable cv_, done_cv_;
+  const std::function<void(int)>* fn_ = nullptr;
+  int n_ = 0, left_ = 0;
+  std::atomic<int> next_{0};
+  unsigned gen_ = 0;
+  bool stop_ = false;
+};
+
+constexpr size_t kCopyChunk = 16384;  // records per chunk of a parallel copy
+
+}  // namespace
 
 struct inc_ring {
   inc_ctx* ctx;
@@ -28,6 +108,7 @@ struct inc_ring {
   unsigned long long* d_dev;      // device: [0] head, [1..2] work queues, [4..5] counters
   Segment* d_seg;
   unsigned long long next_seq;    // head after the last call
+  CopyPool* pool;                 // host copy workers (NULL: the caller copies alone)
 };
 
 namespace {
@@ -68,6 +149,9 @@ int inc_ring_create(inc_ctx* ctx, size_t slots, inc_ring** out) {
     inc_ring_destroy(r);
     return inc_map_hip_error(e);
   }
+  const unsigned hw = std::thread::hardware_concurrency();
+  const int workers = hw > 1 ? (int)std::min(hw - 1, 7u) : 0;
+  if (workers > 0) r->pool = new (std::nothrow) CopyPool(workers);
   *out = r;
   return INC_OK;
 }
@@ -78,6 +162,7 @@ int inc_ring_destroy(inc_ring* r) {
   if (r->h_ctrl) (void)hipHostFree(r->h_ctrl);
   if (r->d_dev) (void)hipFree(r->d_dev);
   if (r->d_seg) (void)hipFree(r->d_seg);
+  delete r->pool;
   delete r;
   return INC_OK;
 }
@@ -136,27 +221,53 @@ int inc_ring_simulate(inc_ring* r, const inc_batch* b, inc_residual* d_res, cons
     const uint32_t* h_tag = r->h_rec;
     const size_t S = r->slots;
     while (true) {
-      // the run of ready records starting at tail, within the ring's linear range
+      // the run of ready records starting at tail, within the ring's linear
+      // range: tags are compared 16 at a time (plain loads; the acquire fence
+      // below orders the record reads after them)
       const size_t j = (size_t)(tail & mask);
+      const size_t lim = std::min<size_t>(S - j, 1u << 18);
       size_t run = 0;
-      while (run < S - j && run < 65536 &&
-             __atomic_load_n(h_tag + j + run, __ATOMIC_RELAXED) == (uint32_t)(tail + run + 1ull))
-        ++run;
+      while (run < lim) {
+        const size_t q = std::min<size_t>(16, lim - run);
+        uint32_t t16[16];
+        memcpy(t16, h_tag + j + run, 4 * q);
+        std::atomic_signal_fence(std::memory_order_seq_cst);
+        size_t ok = 0;
+        while (ok < q && t16[ok] == (uint32_t)(tail + run + ok + 1ull)) ++ok;
+        run += ok;
+        if (ok < q) break;
+      }
       if (run == 0) break;
       __atomic_thread_fence(__ATOMIC_ACQUIRE);
       const unsigned long long k = tail - start;
       if (out && k < cap_out) {
         const size_t m = (size_t)std::min<unsigned long long>(run, cap_out - k);
-        const uint32_t* kind = r->h_rec + 2 * S + j;
-        if (out->sec_event) memcpy(out->sec_event + k, r->h_rec + S + j, 4 * m);
-        if (out->sec_T) memcpy(out->sec_T + k, r->h_rec + 3 * S + j, 4 * m);
-        if (out->sec_ux) memcpy(out->sec_ux + k, r->h_rec + 4 * S + j, 4 * m);
-        if (out->sec_uy) memcpy(out->sec_uy + k, r->h_rec + 5 * S + j, 4 * m);
-        if (out->sec_uz) memcpy(out->sec_uz + k, r->h_rec + 6 * S + j, 4 * m);
-        if (out->sec_species)
-          for (size_t q = 0; q < m; ++q) out->sec_species[k + q] = (uint8_t)(kind[q] & 0xFFu);
-        if (out->sec_stage)
-          for (size_t q = 0; q < m; ++q) out->sec_stage[k + q] = (uint8_t)((kind[q] >> 8) & 0xFFu);
+        const uint32_t* rec = r->h_rec;
+        auto copy = [&, j, k](size_t a, size_t b) {
+          const size_t n = b - a;
+          if (out->sec_event) memcpy(out->sec_event + k + a, rec + S + j + a, 4 * n);
+          if (out->sec_T) memcpy(out->sec_T + k + a, rec + 3 * S + j + a, 4 * n);
+          if (out->sec_ux) memcpy(out->sec_ux + k + a, rec + 4 * S + j + a, 4 * n);
+          if (out->sec_uy) memcpy(out->sec_uy + k + a, rec + 5 * S + j + a, 4 * n);
+          if (out->sec_uz) memcpy(out->sec_uz + k + a, rec + 6 * S + j + a, 4 * n);
+          if (out->sec_species || out->sec_stage) {
+            const uint32_t* kind = rec + 2 * S + j;
+            for (size_t q = a; q < b; ++q) {
+              const uint32_t kd = kind[q];
+              if (out->sec_species) out->sec_species[k + q] = (uint8_t)(kd & 0xFFu);
+              if (out->sec_stage) out->sec_stage[k + q] = (uint8_t)((kd >> 8) & 0xFFu);
+            }
+          }
+        };
+        if (r->pool && m >= 2 * kCopyChunk) {
+          const int nc = (int)((m + kCopyChunk - 1) / kCopyChunk);
+          const std::function<void(int)> fn = [&](int c) {
+            copy((size_t)c * kCopyChunk, std::min(m, (size_t)(c + 1) * kCopyChunk));
+          };
+          r->pool->run(nc, fn);
+        } else {
+          copy(0, m);
+        }
         copied += m;
       }
       tail += run;

@@ -387,6 +387,7 @@ def test_ring_output_equals_direct_output():
         assert r["n_sec_total"] == direct["n_sec_total"]
         kd = np.lexsort((direct["sec_T"], direct["sec_species"], direct["sec_stage"], direct["sec_event"]))
         kr = np.lexsort((r["sec_T"], r["sec_species"], r["sec_stage"], r["sec_event"]))
+        r["sec_u"] = np.stack([r["sec_ux"], r["sec_uy"], r["sec_uz"]], 1)
         for f in ("sec_event", "sec_species", "sec_stage", "sec_T", "sec_u"):
             assert np.array_equal(direct[f][kd], r[f][kr]), (rep, f)
     ring.close()
@@ -410,7 +411,37 @@ def test_ring_staged_mode_equals_direct_staged():
     assert r["n_sec_total"] == direct["n_sec_total"]
     kd = np.lexsort((direct["sec_T"], direct["sec_species"], direct["sec_stage"], direct["sec_event"]))
     kr = np.lexsort((r["sec_T"], r["sec_species"], r["sec_stage"], r["sec_event"]))
+    r["sec_u"] = np.stack([r["sec_ux"], r["sec_uy"], r["sec_uz"]], 1)
     for f in ("sec_event", "sec_species", "sec_stage", "sec_T", "sec_u"):
         assert np.array_equal(direct[f][kd], r[f][kr]), f
+    ring.close()
+    ctx.close()
+
+
+def test_ring_parallel_drain_equals_direct():
+    """Large ring and batch: runs of ready records long enough for the
+    drain's parallel host copy, into reused host arrays (twice)."""
+    import torch
+
+    import paper_1309_7963_amd as inc
+
+    n = 300000
+    tidx, T0 = _mixture(n, IMPLANT, [0.5, 0.5], 70, 250, seed=31)
+    ctx = inc.Context(IMPLANT)
+    direct = run_gpu(IMPLANT, T0, seed=6, tidx=tidx, ctx=ctx, mode="staged")
+    ring = inc.Ring(ctx, slots=1 << 20)
+    buf = inc.Ring.host_buffers(ctx.default_capacity(n))
+    T0_d = torch.as_tensor(T0, device="cuda")
+    ti_d = torch.as_tensor(tidx, device="cuda")
+    kd = np.lexsort((direct["sec_T"], direct["sec_species"], direct["sec_stage"], direct["sec_event"]))
+    for rep in range(2):
+        r = ring.simulate(T0_d, seed=6, target_idx=ti_d, out=buf)
+        assert r["rc"] == 0 and r["stats"]["producer_gave_up"] == 0
+        assert r["res"].tobytes() == direct["res"].tobytes()
+        assert r["n_sec_total"] == direct["n_sec_total"] > 1 << 20
+        kr = np.lexsort((r["sec_T"], r["sec_species"], r["sec_stage"], r["sec_event"]))
+        r["sec_u"] = np.stack([r["sec_ux"], r["sec_uy"], r["sec_uz"]], 1)
+        for f in ("sec_event", "sec_species", "sec_stage", "sec_T", "sec_u"):
+            assert np.array_equal(direct[f][kd], r[f][kr]), (rep, f)
     ring.close()
     ctx.close()
