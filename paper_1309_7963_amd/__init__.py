@@ -145,8 +145,13 @@ class Context:
         return out
 
     def default_capacity(self, n: int) -> int:
-        # at most A + 1 secondaries per event; the mean is far lower
-        return int(n * min(self.max_A + 1, 12)) + 4096
+        """Secondary records to allocate for n events: above the mean
+        multiplicity of every real target up to 250 MeV (about 4.6 for 16O,
+        5.8 for 40Ca, 15 for A = 250), at most A + 1 per event.  A call that
+        needs more reports the required total (counters[0]); allocate that and
+        run again."""
+        per_event = min(self.max_A + 1, 6 + self.max_A // 10)
+        return int(n * per_event) + 4096
 
     def simulate(self, T0, seed: int, target_idx=None, first_event_id: int = 0, mode: str = "staged",
                  out: Optional[DeviceOutput] = None, capacity: Optional[int] = None, stream=None) -> DeviceOutput:

@@ -7,7 +7,8 @@ import numpy as np
 import ledger
 
 
-def run_gpu(targets, T0, seed, tidx=None, mode="persistent", first_id=0, capacity=None, ctx=None, **opts):
+def run_gpu(targets, T0, seed, tidx=None, mode="persistent", first_id=0, capacity=None, ctx=None,
+            allow_overflow=False, **opts):
     import torch
     import paper_1309_7963_amd as inc
 
@@ -18,6 +19,8 @@ def run_gpu(targets, T0, seed, tidx=None, mode="persistent", first_id=0, capacit
     ti_d = None if tidx is None else torch.as_tensor(np.asarray(tidx, dtype=np.uint8), device="cuda")
     out = ctx.simulate(T0_d, seed=seed, target_idx=ti_d, first_event_id=first_id, mode=mode, capacity=capacity)
     torch.cuda.synchronize()
+    if out.n_sec() > out.capacity and not allow_overflow:
+        raise RuntimeError("secondary buffer too small: %d records for capacity %d" % (out.n_sec(), out.capacity))
     host = out.to_numpy()
     if own:
         ctx.close()
