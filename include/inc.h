@@ -197,7 +197,8 @@ typedef struct {            /* one request; all pointers are host memory     */
   const float* T0;          /* n energies in [20, 250] MeV (else flagged)    */
   uint64_t seed;
   uint64_t first_event_id;
-  size_t sec_capacity;      /* 0 = 12 n + 4096                               */
+  size_t sec_capacity;      /* 0 = n min(A, 6 + (A - 1) / 10) + 4096, A the  */
+                            /* context's largest target A + 1               */
 } inc_request;
 
 typedef struct {            /* host buffers receiving a request's results   */

@@ -247,7 +247,7 @@ def simulate_host(A: int, Z: int, energies: np.ndarray, seed: int, capacity: Opt
     L = _lib.load()
     e = np.ascontiguousarray(energies, dtype=np.float32)
     n = e.shape[0]
-    cap = n * min(A + 1, 12) + 4096 if capacity is None else int(capacity)
+    cap = n * min(A + 1, 6 + A // 10) + 4096 if capacity is None else int(capacity)
     res = np.zeros(n, dtype=RESIDUAL_DTYPE)
     ev = np.zeros(max(cap, 1), dtype=np.uint32)
     sp = np.zeros(max(cap, 1), dtype=np.uint8)

@@ -82,6 +82,15 @@ class Pool {
   std::map<size_t, size_t> free_;
 };
 
+// Secondary records reserved for a request that names no capacity: above the
+// mean multiplicity of every real target up to 250 MeV (about 4.6 per event
+// for 16O, 5.8 for 40Ca, 15 for A = 250), at most A + 1 per event.
+size_t default_cap(const inc_ctx* ctx, size_t n) {
+  const size_t a = (size_t)ctx->amax;  // largest target A + 1
+  const size_t per_event = std::min(a, 6 + (a - 1) / 10);
+  return n * per_event + 4096;
+}
+
 // Device bytes a request needs inside a launch (inputs, its share of the
 // staged hand-over buffer, residuals, secondaries, counters, segment entry).
 size_t request_bytes(size_t n, size_t cap) {
@@ -397,7 +406,7 @@ int inc_server_destroy(inc_server* s) {
 
 int inc_server_submit(inc_server* s, const inc_request* q, uint64_t* ticket) {
   if (!s || !q || !ticket || !q->T0 || q->n < 1 || q->n >= (1ull << 31)) return INC_ERR_ARG;
-  const size_t cap = q->sec_capacity ? q->sec_capacity : q->n * 12 + 4096;
+  const size_t cap = q->sec_capacity ? q->sec_capacity : default_cap(s->ctx, q->n);
   const size_t bytes = request_bytes(q->n, cap);
   // a launch of this request alone must fit the pool
   if (bytes + 4 * kAlign > s->budget) return INC_ERR_ARG;
@@ -493,7 +502,7 @@ int inc_server_replay(inc_server* s, int n_req, const double* arrival_s, const i
   if (!s || n_req < 1 || !arrival_s || !reqs || !latency_s) return INC_ERR_ARG;
   for (int i = 0; i < n_req; ++i) {
     if (i && arrival_s[i] < arrival_s[i - 1]) return INC_ERR_ARG;
-    const size_t cap = reqs[i].sec_capacity ? reqs[i].sec_capacity : reqs[i].n * 12 + 4096;
+    const size_t cap = reqs[i].sec_capacity ? reqs[i].sec_capacity : default_cap(s->ctx, reqs[i].n);
     if (request_bytes(reqs[i].n, cap) + 4 * kAlign > s->budget) return INC_ERR_ARG;
   }
   std::vector<uint64_t> ticket(n_req, 0);
