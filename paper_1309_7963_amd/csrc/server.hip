@@ -100,7 +100,7 @@ size_t request_bytes(size_t n, size_t cap) {
 }
 
 enum RState { kQueued = 0, kLaunched = 1, kReady = 2 };
-enum LPhase { kRunning = 0, kCopying = 1, kDone = 2 };
+enum LPhase { kRunning = 0, kDone = 1 };
 
 // Offsets of one request's buffers inside its launch region.
 struct ROffsets {
@@ -130,7 +130,7 @@ struct Launch {
   std::vector<uint64_t> tickets;
   size_t seg_off, queue_off;
   int phase;
-  hipEvent_t ev_kernel, ev_copy;
+  hipEvent_t ev_kernel;  // after the cascade, evaporation and export kernels
   int pending_fetch;
 };
 
@@ -139,7 +139,8 @@ struct Launch {
 struct inc_server {
   inc_ctx* ctx;
   char* d_pool;
-  char* h_pool;
+  char* h_pool;       // pinned host mirror of d_pool (mapped)
+  char* h_pool_dev;   // device address of h_pool
   size_t budget;
   size_t charged;     // bytes promised to admitted, not yet fetched requests
   Pool pool;
@@ -154,6 +155,40 @@ struct inc_server {
 };
 
 namespace {
+
+// Copy every request's results of a launch into the mapped host mirror of the
+// pool (same layout, `delta` bytes away): counters, residuals and the
+// secondaries the request produced (at most its capacity), so that one event
+// after the kernels says the results are on the host.  Grid: (segments, parts).
+__global__ void k_export(const Segment* segs, long long delta) {
+  const Segment& S = segs[blockIdx.x];
+  const unsigned long long produced = S.counters[0];
+  const size_t k = (size_t)(produced < S.cap ? produced : S.cap);
+  const size_t tid = (size_t)blockIdx.y * blockDim.x + threadIdx.x;
+  const size_t stride = (size_t)gridDim.y * blockDim.x;
+  if (tid < 4) ((unsigned long long*)((char*)S.counters + delta))[tid] = S.counters[tid];
+  static_assert(sizeof(inc_residual) % sizeof(uint4) == 0, "residuals move as 16-byte words");
+  const uint4* rs = (const uint4*)S.res;
+  uint4* rd = (uint4*)((char*)S.res + delta);
+  const size_t words = sizeof(inc_residual) / sizeof(uint4) * (size_t)S.n;
+  for (size_t i = tid; i < words; i += stride) rd[i] = rs[i];
+  float* T = (float*)((char*)S.T + delta);
+  float* ux = (float*)((char*)S.ux + delta);
+  float* uy = (float*)((char*)S.uy + delta);
+  float* uz = (float*)((char*)S.uz + delta);
+  uint32_t* ev = (uint32_t*)((char*)S.ev + delta);
+  uint8_t* sp = (uint8_t*)((char*)S.species + delta);
+  uint8_t* st = (uint8_t*)((char*)S.stage + delta);
+  for (size_t i = tid; i < k; i += stride) {
+    T[i] = S.T[i];
+    ux[i] = S.ux[i];
+    uy[i] = S.uy[i];
+    uz[i] = S.uz[i];
+    ev[i] = S.ev[i];
+    sp[i] = S.species[i];
+    st[i] = S.stage[i];
+  }
+}
 
 void complete_launch(inc_server* s, Launch& L, int rc) {
   const double t = now_s();
@@ -179,31 +214,14 @@ void advance_launch(inc_server* s, Launch& L) {
       complete_launch(s, L, inc_map_hip_error(q));
       return;
     }
-    hipStream_t st = s->streams[L.slot];
-    hipError_t e = hipSuccess;
+    // the export kernel has put counters, residuals and secondaries in the mirror
     for (uint64_t tk : L.tickets) {
       Request& r = s->reqs[tk];
       const unsigned long long* cnt = (const unsigned long long*)(s->h_pool + L.off + r.o.cnt);
       r.n_sec = cnt[0];
       if (r.n_sec > r.cap) r.rc = INC_ERR_CAPACITY;
-      const size_t k = (size_t)std::min<unsigned long long>(r.n_sec, r.cap);
-      const size_t offs[7] = {r.o.T, r.o.ux, r.o.uy, r.o.uz, r.o.ev, r.o.sp, r.o.st};
-      const size_t width[7] = {4, 4, 4, 4, 4, 1, 1};
-      for (int f = 0; f < 7 && e == hipSuccess && k; ++f)
-        e = hipMemcpyAsync(s->h_pool + L.off + offs[f], s->d_pool + L.off + offs[f], width[f] * k,
-                           hipMemcpyDeviceToHost, st);
     }
-    if (e == hipSuccess) e = hipEventRecord(L.ev_copy, st);
-    if (e != hipSuccess) {
-      complete_launch(s, L, inc_map_hip_error(e));
-      return;
-    }
-    L.phase = kCopying;
-  }
-  if (L.phase == kCopying) {
-    const hipError_t q = hipEventQuery(L.ev_copy);
-    if (q == hipErrorNotReady) return;
-    complete_launch(s, L, q == hipSuccess ? INC_OK : inc_map_hip_error(q));
+    complete_launch(s, L, INC_OK);
   }
 }
 
@@ -296,7 +314,6 @@ int start_launch(inc_server* s) {
   hipStream_t st = s->streams[slot];
   const size_t in_bytes = L.queue_off;  // T0, tidx and segment table are contiguous at the front
   hipError_t e = hipEventCreateWithFlags(&L.ev_kernel, hipEventDisableTiming);
-  if (e == hipSuccess) e = hipEventCreateWithFlags(&L.ev_copy, hipEventDisableTiming);
   if (e == hipSuccess) e = hipMemcpyAsync(d, h, in_bytes, hipMemcpyHostToDevice, st);
   int rc = inc_map_hip_error(e);
   if (rc == INC_OK) {
@@ -307,11 +324,11 @@ int start_launch(inc_server* s) {
                              (unsigned long long*)(d + L.queue_off), st, INC_MODE_STAGED, blocks, nullptr,
                              (MidState*)(d + mid_off));
   }
-  for (size_t k = 0; k < take.size() && rc == INC_OK; ++k) {
-    const Request& r = s->reqs[take[k]];
-    e = hipMemcpyAsync(h + r.o.cnt, d + r.o.cnt, 4 * sizeof(unsigned long long), hipMemcpyDeviceToHost, st);
-    if (e == hipSuccess) e = hipMemcpyAsync(h + r.o.res, d + r.o.res, sizeof(inc_residual) * r.n, hipMemcpyDeviceToHost, st);
-    rc = inc_map_hip_error(e);
+  if (rc == INC_OK) {
+    // results straight into the mapped mirror, exactly what each request produced
+    hipLaunchKernelGGL(k_export, dim3((unsigned)segs.size(), 16), dim3(256), 0, st, (const Segment*)(d + L.seg_off),
+                       (long long)(s->h_pool_dev - s->d_pool));
+    rc = inc_map_hip_error(hipGetLastError());
   }
   if (rc == INC_OK) rc = inc_map_hip_error(hipEventRecord(L.ev_kernel, st));
   s->slot_busy[slot] = 1;
@@ -343,7 +360,6 @@ void release_request(inc_server* s, uint64_t ticket) {
     if (lt != s->launches.end() && --lt->second.pending_fetch == 0) {
       Launch& L = lt->second;
       (void)hipEventDestroy(L.ev_kernel);
-      (void)hipEventDestroy(L.ev_copy);
       s->pool.release(L.off, L.bytes);
       s->launches.erase(lt);
     }
@@ -368,11 +384,13 @@ int inc_server_create(inc_ctx* ctx, size_t hbm_budget, int max_slots, inc_server
   s->charged = 0;
   s->d_pool = nullptr;
   s->h_pool = nullptr;
+  s->h_pool_dev = nullptr;
   s->next_ticket = 1;
   s->next_launch = 1;
   memset(&s->st, 0, sizeof(s->st));
   hipError_t e = hipMalloc(&s->d_pool, hbm_budget);
-  if (e == hipSuccess) e = hipHostMalloc(&s->h_pool, hbm_budget, hipHostMallocDefault);
+  if (e == hipSuccess) e = hipHostMalloc(&s->h_pool, hbm_budget, hipHostMallocMapped);
+  if (e == hipSuccess) e = hipHostGetDevicePointer((void**)&s->h_pool_dev, s->h_pool, 0);
   for (int i = 0; i < max_slots && e == hipSuccess; ++i) {
     hipStream_t st;
     e = hipStreamCreateWithFlags(&st, hipStreamNonBlocking);
@@ -395,7 +413,6 @@ int inc_server_destroy(inc_server* s) {
   for (hipStream_t st : s->streams) (void)hipStreamSynchronize(st);
   for (auto& kv : s->launches) {
     (void)hipEventDestroy(kv.second.ev_kernel);
-    (void)hipEventDestroy(kv.second.ev_copy);
   }
   for (hipStream_t st : s->streams) (void)hipStreamDestroy(st);
   if (s->d_pool) (void)hipFree(s->d_pool);
