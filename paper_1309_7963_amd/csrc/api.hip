@@ -45,7 +45,7 @@ void release(inc_ctx* c) {
 }  // namespace
 
 int inc_launch_segments(inc_ctx* ctx, size_t n, const uint8_t* tidx, const float* T0, const Segment* d_segs,
-                        int n_seg, unsigned long long* queue, hipStream_t s, int mode, int max_blocks,
+                        int n_seg, uint64_t seed, unsigned long long* queue, hipStream_t s, int mode, int max_blocks,
                         const RingDev* ring, MidState* mid) {
   if (!mid && (mode == INC_MODE_PLAIN || mode == INC_MODE_STAGED) && ctx->mid_cap < n) {
     if (ctx->d_mid) (void)hipFree(ctx->d_mid);
@@ -84,6 +84,7 @@ int inc_launch_segments(inc_ctx* ctx, size_t n, const uint8_t* tidx, const float
   L.T0 = T0;
   L.segs = d_segs;
   L.n_seg = n_seg;
+  L.seed = seed;
   L.queue = queue;
   L.mid = mid ? mid : ctx->d_mid;
   if (ring) L.ring = *ring;
@@ -101,7 +102,6 @@ int inc_launch_batch(inc_ctx* ctx, const inc_batch* b, const inc_output* out, hi
   Segment seg;
   seg.start = 0;
   seg.n = (uint32_t)b->n;
-  seg.seed = b->seed;
   seg.first_id = b->first_event_id;
   seg.res = out->res;
   seg.ev = out->sec_event;
@@ -116,7 +116,8 @@ int inc_launch_batch(inc_ctx* ctx, const inc_batch* b, const inc_output* out, hi
   Segment* slot = ctx->d_segs + (ctx->seg_next++ % kSegSlots);
   const int rc = map_err(inc_upload_segment(seg, slot, s));
   if (rc) return rc;
-  return inc_launch_segments(ctx, b->n, b->target_idx, b->T0, slot, 1, out->counters + 2, s, mode, max_blocks);
+  return inc_launch_segments(ctx, b->n, b->target_idx, b->T0, slot, 1, b->seed, out->counters + 2, s, mode,
+                             max_blocks);
 }
 
 int inc_map_hip_error(hipError_t e) { return map_err(e); }

@@ -30,14 +30,16 @@ struct inc_ctx {
 constexpr int kSegSlots = 64;  // inc_simulate_dev calls that may be in flight per context
 
 // Launch n events described by n_seg device segments (sorted by start, each
-// with its own key, ids and outputs); queue: two device work-queue counters.
+// with its own ids and outputs) that share the random-stream key `seed`;
+// queue: two device work-queue counters.
 // ring: streaming output of the secondaries (NULL: the segments' arrays).
 // mid: plain/staged hand-over buffer of n records (NULL: the context's own,
 // grown on demand; launches that overlap on different streams must each
 // bring their own).
 __attribute__((visibility("hidden"))) int inc_launch_segments(inc_ctx* ctx, size_t n, const uint8_t* tidx,
                                                               const float* T0, const incdev::Segment* d_segs,
-                                                              int n_seg, unsigned long long* queue, hipStream_t s,
+                                                              int n_seg, uint64_t seed, unsigned long long* queue,
+                                                              hipStream_t s,
                                                               int mode, int max_blocks,
                                                               const incdev::RingDev* ring = nullptr,
                                                               incdev::MidState* mid = nullptr);

@@ -88,7 +88,15 @@ struct BindTab {
 };
 
 // --------------------------------------------------------------- Philox
-// Philox4x32-10 (Salmon et al., SC'11).
+// a ^ b ^ k in one instruction: v_bitop3_b32 with truth table 0x96 (odd
+// parity of the three inputs).  k is wave-uniform (a round key).
+__device__ __forceinline__ uint32_t xor3_uniform(uint32_t a, uint32_t b, uint32_t k) {
+  uint32_t r;
+  asm("v_bitop3_b32 %0, %1, %2, %3 bitop3:0x96" : "=v"(r) : "v"(a), "v"(b), "s"(k));
+  return r;
+}
+
+// Philox4x32-10 (Salmon et al., SC'11).  The key must be wave-uniform.
 __device__ __forceinline__ void philox4x32_10(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3,
                                               uint32_t k0, uint32_t k1, uint32_t out[4]) {
 #pragma unroll
@@ -102,8 +110,8 @@ __device__ __forceinline__ void philox4x32_10(uint32_t c0, uint32_t c1, uint32_t
     const uint64_t p1 = (uint64_t)0xCD9E8D57u * (uint64_t)c2;
     const uint32_t hi0 = (uint32_t)(p0 >> 32), lo0 = (uint32_t)p0;
     const uint32_t hi1 = (uint32_t)(p1 >> 32), lo1 = (uint32_t)p1;
-    const uint32_t n0 = hi1 ^ c1 ^ k0;
-    const uint32_t n2 = hi0 ^ c3 ^ k1;
+    const uint32_t n0 = xor3_uniform(hi1, c1, k0);
+    const uint32_t n2 = xor3_uniform(hi0, c3, k1);
     c0 = n0;
     c1 = lo1;
     c2 = n2;
@@ -124,6 +132,10 @@ __device__ __forceinline__ void philox4x32_10(uint32_t c0, uint32_t c1, uint32_t
 // with all lanes of that step together instead of at scattered draw sites;
 // next() generates only the rare word the two blocks could not hold.  The
 // order of the words is the stream order whatever the buffering.
+//
+// The key is the launch's seed, set once before any event starts and never
+// changed, so it stays wave-uniform: the key schedule runs on the scalar unit
+// and only the counter arithmetic takes vector instructions.
 struct Rng {
   uint32_t k0, k1, id0, id1;
   uint32_t blk;    // next block to generate
@@ -131,9 +143,11 @@ struct Rng {
   uint32_t pos;    // next word of a (4 = a used up)
   uint32_t nb;     // words valid in b (0 or 4)
 
-  __device__ __forceinline__ void init(uint64_t seed, uint64_t id) {
+  __device__ __forceinline__ void set_key(uint64_t seed) {
     k0 = (uint32_t)seed;
     k1 = (uint32_t)(seed >> 32);
+  }
+  __device__ __forceinline__ void init(uint64_t id) {
     id0 = (uint32_t)id;
     id1 = (uint32_t)(id >> 32);
     blk = 0;
@@ -155,14 +169,18 @@ struct Rng {
   }
   // Prefetch so that at least k words are buffered when the two blocks can
   // hold them (always for k <= 5); next() generates any word still missing.
+  // One generation site per round, whichever block it fills, so lanes that
+  // refill a and lanes that refill b share one pass of the Philox rounds.
   __device__ __forceinline__ void ensure(uint32_t k) {
     if (pos == 4 && nb == 4) shift();
-    if (avail() < k) {
+    if (avail() < k && (pos == 4 || nb == 0)) {
+      uint32_t w[4];
+      gen(w);
       if (pos == 4) {
-        gen(a);
+        a[0] = w[0]; a[1] = w[1]; a[2] = w[2]; a[3] = w[3];
         pos = 0;
-      } else if (nb == 0) {
-        gen(b);
+      } else {
+        b[0] = w[0]; b[1] = w[1]; b[2] = w[2]; b[3] = w[3];
         nb = 4;
       }
     }
@@ -312,7 +330,7 @@ __device__ __forceinline__ float log_width_integral(float Y, float lnAd) {
 #pragma unroll
     for (int n = 4; n < 22; ++n) {
       sum += (float)((n - 1) * (n - 3)) * term;
-      term *= Y / (float)(n + 1);
+      term *= Y * (1.0f / (float)(n + 1));  // unrolled: a constant reciprocal, no division
     }
     return logf(sum) - (2.0f * lnAd - 2.7725887f);
   }
@@ -335,8 +353,9 @@ __device__ __forceinline__ float spectrum_K(float Y, float s) {
     float c = 1.0f, sm = s * s, sum = 0.0f;
 #pragma unroll
     for (int m = 0; m < 12; ++m) {
-      sum += c * sm * (2.0f / (float)(m + 2) - 3.0f * s / (float)(m + 3) + s * s / (float)(m + 4));
-      c *= -Y / (float)(m + 1);
+      // unrolled: the coefficients are constant reciprocals, no division
+      sum += c * sm * (2.0f / (float)(m + 2) - s * (3.0f / (float)(m + 3)) + s * s * (1.0f / (float)(m + 4)));
+      c *= -Y * (1.0f / (float)(m + 1));
       sm *= s;
     }
     return sum;
@@ -385,14 +404,15 @@ __device__ __forceinline__ float spectrum_sample_s(float Y, float u) {
 constexpr int kWriterCap = 128;  // records per wave buffer
 constexpr int kRecWords = 6;     // event, species | stage << 8 | segment << 16, T, ux, uy, uz
 
-// One segment of a launch: a request with its own random-stream key, event
-// ids and output buffers.  Event i of the launch with start <= i < start + n
-// belongs to the segment, has id first_id + (i - start) and writes its
-// residual to res[i - start] and its secondaries to the segment's arrays
-// (records hold i - start).  counters: [0] secondaries produced, [1] flagged.
+// One segment of a launch: a request with its own event ids and output
+// buffers (all segments of a launch share the launch's random-stream key).
+// Event i of the launch with start <= i < start + n belongs to the segment,
+// has id first_id + (i - start) and writes its residual to res[i - start] and
+// its secondaries to the segment's arrays (records hold i - start).
+// counters: [0] secondaries produced, [1] flagged.
 struct Segment {
   uint32_t start, n;
-  uint64_t seed, first_id;
+  uint64_t first_id;
   inc_residual* res;
   uint32_t* ev;
   uint8_t* species;

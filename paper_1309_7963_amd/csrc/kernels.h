@@ -41,6 +41,7 @@ struct LaunchDesc {
   const float* T0;
   const Segment* segs;   // device
   int n_seg;
+  uint64_t seed;         // random-stream key shared by all segments
   unsigned long long* queue;  // two work-queue heads: [0] cascade, [1] evaporation
   MidState* mid;
   RingDev ring;          // rec == NULL: records go to the segments' arrays

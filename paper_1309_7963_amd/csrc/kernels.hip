@@ -30,6 +30,7 @@ struct KernelArgs {
   const float* T0;
   const Segment* segs;       // requests of the launch, sorted by start
   int n_seg;
+  uint64_t seed;             // random-stream key of every event of the launch
   unsigned long long* queue; // work-queue heads: [0] events, [1] staged evaporation
   MidState* mid;             // plain kernels: cascade -> evaporation hand-over
   RingDev ring;              // streaming output (rec == NULL: segment arrays)
@@ -97,7 +98,7 @@ __device__ __forceinline__ EventRef event_ref(const KernelArgs& a, size_t i) {
   return e;
 }
 __device__ __forceinline__ void init_stream(Rng& rng, const KernelArgs& a, EventRef e) {
-  rng.init(a.segs[e.seg].seed, a.segs[e.seg].first_id + (a.opt.same_stream ? 0 : e.local));
+  rng.init(a.segs[e.seg].first_id + (a.opt.same_stream ? 0 : e.local));
 }
 __device__ __forceinline__ uint32_t kind_of(uint32_t k, EventRef e) { return k | ((uint32_t)e.seg << 16); }
 
@@ -120,6 +121,7 @@ __global__ void __launch_bounds__(256) k_cascade_plain(KernelArgs a) {
   int tgt = 0;
   EventRef er = {0, 0};
   Rng rng;
+  rng.set_key(a.seed);
   if (live) {
     er = event_ref(a, i);
     T0 = a.T0[i];
@@ -184,6 +186,7 @@ __global__ void __launch_bounds__(256) k_evap_plain(KernelArgs a) {
   MidState m = {};
   Nucleus nu = {0, 0, 0.0f, {0.0f, 0.0f, 0.0f}};
   Rng rng;
+  rng.set_key(a.seed);
   EventRef er = {0, 0};
   int nsec = 0, flags = 0;
   if (live) {
@@ -261,6 +264,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) k
   uint32_t ev_idx = 0;
   float Ex_casc = 0.0f;
   Rng rng;
+  rng.set_key(a.seed);
   Cascade c;
   Nucleus nu = {0, 0, 0.0f, {0.0f, 0.0f, 0.0f}};
   StackEntry stk[kStackDepth];
@@ -406,6 +410,7 @@ __global__ void __launch_bounds__(256) k_evap_persistent(KernelArgs a) {
   bool exhausted = false, busy = false;
   EventRef er = {0, 0};
   Rng rng;
+  rng.set_key(a.seed);
   Nucleus nu = {0, 0, 0.0f, {0.0f, 0.0f, 0.0f}};
   int nsec = 0, flags = 0, ncoll = 0, nretry = 0;
   float Ex_casc = 0.0f;
@@ -544,6 +549,7 @@ hipError_t launch_events(const LaunchDesc& L, hipStream_t s) {
   a.T0 = L.T0;
   a.segs = L.segs;
   a.n_seg = L.n_seg;
+  a.seed = L.seed;
   a.queue = L.queue;
   a.mid = L.mid;
   a.ring = L.ring;

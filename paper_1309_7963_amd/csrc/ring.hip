@@ -180,7 +180,6 @@ int inc_ring_simulate(inc_ring* r, const inc_batch* b, inc_residual* d_res, cons
   memset(&seg, 0, sizeof(seg));
   seg.start = 0;
   seg.n = (uint32_t)b->n;
-  seg.seed = b->seed;
   seg.first_id = b->first_event_id;
   seg.res = d_res;
   seg.counters = r->d_dev + 4;
@@ -202,7 +201,8 @@ int inc_ring_simulate(inc_ring* r, const inc_batch* b, inc_residual* d_res, cons
   if (e != hipSuccess) return inc_map_hip_error(e);
   int rc = inc_map_hip_error(inc_upload_segment(seg, r->d_seg, st));
   if (rc == INC_OK)
-    rc = inc_launch_segments(r->ctx, b->n, b->target_idx, b->T0, r->d_seg, 1, r->d_dev + 1, st, mode, 0, &R);
+    rc = inc_launch_segments(r->ctx, b->n, b->target_idx, b->T0, r->d_seg, 1, b->seed, r->d_dev + 1, st, mode, 0,
+                             &R);
   if (rc == INC_OK) rc = inc_map_hip_error(hipEventRecord(done, st));
   if (rc != INC_OK) {
     (void)hipStreamSynchronize(st);

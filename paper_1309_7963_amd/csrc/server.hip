@@ -296,7 +296,6 @@ int start_launch(inc_server* s) {
     Segment& g = segs[k];
     g.start = (uint32_t)start;
     g.n = (uint32_t)r.n;
-    g.seed = r.seed;
     g.first_id = r.first_id;
     g.res = (inc_residual*)(d + r.o.res);
     g.ev = (uint32_t*)(d + r.o.ev);
@@ -320,7 +319,7 @@ int start_launch(inc_server* s) {
     // one lane per event at most: small launches take fewer blocks
     const int blocks = (int)((n + s->ctx->block - 1) / s->ctx->block);
     rc = inc_launch_segments(s->ctx, n, any_tidx ? (const uint8_t*)(d + tidx_off) : nullptr, (const float*)(d + T0_off),
-                             (const Segment*)(d + L.seg_off), (int)segs.size(),
+                             (const Segment*)(d + L.seg_off), (int)segs.size(), key,
                              (unsigned long long*)(d + L.queue_off), st, INC_MODE_STAGED, blocks, nullptr,
                              (MidState*)(d + mid_off));
   }
