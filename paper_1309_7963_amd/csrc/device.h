@@ -42,7 +42,8 @@ struct NucTab {
   float EFmin[2];    // smallest E_F per species (outermost shell)
   float pFmax[2];    // largest p_F per species (innermost shell)
   int A, Z;
-  float pad[7];
+  float EYmax[2];    // total energy of a nucleon at pFmax, sqrt(pFmax^2 + m^2)
+  float pad[5];
 };
 static_assert(sizeof(NucTab) % 16 == 0, "NucTab must stay 16-byte aligned");
 
@@ -241,14 +242,17 @@ __device__ __forceinline__ V3 rotate(V3 a, float c, float s, float u_phi) {
   return {s * cp, s * sp, a.z >= 0.0f ? c : -c};
 }
 
-// Boost a momentum q of mass m from a frame with gamma*beta = u, gamma = g.
-__device__ __forceinline__ void boost_out(V3 q, float m, V3 u, float g, V3& p, float& T) {
+// Boost a momentum q of mass m from a frame with gamma*beta = u, gamma = g;
+// ig1 = 1 / (g + 1) and uu1 = (u.u) / (g + 1) are shared by the products of
+// one decay.  T = (gamma - 1) m + gamma T* + u.q without forming total energies.
+__device__ __forceinline__ void boost_out(V3 q, float m, V3 u, float g, float ig1, float uu1, V3& p, float& T) {
   const float q2 = dot3(q, q);
   const float E = sqrtf(q2 + m * m);
   const float uq = dot3(u, q);
-  p = axpy(uq / (g + 1.0f) + E, u, q);
-  T = g * (q2 / (E + m)) + dot3(u, u) / (g + 1.0f) * m + uq;
+  p = axpy(uq * ig1 + E, u, q);
+  T = g * (q2 / (E + m)) + uu1 * m + uq;
 }
+__device__ __forceinline__ float inv_nucleon_mass(int sp) { return sp ? 1.0f / kMassP : 1.0f / kMassN; }
 
 // -------------------------------------------------------- cross-sections
 // Table coordinate of p_lab: nodes are equally spaced in log p between kPlo and
@@ -278,10 +282,8 @@ __device__ __forceinline__ void majorant(const NucTab& nt, const XsTab& xs, cons
   float sh[2];
 #pragma unroll
   for (int y = 0; y < 2; ++y) {
-    const float my = nucleon_mass(y);
     const float pF = nt.pFmax[y];
-    const float EFy = sqrtf(pF * pF + my * my);
-    const float pmin = fmaxf(0.0f, (p * EFy - Ex * pF) / my) * 1e-3f;
+    const float pmin = fmaxf(0.0f, (p * nt.EYmax[y] - Ex * pF) * inv_nucleon_mass(y)) * 1e-3f;
     float s;
     if (o.const_sigma_mb > 0.0f) {
       s = o.const_sigma_mb;

@@ -207,15 +207,12 @@ __device__ __forceinline__ int flight_core(Cascade& c, StackEntry* stk, const Nu
                  c.pos.x * c.dir.y - c.pos.y * c.dir.x};
   const float b2 = dot3(cx, cx);
   const float rin2 = nt.r2[s], rout2 = nt.r2[s + 1];
-  float t;
-  int dest;
-  if (s > 0 && xd < 0.0f && b2 < rin2) {
-    t = fmaxf(0.0f, -xd - sqrtf(rin2 - b2));
-    dest = s - 1;
-  } else {
-    t = fmaxf(0.0f, -xd + sqrtf(fmaxf(0.0f, rout2 - b2)));
-    dest = s + 1;
-  }
+  // next crossing: the inner sphere when the ray meets it, else the outer one
+  // (one square root whichever way the lanes of the wave go)
+  const bool inward = s > 0 && xd < 0.0f && b2 < rin2;
+  const float root = sqrtf(fmaxf(0.0f, (inward ? rin2 : rout2) - b2));
+  const float t = fmaxf(0.0f, -xd + (inward ? -root : root));
+  const int dest = inward ? s - 1 : s + 1;
   if (c.tau < lam * t) {
     c.pos = axpy(c.tau / lam, c.dir, c.pos);
     return kStTent;
@@ -223,7 +220,7 @@ __device__ __forceinline__ int flight_core(Cascade& c, StackEntry* stk, const Nu
   // ---- boundary crossing (Sec. 2.3 refraction / reflection)
   c.tau -= lam * t;
   c.pos = axpy(t, c.dir, c.pos);
-  const V3 n = scale(1.0f / sqrtf(dot3(c.pos, c.pos)), c.pos);
+  const V3 n = unit(c.pos);
   const float m = nucleon_mass(c.sp);
   const float T_from = c.eps + nt.EF[c.sp][s];
   if (dest == kShells) {
@@ -264,7 +261,7 @@ __device__ __forceinline__ int flight_step(Cascade& c, StackEntry* stk, Rng& rng
 
 // Invariants of the pair (x, y) used by TENT and KIN.
 struct Pair {
-  float mx, my, Tx, Tt, rs, pstar, plab;
+  float mx, my, Tx, Tt, rs, irs, pstar, plab;
   V3 px;
 };
 __device__ __forceinline__ Pair pair_of(const Cascade& c, const NucTab& nt, int y) {
@@ -279,8 +276,9 @@ __device__ __forceinline__ Pair pair_of(const Cascade& c, const NucTab& nt, int 
   const float Q = 2.0f * (q.Tx * q.Tt + q.Tx * q.my + q.Tt * q.mx - dot3(q.px, c.pt));
   const float ss = (q.mx + q.my) * (q.mx + q.my) + Q;
   q.rs = sqrtf(ss);
-  q.pstar = sqrtf(Q * (Q + 4.0f * q.mx * q.my) / (4.0f * ss));
-  q.plab = q.pstar * q.rs / q.my;
+  q.irs = 1.0f / q.rs;
+  q.pstar = 0.5f * sqrtf(Q * (Q + 4.0f * q.mx * q.my)) * q.irs;
+  q.plab = q.pstar * q.rs * inv_nucleon_mass(y);
   return q;
 }
 
@@ -333,9 +331,10 @@ __device__ __forceinline__ int kin_step(Cascade& c, StackEntry* stk, Rng& rng, c
   const float u_ph = rng.next();
   const float b = xs_lerp(xs.slope[like], k, f);
   const V3 P = {q.px.x + c.pt.x, q.px.y + c.pt.y, q.px.z + c.pt.z};
-  const V3 u = scale(1.0f / q.rs, P);
-  const float g = (q.Tx + q.Tt + q.mx + q.my) / q.rs;
-  const V3 qcm = axpy(dot3(u, q.px) / (g + 1.0f) - (q.Tx + q.mx), u, q.px);
+  const V3 u = scale(q.irs, P);
+  const float g = (q.Tx + q.Tt + q.mx + q.my) * q.irs;
+  const float ig1 = 1.0f / (g + 1.0f);
+  const V3 qcm = axpy(dot3(u, q.px) * ig1 - (q.Tx + q.mx), u, q.px);
   const V3 a = unit(qcm);
   const float kk = 2.0f * b * (q.pstar * 1e-3f) * (q.pstar * 1e-3f);
   float yy = (kk < 1e-6f) ? 2.0f * u_th : -log1pf(u_th * expm1f(-2.0f * kk)) / kk;
@@ -345,8 +344,9 @@ __device__ __forceinline__ int kin_step(Cascade& c, StackEntry* stk, Rng& rng, c
   const V3 nn = rotate(a, cth, sth, u_ph);
   V3 qx, qt;
   float Txn, Ttn;
-  boost_out(scale(q.pstar, nn), q.mx, u, g, qx, Txn);
-  boost_out(scale(-q.pstar, nn), q.my, u, g, qt, Ttn);
+  const float uu1 = dot3(u, u) * ig1;
+  boost_out(scale(q.pstar, nn), q.mx, u, g, ig1, uu1, qx, Txn);
+  boost_out(scale(-q.pstar, nn), q.my, u, g, ig1, uu1, qt, Ttn);
   if (like && rng.next() < 0.5f) {
     const V3 tq = qx;
     qx = qt;
@@ -500,10 +500,12 @@ __device__ __forceinline__ bool evap_step(Nucleus& nu, Rng& rng, const BindTab& 
   sincospif(2.0f * rng.next(), &sph, &cph);
   const V3 qv = {ps * st * cph, ps * st * sph, ps * ct};
   const V3 u = scale(1.0f / Mp, nu.P);
-  const float g = sqrtf(1.0f + dot3(u, u));
+  const float uu = dot3(u, u);
+  const float g = sqrtf(1.0f + uu);
+  const float ig1 = 1.0f / (g + 1.0f);
   V3 pf;
   float Tf;
-  boost_out(qv, mj, u, g, pf, Tf);
+  boost_out(qv, mj, u, g, ig1, uu * ig1, pf, Tf);
   em.on = true;
   em.kind = (uint32_t)j | (1u << 8);
   em.T = Tf;

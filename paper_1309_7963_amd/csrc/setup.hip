@@ -111,7 +111,7 @@ __global__ void k_nucleus_setup(const int* AZ, NucTab* out, int uniform_density,
         out[t].pF[sp][15] = 0.0f;
         out[t].EF[sp][15] = 0.0f;
       }
-      for (int k = 0; k < 7; ++k) out[t].pad[k] = 0.0f;
+      for (int k = 0; k < 5; ++k) out[t].pad[k] = 0.0f;
     }
   }
   __syncthreads();
@@ -126,6 +126,8 @@ __global__ void k_nucleus_setup(const int* AZ, NucTab* out, int uniform_density,
       }
       out[t].EFmin[sp] = efmin;
       out[t].pFmax[sp] = pfmax;
+      const double m = sp ? (double)kMassP : (double)kMassN;
+      out[t].EYmax[sp] = (float)sqrt((double)pfmax * (double)pfmax + m * m);
     }
   }
 }
