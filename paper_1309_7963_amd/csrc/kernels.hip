@@ -326,7 +326,15 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) k
     }
     // ---- state selection (wave-uniform)
     int run;
-    if (nK >= a.opt.kin_threshold) run = kStKin;
+    if (exhausted) {
+      // no events left to start: the state with the most lanes
+      run = kStFlight;
+      int best = nF;
+      if (nT > best) { run = kStTent; best = nT; }
+      if (nK > best) { run = kStKin; best = nK; }
+      if (nS > best) { run = kStStart; best = nS; }
+      if (nE > best) { run = kStEvap; best = nE; }
+    } else if (nK >= a.opt.kin_threshold) run = kStKin;
     else if (nT >= a.opt.tent_threshold) run = kStTent;
     else if (nS >= a.opt.start_threshold) run = kStStart;
     else if (nE >= a.opt.evap_threshold) run = kStEvap;
