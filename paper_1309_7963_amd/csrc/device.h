@@ -403,7 +403,8 @@ __device__ __forceinline__ float spectrum_sample_s(float Y, float u) {
 // at (fill + rank among emitting lanes); when the buffer could overflow, the
 // wave reserves space with one global atomic and all 64 lanes copy the
 // buffer out contiguously into the SoA arrays.
-constexpr int kWriterCap = 128;  // records per wave buffer
+constexpr int kWriterCap = 128;      // records per wave buffer (cascade kernels)
+constexpr int kWriterCapEvap = 256;  // records per wave buffer (evaporation kernels)
 constexpr int kRecWords = 6;     // event, species | stage << 8 | segment << 16, T, ux, uy, uz
 
 // One segment of a launch: a request with its own event ids and output
@@ -521,6 +522,33 @@ __device__ __forceinline__ void writer_flush(uint32_t* buf, int& fill, const Seg
     fill = 0;
     return;
   }
+  // Usual case: every record of the buffer belongs to one segment, which
+  // reserves all of them with one atomic.
+  const int seg_first = (int)(buf[1] >> 16);
+  bool mixed = false;
+  for (int i = lane_id(); i < fill; i += 64) mixed |= (int)(buf[i * kRecWords + 1] >> 16) != seg_first;
+  if (!__any(mixed)) {
+    unsigned long long base = 0;
+    if (lane_id() == 0) base = atomicAdd(&segs[seg_first].counters[0], (unsigned long long)fill);
+    const Segment& S = segs[seg_first];
+    base = __shfl(base, 0);
+    for (int i = lane_id(); i < fill; i += 64) {
+      const uint32_t* r = buf + i * kRecWords;
+      const unsigned long long k = base + (unsigned long long)i;
+      if (k < S.cap) {
+        S.ev[k] = r[0];
+        S.species[k] = (uint8_t)(r[1] & 0xFFu);
+        S.stage[k] = (uint8_t)((r[1] >> 8) & 0xFFu);
+        S.T[k] = __uint_as_float(r[2]);
+        S.ux[k] = __uint_as_float(r[3]);
+        S.uy[k] = __uint_as_float(r[4]);
+        S.uz[k] = __uint_as_float(r[5]);
+      }
+    }
+    __builtin_amdgcn_wave_barrier();
+    fill = 0;
+    return;
+  }
   for (int g = 0; g < fill; g += 64) {
     const int i = g + lane_id();
     const bool have = i < fill;
@@ -555,13 +583,15 @@ __device__ __forceinline__ void writer_flush(uint32_t* buf, int& fill, const Seg
 }
 
 // Must be called by all lanes of the wave.  ev: index of the event in its
-// segment; kind: species | stage << 8 | segment << 16.
+// segment; kind: species | stage << 8 | segment << 16.  kCap: records the
+// wave's buffer holds.
+template <int kCap = kWriterCap>
 __device__ __forceinline__ void writer_append(uint32_t* buf, int& fill, const Segment* segs, const RingDev& ring,
                                               bool emit, uint32_t ev, uint32_t kind, float T, V3 u) {
   const uint64_t m = __ballot(emit);
   if (m == 0) return;
   const int cnt = __popcll(m);
-  if (fill + cnt > kWriterCap) writer_flush(buf, fill, segs, ring);
+  if (fill + cnt > kCap) writer_flush(buf, fill, segs, ring);
   if (emit) {
     uint32_t* r = buf + (fill + (int)rank_in(m)) * kRecWords;
     r[0] = ev;

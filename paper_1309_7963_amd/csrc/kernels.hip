@@ -41,8 +41,9 @@ __device__ __forceinline__ bool energy_ok(float T0) { return T0 >= 20.0f && T0 <
 
 // LDS layout of the event kernels: [n_targets NucTab][XsTab][MassTab][writer
 // buffers of the block's waves][LIFO levels: per wave stack_lds x 2 x 64
-// float4].  The plain evaporation kernel stages only the MassTab (n_targets =
-// 0, no XsTab) and has no stack.
+// float4].  The evaporation kernels stage only the MassTab (n_targets = 0,
+// no XsTab: with_xs = false), have no stack and larger writer buffers
+// (kWriterCapEvap records per wave: nearly every lane emits every step).
 __device__ __forceinline__ size_t lds_mass_offset(int n_targets, bool with_xs) {
   return (size_t)n_targets * sizeof(NucTab) + (with_xs ? sizeof(XsTab) : 0);
 }
@@ -179,7 +180,7 @@ __global__ void __launch_bounds__(256) k_evap_plain(KernelArgs a) {
   extern __shared__ __align__(16) char lds[];
   stage_tables(lds, a, 0, false);
   const MassTab& smt = *(const MassTab*)lds;
-  uint32_t* wbuf = (uint32_t*)(lds + sizeof(MassTab)) + (threadIdx.x / 64) * (kWriterCap * kRecWords);
+  uint32_t* wbuf = (uint32_t*)(lds + sizeof(MassTab)) + (threadIdx.x / 64) * (kWriterCapEvap * kRecWords);
   int fill = 0;
   const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
   bool live = i < a.n;
@@ -224,7 +225,7 @@ __global__ void __launch_bounds__(256) k_evap_plain(KernelArgs a) {
         ++nsec;
       }
     }
-    writer_append(wbuf, fill, a.segs, a.ring, em.on, er.local, kind_of(em.kind, er), em.T, em.u);
+    writer_append<kWriterCapEvap>(wbuf, fill, a.segs, a.ring, em.on, er.local, kind_of(em.kind, er), em.T, em.u);
   }
   writer_flush(wbuf, fill, a.segs, a.ring);
 }
@@ -411,7 +412,7 @@ __global__ void __launch_bounds__(256) k_evap_persistent(KernelArgs a) {
   extern __shared__ __align__(16) char lds[];
   stage_tables(lds, a, 0, false);
   const MassTab& smt = *(const MassTab*)lds;
-  uint32_t* wbuf = (uint32_t*)(lds + sizeof(MassTab)) + (threadIdx.x / 64) * (kWriterCap * kRecWords);
+  uint32_t* wbuf = (uint32_t*)(lds + sizeof(MassTab)) + (threadIdx.x / 64) * (kWriterCapEvap * kRecWords);
   int fill = 0;
 
   unsigned long long chunk_next = 0, chunk_end = 0;
@@ -475,7 +476,7 @@ __global__ void __launch_bounds__(256) k_evap_persistent(KernelArgs a) {
         ++nsec;
       }
     }
-    writer_append(wbuf, fill, a.segs, a.ring, em.on, er.local, kind_of(em.kind, er), em.T, em.u);
+    writer_append<kWriterCapEvap>(wbuf, fill, a.segs, a.ring, em.on, er.local, kind_of(em.kind, er), em.T, em.u);
   }
   writer_flush(wbuf, fill, a.segs, a.ring);
 }
@@ -497,7 +498,7 @@ __global__ void k_zero_counters(const Segment* segs, int n_seg, unsigned long lo
 // ================================================================ launchers
 size_t lds_bytes(int n_targets, int block, bool with_xs, int stack_levels) {
   return (size_t)n_targets * sizeof(NucTab) + (with_xs ? sizeof(XsTab) : 0) + sizeof(MassTab) +
-         (size_t)(block / 64) * kWriterCap * kRecWords * sizeof(uint32_t) +
+         (size_t)(block / 64) * (with_xs ? kWriterCap : kWriterCapEvap) * kRecWords * sizeof(uint32_t) +
          (size_t)stack_levels * 2 * block * sizeof(float4);
 }
 
