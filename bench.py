@@ -388,17 +388,15 @@ def main(argv=None):
     if not args.no_extra:
         from paper_1309_7963_amd import autotune
 
-        rate = lambda e: e["n"] / (float(np.mean(e["launch_ms"])) / 1000.0)
+        rate = lambda e: e["n"] / (float(np.median(e["launch_ms"])) / 1000.0)
         for key in ("o16_200", "ca40_200", "tissue_mix", "implant_mix"):
-            e = _time_gpu(wl[key], args.mode, 3, 1)
+            e = _time_gpu(wl[key], args.mode, 5, 1)
             extra[key] = dict(label=wl[key]["label"], events=e["n"], events_per_s=rate(e))
             if key in ("tissue_mix", "implant_mix"):
-                # autotuned launch policy (sweep on the first half of the batch)
+                # autotuned launch policy (swept on the same batch)
                 w = wl[key]
-                half = len(w["T0"]) // 2
-                tuned = autotune.tune(w["targets"], w["T0"][:half], None if w["tidx"] is None else w["tidx"][:half],
-                                      use_cache=False)
-                e = _time_gpu(w, args.mode, 3, 1, **tuned["options"])
+                tuned = autotune.tune(w["targets"], w["T0"], w["tidx"], use_cache=False)
+                e = _time_gpu(w, args.mode, 5, 1, **tuned["options"])
                 p = _time_gpu(w, "plain", 3, 1)
                 extra[key].update(tuned_options=tuned["options"], tuned_events_per_s=rate(e),
                                   plain_events_per_s=rate(p), autotune_sweep_s=tuned["sweep_s"])

@@ -6,7 +6,8 @@
 * the smallest and largest admissible targets (4He, A = 250) at both ends of
   the energy range, including the degenerate 250/1 (no binding: the segment
   guard ends most events, as often as in the oracle);
-* a context with the maximum number of targets (16) and a mixture over all."""
+* a context with the maximum number of targets (16) and a mixture over all;
+* every launch policy the autotuner tries gives the same events."""
 import numpy as np
 import pytest
 
@@ -81,3 +82,26 @@ def test_sixteen_targets_in_one_context():
         for i in sel[:5]:
             single = run_gpu([targets[t]], T0[i:i + 1], seed=4, first_id=int(i))
             assert single["res"].tobytes() == h["res"][i:i + 1].tobytes()
+
+
+def test_autotuned_policy_changes_speed_not_results():
+    """The autotuner picks among launch policies (block size, waves per CU,
+    scheduler thresholds); every candidate must produce the same events."""
+    from paper_1309_7963_amd import autotune
+
+    targets = [(12, 6), (16, 8)]
+    rng = np.random.default_rng(11)
+    n = 20000
+    tidx = rng.integers(0, 2, n).astype(np.uint8)
+    T0 = rng.uniform(20, 250, n).astype(np.float32)
+    grid = {"block_size": (128, 256), "waves_per_cu": (8, 12), "thresholds": ((24, 24, 8), (16, 8, 8))}
+    best = autotune.tune(targets, T0, tidx, grid=grid, repeats=2, use_cache=False)
+    opts = best["options"]
+    assert opts["block_size"] in grid["block_size"] and opts["waves_per_cu"] in grid["waves_per_cu"]
+    assert (opts["kin_threshold"], opts["tent_threshold"], opts["start_threshold"]) in grid["thresholds"]
+    assert len(best["table"]) == 8 and best["ms"] > 0
+    ref = run_gpu(targets, T0, seed=4, tidx=tidx, mode="staged")
+    for cand in best["table"]:
+        h = run_gpu(targets, T0, seed=4, tidx=tidx, mode="staged", **cand["options"])
+        assert h["res"].tobytes() == ref["res"].tobytes(), cand["options"]
+        assert h["n_sec_total"] == ref["n_sec_total"], cand["options"]
