@@ -217,6 +217,15 @@ struct Rng {
 
 // ------------------------------------------------------------ small math
 __device__ __forceinline__ float nucleon_mass(int sp) { return sp ? kMassP : kMassN; }
+
+// log(1 + x) for x > -1 from logf (Goldberg, "What every computer scientist
+// should know about floating-point arithmetic", 1991, Theorem 4): with
+// u = fl(1 + x), log(1 + x) = log(u) x / (u - 1), and x itself when u == 1.
+// A few ulp, at the cost of one logf and one division.
+__device__ __forceinline__ float log1p_acc(float x) {
+  const float u = 1.0f + x;
+  return u == 1.0f ? x : logf(u) * (x / (u - 1.0f));
+}
 __device__ __forceinline__ float kinetic_of(float p, float m) { return p * p / (sqrtf(p * p + m * m) + m); }
 
 struct V3 {
@@ -380,8 +389,8 @@ __device__ __forceinline__ float spectrum_sample_s(float Y, float u) {
   float lo = 0.0f, hi = 1.0f;
   float s = 0.5f;
   if (Y > 4.0f) {
-    const float x0 = -log1pf(-u);
-    s = fminf(fmaxf((x0 + log1pf(x0)) / Y, 1e-4f), 0.95f);
+    const float x0 = -log1p_acc(-u);
+    s = fminf(fmaxf((x0 + log1p_acc(x0)) / Y, 1e-4f), 0.95f);
   }
   for (int it = 0; it < 40; ++it) {
     const float F = spectrum_K(Y, s) - target;

@@ -337,7 +337,7 @@ __device__ __forceinline__ int kin_step(Cascade& c, StackEntry* stk, Rng& rng, c
   const V3 qcm = axpy(dot3(u, q.px) * ig1 - (q.Tx + q.mx), u, q.px);
   const V3 a = unit(qcm);
   const float kk = 2.0f * b * (q.pstar * 1e-3f) * (q.pstar * 1e-3f);
-  float yy = (kk < 1e-6f) ? 2.0f * u_th : -log1pf(u_th * expm1f(-2.0f * kk)) / kk;
+  float yy = (kk < 1e-6f) ? 2.0f * u_th : -log1p_acc(u_th * expm1f(-2.0f * kk)) / kk;
   yy = fminf(fmaxf(yy, 0.0f), 2.0f);
   const float cth = 1.0f - yy;
   const float sth = sqrtf(fmaxf(0.0f, yy * (2.0f - yy)));
