@@ -43,6 +43,7 @@ struct Cascade {
   int ncoll, nretry, nseg, flags, top;
   int started;
   V3 pt;           // target momentum of the pending collision (TENT -> KIN)
+  float ptm;       // its magnitude, as sampled
   int ytgt;        // target species of the pending collision
   int stk_base, stk_levels;  // LDS part of the LIFO (set by the kernel)
 };
@@ -271,8 +272,7 @@ __device__ __forceinline__ Pair pair_of(const Cascade& c, const NucTab& nt, int 
   q.my = nucleon_mass(y);
   q.Tx = c.eps + nt.EF[c.sp][s];
   q.px = scale(sqrtf(q.Tx * q.Tx + 2.0f * q.Tx * q.mx), c.dir);
-  const float ptm = sqrtf(dot3(c.pt, c.pt));
-  q.Tt = kinetic_of(ptm, q.my);
+  q.Tt = kinetic_of(c.ptm, q.my);
   const float Q = 2.0f * (q.Tx * q.Tt + q.Tx * q.my + q.Tt * q.mx - dot3(q.px, c.pt));
   const float ss = (q.mx + q.my) * (q.mx + q.my) + Q;
   q.rs = sqrtf(ss);
@@ -298,6 +298,7 @@ __device__ __forceinline__ int tent_step(Cascade& c, Rng& rng, const NucTab& nt,
   float sph, cph;
   sincospif(2.0f * rng.next(), &sph, &cph);
   c.pt = {ptm * st * cph, ptm * st * sph, ptm * ct};
+  c.ptm = ptm;
   c.ytgt = y;
   const Pair q = pair_of(c, nt, y);
   int k;
@@ -306,7 +307,7 @@ __device__ __forceinline__ int tent_step(Cascade& c, Rng& rng, const NucTab& nt,
   const int like = (c.sp == y);
   const float sig = (o.const_sigma_mb > 0.0f ? o.const_sigma_mb : xs_lerp(xs.sig[like], k, f)) * kMbToFm2;
   const float shy = y ? c.sh1 : c.sh0;
-  if (!(rng.next() < sig / shy)) {
+  if (!(rng.next() * shy < sig)) {  // u < sigma / sigma_hat
     c.tau = -logf(rng.next());
     return kStFlight;
   }
