@@ -240,6 +240,107 @@ __global__ void __launch_bounds__(256) k_evap_plain(KernelArgs a) {
 // depend on the schedule.
 constexpr int kChunk = 64;
 
+// Sources of evaporation work: chunks of kChunk consecutive launch events.
+// The global queue (queue[1]) hands out every chunk of the launch once; a
+// wave's own list hands out the chunks that wave took through the cascade,
+// whose hand-over records its own lanes wrote.
+struct QueueChunks {
+  unsigned long long* head;
+  size_t n;
+  __device__ __forceinline__ bool claim(unsigned long long& base) {
+    unsigned long long b = 0;
+    if (lane_id() == 0) b = atomicAdd(head, (unsigned long long)kChunk);
+    base = __shfl(b, 0);
+    return base < n;
+  }
+};
+struct OwnChunks {
+  uint32_t list;  // lane i: first event of the wave's i-th chunk
+  int count, next;
+  __device__ __forceinline__ bool claim(unsigned long long& base) {
+    if (next >= count) return false;
+    base = (unsigned long long)(uint32_t)__shfl((int)list, next);
+    ++next;
+    return true;
+  }
+};
+
+// Evaporation of handed-over events (Sec. 2.4), every lane in the evaporation
+// state: a lane whose nucleus has de-excited takes the next event of the
+// current chunk, records whose cascade already ended the event (kMidFinal)
+// are skipped.  The random stream resumes after the cascade's draws, so the
+// results equal the fused kernel's whichever kernel runs this.  kMark: flag
+// each finished record kMidFinal so that a later pass skips it.
+template <int kCap, bool kMark, class Src>
+__device__ __forceinline__ void evap_events(const KernelArgs& a, const MassTab& smt, uint32_t* wbuf, int& fill,
+                                            Src& src) {
+  unsigned long long chunk_next = 0, chunk_end = 0;
+  bool exhausted = false, busy = false;
+  EventRef er = {0, 0};
+  Rng rng;
+  rng.set_key(a.seed);
+  Nucleus nu = {0, 0, 0.0f, {0.0f, 0.0f, 0.0f}};
+  int nsec = 0, flags = 0, ncoll = 0, nretry = 0;
+  uint32_t ev_idx = 0;
+  float Ex_casc = 0.0f;
+  for (;;) {
+    const uint64_t need = __ballot(!busy);
+    if (need && !exhausted) {
+      if (chunk_next == chunk_end) {
+        unsigned long long base = 0;
+        if (src.claim(base)) {
+          chunk_next = base;
+          chunk_end = base + kChunk < a.n ? base + kChunk : a.n;
+        } else {
+          exhausted = true;
+          chunk_next = chunk_end = 0;
+        }
+      }
+      const unsigned long long avail = chunk_end - chunk_next;
+      const uint32_t r = rank_in(need);
+      if (!busy && r < avail) {
+        const size_t ev = (size_t)(chunk_next + r);
+        const MidState m = a.mid[ev];
+        if (!(m.flags & kMidFinal)) {
+          ev_idx = (uint32_t)ev;
+          er = event_ref(a, ev);
+          nu.A = m.A;
+          nu.Z = m.Z;
+          nu.E = m.E;
+          nu.P = {m.P[0], m.P[1], m.P[2]};
+          Ex_casc = m.E;
+          nsec = m.nsec;
+          flags = m.flags;
+          ncoll = m.ncoll;
+          nretry = m.nretry;
+          init_stream(rng, a, er);
+          rng.seek(m.drawn);
+          busy = true;
+        }
+      }
+      const unsigned long long cnt = (unsigned long long)__popcll(need);
+      chunk_next += cnt < avail ? cnt : avail;
+    }
+    if (!__any(busy)) {
+      if (exhausted) break;
+      continue;
+    }
+    Emit em;
+    em.on = false;
+    if (busy) {
+      if (evap_step(nu, rng, a.bind, a.evap, smt, em)) {
+        write_residual(a.segs[er.seg].res + er.local, nu, Ex_casc, nsec, flags, ncoll, nretry);
+        if (flags) atomicAdd(&a.segs[er.seg].counters[1], 1ull);
+        if (kMark) a.mid[ev_idx].flags = (uint16_t)(flags | kMidFinal);
+        busy = false;
+      } else {
+        ++nsec;
+      }
+    }
+    writer_append<kCap>(wbuf, fill, a.segs, a.ring, em.on, er.local, kind_of(em.kind, er), em.T, em.u);
+  }
+}
+
 // 3 waves per SIMD (<= 168 VGPRs): the lane scheduler needs many events in
 // flight per CU more than it needs extra registers.
 // kFused: the evaporation runs in the same kernel as a fifth lane state;
@@ -258,6 +359,9 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) k
 
   unsigned long long chunk_next = 0, chunk_end = 0;
   bool exhausted = false;
+  uint32_t own_list = 0;  // staged: lane i holds the first event of this wave's i-th chunk
+  int own_count = 0;
+  bool own_full = false;
   int st = kStDone;
   EventRef er = {0, 0};
   float T0 = 0.0f;
@@ -285,6 +389,18 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) k
         if (base >= a.n) {
           exhausted = true;
           chunk_next = chunk_end = a.n;
+          // the stragglers of the launch go first from here on
+          __builtin_amdgcn_s_setprio(1);
+        } else if (!kFused) {
+          if (own_count < 64) {
+            if (lane_id() == own_count) own_list = (uint32_t)base;
+            ++own_count;
+          } else if (!own_full) {
+            // more chunks than the list holds: the evaporation kernel must
+            // pass over the whole launch (its queue head starts at n, "done")
+            own_full = true;
+            if (lane_id() == 0) atomicExch(a.queue + 1, 0ull);
+          }
         }
       }
       const unsigned long long avail = chunk_end - chunk_next;
@@ -399,91 +515,43 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) k
     }
     writer_append(wbuf, fill, a.segs, a.ring, em.on, er.local, kind_of(em.kind, er), em.T, em.u);
   }
+  if (!kFused) {
+    // Staged mode: this wave's cascades are over and no event is left to
+    // start.  While other waves finish their longest cascades, evaporate the
+    // events this wave handed over (its own lanes wrote those records, so
+    // only wave-level ordering is needed), at the lowest priority; the
+    // evaporation kernel that follows takes whatever is left.
+    __builtin_amdgcn_s_setprio(0);
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
+    OwnChunks src = {own_list, own_count, 0};
+    evap_events<kWriterCap, true>(a, smt, wbuf, fill, src);
+  }
   writer_flush(wbuf, fill, a.segs, a.ring);
 }
 
-// Staged mode, second kernel: the evaporation of every event whose cascade
-// the persistent kernel handed over (MidState), as a persistent work-queue
-// kernel of its own.  Every lane is in the evaporation state, so a wave step
-// runs with all lanes that still have work; a lane whose nucleus has
-// de-excited takes the next event.  The random stream resumes after the
-// cascade's draws, so the results equal the fused kernel's.
+// Staged mode, second kernel: the evaporation of every handed-over event the
+// cascade kernel's waves did not evaporate themselves, as a persistent
+// work-queue kernel of its own (second queue head).
 __global__ void __launch_bounds__(256) k_evap_persistent(KernelArgs a) {
+  // usually nothing is left: the cascade waves evaporated what they handed over
+  if (__hip_atomic_load(a.queue + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) >= a.n) return;
   extern __shared__ __align__(16) char lds[];
   stage_tables(lds, a, 0, false);
   const MassTab& smt = *(const MassTab*)lds;
   uint32_t* wbuf = (uint32_t*)(lds + sizeof(MassTab)) + (threadIdx.x / 64) * (kWriterCapEvap * kRecWords);
   int fill = 0;
-
-  unsigned long long chunk_next = 0, chunk_end = 0;
-  bool exhausted = false, busy = false;
-  EventRef er = {0, 0};
-  Rng rng;
-  rng.set_key(a.seed);
-  Nucleus nu = {0, 0, 0.0f, {0.0f, 0.0f, 0.0f}};
-  int nsec = 0, flags = 0, ncoll = 0, nretry = 0;
-  float Ex_casc = 0.0f;
-  for (;;) {
-    const uint64_t need = __ballot(!busy);
-    if (need && !exhausted) {
-      if (chunk_next == chunk_end) {
-        unsigned long long base = 0;
-        if (lane_id() == 0) base = atomicAdd(a.queue + 1, (unsigned long long)kChunk);
-        base = __shfl(base, 0);
-        chunk_next = base;
-        chunk_end = base + kChunk < a.n ? base + kChunk : a.n;
-        if (base >= a.n) {
-          exhausted = true;
-          chunk_next = chunk_end = a.n;
-        }
-      }
-      const unsigned long long avail = chunk_end - chunk_next;
-      const uint32_t r = rank_in(need);
-      if (!busy && r < avail) {
-        const size_t ev = (size_t)(chunk_next + r);
-        const MidState m = a.mid[ev];
-        if (!(m.flags & kMidFinal)) {
-          er = event_ref(a, ev);
-          nu.A = m.A;
-          nu.Z = m.Z;
-          nu.E = m.E;
-          nu.P = {m.P[0], m.P[1], m.P[2]};
-          Ex_casc = m.E;
-          nsec = m.nsec;
-          flags = m.flags;
-          ncoll = m.ncoll;
-          nretry = m.nretry;
-          init_stream(rng, a, er);
-          rng.seek(m.drawn);
-          busy = true;
-        }
-      }
-      const unsigned long long cnt = (unsigned long long)__popcll(need);
-      chunk_next += cnt < avail ? cnt : avail;
-    }
-    if (!__any(busy)) {
-      if (exhausted) break;
-      continue;
-    }
-    Emit em;
-    em.on = false;
-    if (busy) {
-      if (evap_step(nu, rng, a.bind, a.evap, smt, em)) {
-        write_residual(a.segs[er.seg].res + er.local, nu, Ex_casc, nsec, flags, ncoll, nretry);
-        if (flags) atomicAdd(&a.segs[er.seg].counters[1], 1ull);
-        busy = false;
-      } else {
-        ++nsec;
-      }
-    }
-    writer_append<kWriterCapEvap>(wbuf, fill, a.segs, a.ring, em.on, er.local, kind_of(em.kind, er), em.T, em.u);
-  }
+  QueueChunks src = {a.queue + 1, a.n};
+  evap_events<kWriterCapEvap, false>(a, smt, wbuf, fill, src);
   writer_flush(wbuf, fill, a.segs, a.ring);
 }
 
-// Zero the segments' counters and the two work-queue heads (a fill kernel
-// rather than a memset, so the launch sequence stays capturable in a graph).
-__global__ void k_zero_counters(const Segment* segs, int n_seg, unsigned long long* queue) {
+// Zero the segments' counters and set the two work-queue heads (a fill
+// kernel rather than a memset, so the launch sequence stays capturable in a
+// graph).  The evaporation queue starts at n, empty: in staged mode the
+// cascade kernel's waves evaporate the events they handed over and reset it
+// to 0 only if some wave took more chunks than it can list; the fused and
+// plain kernels do not use it.
+__global__ void k_zero_counters(const Segment* segs, int n_seg, unsigned long long* queue, unsigned long long n) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n_seg) {
     segs[i].counters[0] = 0ull;
@@ -491,7 +559,7 @@ __global__ void k_zero_counters(const Segment* segs, int n_seg, unsigned long lo
   }
   if (i == 0) {
     queue[0] = 0ull;
-    queue[1] = 0ull;
+    queue[1] = n;
   }
 }
 
@@ -563,7 +631,8 @@ hipError_t launch_events(const LaunchDesc& L, hipStream_t s) {
   a.mid = L.mid;
   a.ring = L.ring;
   a.stack_lds = L.stack_lds;
-  hipLaunchKernelGGL(k_zero_counters, dim3((L.n_seg + 63) / 64), dim3(64), 0, s, L.segs, L.n_seg, L.queue);
+  hipLaunchKernelGGL(k_zero_counters, dim3((L.n_seg + 63) / 64), dim3(64), 0, s, L.segs, L.n_seg, L.queue,
+                     (unsigned long long)L.n);
   const int block = L.block;
   if (L.mode == INC_MODE_PLAIN) {
     const unsigned grid = (unsigned)((L.n + block - 1) / block);

@@ -7,7 +7,9 @@
   the energy range, including the degenerate 250/1 (no binding: the segment
   guard ends most events, as often as in the oracle);
 * a context with the maximum number of targets (16) and a mixture over all;
-* every launch policy the autotuner tries gives the same events."""
+* every launch policy the autotuner tries gives the same events;
+* the staged evaporation pass over the whole launch (waves that took more
+  chunks than they list) gives the same events as the in-kernel one."""
 import numpy as np
 import pytest
 
@@ -105,3 +107,19 @@ def test_autotuned_policy_changes_speed_not_results():
         h = run_gpu(targets, T0, seed=4, tidx=tidx, mode="staged", **cand["options"])
         assert h["res"].tobytes() == ref["res"].tobytes(), cand["options"]
         assert h["n_sec_total"] == ref["n_sec_total"], cand["options"]
+
+
+def test_staged_evaporation_overflow_pass():
+    """In staged mode a cascade wave evaporates the events of the chunks it
+    took (it lists up to 64); a wave that took more makes the evaporation
+    kernel pass over the whole launch.  One wave per CU on 1.2e6 events takes
+    that path; the events must equal those of the default grid."""
+    targets = [(16, 8), (40, 20)]
+    rng = np.random.default_rng(21)
+    n = 1_200_000
+    tidx = rng.integers(0, 2, n).astype(np.uint8)
+    T0 = np.full(n, 200.0, np.float32)
+    few = run_gpu(targets, T0, seed=8, tidx=tidx, mode="staged", waves_per_cu=1)
+    ref = run_gpu(targets, T0, seed=8, tidx=tidx, mode="staged")
+    assert few["res"].tobytes() == ref["res"].tobytes()
+    assert few["n_sec_total"] == ref["n_sec_total"]
