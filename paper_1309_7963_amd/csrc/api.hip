@@ -51,7 +51,7 @@ int inc_launch_segments(inc_ctx* ctx, size_t n, const uint8_t* tidx, const float
     if (ctx->d_mid) (void)hipFree(ctx->d_mid);
     ctx->d_mid = nullptr;
     ctx->mid_cap = 0;
-    hipError_t e = hipMalloc(&ctx->d_mid, sizeof(MidState) * n);
+    hipError_t e = hipMalloc(&ctx->d_mid, mid_bytes(n));
     if (e != hipSuccess) return map_err(e);
     ctx->mid_cap = n;
   }

@@ -20,6 +20,18 @@ struct MidState {
 };
 static_assert(sizeof(MidState) == 32, "MidState layout");
 
+// Events per work-queue chunk of the persistent kernels.
+constexpr int kChunkEvents = 64;
+
+// Hand-over buffer of a plain or staged launch of n events: n MidState
+// records, then (staged) the chunks whose evaporation is left to the
+// evaporation kernel: [0] chunks listed, [1] chunks claimed by the
+// evaporation kernel, [2], [3] unused, then the first event of each listed
+// chunk.
+inline size_t mid_bytes(size_t n) {
+  return sizeof(MidState) * n + sizeof(uint32_t) * (4 + (n + kChunkEvents - 1) / kChunkEvents);
+}
+
 struct LaunchDesc {
   int mode;
   int block;

@@ -238,22 +238,25 @@ __global__ void __launch_bounds__(256) k_evap_plain(KernelArgs a) {
 // Lanes in other states wait, so every step runs with many lanes together;
 // each lane still consumes its own random stream in order, so results do not
 // depend on the schedule.
-constexpr int kChunk = 64;
+constexpr int kChunk = kChunkEvents;
 
 // Sources of evaporation work: chunks of kChunk consecutive launch events.
-// The global queue (queue[1]) hands out every chunk of the launch once; a
-// wave's own list hands out the chunks that wave took through the cascade,
-// whose hand-over records its own lanes wrote.
-struct QueueChunks {
-  unsigned long long* head;
-  size_t n;
+// The evaporation kernel takes the chunks listed after the hand-over records
+// (mid_bytes): those of waves that took more chunks than they keep.
+struct LeftChunks {
+  uint32_t* left;
+  uint32_t count;
   __device__ __forceinline__ bool claim(unsigned long long& base) {
-    unsigned long long b = 0;
-    if (lane_id() == 0) b = atomicAdd(head, (unsigned long long)kChunk);
-    base = __shfl(b, 0);
-    return base < n;
+    uint32_t b = 0;
+    if (lane_id() == 0) b = atomicAdd(&left[1], 1u);
+    b = (uint32_t)__shfl((int)b, 0);
+    if (b >= count) return false;
+    base = left[4 + b];
+    return true;
   }
 };
+// A wave's own list: the chunks it took through the cascade, whose hand-over
+// records its own lanes wrote.
 struct OwnChunks {
   uint32_t list;  // lane i: first event of the wave's i-th chunk
   int count, next;
@@ -269,9 +272,8 @@ struct OwnChunks {
 // state: a lane whose nucleus has de-excited takes the next event of the
 // current chunk, records whose cascade already ended the event (kMidFinal)
 // are skipped.  The random stream resumes after the cascade's draws, so the
-// results equal the fused kernel's whichever kernel runs this.  kMark: flag
-// each finished record kMidFinal so that a later pass skips it.
-template <int kCap, bool kMark, class Src>
+// results equal the fused kernel's whichever kernel runs this.
+template <int kCap, class Src>
 __device__ __forceinline__ void evap_events(const KernelArgs& a, const MassTab& smt, uint32_t* wbuf, int& fill,
                                             Src& src) {
   unsigned long long chunk_next = 0, chunk_end = 0;
@@ -281,7 +283,6 @@ __device__ __forceinline__ void evap_events(const KernelArgs& a, const MassTab& 
   rng.set_key(a.seed);
   Nucleus nu = {0, 0, 0.0f, {0.0f, 0.0f, 0.0f}};
   int nsec = 0, flags = 0, ncoll = 0, nretry = 0;
-  uint32_t ev_idx = 0;
   float Ex_casc = 0.0f;
   for (;;) {
     const uint64_t need = __ballot(!busy);
@@ -302,7 +303,6 @@ __device__ __forceinline__ void evap_events(const KernelArgs& a, const MassTab& 
         const size_t ev = (size_t)(chunk_next + r);
         const MidState m = a.mid[ev];
         if (!(m.flags & kMidFinal)) {
-          ev_idx = (uint32_t)ev;
           er = event_ref(a, ev);
           nu.A = m.A;
           nu.Z = m.Z;
@@ -331,7 +331,6 @@ __device__ __forceinline__ void evap_events(const KernelArgs& a, const MassTab& 
       if (evap_step(nu, rng, a.bind, a.evap, smt, em)) {
         write_residual(a.segs[er.seg].res + er.local, nu, Ex_casc, nsec, flags, ncoll, nretry);
         if (flags) atomicAdd(&a.segs[er.seg].counters[1], 1ull);
-        if (kMark) a.mid[ev_idx].flags = (uint16_t)(flags | kMidFinal);
         busy = false;
       } else {
         ++nsec;
@@ -361,7 +360,6 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) k
   bool exhausted = false;
   uint32_t own_list = 0;  // staged: lane i holds the first event of this wave's i-th chunk
   int own_count = 0;
-  bool own_full = false;
   int st = kStDone;
   EventRef er = {0, 0};
   float T0 = 0.0f;
@@ -395,11 +393,10 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) k
           if (own_count < 64) {
             if (lane_id() == own_count) own_list = (uint32_t)base;
             ++own_count;
-          } else if (!own_full) {
-            // more chunks than the list holds: the evaporation kernel must
-            // pass over the whole launch (its queue head starts at n, "done")
-            own_full = true;
-            if (lane_id() == 0) atomicExch(a.queue + 1, 0ull);
+          } else {
+            // more chunks than the wave keeps: listed for the evaporation kernel
+            uint32_t* left = (uint32_t*)(a.mid + a.n);
+            if (lane_id() == 0) left[4 + atomicAdd(&left[0], 1u)] = (uint32_t)base;
           }
         }
       }
@@ -524,34 +521,33 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) k
     __builtin_amdgcn_s_setprio(0);
     __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
     OwnChunks src = {own_list, own_count, 0};
-    evap_events<kWriterCap, true>(a, smt, wbuf, fill, src);
+    evap_events<kWriterCap>(a, smt, wbuf, fill, src);
   }
   writer_flush(wbuf, fill, a.segs, a.ring);
 }
 
-// Staged mode, second kernel: the evaporation of every handed-over event the
-// cascade kernel's waves did not evaporate themselves, as a persistent
-// work-queue kernel of its own (second queue head).
+// Staged mode, second kernel: the evaporation of the handed-over events the
+// cascade kernel's waves did not evaporate themselves (the chunks listed
+// after the hand-over records), as a persistent work-queue kernel.
 __global__ void __launch_bounds__(256) k_evap_persistent(KernelArgs a) {
   // usually nothing is left: the cascade waves evaporated what they handed over
-  if (__hip_atomic_load(a.queue + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) >= a.n) return;
+  uint32_t* left = (uint32_t*)(a.mid + a.n);
+  const uint32_t count = __hip_atomic_load(&left[0], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  if (count == 0) return;
   extern __shared__ __align__(16) char lds[];
   stage_tables(lds, a, 0, false);
   const MassTab& smt = *(const MassTab*)lds;
   uint32_t* wbuf = (uint32_t*)(lds + sizeof(MassTab)) + (threadIdx.x / 64) * (kWriterCapEvap * kRecWords);
   int fill = 0;
-  QueueChunks src = {a.queue + 1, a.n};
-  evap_events<kWriterCapEvap, false>(a, smt, wbuf, fill, src);
+  LeftChunks src = {left, count};
+  evap_events<kWriterCapEvap>(a, smt, wbuf, fill, src);
   writer_flush(wbuf, fill, a.segs, a.ring);
 }
 
-// Zero the segments' counters and set the two work-queue heads (a fill
-// kernel rather than a memset, so the launch sequence stays capturable in a
-// graph).  The evaporation queue starts at n, empty: in staged mode the
-// cascade kernel's waves evaporate the events they handed over and reset it
-// to 0 only if some wave took more chunks than it can list; the fused and
-// plain kernels do not use it.
-__global__ void k_zero_counters(const Segment* segs, int n_seg, unsigned long long* queue, unsigned long long n) {
+// Zero the segments' counters, the work-queue heads and (staged) the list of
+// chunks left to the evaporation kernel (a fill kernel rather than a memset,
+// so the launch sequence stays capturable in a graph).
+__global__ void k_zero_counters(const Segment* segs, int n_seg, unsigned long long* queue, uint32_t* left) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n_seg) {
     segs[i].counters[0] = 0ull;
@@ -559,7 +555,8 @@ __global__ void k_zero_counters(const Segment* segs, int n_seg, unsigned long lo
   }
   if (i == 0) {
     queue[0] = 0ull;
-    queue[1] = n;
+    queue[1] = 0ull;
+    if (left) left[0] = left[1] = 0u;
   }
 }
 
@@ -632,7 +629,7 @@ hipError_t launch_events(const LaunchDesc& L, hipStream_t s) {
   a.ring = L.ring;
   a.stack_lds = L.stack_lds;
   hipLaunchKernelGGL(k_zero_counters, dim3((L.n_seg + 63) / 64), dim3(64), 0, s, L.segs, L.n_seg, L.queue,
-                     (unsigned long long)L.n);
+                     L.mode == INC_MODE_STAGED ? (uint32_t*)(L.mid + L.n) : nullptr);
   const int block = L.block;
   if (L.mode == INC_MODE_PLAIN) {
     const unsigned grid = (unsigned)((L.n + block - 1) / block);

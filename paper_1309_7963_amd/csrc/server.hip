@@ -94,7 +94,7 @@ size_t default_cap(const inc_ctx* ctx, size_t n) {
 // Device bytes a request needs inside a launch (inputs, its share of the
 // staged hand-over buffer, residuals, secondaries, counters, segment entry).
 size_t request_bytes(size_t n, size_t cap) {
-  return align_up(4 * n) + align_up(n) + align_up(sizeof(MidState) * n) + align_up(sizeof(inc_residual) * n) +
+  return align_up(4 * n) + align_up(n) + align_up(incdev::mid_bytes(n)) + align_up(sizeof(inc_residual) * n) +
          5 * align_up(4 * cap) + 2 * align_up(cap) + align_up(4 * sizeof(unsigned long long)) +
          align_up(sizeof(Segment));
 }
@@ -266,7 +266,7 @@ int start_launch(inc_server* s) {
   const size_t tidx_off = o; o += align_up(n);
   L.seg_off = o;             o += align_up(sizeof(Segment) * take.size());
   L.queue_off = o;           o += align_up(2 * sizeof(unsigned long long));
-  const size_t mid_off = o;  o += align_up(sizeof(MidState) * n);
+  const size_t mid_off = o;  o += align_up(incdev::mid_bytes(n));
   char* h = s->h_pool + L.off;
   char* d = s->d_pool + L.off;
   bool any_tidx = false;

@@ -8,8 +8,8 @@
   guard ends most events, as often as in the oracle);
 * a context with the maximum number of targets (16) and a mixture over all;
 * every launch policy the autotuner tries gives the same events;
-* the staged evaporation pass over the whole launch (waves that took more
-  chunks than they list) gives the same events as the in-kernel one."""
+* the staged evaporation kernel's share (chunks of waves that took more than
+  they keep) gives the same events as the cascade waves' own evaporation."""
 import numpy as np
 import pytest
 
@@ -111,9 +111,9 @@ def test_autotuned_policy_changes_speed_not_results():
 
 def test_staged_evaporation_overflow_pass():
     """In staged mode a cascade wave evaporates the events of the chunks it
-    took (it lists up to 64); a wave that took more makes the evaporation
-    kernel pass over the whole launch.  One wave per CU on 1.2e6 events takes
-    that path; the events must equal those of the default grid."""
+    took (it keeps up to 64); a wave that took more lists the others for the
+    evaporation kernel.  One wave per CU on 1.2e6 events takes that path; the
+    events must equal those of the default grid."""
     targets = [(16, 8), (40, 20)]
     rng = np.random.default_rng(21)
     n = 1_200_000
