@@ -89,6 +89,12 @@ typedef struct {
   int start_threshold;   /* persistent kernel: lanes that must wait to begin */
                          /* a flight (entry or stack pop) before the wave    */
                          /* runs that step (1..64; 0 = default)              */
+  int input_order;       /* persistent and staged launches of >= 65536      */
+                         /* events on a context's own buffers start the      */
+                         /* events with the largest expected cost first      */
+                         /* (A^1/3 (T0 + 50 MeV), a counting sort on the     */
+                         /* device); 1: start them in input order instead.   */
+                         /* Results do not depend on it.                     */
 } inc_options;
 
 /* One residual nucleus per event, 32 bytes. */

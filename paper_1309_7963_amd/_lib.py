@@ -43,6 +43,7 @@ class Options(C.Structure):
         ("block_size", C.c_int), ("evap_threshold", C.c_int), ("tent_threshold", C.c_int),
         ("kin_threshold", C.c_int), ("waves_per_cu", C.c_int), ("stack_levels", C.c_int),
         ("same_stream", C.c_int), ("fast_math", C.c_int), ("start_threshold", C.c_int),
+        ("input_order", C.c_int),
     ]
 
 

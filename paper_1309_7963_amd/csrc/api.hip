@@ -38,6 +38,8 @@ void release(inc_ctx* c) {
   if (c->d_mass) (void)hipFree(c->d_mass);
   if (c->d_B) (void)hipFree(c->d_B);
   if (c->d_mid) (void)hipFree(c->d_mid);
+  if (c->d_perm) (void)hipFree(c->d_perm);
+  if (c->d_order_hist) (void)hipFree(c->d_order_hist);
   if (c->d_segs) (void)hipFree(c->d_segs);
   delete c;
 }
@@ -55,9 +57,28 @@ int inc_launch_segments(inc_ctx* ctx, size_t n, const uint8_t* tidx, const float
     if (e != hipSuccess) return map_err(e);
     ctx->mid_cap = n;
   }
+  // the context's own persistent launches start their costliest events first
+  const uint32_t* perm = nullptr;
+  if (!mid && (mode == INC_MODE_PERSISTENT || mode == INC_MODE_STAGED) && n >= kOrderMin && !ctx->opt.input_order) {
+    hipError_t e = hipSuccess;
+    if (!ctx->d_order_hist) e = hipMalloc(&ctx->d_order_hist, sizeof(uint32_t) * kOrderHist);
+    if (e == hipSuccess && ctx->perm_cap < n) {
+      if (ctx->d_perm) (void)hipFree(ctx->d_perm);
+      ctx->d_perm = nullptr;
+      ctx->perm_cap = 0;
+      e = hipMalloc(&ctx->d_perm, sizeof(uint32_t) * n);
+      if (e == hipSuccess) ctx->perm_cap = n;
+    }
+    if (e == hipSuccess)
+      e = inc_launch_order(T0, tidx, n, ctx->d_nuc, ctx->n_targets, ctx->order_inv_cmax, ctx->d_order_hist,
+                           ctx->d_perm, s);
+    if (e != hipSuccess) return map_err(e);
+    perm = ctx->d_perm;
+  }
   LaunchDesc L;
   memset(&L, 0, sizeof(L));
   L.mode = mode;
+  L.perm = perm;
   L.block = ctx->block;
   L.persistent_blocks = ctx->n_cu * ctx->waves_per_cu / (ctx->block / 64);
   if (max_blocks > 0 && max_blocks < L.persistent_blocks) L.persistent_blocks = max_blocks;
@@ -153,7 +174,7 @@ int inc_ctx_create(const inc_nucleus* targets, int n_targets, const inc_options*
   if (o.evap_threshold < 0 || o.evap_threshold > 64 || o.tent_threshold < 0 || o.tent_threshold > 64 ||
       o.kin_threshold < 0 || o.kin_threshold > 64 || o.waves_per_cu < 0 || o.waves_per_cu > 32 ||
       o.stack_levels < -1 || o.stack_levels > incdev::kStackLdsMax || o.fast_math < 0 || o.fast_math > 1 ||
-      o.start_threshold < 0 || o.start_threshold > 64 ||
+      o.start_threshold < 0 || o.start_threshold > 64 || o.input_order < 0 || o.input_order > 1 ||
       o.same_stream < 0 || o.same_stream > 1)
     return INC_ERR_ARG;
   if (!(o.const_sigma_mb >= 0.0f) || o.const_sigma_mb > 1e5f) return INC_ERR_ARG;
@@ -187,6 +208,7 @@ int inc_ctx_create(const inc_nucleus* targets, int n_targets, const inc_options*
     zmax = targets[t].Z + 1 > zmax ? targets[t].Z + 1 : zmax;
   }
   c->amax = amax;
+  c->order_inv_cmax = 1.0f / (cbrtf((float)(amax - 1)) * 300.0f);
   c->zmax = zmax;
 
   int* d_AZ = nullptr;

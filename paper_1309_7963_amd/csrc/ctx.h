@@ -18,6 +18,10 @@ struct inc_ctx {
   incdev::EvapTab evap;
   incdev::MidState* d_mid;
   size_t mid_cap;
+  uint32_t* d_perm;        // start order of the context's own launches (grown on demand)
+  size_t perm_cap;
+  uint32_t* d_order_hist;  // kOrderBins x kOrderBlocks counting-sort scratch
+  float order_inv_cmax;    // 1 / (largest A^1/3 of the targets x 300 MeV)
   incdev::Segment* d_segs;  // kSegSlots single-segment descriptors, used in turn
   unsigned seg_next;
   int n_cu;

@@ -55,6 +55,7 @@ struct LaunchDesc {
   int n_seg;
   uint64_t seed;         // random-stream key shared by all segments
   unsigned long long* queue;  // two work-queue heads: [0] cascade, [1] evaporation
+  const uint32_t* perm;  // start order of the events (NULL: input order)
   MidState* mid;
   RingDev ring;          // rec == NULL: records go to the segments' arrays
 };
@@ -89,3 +90,17 @@ hipError_t inc_launch_setup(const int* d_AZ, int n_targets, incdev::NucTab* d_nu
                             int amax, int zmax, incdev::EvapTab* d_evap, incdev::MassTab* d_mass, const inc_options& o,
                             hipStream_t s);
 hipError_t inc_upload_segment(const incdev::Segment& seg, incdev::Segment* d_slot, hipStream_t s);
+
+// Longest-expected-first start order of a launch's n events: perm (device, n
+// entries) receives the event indices, largest expected cost first (cost ~
+// A^1/3 (T0 + 50 MeV) in kOrderBins buckets; inv_cmax = 1 / the largest
+// cost of the context's targets).  hist: device scratch of kOrderHist counts.
+// Invalid inputs go last.
+namespace incdev {
+constexpr int kOrderBins = 256;
+constexpr int kOrderBlocks = 512;
+constexpr size_t kOrderHist = (size_t)kOrderBins * (kOrderBlocks + 1);
+constexpr size_t kOrderMin = 65536;  // smaller launches start in input order
+}  // namespace incdev
+hipError_t inc_launch_order(const float* T0, const uint8_t* tidx, size_t n, const incdev::NucTab* nuc, int n_targets,
+                            float inv_cmax, uint32_t* hist, uint32_t* perm, hipStream_t s);

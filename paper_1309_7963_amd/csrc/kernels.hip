@@ -32,6 +32,7 @@ struct KernelArgs {
   int n_seg;
   uint64_t seed;             // random-stream key of every event of the launch
   unsigned long long* queue; // work-queue heads: [0] events, [1] staged evaporation
+  const uint32_t* perm;      // start order: queue position -> launch event (NULL: identity)
   MidState* mid;             // plain kernels: cascade -> evaporation hand-over
   RingDev ring;              // streaming output (rec == NULL: segment arrays)
   int stack_lds;             // stack entries per lane held in LDS
@@ -300,7 +301,8 @@ __device__ __forceinline__ void evap_events(const KernelArgs& a, const MassTab& 
       const unsigned long long avail = chunk_end - chunk_next;
       const uint32_t r = rank_in(need);
       if (!busy && r < avail) {
-        const size_t ev = (size_t)(chunk_next + r);
+        const size_t pos = (size_t)(chunk_next + r);
+        const size_t ev = a.perm ? (size_t)a.perm[pos] : pos;
         const MidState m = a.mid[ev];
         if (!(m.flags & kMidFinal)) {
           er = event_ref(a, ev);
@@ -403,7 +405,8 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) k
       const unsigned long long avail = chunk_end - chunk_next;
       const uint32_t r = rank_in(need);
       if (st == kStDone && r < avail) {
-        const size_t ev = (size_t)(chunk_next + r);
+        const size_t pos = (size_t)(chunk_next + r);
+        const size_t ev = a.perm ? (size_t)a.perm[pos] : pos;
         ev_idx = (uint32_t)ev;
         er = event_ref(a, ev);
         T0 = a.T0[ev];
@@ -625,6 +628,7 @@ hipError_t launch_events(const LaunchDesc& L, hipStream_t s) {
   a.n_seg = L.n_seg;
   a.seed = L.seed;
   a.queue = L.queue;
+  a.perm = L.perm;
   a.mid = L.mid;
   a.ring = L.ring;
   a.stack_lds = L.stack_lds;

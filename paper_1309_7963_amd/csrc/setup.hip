@@ -186,6 +186,121 @@ __global__ void k_set_segment(Segment s, Segment* dst) {
   if (threadIdx.x == 0 && blockIdx.x == 0) *dst = s;
 }
 
+// ----------------------------------------------------------- start order
+// A scheduling choice, not physics: the persistent kernels start the events
+// with the largest expected cost first, so that the last events to start are
+// short ones and the launch's drain is shorter.  Counting sort: each of
+// kOrderBlocks blocks counts the buckets of its slice of the events, two scans
+// turn the counts into each (bucket, block) pair's first position, and each
+// block scatters its slice from there.  Order within a (bucket, block) pair is
+// that of LDS atomics.
+
+// Bucket of event i: 0 for the largest expected cost; a13[t] = A_t^1/3.
+__device__ __forceinline__ int order_bin(const float* T0, const uint8_t* tidx, size_t i, const float* a13,
+                                         int n_targets, float inv_cmax) {
+  const float t = T0[i];
+  const int g = tidx ? (int)tidx[i] : 0;
+  if (!(t >= 20.0f && t <= 250.0f) || g >= n_targets) return kOrderBins - 1;
+  const float c = a13[g] * (t + 50.0f) * inv_cmax;  // (0, 1]
+  const int b = (int)((1.0f - c) * (float)kOrderBins);
+  return b < 0 ? 0 : (b >= kOrderBins ? kOrderBins - 1 : b);
+}
+__device__ __forceinline__ void order_slice(size_t n, size_t& lo, size_t& hi) {
+  const size_t per = (n + kOrderBlocks - 1) / kOrderBlocks;
+  lo = (size_t)blockIdx.x * per;
+  hi = lo + per < n ? lo + per : n;
+}
+// Per block: the targets' A^1/3 in LDS (thread t < n_targets).
+__device__ __forceinline__ void order_a13(float* a13, const NucTab* nuc, int n_targets) {
+  if ((int)threadIdx.x < n_targets) a13[threadIdx.x] = cbrtf((float)nuc[threadIdx.x].A);
+}
+// Add one to counter[b] for every active lane, one LDS atomic per distinct
+// bucket of the wave (lanes of a wave mostly share a few buckets); returns
+// the counter's value before this lane's increment.
+__device__ __forceinline__ uint32_t order_bump(uint32_t* counter, int b, bool on) {
+  uint32_t mine = 0;
+  uint64_t todo = __ballot(on);
+  while (todo) {
+    const int lead = __ffsll((unsigned long long)todo) - 1;
+    const int lb = __shfl(b, lead);
+    const uint64_t m = __ballot(on && b == lb);
+    uint32_t base = 0;
+    if (lane_id() == lead) base = atomicAdd(&counter[lb], (uint32_t)__popcll(m));
+    base = (uint32_t)__shfl((int)base, lead);
+    if (on && b == lb) mine = base + rank_in(m);
+    todo &= ~m;
+  }
+  return mine;
+}
+__global__ void __launch_bounds__(256) k_order_count(const float* T0, const uint8_t* tidx, size_t n,
+                                                     const NucTab* nuc, int n_targets, float inv_cmax,
+                                                     uint32_t* hist) {
+  __shared__ uint32_t h[kOrderBins];
+  __shared__ float a13[kMaxTargets];
+  h[threadIdx.x] = 0u;
+  order_a13(a13, nuc, n_targets);
+  __syncthreads();
+  size_t lo, hi;
+  order_slice(n, lo, hi);
+  for (size_t i0 = lo; i0 < hi; i0 += blockDim.x) {
+    const size_t i = i0 + threadIdx.x;
+    const bool on = i < hi;
+    (void)order_bump(h, on ? order_bin(T0, tidx, i, a13, n_targets, inv_cmax) : 0, on);
+  }
+  __syncthreads();
+  hist[(size_t)threadIdx.x * kOrderBlocks + blockIdx.x] = h[threadIdx.x];
+}
+// One block per bucket: the bucket's counts per block become exclusive
+// prefixes within the bucket; the bucket's total goes after all rows.
+__global__ void __launch_bounds__(kOrderBlocks) k_order_rowscan(uint32_t* hist) {
+  __shared__ uint32_t v[kOrderBlocks];
+  uint32_t* row = hist + (size_t)blockIdx.x * kOrderBlocks;
+  const uint32_t x = row[threadIdx.x];
+  v[threadIdx.x] = x;
+  __syncthreads();
+  for (int d = 1; d < kOrderBlocks; d <<= 1) {  // inclusive scan (Hillis-Steele)
+    const uint32_t add = (int)threadIdx.x >= d ? v[threadIdx.x - d] : 0u;
+    __syncthreads();
+    v[threadIdx.x] += add;
+    __syncthreads();
+  }
+  row[threadIdx.x] = v[threadIdx.x] - x;
+  if (threadIdx.x == kOrderBlocks - 1) hist[(size_t)kOrderBins * kOrderBlocks + blockIdx.x] = v[threadIdx.x];
+}
+// One block: the buckets' totals become the buckets' first positions.
+__global__ void __launch_bounds__(kOrderBins) k_order_binscan(uint32_t* hist) {
+  __shared__ uint32_t v[kOrderBins];
+  uint32_t* tot = hist + (size_t)kOrderBins * kOrderBlocks;
+  const uint32_t x = tot[threadIdx.x];
+  v[threadIdx.x] = x;
+  __syncthreads();
+  for (int d = 1; d < kOrderBins; d <<= 1) {
+    const uint32_t add = (int)threadIdx.x >= d ? v[threadIdx.x - d] : 0u;
+    __syncthreads();
+    v[threadIdx.x] += add;
+    __syncthreads();
+  }
+  tot[threadIdx.x] = v[threadIdx.x] - x;
+}
+__global__ void __launch_bounds__(256) k_order_scatter(const float* T0, const uint8_t* tidx, size_t n,
+                                                       const NucTab* nuc, int n_targets, float inv_cmax,
+                                                       const uint32_t* hist, uint32_t* perm) {
+  __shared__ uint32_t cur[kOrderBins];
+  __shared__ float a13[kMaxTargets];
+  cur[threadIdx.x] =
+      hist[(size_t)kOrderBins * kOrderBlocks + threadIdx.x] + hist[(size_t)threadIdx.x * kOrderBlocks + blockIdx.x];
+  order_a13(a13, nuc, n_targets);
+  __syncthreads();
+  size_t lo, hi;
+  order_slice(n, lo, hi);
+  for (size_t i0 = lo; i0 < hi; i0 += blockDim.x) {
+    const size_t i = i0 + threadIdx.x;
+    const bool on = i < hi;
+    const uint32_t pos = order_bump(cur, on ? order_bin(T0, tidx, i, a13, n_targets, inv_cmax) : 0, on);
+    if (on) perm[pos] = (uint32_t)i;
+  }
+}
+
 }  // namespace incdev
 
 using namespace incdev;
@@ -197,6 +312,17 @@ hipError_t inc_launch_setup(const int* d_AZ, int n_targets, NucTab* d_nuc, XsTab
   hipLaunchKernelGGL(k_xs_table, dim3(1), dim3(kXsNodes), 0, s, d_xs, o.const_sigma_mb);
   const int cells = (amax + 1) * (zmax + 1) > kMaxA + 1 ? (amax + 1) * (zmax + 1) : kMaxA + 1;
   hipLaunchKernelGGL(k_bind_table, dim3((cells + 255) / 256), dim3(256), 0, s, d_B, amax, zmax, d_evap, d_mass);
+  return hipGetLastError();
+}
+
+hipError_t inc_launch_order(const float* T0, const uint8_t* tidx, size_t n, const NucTab* nuc, int n_targets,
+                            float inv_cmax, uint32_t* hist, uint32_t* perm, hipStream_t s) {
+  static_assert(kOrderBins == 256, "one thread per bucket");
+  hipLaunchKernelGGL(k_order_count, dim3(kOrderBlocks), dim3(256), 0, s, T0, tidx, n, nuc, n_targets, inv_cmax, hist);
+  hipLaunchKernelGGL(k_order_rowscan, dim3(kOrderBins), dim3(kOrderBlocks), 0, s, hist);
+  hipLaunchKernelGGL(k_order_binscan, dim3(1), dim3(kOrderBins), 0, s, hist);
+  hipLaunchKernelGGL(k_order_scatter, dim3(kOrderBlocks), dim3(256), 0, s, T0, tidx, n, nuc, n_targets, inv_cmax, hist,
+                     perm);
   return hipGetLastError();
 }
 

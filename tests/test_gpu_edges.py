@@ -9,7 +9,8 @@
 * a context with the maximum number of targets (16) and a mixture over all;
 * every launch policy the autotuner tries gives the same events;
 * the staged evaporation kernel's share (chunks of waves that took more than
-  they keep) gives the same events as the cascade waves' own evaporation."""
+  they keep) gives the same events as the cascade waves' own evaporation;
+* the costliest-first start order gives the same events as input order."""
 import numpy as np
 import pytest
 
@@ -123,3 +124,20 @@ def test_staged_evaporation_overflow_pass():
     ref = run_gpu(targets, T0, seed=8, tidx=tidx, mode="staged")
     assert few["res"].tobytes() == ref["res"].tobytes()
     assert few["n_sec_total"] == ref["n_sec_total"]
+
+
+@pytest.mark.parametrize("mode", ["persistent", "staged"])
+def test_costliest_first_start_order_changes_nothing(mode):
+    """Launches of >= 65536 events on a context's own buffers start the events
+    with the largest expected cost first (a device counting sort); starting
+    them in input order must give the same events."""
+    targets = [(12, 6), (16, 8), (40, 20)]
+    rng = np.random.default_rng(31)
+    n = 150_000
+    tidx = rng.integers(0, 3, n).astype(np.uint8)
+    T0 = rng.uniform(20, 250, n).astype(np.float32)
+    T0[::997] = 300.0  # out of range: flagged, sorted last
+    ordered = run_gpu(targets, T0, seed=6, tidx=tidx, mode=mode)
+    inorder = run_gpu(targets, T0, seed=6, tidx=tidx, mode=mode, input_order=1)
+    assert ordered["res"].tobytes() == inorder["res"].tobytes()
+    assert ordered["n_sec_total"] == inorder["n_sec_total"]
