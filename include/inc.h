@@ -157,11 +157,13 @@ int inc_ctx_tables(const inc_ctx* ctx, float* host_out);
                                  evaporation kernel (the paper's Sec. 3 shape) */
 #define INC_MODE_PERSISTENT 1 /* one fused persistent kernel: lanes refill
                                  from a global work queue                     */
-#define INC_MODE_STAGED 2     /* persistent cascade kernel, then persistent
-                                 evaporation kernel; the post-cascade nucleus
-                                 and stream position are handed over in device
-                                 memory (32 B per event).  Same results as
-                                 INC_MODE_PERSISTENT                          */
+#define INC_MODE_STAGED 2     /* persistent cascade kernel that hands each
+                                 post-cascade nucleus and stream position over
+                                 in device memory (32 B per event) and, once
+                                 its own cascades are over, evaporates the
+                                 events it handed over; a persistent
+                                 evaporation kernel takes any rest.  Same
+                                 results as INC_MODE_PERSISTENT               */
 
 /* Generate batch->n non-elastic events asynchronously on `stream` (a
  * hipStream_t; NULL = the default stream).  All batch and output pointers
@@ -169,7 +171,11 @@ int inc_ctx_tables(const inc_ctx* ctx, float* host_out);
  * out-of-range events are skipped and counted in counters[1] with
  * flags = 0x8000 in their residual record; the host wrapper inc_simulate
  * turns that into INC_ERR_RANGE.  Returns INC_ERR_ARG for bad sizes or
- * pointers, INC_ERR_DEVICE if a launch fails. */
+ * pointers, INC_ERR_DEVICE if a launch fails.  Plain and staged launches use
+ * a hand-over buffer, and persistent and staged launches of >= 65536 events
+ * a start-order buffer, that the context owns and grows: launches of one
+ * context must not overlap on the device (one stream, or synchronise
+ * between streams). */
 int inc_simulate_dev(inc_ctx* ctx, const inc_batch* batch, const inc_output* out, void* stream, int mode);
 
 /* Convenience form (the spec call shape): synchronous, host arrays.
