@@ -256,7 +256,7 @@ def _ring_run(w, slots: int, reps: int = 2):
     ring = inc.Ring(ctx, slots=slots)
     T0 = torch.as_tensor(w["T0"], device="cuda")
     tidx = torch.as_tensor(w["tidx"], device="cuda")
-    buf = inc.Ring.host_buffers(ctx.default_capacity(len(w["T0"])))  # reused host arrays
+    buf = inc.Ring.host_buffers(ctx.default_capacity(len(w["T0"])), len(w["T0"]))  # reused host arrays
     ring.simulate(T0, seed=1, target_idx=tidx, out=buf)  # warm-up
     best = None
     for k in range(reps):

@@ -277,7 +277,9 @@ int inc_ring_destroy(inc_ring* ring);
 /* Generate batch->n events (device inputs, as inc_simulate_dev) with their
  * residuals written to d_res (device, n entries) and their secondaries
  * streamed through the ring into out (host arrays, out->sec_capacity each;
- * *out->n_sec receives the total).  Blocks until the batch is drained.
+ * *out->n_sec receives the total).  If out->res is not NULL the residuals
+ * are also copied there (n entries; from pinned host memory the copy
+ * overlaps the drain).  Blocks until the batch is drained.
  * Returns INC_ERR_CAPACITY if the host arrays were too small (the rest was
  * drained and dropped).  Not thread-safe; one call at a time per ring. */
 int inc_ring_simulate(inc_ring* ring, const inc_batch* batch, inc_residual* d_res, const inc_host_output* out,

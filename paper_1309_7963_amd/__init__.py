@@ -392,23 +392,30 @@ class Ring:
             pass
 
     @staticmethod
-    def host_buffers(capacity: int) -> dict:
+    def host_buffers(capacity: int, n_events: int = 0) -> dict:
         """Host arrays for `capacity` secondaries (written once, so that a
-        later drain into them takes no first-touch page faults); pass them to
-        simulate(out=...) to reuse them across batches."""
+        later drain into them takes no first-touch page faults) and, with
+        n_events, pinned host memory for that many residuals (their copy then
+        overlaps the drain); pass them to simulate(out=...) to reuse them
+        across batches."""
         out = dict(ev=np.zeros(capacity, np.uint32), sp=np.zeros(capacity, np.uint8),
                    st=np.zeros(capacity, np.uint8), T=np.zeros(capacity, np.float32),
                    ux=np.zeros(capacity, np.float32), uy=np.zeros(capacity, np.float32),
                    uz=np.zeros(capacity, np.float32))
         for a in out.values():
             a.fill(0)
+        if n_events:
+            torch = _torch()
+            pinned = torch.zeros(int(n_events) * RESIDUAL_DTYPE.itemsize, dtype=torch.uint8, pin_memory=True)
+            out["res_pinned"] = pinned  # keeps the allocation alive
+            out["res"] = pinned.numpy().view(RESIDUAL_DTYPE)
         return out
 
     def simulate(self, T0, seed: int, target_idx=None, first_event_id: int = 0, mode: str = "staged",
                  capacity: Optional[int] = None, stream=None, out: Optional[dict] = None) -> dict:
         """T0 / target_idx: CUDA tensors as in Context.simulate.  Returns host
-        arrays of the secondaries (views of `out` when given, see
-        host_buffers), the residuals and the ring statistics."""
+        arrays of the secondaries and residuals (views of `out` when given,
+        see host_buffers) and the ring statistics."""
         torch = _torch()
         n = int(T0.shape[0])
         if out is not None:
@@ -420,9 +427,12 @@ class Ring:
                        uz=np.zeros(cap, np.float32))
         res_d = torch.empty(n * 32, dtype=torch.uint8, device=T0.device)
         ev, sp, st, T, ux, uy, uz = (out[k] for k in ("ev", "sp", "st", "T", "ux", "uy", "uz"))
+        res_h = out.get("res")
+        if res_h is None or res_h.shape[0] < n:
+            res_h = np.empty(n, RESIDUAL_DTYPE)
         nsec = C.c_ulonglong()
-        o = _lib.HostOutput(None, ev.ctypes.data, sp.ctypes.data, st.ctypes.data, T.ctypes.data, ux.ctypes.data,
-                            uy.ctypes.data, uz.ctypes.data, cap, C.pointer(nsec), None)
+        o = _lib.HostOutput(res_h.ctypes.data, ev.ctypes.data, sp.ctypes.data, st.ctypes.data, T.ctypes.data,
+                            ux.ctypes.data, uy.ctypes.data, uz.ctypes.data, cap, C.pointer(nsec), None)
         b = _lib.Batch()
         b.n = n
         b.target_idx = target_idx.data_ptr() if target_idx is not None else None
@@ -437,7 +447,7 @@ class Ring:
         if rc not in (_lib.INC_OK, _lib.INC_ERR_CAPACITY):
             _lib.check(rc, "inc_ring_simulate")
         k = min(nsec.value, cap)
-        return dict(rc=rc, res=res_d.cpu().numpy().view(RESIDUAL_DTYPE), n_sec_total=nsec.value,
+        return dict(rc=rc, res=res_h[:n], n_sec_total=nsec.value,
                     sec_event=ev[:k], sec_species=sp[:k], sec_stage=st[:k], sec_T=T[:k],
                     sec_ux=ux[:k], sec_uy=uy[:k], sec_uz=uz[:k],
                     stats={f: getattr(stats, f) for f, _ in stats._fields_})

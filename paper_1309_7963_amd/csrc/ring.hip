@@ -204,6 +204,21 @@ int inc_ring_simulate(inc_ring* r, const inc_batch* b, inc_residual* d_res, cons
     rc = inc_launch_segments(r->ctx, b->n, b->target_idx, b->T0, r->d_seg, 1, b->seed, r->d_dev + 1, st, mode, 0,
                              &R);
   if (rc == INC_OK) rc = inc_map_hip_error(hipEventRecord(done, st));
+  // residuals to the host as well: into pinned memory the copy is queued
+  // behind the kernel now and overlaps the drain; pageable memory is copied
+  // once the drain is over (a blocking copy now would stall the drain the
+  // kernel waits on)
+  bool res_queued = false;
+  if (rc == INC_OK && out && out->res) {
+    hipPointerAttribute_t pa;
+    if (hipPointerGetAttributes(&pa, out->res) == hipSuccess && pa.type == hipMemoryTypeHost) {
+      rc = inc_map_hip_error(
+          hipMemcpyAsync(out->res, d_res, sizeof(inc_residual) * b->n, hipMemcpyDeviceToHost, st));
+      res_queued = rc == INC_OK;
+    } else {
+      (void)hipGetLastError();  // pageable memory is not an error here
+    }
+  }
   if (rc != INC_OK) {
     (void)hipStreamSynchronize(st);
     (void)hipEventDestroy(done);
@@ -306,6 +321,14 @@ int inc_ring_simulate(inc_ring* r, const inc_batch* b, inc_residual* d_res, cons
     }
   }
   (void)hipEventDestroy(done);
+  if (out && out->res && rc == INC_OK) {
+    const hipError_t ce =
+        res_queued ? hipStreamSynchronize(st)
+                   : hipMemcpy(out->res, d_res, sizeof(inc_residual) * b->n, hipMemcpyDeviceToHost);
+    if (ce != hipSuccess) rc = inc_map_hip_error(ce);
+  } else if (res_queued) {
+    (void)hipStreamSynchronize(st);
+  }
   if (kernel_done) r->next_seq = final_head;
   if (rc == INC_OK && *err_p) rc = INC_ERR_DEVICE;
   const unsigned long long produced = kernel_done ? final_head - start : tail - start;

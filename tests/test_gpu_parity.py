@@ -420,7 +420,8 @@ def test_ring_staged_mode_equals_direct_staged():
 
 def test_ring_parallel_drain_equals_direct():
     """Large ring and batch: runs of ready records long enough for the
-    drain's parallel host copy, into reused host arrays (twice)."""
+    drain's parallel host copy, into reused host arrays (twice; the second
+    time with pinned residual memory, whose copy overlaps the drain)."""
     import torch
 
     import paper_1309_7963_amd as inc
@@ -435,6 +436,8 @@ def test_ring_parallel_drain_equals_direct():
     ti_d = torch.as_tensor(tidx, device="cuda")
     kd = np.lexsort((direct["sec_T"], direct["sec_species"], direct["sec_stage"], direct["sec_event"]))
     for rep in range(2):
+        if rep == 1:
+            buf = inc.Ring.host_buffers(ctx.default_capacity(n), n)
         r = ring.simulate(T0_d, seed=6, target_idx=ti_d, out=buf)
         assert r["rc"] == 0 and r["stats"]["producer_gave_up"] == 0
         assert r["res"].tobytes() == direct["res"].tobytes()
