@@ -59,13 +59,19 @@ KERNELS = {"plain": "k_cascade_plain+k_evap_plain", "persistent": "k_persistent"
            "staged": "k_persistent+k_evap_persistent"}
 
 
+# The sources the profiled event launch is compiled from (kernels, their
+# headers, the setup and start-order kernels, the launch policy); the server
+# and ring front ends are not part of it.
+KERNEL_SOURCES = ("api.hip", "ctx.h", "device.h", "event.h", "kernels.h", "kernels.hip", "setup.hip")
+
+
 def kernel_sources_hash() -> str:
-    """sha256 (first 16 hex digits) over the HIP library's sources."""
+    """sha256 (first 16 hex digits) over the sources of the profiled launch."""
     import hashlib
 
     h = hashlib.sha256()
     csrc = os.path.join(ROOT, "paper_1309_7963_amd", "csrc")
-    for f in sorted(os.listdir(csrc)):
+    for f in KERNEL_SOURCES:
         h.update(f.encode())
         with open(os.path.join(csrc, f), "rb") as fh:
             h.update(fh.read())
