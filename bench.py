@@ -66,15 +66,21 @@ KERNEL_SOURCES = ("api.hip", "ctx.h", "device.h", "event.h", "kernels.h", "kerne
 
 
 def kernel_sources_hash() -> str:
-    """sha256 (first 16 hex digits) over the sources of the profiled launch."""
+    """sha256 (first 16 hex digits) over the code of the profiled launch's
+    sources: comments removed and whitespace collapsed, so that only a code
+    change voids a profile."""
     import hashlib
+    import re
 
     h = hashlib.sha256()
     csrc = os.path.join(ROOT, "paper_1309_7963_amd", "csrc")
     for f in KERNEL_SOURCES:
+        with open(os.path.join(csrc, f)) as fh:
+            text = fh.read()
+        text = re.sub(r"/\*.*?\*/", " ", text, flags=re.S)
+        text = re.sub(r"//[^\n]*", " ", text)
         h.update(f.encode())
-        with open(os.path.join(csrc, f), "rb") as fh:
-            h.update(fh.read())
+        h.update(" ".join(text.split()).encode())
     return h.hexdigest()[:16]
 
 

@@ -1,6 +1,9 @@
 // kernels.hip — the event kernels: the plain cascade / evaporation pair (the
 // paper's Sec. 3 organisation: one cascade per thread, then one de-excitation
-// per thread) and the fused persistent work-queue kernel.
+// per thread), the persistent work-queue kernel (fused: cascade and
+// evaporation as lane states; staged: cascades handed over, then evaporated
+// by the same waves once their cascades are over) and the evaporation kernel
+// that takes what the staged waves leave.
 //
 // This file is compiled twice into one library: as is (namespace
 // incdev::precise: IEEE division and square root, precise transcendentals)
@@ -231,14 +234,16 @@ __global__ void __launch_bounds__(256) k_evap_plain(KernelArgs a) {
   writer_flush(wbuf, fill, a.segs, a.ring);
 }
 
-// Persistent fused kernel.  Every wave keeps 64 events in flight; finished
-// lanes refill from a global work queue (one atomic per 64 events per wave).
-// Each iteration the wave advances the lanes of ONE state (FLIGHT, TENT, KIN
-// or EVAP), chosen by ballot: a deeper state runs once enough lanes wait in it
-// (kin / tent / evap thresholds), else FLIGHT, else whatever state has lanes.
-// Lanes in other states wait, so every step runs with many lanes together;
-// each lane still consumes its own random stream in order, so results do not
-// depend on the schedule.
+// Persistent kernels.  Every wave keeps 64 events in flight; finished lanes
+// refill from a global work queue (one atomic per chunk of 64 events per
+// wave; the queue hands out the launch's start order when there is one).
+// Each iteration the wave advances the lanes of ONE state (START, FLIGHT,
+// TENT, KIN or EVAP), chosen by ballot: a costly state runs once enough lanes
+// wait in it (thresholds), else FLIGHT, else whatever state has lanes; once
+// no event is left to start, the state with the most lanes.  Lanes in other
+// states wait, so every step runs with many lanes together; each lane still
+// consumes its own random stream in order, so results do not depend on the
+// schedule.
 constexpr int kChunk = kChunkEvents;
 
 // Sources of evaporation work: chunks of kChunk consecutive launch events.
@@ -344,9 +349,10 @@ __device__ __forceinline__ void evap_events(const KernelArgs& a, const MassTab& 
 
 // 3 waves per SIMD (<= 168 VGPRs): the lane scheduler needs many events in
 // flight per CU more than it needs extra registers.
-// kFused: the evaporation runs in the same kernel as a fifth lane state;
-// otherwise (staged mode) the kernel hands each finished cascade over and has
-// no evaporation code at all, which leaves it fewer live registers.
+// kFused: the evaporation runs in the same loop as a fifth lane state;
+// otherwise (staged mode) the loop hands each finished cascade over and has
+// no evaporation state, which leaves it fewer live registers; the wave
+// evaporates its hand-overs in a second loop once its cascades are over.
 template <bool kFused>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) k_persistent(KernelArgs a) {
   extern __shared__ __align__(16) char lds[];
