@@ -37,6 +37,7 @@ void release(inc_ctx* c) {
   if (c->d_xs) (void)hipFree(c->d_xs);
   if (c->d_mass) (void)hipFree(c->d_mass);
   if (c->d_B) (void)hipFree(c->d_B);
+  if (c->d_chan) (void)hipFree(c->d_chan);
   if (c->d_mid) (void)hipFree(c->d_mid);
   if (c->d_perm) (void)hipFree(c->d_perm);
   if (c->d_order_hist) (void)hipFree(c->d_order_hist);
@@ -95,6 +96,7 @@ int inc_launch_segments(inc_ctx* ctx, size_t n, const uint8_t* tidx, const float
   L.xs = ctx->d_xs;
   L.mass = ctx->d_mass;
   L.bind = ctx->d_B;
+  L.chan = ctx->d_chan;
   L.amax = ctx->amax;
   L.zmax = ctx->zmax;
   L.evap = ctx->evap;
@@ -220,10 +222,12 @@ int inc_ctx_create(const inc_nucleus* targets, int n_targets, const inc_options*
     if ((e = hipMalloc(&c->d_mass, sizeof(MassTab))) != hipSuccess) break;
     if ((e = hipMalloc(&c->d_segs, sizeof(Segment) * kSegSlots)) != hipSuccess) break;
     if ((e = hipMalloc(&c->d_B, sizeof(double) * (amax + 1) * (zmax + 1))) != hipSuccess) break;
+    if ((e = hipMalloc(&c->d_chan, sizeof(ChanRow) * (amax + 1) * (zmax + 1))) != hipSuccess) break;
     if ((e = hipMalloc(&d_AZ, sizeof(int) * 2 * n_targets)) != hipSuccess) break;
     if ((e = hipMalloc(&d_evap, sizeof(EvapTab))) != hipSuccess) break;
     if ((e = hipMemcpy(d_AZ, c->AZ, sizeof(int) * 2 * n_targets, hipMemcpyHostToDevice)) != hipSuccess) break;
-    if ((e = inc_launch_setup(d_AZ, n_targets, c->d_nuc, c->d_xs, c->d_B, amax, zmax, d_evap, c->d_mass, o, nullptr)) !=
+    if ((e = inc_launch_setup(d_AZ, n_targets, c->d_nuc, c->d_xs, c->d_B, c->d_chan, amax, zmax, d_evap, c->d_mass, o,
+                              nullptr)) !=
         hipSuccess)
       break;
     if ((e = hipDeviceSynchronize()) != hipSuccess) break;

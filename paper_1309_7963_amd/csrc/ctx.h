@@ -14,6 +14,7 @@ struct inc_ctx {
   incdev::XsTab* d_xs;
   incdev::MassTab* d_mass;
   double* d_B;
+  incdev::ChanRow* d_chan;  // evaporation rows of every (A, Z) of d_B
   int amax, zmax;
   incdev::EvapTab evap;
   incdev::MidState* d_mid;

@@ -81,11 +81,23 @@ struct Opts {
   int same_stream;       // every event uses its segment's first id
 };
 
-// Binding energies B(A, Z) in double for A <= amax, Z <= zmax.
+// Evaporation constants of one nucleus (A, Z) (Sec. 2.4), computed once per
+// context from the binding table: per channel j the separation energy S_j
+// (+inf when the daughter does not exist), the Coulomb barrier V_j and
+// ln(g_j m_j) + ln R_j^2; and the nuclear mass M(A, Z).
+struct ChanRow {
+  float S[6], V[6], P[6];
+  float M, pad;
+};
+static_assert(sizeof(ChanRow) == 80, "ChanRow layout");
+
+// Binding energies B(A, Z) in double and the evaporation rows, for A <= amax,
+// Z <= zmax (row of (A, Z) at A * zstride + Z).
 struct BindTab {
   const double* B;
   int zstride;  // zmax + 1
   int amax, zmax;
+  const ChanRow* chan;
 };
 
 // --------------------------------------------------------------- Philox

@@ -417,7 +417,6 @@ __device__ __forceinline__ Nucleus cascade_residual(const Cascade& c, const NucT
   return r;
 }
 
-__device__ __forceinline__ double binding_of(const BindTab& bt, int A, int Z) { return bt.B[A * bt.zstride + Z]; }
 
 // EVAP: one evaporation step (Sec. 2.4, Weisskopf-Ewing reading).  Returns true
 // when no channel is open (the nucleus is final).  Draws at most 4 uniforms.
@@ -427,30 +426,22 @@ __device__ __forceinline__ bool evap_step(Nucleus& nu, Rng& rng, const BindTab& 
   rng.ensure(4);
   constexpr int fa[6] = {1, 1, 2, 3, 3, 4};
   constexpr int fz[6] = {0, 1, 1, 1, 2, 2};
-  const double BAZ = binding_of(bt, nu.A, nu.Z);
+  // this nucleus's channel constants (S_j = +inf for a missing daughter)
+  const ChanRow& row = bt.chan[nu.A * bt.zstride + nu.Z];
   float lw[6], U[6], V[6], Y[6];
   float lmax = -INFINITY;
 #pragma unroll
   for (int j = 0; j < 6; ++j) {
     lw[j] = -INFINITY;
-    U[j] = 0.0f;
-    V[j] = 0.0f;
     Y[j] = 0.0f;
-    const int Ad = nu.A - fa[j], Zd = nu.Z - fz[j];
-    if (Ad >= 1 && Zd >= 0 && Zd <= Ad) {
-      const float S = (float)(BAZ - binding_of(bt, Ad, Zd) - et.B[j]);
-      const float ad13 = mt.a13[Ad];
-      V[j] = fz[j] ? kE2 * (float)(fz[j] * Zd) / (1.5f * (ad13 + et.a13[j])) : 0.0f;
-      U[j] = nu.E - S - V[j];
-      if (U[j] > 0.0f) {
-        const float a = (float)Ad * 0.125f;
-        const float lnAd = mt.lnA[Ad];
-        // ln R_j^2: R_j = 1.5 A_d^1/3 (n, p) or 1.5 (A_d^1/3 + a_j^1/3)
-        const float lnR2 = j <= 1 ? 0.8109302f + (2.0f / 3.0f) * lnAd : 2.0f * logf(1.5f * (ad13 + et.a13[j]));
-        Y[j] = 2.0f * sqrtf(a * U[j]);
-        lw[j] = et.lngm[j] + lnR2 + log_width_integral(Y[j], lnAd);
-        lmax = fmaxf(lmax, lw[j]);
-      }
+    V[j] = row.V[j];
+    U[j] = nu.E - row.S[j] - V[j];
+    if (U[j] > 0.0f) {
+      const int Ad = nu.A - fa[j];
+      const float a = (float)Ad * 0.125f;
+      Y[j] = 2.0f * sqrtf(a * U[j]);
+      lw[j] = row.P[j] + log_width_integral(Y[j], mt.lnA[Ad]);
+      lmax = fmaxf(lmax, lw[j]);
     }
   }
   if (lmax == -INFINITY) return true;
@@ -490,8 +481,8 @@ __device__ __forceinline__ bool evap_step(Nucleus& nu, Rng& rng, const BindTab& 
   const float Ed = Uj * (1.0f - s) * (1.0f - s);
   const float eps = Vj + x;
   const int Ad = nu.A - aj, Zd = nu.Z - zj;
-  const float Mp = (float)((double)nu.Z * kMassP + (double)(nu.A - nu.Z) * kMassN - BAZ) + nu.E;
-  const float Mb = (float)((double)Zd * kMassP + (double)(Ad - Zd) * kMassN - binding_of(bt, Ad, Zd)) + Ed;
+  const float Mp = row.M + nu.E;
+  const float Mb = bt.chan[Ad * bt.zstride + Zd].M + Ed;
   const float inv2a = 0.5f / Mp;
   const float p2 = eps * (eps + 2.0f * mj) * ((eps + 2.0f * Mb) * inv2a) * ((eps + 2.0f * Mb + 2.0f * mj) * inv2a);
   const float ps = sqrtf(fmaxf(p2, 0.0f));

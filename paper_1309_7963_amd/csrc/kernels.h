@@ -44,6 +44,7 @@ struct LaunchDesc {
   const XsTab* xs;
   const MassTab* mass;
   const double* bind;
+  const ChanRow* chan;
   int amax, zmax;
   EvapTab evap;
   inc_options opt;
@@ -87,8 +88,8 @@ hipError_t launch_events(const LaunchDesc& L, hipStream_t s);
 }  // namespace incdev
 
 hipError_t inc_launch_setup(const int* d_AZ, int n_targets, incdev::NucTab* d_nuc, incdev::XsTab* d_xs, double* d_B,
-                            int amax, int zmax, incdev::EvapTab* d_evap, incdev::MassTab* d_mass, const inc_options& o,
-                            hipStream_t s);
+                            incdev::ChanRow* d_chan, int amax, int zmax, incdev::EvapTab* d_evap,
+                            incdev::MassTab* d_mass, const inc_options& o, hipStream_t s);
 hipError_t inc_upload_segment(const incdev::Segment& seg, incdev::Segment* d_slot, hipStream_t s);
 
 // Longest-expected-first start order of a launch's n events: perm (device, n

@@ -615,7 +615,7 @@ hipError_t launch_events(const LaunchDesc& L, hipStream_t s) {
   a.n_targets = L.n_targets;
   a.xs = L.xs;
   a.mass = L.mass;
-  a.bind = {L.bind, L.zmax + 1, L.amax, L.zmax};
+  a.bind = {L.bind, L.zmax + 1, L.amax, L.zmax, L.chan};
   a.evap = L.evap;
   a.opt.no_pauli = L.opt.no_pauli;
   a.opt.no_evaporation = L.opt.no_evaporation;

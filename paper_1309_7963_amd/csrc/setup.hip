@@ -51,6 +51,38 @@ __global__ void k_bind_table(double* B, int amax, int zmax, EvapTab* et, MassTab
   }
 }
 
+// Evaporation rows (ChanRow) of every (A, Z) of the binding table, with the
+// arithmetic the evaporation step would otherwise repeat every step.
+__global__ void k_chan_table(const double* B, int amax, int zmax, const EvapTab* et, const MassTab* mt,
+                             ChanRow* chan) {
+  const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+  const int zs = zmax + 1;
+  if (idx >= (amax + 1) * zs) return;
+  const int A = idx / zs, Z = idx % zs;
+  const int fa[6] = {1, 1, 2, 3, 3, 4}, fz[6] = {0, 1, 1, 1, 2, 2};
+  const double BAZ = B[idx];
+  ChanRow r;
+  r.M = (float)((double)Z * kMassP + (double)(A - Z) * kMassN - BAZ);
+  r.pad = 0.0f;
+  for (int j = 0; j < 6; ++j) {
+    const int Ad = A - fa[j], Zd = Z - fz[j];
+    if (Z <= A && Ad >= 1 && Zd >= 0 && Zd <= Ad) {
+      r.S[j] = (float)(BAZ - B[Ad * zs + Zd] - et->B[j]);
+      const float ad13 = mt->a13[Ad];
+      r.V[j] = fz[j] ? kE2 * (float)(fz[j] * Zd) / (1.5f * (ad13 + et->a13[j])) : 0.0f;
+      const float lnAd = mt->lnA[Ad];
+      // ln R_j^2: R_j = 1.5 A_d^1/3 (n, p) or 1.5 (A_d^1/3 + a_j^1/3)
+      const float lnR2 = j <= 1 ? 0.8109302f + (2.0f / 3.0f) * lnAd : 2.0f * logf(1.5f * (ad13 + et->a13[j]));
+      r.P[j] = et->lngm[j] + lnR2;
+    } else {
+      r.S[j] = INFINITY;
+      r.V[j] = 0.0f;
+      r.P[j] = -INFINITY;
+    }
+  }
+  chan[idx] = r;
+}
+
 // Fermi density of Eq. (1), c = 1.07 A^1/3, delta = 0.545, R = c + 2.5 fm,
 // 15 equal shells; each shell's density is its share of the A nucleons over
 // its volume (integrals by 64-panel 5-point Gauss-Legendre, double).
@@ -305,13 +337,17 @@ __global__ void __launch_bounds__(256) k_order_scatter(const float* T0, const ui
 
 using namespace incdev;
 
-hipError_t inc_launch_setup(const int* d_AZ, int n_targets, NucTab* d_nuc, XsTab* d_xs, double* d_B, int amax,
-                            int zmax, EvapTab* d_evap, MassTab* d_mass, const inc_options& o, hipStream_t s) {
+hipError_t inc_launch_setup(const int* d_AZ, int n_targets, NucTab* d_nuc, XsTab* d_xs, double* d_B, ChanRow* d_chan,
+                            int amax, int zmax, EvapTab* d_evap, MassTab* d_mass, const inc_options& o,
+                            hipStream_t s) {
   hipLaunchKernelGGL(k_nucleus_setup, dim3(n_targets), dim3(64), 0, s, d_AZ, d_nuc, o.uniform_density, o.zero_fermi,
                      o.zero_binding);
   hipLaunchKernelGGL(k_xs_table, dim3(1), dim3(kXsNodes), 0, s, d_xs, o.const_sigma_mb);
   const int cells = (amax + 1) * (zmax + 1) > kMaxA + 1 ? (amax + 1) * (zmax + 1) : kMaxA + 1;
   hipLaunchKernelGGL(k_bind_table, dim3((cells + 255) / 256), dim3(256), 0, s, d_B, amax, zmax, d_evap, d_mass);
+  const int rows = (amax + 1) * (zmax + 1);
+  hipLaunchKernelGGL(k_chan_table, dim3((rows + 255) / 256), dim3(256), 0, s, d_B, amax, zmax, d_evap, d_mass,
+                     d_chan);
   return hipGetLastError();
 }
 
