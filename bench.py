@@ -228,6 +228,46 @@ def _end_to_end(w, steps: int, seed: int = 1):
                 note="pinned host inputs -> device -> pinned host residuals and secondaries, serial")
 
 
+def _evaporation_stage(w, reps: int = 5, seed: int = 1):
+    """The evaporation stage alone (inc_evaporate_dev) on the workload's own
+    post-cascade nuclei: a cascade-only launch (no_evaporation) supplies
+    (A', Z', E*, p) per event, which are then evaporated `reps` times."""
+    import torch
+
+    import paper_1309_7963_amd as inc
+
+    casc = inc.Context(w["targets"], no_evaporation=1)
+    T0 = torch.as_tensor(w["T0"], device="cuda")
+    tidx = None if w["tidx"] is None else torch.as_tensor(w["tidx"], device="cuda")
+    n = int(T0.shape[0])
+    first = casc.simulate(T0, seed=seed, target_idx=tidx)
+    torch.cuda.synchronize()
+    casc.close()
+    r16 = first.res.view(torch.int16).view(n, 16)
+    r32 = first.res.view(torch.float32).view(n, 8)
+    A, Z = r16[:, 0].contiguous(), r16[:, 1].contiguous()
+    Ex, P = r32[:, 3].contiguous(), r32[:, 4:7].contiguous()
+    del first
+    ctx = inc.Context(w["targets"])
+    out = inc.DeviceOutput.allocate(n, ctx.default_capacity(n))
+    stream = torch.cuda.current_stream()
+    ctx.evaporate(A, Z, Ex, seed=seed, P=P, out=out)
+    ms = []
+    for k in range(reps):
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record(stream)
+        ctx.evaporate(A, Z, Ex, seed=seed, P=P, out=out, first_event_id=(k + 1) * n)
+        b.record(stream)
+        b.synchronize()
+        ms.append(a.elapsed_time(b))
+    mean_steps = out.n_sec() / n
+    flagged = out.n_flagged()
+    ctx.close()
+    med = float(np.median(ms))
+    return dict(nuclei=n, ms=med, nuclei_per_s=n / (med / 1000.0), fragments_per_nucleus=mean_steps,
+                not_evaporated=flagged)
+
+
 def _tally_run(w, n_ebins: int = 23, reps: int = 5):
     """Residual-nuclide tally of one generated batch (positron-emitter
     yields per energy bin): kernel time and the main emitters' yields."""
@@ -427,6 +467,7 @@ def main(argv=None):
         extra["divergence_ceiling"] = dict(workload=wl["o16_200"]["label"], **dc)
         extra["end_to_end_host"] = _end_to_end(main_w, 3)
         extra["nuclide_tally"] = dict(workload=wl["tissue_mix"]["label"], **_tally_run(wl["tissue_mix"]))
+        extra["evaporation_stage"] = dict(workload=main_w["label"], **_evaporation_stage(main_w))
         # fast-math build of the event kernels (same workloads)
         fm = {}
         for key, w in (("o16_ca40_200", main_w), ("o16_200", wl["o16_200"]), ("ca40_200", wl["ca40_200"]),

@@ -178,6 +178,40 @@ int inc_ctx_tables(const inc_ctx* ctx, float* host_out);
  * between streams). */
 int inc_simulate_dev(inc_ctx* ctx, const inc_batch* batch, const inc_output* out, void* stream, int mode);
 
+/* ------------------------------------------------ evaporation alone
+ * The de-excitation stage of Sec. 2.4 (Weisskopf-Ewing evaporation of n, p,
+ * d, t, 3He and alpha until no channel is open) applied to given excited
+ * nuclei, e.g. residuals of another cascade model or fixed-excitation
+ * studies. */
+typedef struct {            /* all arrays are device memory                  */
+  size_t n;                 /* nuclei, 1 <= n < 2^32                         */
+  const uint16_t* A;        /* n mass numbers, 1 <= A <= amax                */
+  const uint16_t* Z;        /* n charges, 0 <= Z <= min(A, zmax)             */
+  const float* Ex;          /* n excitation energies, MeV, [0, 500]          */
+  const float* P;           /* 3n momenta (x, y, z per nucleus, MeV/c) in the
+                               lab frame, or NULL: every nucleus at rest     */
+  uint64_t seed;
+  uint64_t first_event_id;
+} inc_excited;
+
+/* Evaporate in->n excited nuclei asynchronously on `stream` (device memory
+ * throughout).  amax and zmax are those of inc_ctx_tally_shape (the
+ * heaviest target + 1 nucleon).  Nucleus i draws from the random stream of
+ * (seed, first_event_id + i) from its first draw, the same stream
+ * inc_simulate_dev gives event first_event_id + i.  out->res[i] receives the
+ * final nucleus (A_f, Z_f, Ex_f, p_f), Ex_casc = the given excitation, n_sec
+ * = fragments emitted, n_coll = n_retry = 0.  Fragments go to the secondary
+ * arrays with stage 1 and sec_event = i, in emission order within a nucleus.
+ * A nucleus outside those ranges, or with a non-finite momentum, is not
+ * evaporated: its residual is all zero with flags 0x8000 and it is counted
+ * in counters[1].  Capacity overflow behaves as in inc_simulate_dev.  Uses
+ * the context's hand-over buffer: calls on one context must not overlap
+ * on the device with each other or with inc_simulate_dev.
+ * Returns INC_ERR_ARG for a NULL context, input or output pointer, n out of
+ * range or secondary arrays missing while sec_capacity > 0; INC_ERR_OOM /
+ * INC_ERR_DEVICE if a buffer cannot be grown or a launch fails. */
+int inc_evaporate_dev(inc_ctx* ctx, const inc_excited* in, const inc_output* out, void* stream);
+
 /* Convenience form (the spec call shape): synchronous, host arrays.
  * energies_MeV: host, n_events floats.  Results are copied to host arrays
  * res (n_events) and the secondary arrays (sec_capacity each); *n_sec

@@ -183,6 +183,40 @@ class Context:
                    "inc_simulate_dev")
         return out
 
+    def evaporate(self, A, Z, Ex, seed: int, P=None, first_event_id: int = 0, out: Optional[DeviceOutput] = None,
+                  capacity: Optional[int] = None, stream=None) -> DeviceOutput:
+        """Evaporate given excited nuclei asynchronously (inc_evaporate_dev).
+        A, Z: int16 or uint16 CUDA tensors; Ex: float32 CUDA tensor (MeV);
+        P: float32 CUDA tensor of shape (n, 3) (MeV/c) or None (at rest)."""
+        torch = _torch()
+        n = int(Ex.shape[0]) if torch.is_tensor(Ex) else -1
+        for name, t, dts in (("A", A, (torch.int16, torch.uint16)), ("Z", Z, (torch.int16, torch.uint16)),
+                             ("Ex", Ex, (torch.float32,))):
+            if not (torch.is_tensor(t) and t.is_cuda and t.dtype in dts and t.is_contiguous() and t.dim() == 1
+                    and int(t.shape[0]) == n):
+                raise TypeError("%s must be a contiguous 1-D CUDA tensor of %s and len(Ex)" % (name, dts))
+        if P is not None and not (torch.is_tensor(P) and P.is_cuda and P.dtype == torch.float32 and P.is_contiguous()
+                                  and tuple(P.shape) == (n, 3)):
+            raise TypeError("P must be a contiguous float32 CUDA tensor of shape (len(Ex), 3)")
+        if out is None:
+            cap = min(self.max_A + 1, 4 + self.max_A // 4) * n + 4096 if capacity is None else capacity
+            out = DeviceOutput.allocate(n, cap, Ex.device)
+        elif out.n < n:
+            raise ValueError("output buffers hold %d nuclei, batch has %d" % (out.n, n))
+        x = _lib.Excited()
+        x.n = n
+        x.A = A.data_ptr()
+        x.Z = Z.data_ptr()
+        x.Ex = Ex.data_ptr()
+        x.P = P.data_ptr() if P is not None else None
+        x.seed = int(seed)
+        x.first_event_id = int(first_event_id)
+        o = out.c_struct(capacity)
+        s = stream if stream is not None else torch.cuda.current_stream()
+        _lib.check(_lib.load().inc_evaporate_dev(self._h, C.byref(x), C.byref(o), C.c_void_p(s.cuda_stream)),
+                   "inc_evaporate_dev")
+        return out
+
 
     def tally_shape(self):
         """(n_targets, amax, zmax) of the residual-nuclide table (inc_ctx_tally_shape)."""

@@ -24,7 +24,7 @@ MODE_STAGED = 2
 # exported symbols, in the order include/inc.h declares them
 SYMBOLS = (
     "inc_strerror", "inc_ctx_create", "inc_ctx_destroy", "inc_ctx_tables",
-    "inc_simulate_dev", "inc_simulate", "inc_server_create", "inc_server_destroy",
+    "inc_simulate_dev", "inc_evaporate_dev", "inc_simulate", "inc_server_create", "inc_server_destroy",
     "inc_server_submit", "inc_server_poll", "inc_server_wait", "inc_server_fetch",
     "inc_server_stats_get", "inc_server_replay", "inc_ring_create", "inc_ring_destroy",
     "inc_ring_simulate", "inc_ctx_tally_shape", "inc_tally_residuals", "inc_contract_version",
@@ -59,6 +59,13 @@ class Output(C.Structure):
 class Batch(C.Structure):
     _fields_ = [
         ("n", C.c_size_t), ("target_idx", C.c_void_p), ("T0", C.c_void_p),
+        ("seed", C.c_uint64), ("first_event_id", C.c_uint64),
+    ]
+
+
+class Excited(C.Structure):
+    _fields_ = [
+        ("n", C.c_size_t), ("A", C.c_void_p), ("Z", C.c_void_p), ("Ex", C.c_void_p), ("P", C.c_void_p),
         ("seed", C.c_uint64), ("first_event_id", C.c_uint64),
     ]
 
@@ -137,6 +144,8 @@ def load():
         L.inc_ctx_tables.restype = C.c_int
         L.inc_simulate_dev.argtypes = [C.c_void_p, C.POINTER(Batch), C.POINTER(Output), C.c_void_p, C.c_int]
         L.inc_simulate_dev.restype = C.c_int
+        L.inc_evaporate_dev.argtypes = [C.c_void_p, C.POINTER(Excited), C.POINTER(Output), C.c_void_p]
+        L.inc_evaporate_dev.restype = C.c_int
         L.inc_simulate.argtypes = [
             C.c_int, C.c_int, C.c_void_p, C.c_size_t, C.c_uint64, C.c_void_p,
             C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,

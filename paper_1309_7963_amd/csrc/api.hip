@@ -45,41 +45,23 @@ void release(inc_ctx* c) {
   delete c;
 }
 
-}  // namespace
 
-int inc_launch_segments(inc_ctx* ctx, size_t n, const uint8_t* tidx, const float* T0, const Segment* d_segs,
-                        int n_seg, uint64_t seed, unsigned long long* queue, hipStream_t s, int mode, int max_blocks,
-                        const RingDev* ring, MidState* mid) {
-  if (!mid && (mode == INC_MODE_PLAIN || mode == INC_MODE_STAGED) && ctx->mid_cap < n) {
-    if (ctx->d_mid) (void)hipFree(ctx->d_mid);
-    ctx->d_mid = nullptr;
-    ctx->mid_cap = 0;
-    hipError_t e = hipMalloc(&ctx->d_mid, mid_bytes(n));
-    if (e != hipSuccess) return map_err(e);
-    ctx->mid_cap = n;
-  }
-  // the context's own persistent launches start their costliest events first
-  const uint32_t* perm = nullptr;
-  if (!mid && (mode == INC_MODE_PERSISTENT || mode == INC_MODE_STAGED) && n >= kOrderMin && !ctx->opt.input_order) {
-    hipError_t e = hipSuccess;
-    if (!ctx->d_order_hist) e = hipMalloc(&ctx->d_order_hist, sizeof(uint32_t) * kOrderHist);
-    if (e == hipSuccess && ctx->perm_cap < n) {
-      if (ctx->d_perm) (void)hipFree(ctx->d_perm);
-      ctx->d_perm = nullptr;
-      ctx->perm_cap = 0;
-      e = hipMalloc(&ctx->d_perm, sizeof(uint32_t) * n);
-      if (e == hipSuccess) ctx->perm_cap = n;
-    }
-    if (e == hipSuccess)
-      e = inc_launch_order(T0, tidx, n, ctx->d_nuc, ctx->n_targets, ctx->order_inv_cmax, ctx->d_order_hist,
-                           ctx->d_perm, s);
-    if (e != hipSuccess) return map_err(e);
-    perm = ctx->d_perm;
-  }
+// The context's hand-over buffer, grown to n events.
+hipError_t ensure_mid(inc_ctx* ctx, size_t n) {
+  if (ctx->mid_cap >= n) return hipSuccess;
+  if (ctx->d_mid) (void)hipFree(ctx->d_mid);
+  ctx->d_mid = nullptr;
+  ctx->mid_cap = 0;
+  hipError_t e = hipMalloc(&ctx->d_mid, mid_bytes(n));
+  if (e == hipSuccess) ctx->mid_cap = n;
+  return e;
+}
+
+// Launch policy and resident tables of a launch of n events.
+LaunchDesc launch_desc(const inc_ctx* ctx, size_t n, int mode, int max_blocks) {
   LaunchDesc L;
   memset(&L, 0, sizeof(L));
   L.mode = mode;
-  L.perm = perm;
   L.block = ctx->block;
   L.persistent_blocks = ctx->n_cu * ctx->waves_per_cu / (ctx->block / 64);
   if (max_blocks > 0 && max_blocks < L.persistent_blocks) L.persistent_blocks = max_blocks;
@@ -103,6 +85,63 @@ int inc_launch_segments(inc_ctx* ctx, size_t n, const uint8_t* tidx, const float
   L.opt = ctx->opt;
   L.fixed_b_set = ctx->fixed_b_set;
   L.n = n;
+  return L;
+}
+
+// One segment covering a whole batch with the caller's output buffers.
+Segment batch_segment(const inc_output* out, size_t n, uint64_t first_event_id) {
+  Segment seg;
+  seg.start = 0;
+  seg.n = (uint32_t)n;
+  seg.first_id = first_event_id;
+  seg.res = out->res;
+  seg.ev = out->sec_event;
+  seg.species = out->sec_species;
+  seg.stage = out->sec_stage;
+  seg.T = out->sec_T;
+  seg.ux = out->sec_ux;
+  seg.uy = out->sec_uy;
+  seg.uz = out->sec_uz;
+  seg.cap = out->sec_capacity;
+  seg.counters = out->counters;
+  return seg;
+}
+
+bool valid_output(const inc_output* out) {
+  if (!out || !out->res || !out->counters) return false;
+  return !(out->sec_capacity && (!out->sec_event || !out->sec_species || !out->sec_stage || !out->sec_T ||
+                                 !out->sec_ux || !out->sec_uy || !out->sec_uz));
+}
+
+}  // namespace
+
+int inc_launch_segments(inc_ctx* ctx, size_t n, const uint8_t* tidx, const float* T0, const Segment* d_segs,
+                        int n_seg, uint64_t seed, unsigned long long* queue, hipStream_t s, int mode, int max_blocks,
+                        const RingDev* ring, MidState* mid) {
+  if (!mid && (mode == INC_MODE_PLAIN || mode == INC_MODE_STAGED)) {
+    const hipError_t e = ensure_mid(ctx, n);
+    if (e != hipSuccess) return map_err(e);
+  }
+  // the context's own persistent launches start their costliest events first
+  const uint32_t* perm = nullptr;
+  if (!mid && (mode == INC_MODE_PERSISTENT || mode == INC_MODE_STAGED) && n >= kOrderMin && !ctx->opt.input_order) {
+    hipError_t e = hipSuccess;
+    if (!ctx->d_order_hist) e = hipMalloc(&ctx->d_order_hist, sizeof(uint32_t) * kOrderHist);
+    if (e == hipSuccess && ctx->perm_cap < n) {
+      if (ctx->d_perm) (void)hipFree(ctx->d_perm);
+      ctx->d_perm = nullptr;
+      ctx->perm_cap = 0;
+      e = hipMalloc(&ctx->d_perm, sizeof(uint32_t) * n);
+      if (e == hipSuccess) ctx->perm_cap = n;
+    }
+    if (e == hipSuccess)
+      e = inc_launch_order(T0, tidx, n, ctx->d_nuc, ctx->n_targets, ctx->order_inv_cmax, ctx->d_order_hist,
+                           ctx->d_perm, s);
+    if (e != hipSuccess) return map_err(e);
+    perm = ctx->d_perm;
+  }
+  LaunchDesc L = launch_desc(ctx, n, mode, max_blocks);
+  L.perm = perm;
   L.tidx = tidx;
   L.T0 = T0;
   L.segs = d_segs;
@@ -115,27 +154,10 @@ int inc_launch_segments(inc_ctx* ctx, size_t n, const uint8_t* tidx, const float
 }
 
 int inc_launch_batch(inc_ctx* ctx, const inc_batch* b, const inc_output* out, hipStream_t s, int mode, int max_blocks) {
-  if (!ctx || !b || !out) return INC_ERR_ARG;
+  if (!ctx || !b || !valid_output(out)) return INC_ERR_ARG;
   if (mode != INC_MODE_PLAIN && mode != INC_MODE_PERSISTENT && mode != INC_MODE_STAGED) return INC_ERR_ARG;
   if (b->n < 1 || b->n >= (1ull << 32) || !b->T0) return INC_ERR_ARG;
-  if (!out->res || !out->counters) return INC_ERR_ARG;
-  if (out->sec_capacity && (!out->sec_event || !out->sec_species || !out->sec_stage || !out->sec_T ||
-                            !out->sec_ux || !out->sec_uy || !out->sec_uz))
-    return INC_ERR_ARG;
-  Segment seg;
-  seg.start = 0;
-  seg.n = (uint32_t)b->n;
-  seg.first_id = b->first_event_id;
-  seg.res = out->res;
-  seg.ev = out->sec_event;
-  seg.species = out->sec_species;
-  seg.stage = out->sec_stage;
-  seg.T = out->sec_T;
-  seg.ux = out->sec_ux;
-  seg.uy = out->sec_uy;
-  seg.uz = out->sec_uz;
-  seg.cap = out->sec_capacity;
-  seg.counters = out->counters;
+  const Segment seg = batch_segment(out, b->n, b->first_event_id);
   Segment* slot = ctx->d_segs + (ctx->seg_next++ % kSegSlots);
   const int rc = map_err(inc_upload_segment(seg, slot, s));
   if (rc) return rc;
@@ -283,6 +305,25 @@ int inc_ctx_tables(const inc_ctx* ctx, float* host_out) {
 
 int inc_simulate_dev(inc_ctx* ctx, const inc_batch* b, const inc_output* out, void* stream, int mode) {
   return inc_launch_batch(ctx, b, out, (hipStream_t)stream, mode, 0);
+}
+
+int inc_evaporate_dev(inc_ctx* ctx, const inc_excited* in, const inc_output* out, void* stream) {
+  if (!ctx || !in || !valid_output(out)) return INC_ERR_ARG;
+  if (in->n < 1 || in->n >= (1ull << 32) || !in->A || !in->Z || !in->Ex) return INC_ERR_ARG;
+  const hipStream_t s = (hipStream_t)stream;
+  hipError_t e = ensure_mid(ctx, in->n);
+  if (e != hipSuccess) return map_err(e);
+  Segment* slot = ctx->d_segs + (ctx->seg_next++ % kSegSlots);
+  e = inc_upload_segment(batch_segment(out, in->n, in->first_event_id), slot, s);
+  if (e != hipSuccess) return map_err(e);
+  LaunchDesc L = launch_desc(ctx, in->n, INC_MODE_STAGED, 0);
+  L.segs = slot;
+  L.n_seg = 1;
+  L.seed = in->seed;
+  L.queue = out->counters + 2;
+  L.mid = ctx->d_mid;
+  const ExcitedDesc x = {in->A, in->Z, in->Ex, in->P};
+  return map_err(ctx->opt.fast_math ? fast::launch_evaporation(L, x, s) : precise::launch_evaporation(L, x, s));
 }
 
 int inc_simulate(int target_A, int target_Z, const float* energies, size_t n, uint64_t seed, inc_residual* res,

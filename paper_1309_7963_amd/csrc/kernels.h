@@ -61,6 +61,16 @@ struct LaunchDesc {
   RingDev ring;          // rec == NULL: records go to the segments' arrays
 };
 
+// Excited nuclei of an evaporation-only launch (device arrays, see
+// inc_excited).
+struct ExcitedDesc {
+  const uint16_t* A;
+  const uint16_t* Z;
+  const float* Ex;
+  const float* P;  // 3 per nucleus, or NULL (at rest)
+};
+constexpr float kMaxExcitation = 500.0f;  // MeV
+
 // The event kernels exist in two builds of one source (kernels.hip): IEEE
 // arithmetic and precise transcendentals (precise, the default) and the
 // fast-math build (fast, Sec. 4.2).  Each namespace provides:
@@ -72,17 +82,21 @@ struct LaunchDesc {
 //   evap_blocks_per_cu  resident blocks per CU of the staged evaporation
 //                 kernel (its own occupancy: it needs fewer registers);
 //   launch_events zero the counters, then launch the event kernel(s) of L.mode.
+//   launch_evaporation  evaporation alone of L.n given excited nuclei
+//                 (L.mid: the hand-over buffer; L.T0, L.tidx unused).
 namespace precise {
 size_t lds_bytes(int n_targets, int block, bool with_xs, int stack_levels);
 int stack_levels(int mode, int n_targets, int block, int waves_per_cu);
 int evap_blocks_per_cu(int block);
 hipError_t launch_events(const LaunchDesc& L, hipStream_t s);
+hipError_t launch_evaporation(const LaunchDesc& L, const ExcitedDesc& x, hipStream_t s);
 }  // namespace precise
 namespace fast {
 size_t lds_bytes(int n_targets, int block, bool with_xs, int stack_levels);
 int stack_levels(int mode, int n_targets, int block, int waves_per_cu);
 int evap_blocks_per_cu(int block);
 hipError_t launch_events(const LaunchDesc& L, hipStream_t s);
+hipError_t launch_evaporation(const LaunchDesc& L, const ExcitedDesc& x, hipStream_t s);
 }  // namespace fast
 
 }  // namespace incdev

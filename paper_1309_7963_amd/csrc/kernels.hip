@@ -553,6 +553,49 @@ __global__ void __launch_bounds__(256) k_evap_persistent(KernelArgs a) {
   writer_flush(wbuf, fill, a.segs, a.ring);
 }
 
+// Evaporation alone (Sec. 2.4) of given excited nuclei: each nucleus becomes a
+// hand-over record with no draws consumed, so it evaporates on its event's
+// stream from the first draw, and every chunk of the launch is listed for the
+// evaporation kernel.  A nucleus outside the tables' (A, Z) range, with an
+// excitation outside [0, kMaxExcitation] or a non-finite momentum is final
+// at once, flagged out of range.
+__global__ void k_excited_setup(KernelArgs a, ExcitedDesc x) {
+  const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  uint32_t* left = (uint32_t*)(a.mid + a.n);
+  if (i == 0) {
+    left[0] = (uint32_t)((a.n + kChunk - 1) / kChunk);
+    left[1] = 0u;
+  }
+  if (i >= a.n) return;
+  if (i % kChunk == 0) left[4 + i / kChunk] = (uint32_t)i;
+  const int A = x.A[i], Z = x.Z[i];
+  const float E = x.Ex[i];
+  float P[3] = {0.0f, 0.0f, 0.0f};
+  if (x.P) {
+    P[0] = x.P[3 * i];
+    P[1] = x.P[3 * i + 1];
+    P[2] = x.P[3 * i + 2];
+  }
+  const bool ok = A >= 1 && A <= a.bind.amax && Z <= A && Z <= a.bind.zmax && E >= 0.0f && E <= kMaxExcitation &&
+                  isfinite(P[0]) && isfinite(P[1]) && isfinite(P[2]);
+  MidState m = {};
+  if (ok) {
+    m.A = (int16_t)A;
+    m.Z = (int16_t)Z;
+    m.E = E;
+    m.P[0] = P[0];
+    m.P[1] = P[1];
+    m.P[2] = P[2];
+  } else {
+    m.flags = kFlagRange | kMidFinal;
+    const EventRef er = event_ref(a, i);
+    const Nucleus z = {0, 0, 0.0f, {0.0f, 0.0f, 0.0f}};
+    write_residual(a.segs[er.seg].res + er.local, z, 0.0f, 0, kFlagRange, 0, 0);
+    atomicAdd(&a.segs[er.seg].counters[1], 1ull);
+  }
+  a.mid[i] = m;
+}
+
 // Zero the segments' counters, the work-queue heads and (staged) the list of
 // chunks left to the evaporation kernel (a fill kernel rather than a memset,
 // so the launch sequence stays capturable in a graph).
@@ -609,7 +652,7 @@ int evap_blocks_per_cu(int block) {
   return occ;
 }
 
-hipError_t launch_events(const LaunchDesc& L, hipStream_t s) {
+static KernelArgs kernel_args(const LaunchDesc& L) {
   KernelArgs a;
   a.nuc = L.nuc;
   a.n_targets = L.n_targets;
@@ -638,6 +681,11 @@ hipError_t launch_events(const LaunchDesc& L, hipStream_t s) {
   a.mid = L.mid;
   a.ring = L.ring;
   a.stack_lds = L.stack_lds;
+  return a;
+}
+
+hipError_t launch_events(const LaunchDesc& L, hipStream_t s) {
+  const KernelArgs a = kernel_args(L);
   hipLaunchKernelGGL(k_zero_counters, dim3((L.n_seg + 63) / 64), dim3(64), 0, s, L.segs, L.n_seg, L.queue,
                      L.mode == INC_MODE_STAGED ? (uint32_t*)(L.mid + L.n) : nullptr);
   const int block = L.block;
@@ -656,6 +704,15 @@ hipError_t launch_events(const LaunchDesc& L, hipStream_t s) {
     if (L.mode == INC_MODE_STAGED)
       hipLaunchKernelGGL(k_evap_persistent, dim3(L.evap_blocks), dim3(block), lds_bytes(0, block, false, 0), s, a);
   }
+  return hipGetLastError();
+}
+
+hipError_t launch_evaporation(const LaunchDesc& L, const ExcitedDesc& x, hipStream_t s) {
+  const KernelArgs a = kernel_args(L);
+  hipLaunchKernelGGL(k_zero_counters, dim3((L.n_seg + 63) / 64), dim3(64), 0, s, L.segs, L.n_seg, L.queue,
+                     (uint32_t*)nullptr);
+  hipLaunchKernelGGL(k_excited_setup, dim3((unsigned)((L.n + 255) / 256)), dim3(256), 0, s, a, x);
+  hipLaunchKernelGGL(k_evap_persistent, dim3(L.evap_blocks), dim3(L.block), lds_bytes(0, L.block, false, 0), s, a);
   return hipGetLastError();
 }
 

@@ -83,6 +83,34 @@ def from_oracle(out, targets, T0, tidx=None) -> Events:
     )
 
 
+def evaporate_oracle(A, Z, Ex, P=None, seed: int = 1, first_id: int = 0) -> Events:
+    """Evaporation alone of nuclei (A[i], Z[i], Ex[i], P[i]) by the oracle, nucleus
+    i on the stream of (seed, first_id + i), as an Events batch (T0 = 0)."""
+    n = len(A)
+    P = np.zeros((n, 3)) if P is None else np.asarray(P, dtype=np.float64).reshape(n, 3)
+    rows, secs = [], []
+    for i in range(n):
+        r, s = oracle.evaporate(int(A[i]), int(Z[i]), float(Ex[i]), tuple(P[i]), seed=seed, event_id=first_id + i)
+        r = r.copy()
+        r["n_sec"] = len(s)
+        rows.append(r)
+        s = s.copy()
+        s["event"] = i
+        secs.append(s)
+    r = np.array(rows)
+    s = np.concatenate(secs) if secs else np.zeros(0, dtype=oracle.SECONDARY_DTYPE)
+    return Events(
+        A=np.asarray(A, dtype=np.int64), Z=np.asarray(Z, dtype=np.int64), T0=np.zeros(n),
+        A_f=r["A_f"].astype(np.int64), Z_f=r["Z_f"].astype(np.int64),
+        Ex_casc=np.asarray(Ex, dtype=np.float64), Ex_f=r["Ex_f"].astype(np.float64),
+        p_f=np.asarray(r["p_f"], dtype=np.float64), n_sec=r["n_sec"].astype(np.int64),
+        flags=r["flags"].astype(np.int64),
+        sec_event=s["event"].astype(np.int64), sec_species=s["species"].astype(np.int64),
+        sec_stage=s["stage"].astype(np.int64), sec_T=s["T"].astype(np.float64),
+        sec_u=np.asarray(s["u"], dtype=np.float64),
+    )
+
+
 def _sum_by_event(idx, w, n):
     return np.bincount(idx, weights=w, minlength=n)
 
@@ -146,8 +174,16 @@ def check(ev: Events, tol_E: float = 1e-3, tol_p: float = 1e-3, tol_u: float = 1
     out["bad_T"] = int(np.sum(T < 0))
     un = np.sqrt(np.sum(ev.sec_u ** 2, axis=1))
     out["bad_u"] = int(np.sum(np.abs(un - 1.0) > tol_u))
-    # no open channel is left: E*_f < S_j + V_j for every valid channel
-    bad_thr = np.zeros(n, dtype=bool)
+    out["bad_threshold"] = _open_channel_left(ev, B)
+    out["n_events"] = n
+    out["n_secondaries"] = int(e.shape[0])
+    return out
+
+
+def _open_channel_left(ev: Events, B) -> int:
+    """Events whose final nucleus still has an open channel: E*_f >= S_j + V_j
+    for some valid channel j (beyond 1e-4 MeV of FP32 slack)."""
+    bad_thr = np.zeros(ev.n, dtype=bool)
     Af, Zf = ev.A_f, ev.Z_f
     for j in range(6):
         Ad = Af - FRAG_A[j]
@@ -161,7 +197,52 @@ def check(ev: Events, tol_E: float = 1e-3, tol_p: float = 1e-3, tol_u: float = 1
             0.0,
         )
         bad_thr |= valid & (ev.Ex_f - S - V > 1e-4) & (ev.flags & 4 == 0)
-    out["bad_threshold"] = int(np.sum(bad_thr))
+    return int(np.sum(bad_thr))
+
+
+def check_evaporation(ev: Events, P_in, tol_E: float = 1e-3, tol_p: float = 1e-3, tol_u: float = 1e-5) -> dict:
+    """Per-nucleus checks of an evaporation-only batch (Sec. 2.4): nucleus i,
+    (A, Z) with excitation Ex_casc and lab momentum P_in[i], decays into its
+    records (all stage 1) and the final nucleus.
+
+    * integers: A_f + sum a_k = A, Z_f + sum z_k = Z, records = n_sec;
+    * energy: sqrt(P^2 + (M(A,Z) + E*)^2) = sum (T_k + m_k) + sqrt(p_f^2 + (M_f + E*_f)^2);
+    * momentum: P = sum p_k + p_f;
+    * E*_f >= 0, T >= 0, |u| = 1, and no channel left open."""
+    M, B = mass_table()
+    n = ev.n
+    e = ev.sec_event
+    sp = ev.sec_species
+    a_k = FRAG_A[sp]
+    z_k = FRAG_Z[sp]
+    m_k = M[a_k, z_k]
+    T = ev.sec_T
+    pk = ev.sec_u * np.sqrt(T * T + 2.0 * T * m_k)[:, None]
+    P_in = np.asarray(P_in, dtype=np.float64).reshape(n, 3)
+    out = {}
+    cnt = np.bincount(e, minlength=n)
+    sumA = _sum_by_event(e, a_k.astype(np.float64), n).round().astype(np.int64)
+    sumZ = _sum_by_event(e, z_k.astype(np.float64), n).round().astype(np.int64)
+    out["bad_A"] = int(np.sum(ev.A_f + sumA != ev.A))
+    out["bad_Z"] = int(np.sum(ev.Z_f + sumZ != ev.Z))
+    out["bad_nsec"] = int(np.sum(cnt != ev.n_sec))
+    out["bad_stage"] = int(np.sum(ev.sec_stage != 1))
+    E_before = np.sqrt(np.sum(P_in ** 2, axis=1) + (M[ev.A, ev.Z] + ev.Ex_casc) ** 2)
+    E_evap = _sum_by_event(e, T + m_k, n)
+    Mf = M[np.clip(ev.A_f, 0, None), np.clip(ev.Z_f, 0, None)]
+    E_after = np.sqrt(np.sum(ev.p_f ** 2, axis=1) + (Mf + ev.Ex_f) ** 2)
+    E2 = E_before - E_evap - E_after
+    out["max_E2"] = float(np.max(np.abs(E2))) if n else 0.0
+    out["bad_E2"] = int(np.sum(np.abs(E2) > tol_E))
+    ptot = np.stack([_sum_by_event(e, pk[:, c], n) for c in range(3)], axis=1) + ev.p_f - P_in
+    P = np.sqrt(np.sum(ptot ** 2, axis=1))
+    out["max_P"] = float(np.max(P)) if n else 0.0
+    out["bad_P"] = int(np.sum(P > tol_p))
+    out["bad_Ex"] = int(np.sum(ev.Ex_f < 0))
+    out["bad_T"] = int(np.sum(T < 0))
+    un = np.sqrt(np.sum(ev.sec_u ** 2, axis=1))
+    out["bad_u"] = int(np.sum(np.abs(un - 1.0) > tol_u))
+    out["bad_threshold"] = _open_channel_left(ev, B)
     out["n_events"] = n
     out["n_secondaries"] = int(e.shape[0])
     return out

@@ -5,6 +5,7 @@ special cases with textbook answers, and conservation laws.
 Each test names the passage of arXiv:1309.7963 (or the reading of it) that
 the pinned function implements.
 """
+import dataclasses
 import math
 import os
 
@@ -12,8 +13,9 @@ import numpy as np
 import pytest
 from scipy import integrate, stats
 
-import oracle
+import evap_ref
 import ledger
+import oracle
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 M_P, M_N = 938.272088, 939.565420
@@ -411,17 +413,9 @@ def test_spectrum_sampler_histogram(a, U):
     assert stats.kstest(xs, lambda v: np.array([oracle.spectrum_cdf(a, U, t) for t in np.atleast_1d(v)])).pvalue > 1e-3
 
 
-def _threshold(A, Z, j):
-    a, z = ledger.FRAG_A[j], ledger.FRAG_Z[j]
-    Ad, Zd = A - a, Z - z
-    Q = oracle.mass(Ad, Zd) + oracle.mass(a, z) - oracle.mass(A, Z)
-    V = 1.44 * z * Zd / (1.5 * (Ad ** (1 / 3) + a ** (1 / 3))) if z else 0.0
-    return Q + V
-
-
 def test_emission_thresholds():
     A, Z = 16, 8
-    thr = [_threshold(A, Z, j) for j in range(6)]
+    thr = [evap_ref.threshold(A, Z, j) for j in range(6)]
     lowest = min(thr)
     r, s = oracle.evaporate(A, Z, lowest - 1e-6, seed=1)
     assert len(s) == 0 and r["A_f"] == A and r["Ex_f"] == pytest.approx(lowest - 1e-6)
@@ -449,24 +443,40 @@ def test_evaporation_ledger_at_fixed_excitation():
             assert r["A_f"] + ledger.FRAG_A[s["species"]].sum() == A
 
 
+def test_evaporation_batch_checks_catch_mistakes():
+    # the per-nucleus checks applied to the GPU's evaporation-only output hold
+    # on the oracle's, and each catches a mistake planted in that output
+    rng = np.random.default_rng(5)
+    n = 2000
+    A = rng.integers(5, 58, n)
+    Z = np.clip(A // 2 + rng.integers(-2, 3, n), 1, np.minimum(A - 1, 27))
+    Ex = rng.uniform(0.0, 200.0, n)
+    P = rng.normal(size=(n, 3)) * 200.0
+    ev = ledger.evaporate_oracle(A, Z, Ex, P, seed=3)
+    ledger.assert_clean(ledger.check_evaporation(ev, P, tol_E=1e-8, tol_p=1e-8))
+    k = int(np.argmax(ev.sec_T))
+    bad = dataclasses.replace(ev, sec_T=ev.sec_T.copy())
+    bad.sec_T[k] += 0.01
+    assert ledger.check_evaporation(bad, P)["bad_E2"] == 1
+    bad = dataclasses.replace(ev, sec_u=ev.sec_u.copy())
+    bad.sec_u[k] *= -1.0
+    r = ledger.check_evaporation(bad, P)
+    assert r["bad_P"] == 1 and r["bad_E2"] == 0
+    keep = np.arange(ev.sec_event.size) != k
+    fields = ("sec_event", "sec_species", "sec_stage", "sec_T", "sec_u")
+    bad = dataclasses.replace(ev, **{f: getattr(ev, f)[keep] for f in fields})
+    r = ledger.check_evaporation(bad, P)
+    assert r["bad_A"] == 1 and r["bad_nsec"] == 1 and r["bad_E2"] == 1
+    bad = dataclasses.replace(ev, Ex_f=ev.Ex_f + 30.0)
+    assert ledger.check_evaporation(bad, P)["bad_threshold"] > 0
+
+
 def test_channel_branching_matches_widths():
     # first-step channel frequencies follow Gamma_j / sum Gamma (multinomial chi-square)
     A, Z, E = 40, 20, 60.0
     n = 6000
     first = np.array([oracle.evaporate(A, Z, E, seed=4, event_id=k)[1][0]["species"] for k in range(n)])
-    w = []
-    for j in range(6):
-        a, z = ledger.FRAG_A[j], ledger.FRAG_Z[j]
-        Ad, Zd = A - a, Z - z
-        U = E - _threshold(A, Z, j)
-        Rj = 1.5 * Ad ** (1 / 3) if j <= 1 else 1.5 * (Ad ** (1 / 3) + a ** (1 / 3))
-        if U <= 0:
-            w.append(0.0)
-            continue
-        aa = Ad / 8.0
-        I = integrate.quad(lambda x: x * math.exp(2 * math.sqrt(aa * max(U - x, 0))), 0, U, epsrel=1e-12)[0]
-        w.append(ledger.FRAG_G[j] * oracle.mass(a, z) * Rj * Rj * I)
-    w = np.array(w) / sum(w)
+    w = evap_ref.branching(A, Z, E)
     obs = np.bincount(first, minlength=6)
     use = w * n >= 5
     exp = w[use] * n
