@@ -342,3 +342,18 @@ def test_evaporation_invalid_nuclei_flagged(ctx):
     empty = torch.zeros(0, dtype=torch.int16, device="cuda")
     with pytest.raises(inc.IncError):
         ctx.evaporate(empty, empty, torch.zeros(0, dtype=torch.float32, device="cuda"), seed=1)
+
+
+@pytest.mark.parametrize("n", [1, 63, 65, 257])
+def test_evaporation_ragged_batches_are_prefixes(ctx, n):
+    # nucleus i's result depends only on its stream (seed, first_event_id + i):
+    # a short batch equals the head of a longer one, whatever the chunking
+    A, Z, Ex, P = _mixture(1000, seed=29)
+    full = _run(ctx, A, Z, Ex, P, seed=12, first_id=77, raw=True)
+    part = _run(ctx, A[:n], Z[:n], Ex[:n], P[:n], seed=12, first_id=77, raw=True)
+    assert part["res"].tobytes() == full["res"][:n].tobytes()
+    keep = full["sec_event"] < n
+    oa = np.argsort(part["sec_event"], kind="stable")
+    ob = np.argsort(full["sec_event"][keep], kind="stable")
+    for f in ("sec_event", "sec_species", "sec_stage", "sec_T", "sec_u"):
+        assert np.array_equal(part[f][oa], full[f][keep][ob]), f
