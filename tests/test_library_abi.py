@@ -78,6 +78,10 @@ def test_argument_errors_before_device(lib):
     arr = (_lib.Nucleus * 1)(_lib.Nucleus(16, 8))
     assert L.inc_ctx_create(arr, 0, None, C.byref(h)) == inc.INC_ERR_ARG
     assert L.inc_simulate_dev(None, None, None, None, 0) == inc.INC_ERR_ARG
+    assert L.inc_evaporate_dev(None, None, None, None) == inc.INC_ERR_ARG
+    x = _lib.Excited()
+    x.n = 1
+    assert L.inc_evaporate_dev(None, C.byref(x), None, None) == inc.INC_ERR_ARG
     # option ranges are checked before the device is looked for
     for field, bad in (("fast_math", 2), ("same_stream", -1), ("stack_levels", 5), ("block_size", 96),
                        ("waves_per_cu", 33), ("kin_threshold", 65), ("start_threshold", 65), ("input_order", 2)):
