@@ -450,7 +450,7 @@ def main(argv=None):
                 tuned = autotune.tune(w["targets"], w["T0"], w["tidx"], use_cache=False)
                 e = _time_gpu(w, args.mode, 5, 1, **tuned["options"])
                 p = _time_gpu(w, "plain", 3, 1)
-                extra[key].update(tuned_options=tuned["options"], tuned_events_per_s=rate(e),
+                extra[key].update(tuned_options=tuned["options"] or "library default", tuned_events_per_s=rate(e),
                                   plain_events_per_s=rate(p), autotune_sweep_s=tuned["sweep_s"])
             print("bench: %s done" % key, file=sys.stderr, flush=True)
         e = _time_gpu(main_w, "plain", 3, 1)

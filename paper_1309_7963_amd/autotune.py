@@ -5,9 +5,13 @@ block size (waves per workgroup), resident waves per CU (events in flight)
 and the per-state lane thresholds of the wave scheduler (how many lanes must
 wait in the kinematics, tentative-collision or flight-start state before the
 wave runs that state).  Each candidate is timed on the caller's workload with
-HIP events (a warm-up launch, then the median of `repeats` launches), the
-three fastest again with twice the launches; the best is cached in a JSON file keyed by GPU architecture and workload
-signature (targets, energy range), so later contexts can reuse it.
+HIP events (a warm-up launch, then the median of `repeats` launches).  The
+three fastest and the library's default policy are then re-timed in
+interleaved rounds, and a candidate replaces the default only if it is faster
+by more than `margin` (launch times drift by a few per cent, so a noisy
+winner would otherwise make the launch slower).  The result (options {} =
+the library default) is cached in a JSON file keyed by GPU architecture and
+workload signature (targets, energy range), so later contexts can reuse it.
 
     from paper_1309_7963_amd import autotune
     best = autotune.tune([(16, 8), (40, 20)], T0, tidx)
@@ -70,9 +74,10 @@ def _time(targets, T0_d, tidx_d, opts, repeats, mode):
 
 
 def tune(targets, T0, tidx=None, grid: Optional[dict] = None, repeats: int = 3, use_cache: bool = True,
-         verbose: bool = False, mode: str = "staged") -> dict:
-    """Return {"options": {...}, "ms": best, "table": [...]} for the workload
-    (T0: host float32 array, tidx: host uint8 array or None)."""
+         verbose: bool = False, mode: str = "staged", rounds: int = 3, margin: float = 0.02) -> dict:
+    """Return {"options": {...}, "ms": best, "default_ms": ..., "table": [...]}
+    for the workload (T0: host float32 array, tidx: host uint8 array or
+    None); options {} means the library default was kept."""
     import torch
 
     grid = grid or DEFAULT_GRID
@@ -101,15 +106,23 @@ def tune(targets, T0, tidx=None, grid: Optional[dict] = None, repeats: int = 3, 
                 if verbose:
                     print("autotune", opts, "%.3f ms" % ms, flush=True)
     # launch times vary by a few per cent: re-time the three best candidates
-    # with twice the launches and keep the fastest
+    # and the library default in interleaved rounds; a candidate replaces the
+    # default only if it is faster by more than `margin`
     finalists = sorted(table, key=lambda r: r["ms"])[:3]
-    for r in finalists:
-        r["ms_final"] = _time(targets, T0_d, tidx_d, r["options"], 2 * repeats, mode)
+    default = dict(options={})
+    samples = {id(r): [] for r in finalists + [default]}
+    for _ in range(rounds):
+        for r in finalists + [default]:
+            samples[id(r)].append(_time(targets, T0_d, tidx_d, r["options"], repeats, mode))
+    for r in finalists + [default]:
+        r["ms_final"] = float(np.median(samples[id(r)]))
         if verbose:
-            print("autotune final", r["options"], "%.3f ms" % r["ms_final"], flush=True)
+            print("autotune final", r["options"] or "library default", "%.3f ms" % r["ms_final"], flush=True)
     best = min(finalists, key=lambda r: r["ms_final"])
-    result = {"options": best["options"], "ms": best["ms_final"], "events": int(len(T0)),
-              "sweep_s": time.perf_counter() - t0, "table": table}
+    if best["ms_final"] > default["ms_final"] * (1.0 - margin):
+        best = default
+    result = {"options": best["options"], "ms": best["ms_final"], "default_ms": default["ms_final"],
+              "events": int(len(T0)), "sweep_s": time.perf_counter() - t0, "table": table}
     if use_cache:
         cache[key] = result
         try:

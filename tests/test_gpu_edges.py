@@ -100,9 +100,11 @@ def test_autotuned_policy_changes_speed_not_results():
     grid = {"block_size": (128, 256), "waves_per_cu": (8, 12), "thresholds": ((24, 24, 8), (16, 8, 8))}
     best = autotune.tune(targets, T0, tidx, grid=grid, repeats=2, use_cache=False)
     opts = best["options"]
-    assert opts["block_size"] in grid["block_size"] and opts["waves_per_cu"] in grid["waves_per_cu"]
-    assert (opts["kin_threshold"], opts["tent_threshold"], opts["start_threshold"]) in grid["thresholds"]
-    assert len(best["table"]) == 8 and best["ms"] > 0
+    if opts:  # else the library default was kept (no candidate was clearly faster)
+        assert opts["block_size"] in grid["block_size"] and opts["waves_per_cu"] in grid["waves_per_cu"]
+        assert (opts["kin_threshold"], opts["tent_threshold"], opts["start_threshold"]) in grid["thresholds"]
+        assert best["ms"] < best["default_ms"]
+    assert len(best["table"]) == 8 and best["ms"] > 0 and best["default_ms"] > 0
     ref = run_gpu(targets, T0, seed=4, tidx=tidx, mode="staged")
     for cand in best["table"]:
         h = run_gpu(targets, T0, seed=4, tidx=tidx, mode="staged", **cand["options"])
