@@ -204,7 +204,9 @@ typedef struct {            /* all arrays are device memory                  */
  * arrays with stage 1 and sec_event = i, in emission order within a nucleus.
  * A nucleus outside those ranges, or with a non-finite momentum, is not
  * evaporated: its residual is all zero with flags 0x8000 and it is counted
- * in counters[1].  Capacity overflow behaves as in inc_simulate_dev.  Uses
+ * in counters[1].  Capacity overflow behaves as in inc_simulate_dev.  Of the
+ * context's options, fast_math and same_stream apply; no_evaporation (a
+ * cascade hook) does not.  Uses
  * the context's hand-over buffer: calls on one context must not overlap
  * on the device with each other or with inc_simulate_dev.
  * Returns INC_ERR_ARG for a NULL context, input or output pointer, n out of
