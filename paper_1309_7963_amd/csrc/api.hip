@@ -45,7 +45,6 @@ void release(inc_ctx* c) {
   delete c;
 }
 
-
 // The context's hand-over buffer, grown to n events.
 hipError_t ensure_mid(inc_ctx* ctx, size_t n) {
   if (ctx->mid_cap >= n) return hipSuccess;
