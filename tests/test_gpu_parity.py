@@ -394,6 +394,33 @@ def test_ring_output_equals_direct_output():
     ctx.close()
 
 
+def test_chi2_implant_through_the_ring():
+    # C4: 10^6 events, 48Ti/56Fe 50/50 at U(70, 250) MeV, secondaries through a
+    # 2^20-record ring (several wraps): every event's ledgers, and GPU seed 1
+    # vs oracle seed 2 in distribution
+    import torch
+
+    import paper_1309_7963_amd as inc
+
+    n = 1_000_000
+    tidx, T0 = _mixture(n, IMPLANT, [0.5, 0.5], 70, 250, seed=33)
+    ctx = inc.Context(IMPLANT)
+    ring = inc.Ring(ctx, slots=1 << 20)
+    try:
+        r = ring.simulate(torch.as_tensor(T0, device="cuda"), seed=1, target_idx=torch.as_tensor(tidx, device="cuda"))
+    finally:
+        ring.close()
+        ctx.close()
+    assert r["rc"] == 0 and r["stats"]["producer_gave_up"] == 0
+    assert r["stats"]["wraps"] >= 5
+    h = dict(res=r["res"], sec_event=r["sec_event"], sec_species=r["sec_species"], sec_stage=r["sec_stage"],
+             sec_T=r["sec_T"], sec_u=np.stack([r["sec_ux"], r["sec_uy"], r["sec_uz"]], 1))
+    g = events_from_gpu(h, IMPLANT, T0, tidx)
+    ledger.assert_clean(ledger.check(g))
+    o, _ = _oracle_events(IMPLANT, T0, seed=2, tidx=tidx)
+    _chi2_gate(g, o, 250.0, "C4 ring")
+
+
 def test_ring_staged_mode_equals_direct_staged():
     import torch
 
