@@ -114,13 +114,15 @@ def test_chi2_paper_scale(target):
     _chi2_gate(g, o, 200.0, "C2 %s" % (target,))
 
 
-def test_chi2_mixed_persistent():
-    # C3-shaped mixture, persistent kernel
+@pytest.mark.parametrize("mode", ["plain", "persistent", "staged"])
+def test_chi2_mixed(mode):
+    # C3: 10^6 events of the tissue mixture at U(20, 250) MeV, one input array
+    # for every mode and the oracle; GPU seed 1 vs oracle seed 2
     n = 1_000_000
     tidx, T0 = _mixture(n, TISSUE, TISSUE_W, 20, 250, seed=11)
-    g = events_from_gpu(run_gpu(TISSUE, T0, seed=1, tidx=tidx, mode="persistent"), TISSUE, T0, tidx)
+    g = events_from_gpu(run_gpu(TISSUE, T0, seed=1, tidx=tidx, mode=mode), TISSUE, T0, tidx)
     o, _ = _oracle_events(TISSUE, T0, seed=2, tidx=tidx)
-    _chi2_gate(g, o, 250.0, "C3")
+    _chi2_gate(g, o, 250.0, "C3 %s" % mode)
 
 
 def test_plain_and_persistent_agree_per_event():
