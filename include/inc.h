@@ -152,6 +152,19 @@ int inc_ctx_destroy(inc_ctx* ctx);
  * (108 floats per target).  host_out must hold 108 * n_targets floats. */
 int inc_ctx_tables(const inc_ctx* ctx, float* host_out);
 
+/* Copy the context's NN elastic table (Sec. 2.3: the cross-sections, their
+ * majorant and the slope of the angular distribution, tabulated for the
+ * flights and collisions) to host memory.  *n_nodes receives the number of
+ * nodes N and *p_lo, *p_hi the grid's ends (GeV/c): node k sits at
+ * p_lab = p_lo (p_hi / p_lo)^(k / (N - 1)), kernels interpolate linearly in
+ * log p_lab and clamp outside [p_lo, p_hi].  host_out (NULL: only the sizes
+ * are returned) must hold 6 N floats: sigma (mb) of unlike then like pairs,
+ * the suffix maximum of sigma over the nodes (the flight majorant) of unlike
+ * then like pairs, the slope b ((GeV/c)^-2) of unlike then like pairs.  With
+ * const_sigma_mb set, both sigma columns and their maxima hold that value.
+ * Synchronous.  Returns INC_ERR_ARG for a NULL context or out-param. */
+int inc_ctx_xs_table(const inc_ctx* ctx, float* host_out, int* n_nodes, float* p_lo, float* p_hi);
+
 /* Launch modes */
 #define INC_MODE_PLAIN 0      /* one event per thread; cascade kernel then
                                  evaporation kernel (the paper's Sec. 3 shape) */

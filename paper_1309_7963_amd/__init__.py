@@ -144,6 +144,21 @@ class Context:
         _lib.check(_lib.load().inc_ctx_tables(self._h, out.ctypes.data), "inc_ctx_tables")
         return out
 
+    def xs_table(self) -> dict:
+        """The context's NN elastic table (inc_ctx_xs_table): node momenta
+        p_lab (GeV/c, float64 from the float32 grid ends) and per column
+        (unlike, like) sigma (mb), its suffix maximum and the slope b."""
+        L = _lib.load()
+        n, lo, hi = C.c_int(), C.c_float(), C.c_float()
+        _lib.check(L.inc_ctx_xs_table(self._h, None, C.byref(n), C.byref(lo), C.byref(hi)), "inc_ctx_xs_table")
+        buf = np.zeros(6 * n.value, dtype=np.float32)
+        _lib.check(L.inc_ctx_xs_table(self._h, buf.ctypes.data, C.byref(n), C.byref(lo), C.byref(hi)),
+                   "inc_ctx_xs_table")
+        t = buf.reshape(3, 2, n.value)
+        k = np.arange(n.value, dtype=np.float64)
+        p = float(lo.value) * np.exp(np.log(float(hi.value) / float(lo.value)) * k / (n.value - 1))
+        return dict(p=p, p_lo=float(lo.value), p_hi=float(hi.value), sigma=t[0], sigma_max=t[1], slope=t[2])
+
     def default_capacity(self, n: int) -> int:
         """Secondary records to allocate for n events: above the mean
         multiplicity of every real target up to 250 MeV (about 4.6 for 16O,

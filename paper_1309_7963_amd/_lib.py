@@ -23,7 +23,7 @@ MODE_STAGED = 2
 
 # exported symbols, in the order include/inc.h declares them
 SYMBOLS = (
-    "inc_strerror", "inc_ctx_create", "inc_ctx_destroy", "inc_ctx_tables",
+    "inc_strerror", "inc_ctx_create", "inc_ctx_destroy", "inc_ctx_tables", "inc_ctx_xs_table",
     "inc_simulate_dev", "inc_evaporate_dev", "inc_simulate", "inc_server_create", "inc_server_destroy",
     "inc_server_submit", "inc_server_poll", "inc_server_wait", "inc_server_fetch",
     "inc_server_stats_get", "inc_server_replay", "inc_ring_create", "inc_ring_destroy",
@@ -142,6 +142,9 @@ def load():
         L.inc_ctx_destroy.restype = C.c_int
         L.inc_ctx_tables.argtypes = [C.c_void_p, C.c_void_p]
         L.inc_ctx_tables.restype = C.c_int
+        L.inc_ctx_xs_table.argtypes = [C.c_void_p, C.c_void_p, C.POINTER(C.c_int), C.POINTER(C.c_float),
+                                       C.POINTER(C.c_float)]
+        L.inc_ctx_xs_table.restype = C.c_int
         L.inc_simulate_dev.argtypes = [C.c_void_p, C.POINTER(Batch), C.POINTER(Output), C.c_void_p, C.c_int]
         L.inc_simulate_dev.restype = C.c_int
         L.inc_evaporate_dev.argtypes = [C.c_void_p, C.POINTER(Excited), C.POINTER(Output), C.c_void_p]

@@ -302,6 +302,16 @@ int inc_ctx_tables(const inc_ctx* ctx, float* host_out) {
   return INC_OK;
 }
 
+int inc_ctx_xs_table(const inc_ctx* ctx, float* host_out, int* n_nodes, float* p_lo, float* p_hi) {
+  if (!ctx || !n_nodes || !p_lo || !p_hi) return INC_ERR_ARG;
+  static_assert(sizeof(XsTab) == sizeof(float) * 6 * kXsNodes, "six columns of kXsNodes floats");
+  *n_nodes = kXsNodes;
+  *p_lo = kPlo;
+  *p_hi = kPhi;
+  if (!host_out) return INC_OK;
+  return map_err(hipMemcpy(host_out, ctx->d_xs, sizeof(XsTab), hipMemcpyDeviceToHost));
+}
+
 int inc_simulate_dev(inc_ctx* ctx, const inc_batch* b, const inc_output* out, void* stream, int mode) {
   return inc_launch_batch(ctx, b, out, (hipStream_t)stream, mode, 0);
 }

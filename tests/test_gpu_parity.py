@@ -59,6 +59,46 @@ def test_nucleus_tables_match_oracle():
         assert tab[t, 107] == pytest.approx(nu.R, rel=1e-6)
 
 
+def test_cross_section_table_matches_oracle():
+    # the device's NN table (Sec. 2.3): node values are the oracle's closed
+    # forms rounded to FP32, the majorant column is the suffix maximum of the
+    # sigma nodes, linear interpolation in log p stays within 1e-3 of the
+    # formula at 10^4 random momenta (away from the parameterisation's one
+    # step, at 0.8 GeV/c), and the 200 MeV anchors hold
+    import paper_1309_7963_amd as inc
+
+    ctx = inc.Context([O16])
+    t = ctx.xs_table()
+    ctx.close()
+    p, N = t["p"], len(t["p"])
+    for like in (0, 1):
+        sig = t["sigma"][like].astype(np.float64)
+        assert np.allclose(sig, [oracle.sigma(like, x) for x in p], rtol=2.0 ** -22, atol=0.0)
+        assert np.allclose(t["slope"][like], [oracle.slope(like, x) for x in p], rtol=2.0 ** -22, atol=1e-6)
+        assert np.array_equal(t["sigma_max"][like], np.maximum.accumulate(t["sigma"][like][::-1])[::-1])
+        rng = np.random.default_rng(7 + like)
+        q = np.exp(rng.uniform(np.log(t["p_lo"]), np.log(t["p_hi"]), 10000))
+        x = np.log(q / t["p_lo"]) / np.log(t["p_hi"] / t["p_lo"]) * (N - 1)
+        k = np.minimum(x.astype(np.int64), N - 2)
+        f = x - k
+        interp = sig[k] + f * (sig[k + 1] - sig[k])
+        exact = np.array([oracle.sigma(like, v) for v in q])
+        away = np.abs(np.log(q / 0.8)) > np.log(t["p_hi"] / t["p_lo"]) / (N - 1)
+        rel = np.abs(interp / exact - 1.0)[away]
+        print("sigma table (like=%d): max interpolation error %.2e" % (like, rel.max()))
+        assert rel.max() < 1e-3
+    p200 = math.sqrt(200.0 ** 2 + 2 * 200.0 * ledger.M_PROTON) / 1000.0
+    x = math.log(p200 / t["p_lo"]) / math.log(t["p_hi"] / t["p_lo"]) * (N - 1)
+    k = int(x)
+    at = lambda col: float(col[k] + (x - k) * (col[k + 1] - col[k]))
+    assert at(t["sigma"][1]) == pytest.approx(23.5, abs=0.05)
+    assert at(t["sigma"][0]) == pytest.approx(43.1, abs=0.1)
+    ctx = inc.Context([O16], const_sigma_mb=40.0)
+    t = ctx.xs_table()
+    ctx.close()
+    assert (t["sigma"] == 40.0).all() and (t["sigma_max"] == 40.0).all()
+
+
 @pytest.mark.parametrize("mode", ["plain", "persistent", "staged"])
 @pytest.mark.parametrize("target,T", [(O16, 200.0), (CA40, 200.0), ((12, 6), 20.0), ((56, 26), 250.0)])
 def test_ledgers_every_event(mode, target, T):
