@@ -113,6 +113,27 @@ def test_ledgers_every_event(mode, target, T):
     assert s["max_E1"] < 1e-3 and s["max_E2"] < 1e-3 and s["max_P"] < 1e-3
 
 
+@pytest.mark.parametrize("target", [O16, CA40])
+def test_cutoff_bounds_the_escape_energies(target):
+    # the cutoff rule (capture below E_B, + E_C for protons) seen in the
+    # output: cascade neutrons leave with T >= 0 and protons with T >= E_C
+    # (the device's E_C), both bounds reached
+    import paper_1309_7963_amd as inc
+
+    ctx = inc.Context([target], no_evaporation=1)
+    E_C = float(ctx.tables()[0, 106])
+    n = 1_000_000
+    h = run_gpu([target], np.full(n, 200.0, dtype=np.float32), seed=19, ctx=ctx)
+    ctx.close()
+    assert E_C == pytest.approx(oracle.nucleus(*target).EC, rel=1e-6)
+    st0 = h["sec_stage"] == 0
+    Tn = h["sec_T"][st0 & (h["sec_species"] == 0)]
+    Tp = h["sec_T"][st0 & (h["sec_species"] == 1)]
+    print("cutoff: E_C %.4f, min T_p %.4f, min T_n %.5f" % (E_C, Tp.min(), Tn.min()))
+    assert Tn.min() >= 0.0 and Tp.min() >= E_C - 1e-4
+    assert np.sum(Tn < 0.2) > 0 and np.sum(Tp < E_C + 0.2) > 0
+
+
 def test_ledgers_mixed_targets():
     tidx, T0 = _mixture(50000, TISSUE, TISSUE_W, 20, 250, seed=3)
     for mode in ("plain", "persistent"):

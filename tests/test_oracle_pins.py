@@ -342,6 +342,22 @@ def test_pauli_never_blocks_without_a_fermi_sea():
     assert out.results["n_pauli"].sum() > 0
 
 
+@pytest.mark.parametrize("A,Z", [(16, 8), (40, 20)])
+def test_cutoff_bounds_the_escape_energies(A, Z):
+    # A15: after each collision a product stays in the nucleus unless its
+    # excess energy reaches E_B (+ E_C for a proton); the excess is invariant
+    # under refraction and an escaping nucleon keeps T = excess - E_B, so
+    # cascade neutrons leave with T >= 0 and protons with T >= E_C, and both
+    # bounds are reached
+    nu = oracle.nucleus(A, Z)
+    out = oracle.run([(A, Z)], np.full(100000, 200.0), seed=17, n_threads=8, no_evaporation=1)
+    s = out.secondaries
+    Tn = s["T"][(s["stage"] == 0) & (s["species"] == 0)]
+    Tp = s["T"][(s["stage"] == 0) & (s["species"] == 1)]
+    assert Tn.min() >= 0.0 and Tp.min() >= nu.EC - 1e-9
+    assert np.sum(Tn < 0.2) > 0 and np.sum(Tp < nu.EC + 0.2) > 0
+
+
 def test_reaction_cross_section_band():
     # sigma_R = pi R^2 * events / passes; a unit slip (mb vs fm^2) would move it 10x
     out = oracle.run([(16, 8)], np.full(20000, 200.0), seed=8)
