@@ -56,7 +56,7 @@ def test_fast_chi2_o16_paper_scale():
     T0 = np.full(n, 200.0, dtype=np.float32)
     g = events_from_gpu(run_gpu([O16], T0, seed=1, fast_math=1), [O16], T0)
     o = ledger.from_oracle(oracle.run([O16], T0.astype(np.float64), seed=2, n_threads=16), [O16], T0)
-    _chi2_gate(g, o, 200.0, "fast C2 O16")
+    _chi2_gate(g, o, 200.0, "fast 16O 200 MeV")
 
 
 def test_fast_chi2_mixed():
@@ -67,4 +67,4 @@ def test_fast_chi2_mixed():
     g = events_from_gpu(run_gpu(TISSUE, T0, seed=1, tidx=tidx, fast_math=1), TISSUE, T0, tidx)
     o = ledger.from_oracle(oracle.run(TISSUE, T0.astype(np.float64), seed=2, tidx=tidx, n_threads=16), TISSUE, T0,
                            tidx)
-    _chi2_gate(g, o, 250.0, "fast C3")
+    _chi2_gate(g, o, 250.0, "fast tissue mixture")

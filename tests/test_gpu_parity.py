@@ -143,7 +143,7 @@ def test_ledgers_mixed_targets():
 
 @pytest.mark.parametrize("target", [O16, CA40])
 def test_replay_same_stream(target):
-    # C1-sized: 10^4 events, same seed on both sides
+    # 10^4 events at 200 MeV, same seed on both sides
     n = 10000
     T0 = np.full(n, 200.0, dtype=np.float32)
     g = events_from_gpu(run_gpu([target], T0, seed=1), [target], T0)
@@ -167,23 +167,23 @@ def _chi2_gate(g, o, T_max, label):
 
 @pytest.mark.parametrize("target", [O16, CA40])
 def test_chi2_paper_scale(target):
-    # C2: 10^6 events at 200 MeV, GPU seed 1 vs oracle seed 2
+    # 10^6 events at 200 MeV, GPU seed 1 vs oracle seed 2
     n = 1_000_000
     T0 = np.full(n, 200.0, dtype=np.float32)
     g = events_from_gpu(run_gpu([target], T0, seed=1, mode="plain"), [target], T0)
     o, _ = _oracle_events([target], T0, seed=2)
-    _chi2_gate(g, o, 200.0, "C2 %s" % (target,))
+    _chi2_gate(g, o, 200.0, "200 MeV %s" % (target,))
 
 
 @pytest.mark.parametrize("mode", ["plain", "persistent", "staged"])
 def test_chi2_mixed(mode):
-    # C3: 10^6 events of the tissue mixture at U(20, 250) MeV, one input array
+    # 10^6 events of the tissue mixture at U(20, 250) MeV, one input array
     # for every mode and the oracle; GPU seed 1 vs oracle seed 2
     n = 1_000_000
     tidx, T0 = _mixture(n, TISSUE, TISSUE_W, 20, 250, seed=11)
     g = events_from_gpu(run_gpu(TISSUE, T0, seed=1, tidx=tidx, mode=mode), TISSUE, T0, tidx)
     o, _ = _oracle_events(TISSUE, T0, seed=2, tidx=tidx)
-    _chi2_gate(g, o, 250.0, "C3 %s" % mode)
+    _chi2_gate(g, o, 250.0, "tissue mixture %s" % mode)
 
 
 def test_plain_and_persistent_agree_per_event():
@@ -458,7 +458,7 @@ def test_ring_output_equals_direct_output():
 
 
 def test_chi2_implant_through_the_ring():
-    # C4: 10^6 events, 48Ti/56Fe 50/50 at U(70, 250) MeV, secondaries through a
+    # 10^6 events, 48Ti/56Fe 50/50 at U(70, 250) MeV, secondaries through a
     # 2^20-record ring (several wraps): every event's ledgers, and GPU seed 1
     # vs oracle seed 2 in distribution
     import torch
@@ -481,7 +481,7 @@ def test_chi2_implant_through_the_ring():
     g = events_from_gpu(h, IMPLANT, T0, tidx)
     ledger.assert_clean(ledger.check(g))
     o, _ = _oracle_events(IMPLANT, T0, seed=2, tidx=tidx)
-    _chi2_gate(g, o, 250.0, "C4 ring")
+    _chi2_gate(g, o, 250.0, "Ti/Fe through the ring")
 
 
 def test_ring_staged_mode_equals_direct_staged():

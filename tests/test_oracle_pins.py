@@ -22,7 +22,7 @@ M_P, M_N = 938.272088, 939.565420
 HBARC = 197.3269804
 
 
-# ---------------------------------------------------------------- P1, P2 RNG
+# ------------------------------------------------- Philox stream and uniforms
 def _kat_rows():
     rows = []
     with open(os.path.join(HERE, "golden", "philox_kat.txt")) as f:
@@ -58,7 +58,7 @@ def test_stream_layout():
         assert oracle.stream_uniform(seed, eid, k) == oracle.uniform(w)
 
 
-# ------------------------------------------------------- P3 nucleus (Sec. 2.2)
+# -------------------------------------------------- nucleus shells (Sec. 2.2)
 @pytest.mark.parametrize("A,Z", [(12, 6), (16, 8), (40, 20), (56, 26)])
 def test_shell_integrals_quadrature(A, Z):
     nu = oracle.nucleus(A, Z)
@@ -122,7 +122,7 @@ def test_binding_energy_systematics():
     assert oracle.mass(1, 1) == pytest.approx(M_P) and oracle.mass(1, 0) == pytest.approx(M_N)
 
 
-# ---------------------------------------------------- P4 Fermi sphere (Sec. 2.2)
+# ------------------------------------------------------- Fermi sphere (Sec. 2.2)
 def test_fermi_sampling_distribution():
     rng = np.random.default_rng(11)
     pF = 250.0
@@ -135,7 +135,7 @@ def test_fermi_sampling_distribution():
     assert np.mean(mag ** 2) == pytest.approx(0.6 * pF ** 2, rel=0.02)
 
 
-# ----------------------------------------------- P5 NN cross-sections (Sec. 2.3)
+# -------------------------------------------------- NN cross-sections (Sec. 2.3)
 def test_sigma_anchor_values():
     # stand-in parameterisation at 200 MeV lab kinetic energy
     p = math.sqrt(200.0 ** 2 + 2 * 200.0 * M_P) / 1000
@@ -189,7 +189,7 @@ def test_plab_min_is_the_minimum_over_the_sphere():
         assert best - lo < 0.05 * p + 5.0
 
 
-# ---------------------------------------- P6, P7 elastic kinematics (Sec. 2.3)
+# ------------------------------------------------ elastic kinematics (Sec. 2.3)
 def test_elastic_four_momentum_conservation():
     rng = np.random.default_rng(3)
     for _ in range(300):
@@ -236,7 +236,7 @@ def test_angular_distribution_truncated_exponential(b):
     assert stats.kstest(y, cdf).pvalue > 1e-3
 
 
-# ------------------------------------------------- P8, P9 flight (Sec. 2.3)
+# ------------------------------------------------------------ flight (Sec. 2.3)
 FREE = dict(uniform_density=1, zero_fermi=1, zero_binding=1, no_pauli=1,
             no_evaporation=1, stop_after_first=1)
 
@@ -267,7 +267,7 @@ def test_first_collision_depth_exponential():
     assert stats.kstest(depth, cdf).pvalue > 1e-3
 
 
-# ---------------------------------------------- P10 refraction (Sec. 2.3)
+# -------------------------------------------------------- refraction (Sec. 2.3)
 def test_refraction_cases():
     n = np.array([0.0, 0.0, 1.0])
     # normal incidence transmits and keeps its direction
@@ -306,7 +306,7 @@ def test_refraction_critical_angle():
         assert ok == want
 
 
-# ------------------------------------------ P11, P12, P16 whole events (Sec. 2)
+# ---------------------------------------------------------- whole events (Sec. 2)
 @pytest.mark.parametrize("target,T", [((16, 8), 200.0), ((40, 20), 200.0), ((12, 6), 70.0), ((56, 26), 250.0)])
 def test_event_ledgers(target, T):
     n = 4000
@@ -344,7 +344,7 @@ def test_pauli_never_blocks_without_a_fermi_sea():
 
 @pytest.mark.parametrize("A,Z", [(16, 8), (40, 20)])
 def test_cutoff_bounds_the_escape_energies(A, Z):
-    # A15: after each collision a product stays in the nucleus unless its
+    # cutoff (Sec. 2.3): after each collision a product stays in the nucleus unless its
     # excess energy reaches E_B (+ E_C for a proton); the excess is invariant
     # under refraction and an escaping nucleon keeps T = excess - E_B, so
     # cascade neutrons leave with T >= 0 and protons with T >= E_C, and both
@@ -396,7 +396,7 @@ def test_argument_validation():
         oracle.run([(16, 16)], np.array([100.0]), seed=1)
 
 
-# ------------------------------------------ P13-P15 evaporation (Sec. 2.4)
+# ------------------------------------------------------- evaporation (Sec. 2.4)
 @pytest.mark.parametrize("a,U", [(2.0, 0.001), (1.0, 0.3), (2.0, 0.49), (2.0, 0.51), (5.0, 10.0), (7.0, 150.0), (0.125, 3.0)])
 def test_width_integral_quadrature(a, U):
     f = lambda x: x * math.exp(2 * math.sqrt(a * max(U - x, 0.0)))
