@@ -334,6 +334,37 @@ int inc_ring_destroy(inc_ring* ring);
 int inc_ring_simulate(inc_ring* ring, const inc_batch* batch, inc_residual* d_res, const inc_host_output* out,
                       void* stream, int mode, inc_ring_stats* stats);
 
+/* One run of consecutive records handed to a ring consumer (Sec. 3.2, 3.3:
+ * the secondaries of the batch).  The arrays point into the ring's pinned
+ * host memory and are valid only during the callback; their slots go back
+ * to the producer when it returns. */
+typedef struct {
+  unsigned long long first; /* index of the run's first record in the batch's
+                               output sequence (runs arrive in order,
+                               without gaps)                                  */
+  size_t n;                 /* records in the run                             */
+  const uint32_t* event;    /* n indices of the event in the batch            */
+  const uint32_t* kind;     /* n words: species in bits 0-7, stage in bits
+                               8-15 (higher bits are internal)                */
+  const float* T;           /* n kinetic energies (MeV)                       */
+  const float* ux;          /* n direction cosines                            */
+  const float* uy;
+  const float* uz;
+} inc_ring_chunk;
+
+typedef void (*inc_ring_consumer)(const inc_ring_chunk* chunk, void* user);
+
+/* As inc_ring_simulate, but every run of records is handed to consumer(chunk,
+ * user) on the calling thread as it becomes ready, so the output needs no
+ * host array sized by the batch (a consumer may histogram, filter or write
+ * the records out).  h_res: host, n residuals, or NULL.  *n_sec receives the
+ * number of records produced.  A slow consumer makes the producer wait, as
+ * a full ring does.  The consumer must not call into this ring.  Returns
+ * INC_ERR_ARG for a NULL ring, batch, d_res, consumer or n_sec. */
+int inc_ring_simulate_to(inc_ring* ring, const inc_batch* batch, inc_residual* d_res, inc_residual* h_res,
+                         inc_ring_consumer consumer, void* user, unsigned long long* n_sec, void* stream,
+                         int mode, inc_ring_stats* stats);
+
 /* ------------------------------------------------------ nuclide tally
  * Residual-nuclide counts, the reduction behind positron-emitter yields
  * (11C, 13N, 15O, 30P, 38K ... for range verification: the application the

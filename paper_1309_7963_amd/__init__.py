@@ -502,5 +502,57 @@ class Ring:
                     stats={f: getattr(stats, f) for f, _ in stats._fields_})
 
 
+    def stream(self, T0, seed: int, consumer, target_idx=None, first_event_id: int = 0, mode: str = "staged",
+               res=None, stream=None) -> dict:
+        """Generate len(T0) events and hand their secondaries to
+        consumer(chunk) run by run as they leave the ring
+        (inc_ring_simulate_to).  chunk: dict with "first" (index of the run's
+        first record in the batch's output sequence) and numpy views "event",
+        "species", "stage", "T", "ux", "uy", "uz" into the ring, valid only
+        during the call (copy what you keep).  res: host RESIDUAL_DTYPE array
+        of len(T0) (pinned memory lets its copy overlap the drain) or None.
+        Returns the record count, the ring statistics and any exception the
+        consumer raised."""
+        torch = _torch()
+        n = int(T0.shape[0])
+        if res is not None and (res.dtype != RESIDUAL_DTYPE or res.shape[0] < n):
+            raise TypeError("res must be a RESIDUAL_DTYPE array of at least len(T0) records")
+        errors = []
+
+        def on_chunk(cp, _user):
+            if errors:
+                return
+            c = cp.contents
+            m = int(c.n)
+            view = lambda ptr: np.ctypeslib.as_array(ptr, shape=(m,))
+            kind = view(c.kind)
+            try:
+                consumer(dict(first=int(c.first), event=view(c.event), species=(kind & 0xFF).astype(np.uint8),
+                              stage=((kind >> 8) & 0xFF).astype(np.uint8), T=view(c.T), ux=view(c.ux),
+                              uy=view(c.uy), uz=view(c.uz)))
+            except BaseException as e:  # noqa: BLE001  (reported after the drain)
+                errors.append(e)
+
+        cb = _lib.RING_CONSUMER(on_chunk)
+        res_d = torch.empty(n * 32, dtype=torch.uint8, device=T0.device)
+        b = _lib.Batch()
+        b.n = n
+        b.target_idx = target_idx.data_ptr() if target_idx is not None else None
+        b.T0 = T0.data_ptr()
+        b.seed = int(seed)
+        b.first_event_id = int(first_event_id)
+        stats = _lib.RingStats()
+        nsec = C.c_ulonglong()
+        s = stream if stream is not None else torch.cuda.current_stream()
+        rc = _lib.load().inc_ring_simulate_to(self._h, C.byref(b), C.c_void_p(res_d.data_ptr()),
+                                              None if res is None else C.c_void_p(res.ctypes.data), cb, None,
+                                              C.byref(nsec), C.c_void_p(s.cuda_stream), MODES[mode],
+                                              C.byref(stats))
+        _lib.check(rc, "inc_ring_simulate_to")
+        if errors:
+            raise errors[0]
+        return dict(n_sec_total=nsec.value, stats={f: getattr(stats, f) for f, _ in stats._fields_})
+
+
 def contract_version() -> int:
     return _lib.load().inc_contract_version()

@@ -27,7 +27,7 @@ SYMBOLS = (
     "inc_simulate_dev", "inc_evaporate_dev", "inc_simulate", "inc_server_create", "inc_server_destroy",
     "inc_server_submit", "inc_server_poll", "inc_server_wait", "inc_server_fetch",
     "inc_server_stats_get", "inc_server_replay", "inc_ring_create", "inc_ring_destroy",
-    "inc_ring_simulate", "inc_ctx_tally_shape", "inc_tally_residuals", "inc_contract_version",
+    "inc_ring_simulate", "inc_ring_simulate_to", "inc_ctx_tally_shape", "inc_tally_residuals", "inc_contract_version",
 )
 
 
@@ -99,6 +99,17 @@ class RingStats(C.Structure):
         ("records", C.c_ulonglong), ("slots", C.c_ulonglong), ("wraps", C.c_ulonglong),
         ("consumer_idle_polls", C.c_ulonglong), ("seconds", C.c_double), ("producer_gave_up", C.c_uint),
     ]
+
+
+class RingChunk(C.Structure):
+    _fields_ = [
+        ("first", C.c_ulonglong), ("n", C.c_size_t), ("event", C.POINTER(C.c_uint32)),
+        ("kind", C.POINTER(C.c_uint32)), ("T", C.POINTER(C.c_float)), ("ux", C.POINTER(C.c_float)),
+        ("uy", C.POINTER(C.c_float)), ("uz", C.POINTER(C.c_float)),
+    ]
+
+
+RING_CONSUMER = C.CFUNCTYPE(None, C.POINTER(RingChunk), C.c_void_p)
 
 
 RESIDUAL_DTYPE = np.dtype(
@@ -179,6 +190,9 @@ def load():
         L.inc_ring_simulate.argtypes = [vp, C.POINTER(Batch), vp, C.POINTER(HostOutput), vp, C.c_int,
                                         C.POINTER(RingStats)]
         L.inc_ring_simulate.restype = C.c_int
+        L.inc_ring_simulate_to.argtypes = [vp, C.POINTER(Batch), vp, vp, RING_CONSUMER, vp, C.POINTER(C.c_ulonglong),
+                                           vp, C.c_int, C.POINTER(RingStats)]
+        L.inc_ring_simulate_to.restype = C.c_int
         L.inc_ctx_tally_shape.argtypes = [vp, C.POINTER(C.c_int), C.POINTER(C.c_int), C.POINTER(C.c_int)]
         L.inc_ctx_tally_shape.restype = C.c_int
         L.inc_tally_residuals.argtypes = [vp, C.POINTER(Batch), vp, C.c_int, vp, vp]

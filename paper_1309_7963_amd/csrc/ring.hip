@@ -167,8 +167,16 @@ int inc_ring_destroy(inc_ring* r) {
   return INC_OK;
 }
 
-int inc_ring_simulate(inc_ring* r, const inc_batch* b, inc_residual* d_res, const inc_host_output* out, void* stream,
-                      int mode, inc_ring_stats* stats) {
+}  // extern "C"
+
+namespace {
+
+// One batch through the ring: launch, drain while the kernel runs, and hand
+// each run of ready records either to `consumer` or into the host arrays of
+// `out` (one of the two), then the slots back to the producer.
+int ring_run(inc_ring* r, const inc_batch* b, inc_residual* d_res, inc_residual* h_res, const inc_host_output* out,
+             inc_ring_consumer consumer, void* user, unsigned long long* n_sec_out, void* stream, int mode,
+             inc_ring_stats* stats) {
   if (!r || !b || !d_res || !b->T0 || b->n < 1 || b->n >= (1ull << 32)) return INC_ERR_ARG;
   if (mode != INC_MODE_PLAIN && mode != INC_MODE_PERSISTENT && mode != INC_MODE_STAGED) return INC_ERR_ARG;
   hipStream_t st = (hipStream_t)stream;
@@ -209,11 +217,11 @@ int inc_ring_simulate(inc_ring* r, const inc_batch* b, inc_residual* d_res, cons
   // once the drain is over (a blocking copy now would stall the drain the
   // kernel waits on)
   bool res_queued = false;
-  if (rc == INC_OK && out && out->res) {
+  if (rc == INC_OK && h_res) {
     hipPointerAttribute_t pa;
-    if (hipPointerGetAttributes(&pa, out->res) == hipSuccess && pa.type == hipMemoryTypeHost) {
+    if (hipPointerGetAttributes(&pa, h_res) == hipSuccess && pa.type == hipMemoryTypeHost) {
       rc = inc_map_hip_error(
-          hipMemcpyAsync(out->res, d_res, sizeof(inc_residual) * b->n, hipMemcpyDeviceToHost, st));
+          hipMemcpyAsync(h_res, d_res, sizeof(inc_residual) * b->n, hipMemcpyDeviceToHost, st));
       res_queued = rc == INC_OK;
     } else {
       (void)hipGetLastError();  // pageable memory is not an error here
@@ -255,7 +263,20 @@ int inc_ring_simulate(inc_ring* r, const inc_batch* b, inc_residual* d_res, cons
       if (run == 0) break;
       __atomic_thread_fence(__ATOMIC_ACQUIRE);
       const unsigned long long k = tail - start;
-      if (out && k < cap_out) {
+      if (consumer) {
+        const uint32_t* rec = r->h_rec;
+        inc_ring_chunk c;
+        c.first = k;
+        c.n = run;
+        c.event = rec + S + j;
+        c.kind = rec + 2 * S + j;
+        c.T = (const float*)(rec + 3 * S + j);
+        c.ux = (const float*)(rec + 4 * S + j);
+        c.uy = (const float*)(rec + 5 * S + j);
+        c.uz = (const float*)(rec + 6 * S + j);
+        consumer(&c, user);
+        copied += run;
+      } else if (out && k < cap_out) {
         const size_t m = (size_t)std::min<unsigned long long>(run, cap_out - k);
         const uint32_t* rec = r->h_rec;
         auto copy = [&, j, k](size_t a, size_t b) {
@@ -321,10 +342,10 @@ int inc_ring_simulate(inc_ring* r, const inc_batch* b, inc_residual* d_res, cons
     }
   }
   (void)hipEventDestroy(done);
-  if (out && out->res && rc == INC_OK) {
+  if (h_res && rc == INC_OK) {
     const hipError_t ce =
         res_queued ? hipStreamSynchronize(st)
-                   : hipMemcpy(out->res, d_res, sizeof(inc_residual) * b->n, hipMemcpyDeviceToHost);
+                   : hipMemcpy(h_res, d_res, sizeof(inc_residual) * b->n, hipMemcpyDeviceToHost);
     if (ce != hipSuccess) rc = inc_map_hip_error(ce);
   } else if (res_queued) {
     (void)hipStreamSynchronize(st);
@@ -332,7 +353,7 @@ int inc_ring_simulate(inc_ring* r, const inc_batch* b, inc_residual* d_res, cons
   if (kernel_done) r->next_seq = final_head;
   if (rc == INC_OK && *err_p) rc = INC_ERR_DEVICE;
   const unsigned long long produced = kernel_done ? final_head - start : tail - start;
-  if (out && out->n_sec) *out->n_sec = produced;
+  if (n_sec_out) *n_sec_out = produced;
   if (stats) {
     stats->records = produced;
     stats->slots = r->slots;
@@ -342,9 +363,26 @@ int inc_ring_simulate(inc_ring* r, const inc_batch* b, inc_residual* d_res, cons
     stats->producer_gave_up = *err_p;
   }
   (void)max_fill;
-  if (rc == INC_OK && produced > cap_out && out) rc = INC_ERR_CAPACITY;
+  if (rc == INC_OK && !consumer && out && produced > cap_out) rc = INC_ERR_CAPACITY;
   (void)copied;
   return rc;
+}
+
+}  // namespace
+
+extern "C" {
+
+int inc_ring_simulate(inc_ring* r, const inc_batch* b, inc_residual* d_res, const inc_host_output* out, void* stream,
+                      int mode, inc_ring_stats* stats) {
+  return ring_run(r, b, d_res, out ? out->res : nullptr, out, nullptr, nullptr, out ? out->n_sec : nullptr, stream,
+                  mode, stats);
+}
+
+int inc_ring_simulate_to(inc_ring* r, const inc_batch* b, inc_residual* d_res, inc_residual* h_res,
+                         inc_ring_consumer consumer, void* user, unsigned long long* n_sec, void* stream, int mode,
+                         inc_ring_stats* stats) {
+  if (!consumer || !n_sec) return INC_ERR_ARG;
+  return ring_run(r, b, d_res, h_res, nullptr, consumer, user, n_sec, stream, mode, stats);
 }
 
 }  // extern "C"
