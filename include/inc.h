@@ -359,7 +359,11 @@ typedef void (*inc_ring_consumer)(const inc_ring_chunk* chunk, void* user);
  * host array sized by the batch (a consumer may histogram, filter or write
  * the records out).  h_res: host, n residuals, or NULL.  *n_sec receives the
  * number of records produced.  A slow consumer makes the producer wait, as
- * a full ring does.  The consumer must not call into this ring.  Returns
+ * a full ring does.  The kernel may be waiting for the consumer to return,
+ * so the consumer must not call into this ring, nor make or cause HIP calls
+ * that wait for the device (hipFree, device, stream or event
+ * synchronisation): they would stall both sides until the producer's
+ * bounded wait fails the call with INC_ERR_DEVICE.  Returns
  * INC_ERR_ARG for a NULL ring, batch, d_res, consumer or n_sec. */
 int inc_ring_simulate_to(inc_ring* ring, const inc_batch* batch, inc_residual* d_res, inc_residual* h_res,
                          inc_ring_consumer consumer, void* user, unsigned long long* n_sec, void* stream,

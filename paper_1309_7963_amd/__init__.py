@@ -15,6 +15,7 @@ from dataclasses import dataclass
 from typing import Optional, Sequence
 
 import ctypes as C
+import gc
 
 import numpy as np
 
@@ -511,8 +512,11 @@ class Ring:
         "species", "stage", "T", "ux", "uy", "uz" into the ring, valid only
         during the call (copy what you keep).  res: host RESIDUAL_DTYPE array
         of len(T0) (pinned memory lets its copy overlap the drain) or None.
-        Returns the record count, the ring statistics and any exception the
-        consumer raised."""
+        The kernel may be waiting for the consumer: it must not synchronise
+        with the device or release device objects (Python's cyclic garbage
+        collector is paused for the call).  Returns the record count and the
+        ring statistics; an exception the consumer raised is re-raised after
+        the drain."""
         torch = _torch()
         n = int(T0.shape[0])
         if res is not None and (res.dtype != RESIDUAL_DTYPE or res.shape[0] < n):
@@ -544,10 +548,20 @@ class Ring:
         stats = _lib.RingStats()
         nsec = C.c_ulonglong()
         s = stream if stream is not None else torch.cuda.current_stream()
-        rc = _lib.load().inc_ring_simulate_to(self._h, C.byref(b), C.c_void_p(res_d.data_ptr()),
-                                              None if res is None else C.c_void_p(res.ctypes.data), cb, None,
-                                              C.byref(nsec), C.c_void_p(s.cuda_stream), MODES[mode],
-                                              C.byref(stats))
+        # The consumer runs while the kernel may wait for it to drain: a
+        # garbage-collection pass inside it could finalize an unrelated
+        # object whose release waits on the device (a Context's hipFree), and
+        # then neither side moves until the producer's bounded wait fails.
+        gc_was_enabled = gc.isenabled()
+        gc.disable()
+        try:
+            rc = _lib.load().inc_ring_simulate_to(self._h, C.byref(b), C.c_void_p(res_d.data_ptr()),
+                                                  None if res is None else C.c_void_p(res.ctypes.data), cb, None,
+                                                  C.byref(nsec), C.c_void_p(s.cuda_stream), MODES[mode],
+                                                  C.byref(stats))
+        finally:
+            if gc_was_enabled:
+                gc.enable()
         _lib.check(rc, "inc_ring_simulate_to")
         if errors:
             raise errors[0]

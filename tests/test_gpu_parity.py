@@ -8,6 +8,7 @@
 * distributions: two-sample chi-square (independent seeds) on 100-bin n/p
   energy and angle histograms and the residual (A, Z) table, p > 0.01.
 """
+import gc
 import math
 
 import numpy as np
@@ -44,6 +45,7 @@ def test_nucleus_tables_match_oracle():
     targets = TISSUE + IMPLANT
     ctx = inc.Context(targets)
     tab = ctx.tables()
+    ctx.close()
     for t, (A, Z) in enumerate(targets):
         nu = oracle.nucleus(A, Z)
         g = tab[t, :105].reshape(15, 7)
@@ -384,6 +386,7 @@ def test_serving_result_same_alone_and_in_the_mix():
         for f in ("sec_event", "sec_species", "sec_stage", "sec_T", "sec_u"):
             assert np.array_equal(alone[f][ka], mix[f][km]), (k, f)
     srv.close()
+    ctx.close()
 
 
 def test_serving_admission_by_budget():
@@ -412,6 +415,7 @@ def test_serving_admission_by_budget():
         assert r["rc"] == 0
     assert srv.submit(small, seed=1) is not None
     srv.close()
+    ctx.close()
 
 
 def test_serving_replay_latencies():
@@ -426,6 +430,7 @@ def test_serving_replay_latencies():
     assert span > 0
     assert srv.stats()["completed"] == len(reqs)
     srv.close()
+    ctx.close()
 
 
 # ------------------------------------------------------------------- ring
@@ -511,10 +516,17 @@ def test_ring_consumer_receives_every_record_once():
     try:
         with pytest.raises(Boom):
             ring.stream(T0_d, seed=5, consumer=failing, target_idx=ti_d)
+        # an unclosed Context kept only by a reference cycle: its release
+        # (hipFree) waits on the device, so it must not be finalized inside the
+        # consumer while the kernel waits for the drain
+        leak = [inc.Context(IMPLANT)]
+        leak.append(leak)
+        del leak
         runs = []
         res = np.zeros(n, dtype=inc.RESIDUAL_DTYPE)
         out = ring.stream(T0_d, seed=5, consumer=lambda c: runs.append((c["first"], {k: np.array(c[k]) for k in fields})),
                           target_idx=ti_d, res=res)
+        gc.collect()
     finally:
         ring.close()
         ctx.close()
