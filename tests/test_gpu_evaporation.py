@@ -40,6 +40,17 @@ def ctx():
     c.close()
 
 
+@pytest.fixture(scope="module", params=[0, 1], ids=["ieee", "fast_math"])
+def any_ctx(request):
+    """A context of the default build, then one of the fast-math build (the
+    statistical pins must hold for both, Sec. 4.2)."""
+    import paper_1309_7963_amd as inc
+
+    c = inc.Context(TARGETS, fast_math=request.param)
+    yield c
+    c.close()
+
+
 def _inputs(A, Z, Ex, P):
     """The float32/int16 inputs as the device sees them, back in float64."""
     n = len(Ex)
@@ -244,10 +255,10 @@ def test_evaporation_thresholds(ctx):
     assert (first == j0).all(), np.bincount(first + 1)
 
 
-def test_evaporation_branching_matches_widths(ctx):
+def test_evaporation_branching_matches_widths(any_ctx):
     A, Z, E = 40, 20, 60.0
     n = 1_000_000
-    ev = _run(ctx, np.full(n, A), np.full(n, Z), np.full(n, E), seed=4)
+    ev = _run(any_ctx, np.full(n, A), np.full(n, Z), np.full(n, E), seed=4)
     first = _first_species(ev)
     assert (first >= 0).all()
     w = evap_ref.branching(A, Z, E)
@@ -262,7 +273,7 @@ def test_evaporation_branching_matches_widths(ctx):
     assert p > 0.01
 
 
-def test_evaporation_single_neutron_spectrum(ctx):
+def test_evaporation_single_neutron_spectrum(any_ctx):
     # 41Ar at E* = 14 MeV: only the neutron channel is open (threshold 6.08 MeV,
     # the next one above 16.6 MeV) and the daughter 40Ar stays below all of
     # its thresholds, so each nucleus emits exactly one neutron and keeps
@@ -272,7 +283,7 @@ def test_evaporation_single_neutron_spectrum(ctx):
     assert np.argmin(thr) == 0 and sorted(thr)[1] > E
     assert thr[0] + min(evap_ref.threshold(A - 1, Z, j) for j in range(6)) > E
     n = 1_000_000
-    ev = _run(ctx, np.full(n, A), np.full(n, Z), np.full(n, E), seed=6)
+    ev = _run(any_ctx, np.full(n, A), np.full(n, Z), np.full(n, E), seed=6)
     assert (ev.n_sec == 1).all() and (ev.sec_species == 0).all()
     U = E - thr[0]
     a = (A - 1) / 8.0
@@ -299,10 +310,10 @@ def test_evaporation_replay_matches_oracle(ctx):
     assert np.median(np.abs(g.Ex_f[same] - o.Ex_f[same])) < 1e-3
 
 
-def test_evaporation_distributions_match_oracle(ctx):
+def test_evaporation_distributions_match_oracle(any_ctx):
     # same input mixture, GPU seed 1 (10^6 nuclei) vs oracle seed 2 (10^5)
     A, Z, Ex, P = _mixture(1_000_000, seed=25, E_max=150.0)
-    g = _run(ctx, A, Z, Ex, P, seed=1)
+    g = _run(any_ctx, A, Z, Ex, P, seed=1)
     m = 100_000
     A16, Z16, Ex32, P32 = _inputs(A[:m], Z[:m], Ex[:m], P[:m])
     o = ledger.evaporate_oracle(A16, Z16, Ex32.astype(np.float64), P32.astype(np.float64), seed=2)
