@@ -23,6 +23,7 @@ from __future__ import annotations
 
 import argparse
 import json
+import math
 import os
 import sys
 import time
@@ -297,6 +298,25 @@ def _end_to_end_pipelined(w, steps: int, seed: int = 1):
                      "copies of one batch overlapping the next batch's kernels")
 
 
+def _reaction_cross_sections(n: int = 1_000_000, T: float = 200.0, seed: int = 3):
+    """Diagnostic of the transparent-pass reading (Sec. 2.1): sigma_R = pi R^2 x
+    events / (events + transparent passes), from the retries every residual
+    records, per target at one energy (mb; no measured value is compared)."""
+    import torch
+
+    import paper_1309_7963_amd as inc
+
+    out = {}
+    for name, AZ in (("12C", (12, 6)), ("16O", (16, 8)), ("40Ca", (40, 20)), ("56Fe", (56, 26))):
+        ctx = inc.Context([AZ])
+        R = float(ctx.tables()[0, 107])
+        d = ctx.simulate(torch.full((n,), T, device="cuda"), seed=seed)
+        retries = int((d.res.view(torch.int16).view(n, 16)[:, 15].to(torch.int64) & 0xFFFF).sum())
+        ctx.close()
+        out[name] = dict(sigma_R_mb=math.pi * R * R * 10.0 * n / (n + retries), transparent_per_event=retries / n)
+    return dict(T0_MeV=T, events=n, **out)
+
+
 def _evaporation_stage(w, reps: int = 5, seed: int = 1):
     """The two stages apart, the paper's run-time split: cascade-only launches
     (no_evaporation) of the workload, whose first supplies (A', Z', E*, p) per
@@ -550,6 +570,7 @@ def main(argv=None):
         extra["end_to_end_host_pipelined"] = _end_to_end_pipelined(main_w, 5)
         extra["nuclide_tally"] = dict(workload=wl["tissue_mix"]["label"], **_tally_run(wl["tissue_mix"]))
         extra["evaporation_stage"] = dict(workload=main_w["label"], **_evaporation_stage(main_w))
+        extra["reaction_cross_section"] = _reaction_cross_sections()
         # fast-math build of the event kernels (same workloads)
         fm = {}
         for key, w in (("o16_ca40_200", main_w), ("o16_200", wl["o16_200"]), ("ca40_200", wl["ca40_200"]),
