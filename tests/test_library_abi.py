@@ -82,6 +82,11 @@ def test_argument_errors_before_device(lib):
     x = _lib.Excited()
     x.n = 1
     assert L.inc_evaporate_dev(None, C.byref(x), None, None) == inc.INC_ERR_ARG
+    nn, lo, hi = C.c_int(), C.c_float(), C.c_float()
+    assert L.inc_ctx_xs_table(None, None, C.byref(nn), C.byref(lo), C.byref(hi)) == inc.INC_ERR_ARG
+    nsec_r = C.c_ulonglong()
+    noop = _lib.RING_CONSUMER(lambda chunk, user: None)
+    assert L.inc_ring_simulate_to(None, None, None, None, noop, None, C.byref(nsec_r), None, 0, None) == inc.INC_ERR_ARG
     # option ranges are checked before the device is looked for
     for field, bad in (("fast_math", 2), ("same_stream", -1), ("stack_levels", 5), ("block_size", 96),
                        ("waves_per_cu", 33), ("kin_threshold", 65), ("start_threshold", 65), ("input_order", 2)):
