@@ -510,6 +510,9 @@ def main(argv=None):
     ap.add_argument("--no-extra", action="store_true", help="skip the per-target and mixture rates")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--serving-requests", type=int, default=1000, help="requests per load point (0: skip)")
+    ap.add_argument("--stage-split", action="store_true",
+                    help="only time the cascade and evaporation stages apart on the main workload "
+                         "(one JSON line; for profiling the evaporation-only launch)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="first copy 256 MiB device to device (a plain copy kernel of known size, "
                          "to scale the HBM byte counters)")
@@ -531,6 +534,9 @@ def main(argv=None):
         del src, dst
     wl = _workloads(args.events)
     main_w = wl["o16_ca40_200"]
+    if args.stage_split:
+        print(json.dumps(dict(workload=main_w["label"], **_evaporation_stage(main_w, reps=args.steps))))
+        return 0
     r = _time_gpu(main_w, args.mode, args.steps, args.warmup)
     print("bench: main workload done (%.1f ms/launch)" % float(np.mean(r["launch_ms"])), file=sys.stderr, flush=True)
     ms = float(np.mean(r["launch_ms"]))
