@@ -122,6 +122,16 @@ def test_binding_energy_systematics():
     assert oracle.mass(1, 1) == pytest.approx(M_P) and oracle.mass(1, 0) == pytest.approx(M_N)
 
 
+def test_binding_energies_near_measured():
+    # the semi-empirical formula of the binding-energy reading against measured
+    # total binding energies (atomic mass evaluation, MeV): within 3 % from 12C
+    # on and 1 % from 40Ca on, so a slip in any coefficient shows
+    measured = {(12, 6): 92.162, (16, 8): 127.619, (40, 20): 342.052, (56, 26): 492.254, (208, 82): 1636.43}
+    for (A, Z), b in measured.items():
+        rel = abs(oracle.binding(A, Z) / b - 1.0)
+        assert rel < (0.01 if A >= 40 else 0.03), (A, Z, rel)
+
+
 # ------------------------------------------------------- Fermi sphere (Sec. 2.2)
 def test_fermi_sampling_distribution():
     rng = np.random.default_rng(11)
