@@ -203,7 +203,11 @@ class Context:
                   capacity: Optional[int] = None, stream=None) -> DeviceOutput:
         """Evaporate given excited nuclei asynchronously (inc_evaporate_dev).
         A, Z: int16 or uint16 CUDA tensors; Ex: float32 CUDA tensor (MeV);
-        P: float32 CUDA tensor of shape (n, 3) (MeV/c) or None (at rest)."""
+        P: float32 CUDA tensor of shape (n, 3) (MeV/c) or None (at rest).
+        The default capacity allows min(A + 1, 4 + A / 4) fragments per
+        nucleus for the context's heaviest target; out.n_sec() above
+        out.capacity means records were dropped: allocate that many and run
+        again."""
         torch = _torch()
         n = int(Ex.shape[0]) if torch.is_tensor(Ex) else -1
         for name, t, dts in (("A", A, (torch.int16, torch.uint16)), ("Z", Z, (torch.int16, torch.uint16)),
