@@ -498,6 +498,14 @@ __device__ __forceinline__ bool evap_step(Nucleus& nu, Rng& rng, const BindTab& 
   V3 pf;
   float Tf;
   boost_out(qv, mj, u, g, ig1, uu * ig1, pf, Tf);
+  // the record's kinetic energy from the boosted momentum itself: the boost
+  // form cancels for a fragment sent backward out of a moving nucleus, and a
+  // heavy fragment left nearly at rest then has |p| = sqrt(T^2 + 2 T m)
+  // badly determined by T; p^2 / (E + m) is accurate to a few ulps always
+  {
+    const float pf2 = dot3(pf, pf);
+    Tf = pf2 / (sqrtf(pf2 + mj * mj) + mj);
+  }
   em.on = true;
   em.kind = (uint32_t)j | (1u << 8);
   em.T = Tf;

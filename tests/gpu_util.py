@@ -59,3 +59,15 @@ def outcome_keys(ev: ledger.Events):
     for i in range(ev.n):
         keys.append((int(ev.A_f[i]), int(ev.Z_f[i]), tuple(code[bounds[i]:bounds[i + 1]].tolist())))
     return keys
+
+
+def events_slice(ev: ledger.Events, start: int, stop: int) -> ledger.Events:
+    """Events [start, stop) of a batch with their records, indices rebased to 0."""
+    sel = (ev.sec_event >= start) & (ev.sec_event < stop)
+    sl = slice(start, stop)
+    return ledger.Events(
+        A=ev.A[sl], Z=ev.Z[sl], T0=ev.T0[sl], A_f=ev.A_f[sl], Z_f=ev.Z_f[sl], Ex_casc=ev.Ex_casc[sl],
+        Ex_f=ev.Ex_f[sl], p_f=ev.p_f[sl], n_sec=ev.n_sec[sl], flags=ev.flags[sl],
+        sec_event=ev.sec_event[sel] - start, sec_species=ev.sec_species[sel], sec_stage=ev.sec_stage[sel],
+        sec_T=ev.sec_T[sel], sec_u=ev.sec_u[sel],
+    )

@@ -13,7 +13,7 @@ import pytest
 
 import ledger
 import oracle
-from gpu_util import events_from_gpu, outcome_keys, run_gpu
+from gpu_util import events_from_gpu, events_slice, outcome_keys, run_gpu
 
 pytestmark = pytest.mark.gpu
 
@@ -39,4 +39,32 @@ def test_bench_size_ledgers_and_sampled_replay():
         ko = outcome_keys(ledger.from_oracle(out, TARGETS, T0[sl], tidx[sl]))
         agree = np.mean([a == b for a, b in zip(keys[sl], ko)])
         print("bench-size replay block at", start, agree)
+        assert agree > 0.97
+
+
+def test_four_times_the_bench_size():
+    # 8x10^6 events of the tissue mixture (12C/14N/16O/31P/40Ca, U(20, 250) MeV)
+    # in one staged launch: the work queue, the costliest-first start order
+    # over many cost buckets and the hand-over buffer at four times the
+    # benchmark's size; ledgers on every event and the oracle's replay of a
+    # block at each end of the batch
+    targets = [(12, 6), (14, 7), (16, 8), (31, 15), (40, 20)]
+    n = 8_000_000
+    rng = np.random.default_rng(41)
+    tidx = rng.choice(5, n, p=[0.18, 0.03, 0.65, 0.01, 0.13]).astype(np.uint8)
+    T0 = rng.uniform(20.0, 250.0, n).astype(np.float32)
+    h = run_gpu(targets, T0, seed=2, tidx=tidx, mode="staged")
+    ev = events_from_gpu(h, targets, T0, tidx)
+    s = ledger.check(ev)
+    print("8x10^6 events: max momentum residual %.2e MeV/c" % s["max_P"])
+    ledger.assert_clean(s)
+    assert h["n_sec_total"] == int(h["res"]["n_sec"].sum())
+    m = 2000
+    for start in (0, n - m):
+        sl = slice(start, start + m)
+        out = oracle.run(targets, T0[sl].astype(np.float64), seed=2, tidx=tidx[sl], first_id=start, n_threads=16)
+        ko = outcome_keys(ledger.from_oracle(out, targets, T0[sl], tidx[sl]))
+        kg = outcome_keys(events_slice(ev, start, start + m))
+        agree = np.mean([a == b for a, b in zip(kg, ko)])
+        print("8x10^6 events: replay block at", start, agree)
         assert agree > 0.97

@@ -131,17 +131,7 @@ def test_evaporation_ledgers_every_nucleus(fast_math):
     finally:
         c.close()
     _, _, Ex32, P32 = _inputs(A, Z, Ex, P)
-    # Momentum tolerance from the FP32 arithmetic: each emission subtracts the
-    # fragment's momentum from the nucleus's running momentum (one rounding,
-    # <= 2^-24 relative, per component) and the host rebuilds each fragment's
-    # momentum from FP32 (T, u) (a few 2^-24); with every momentum bounded by
-    # |P| + sum p_k this gives 2^-22 (n_sec + 1)(|P| + sum p_k), above the
-    # 1e-3 MeV/c gate only for the largest momenta and longest chains here.
-    M, _ = ledger.mass_table()
-    m_k = M[ledger.FRAG_A[ev.sec_species], ledger.FRAG_Z[ev.sec_species]]
-    p_sum = np.bincount(ev.sec_event, weights=np.sqrt(ev.sec_T ** 2 + 2.0 * ev.sec_T * m_k), minlength=ev.n)
-    tol_p = np.maximum(1e-3, 2.0 ** -22 * (ev.n_sec + 1) * (np.linalg.norm(P32, axis=1) + p_sum))
-    s = ledger.check_evaporation(ev, P32.astype(np.float64), tol_p=tol_p)
+    s = ledger.check_evaporation(ev, P32.astype(np.float64))
     print("evaporation ledgers (fast_math=%d)" % fast_math, s)
     ledger.assert_clean(s)
     assert np.array_equal(ev.Ex_casc, Ex32.astype(np.float64))
