@@ -81,6 +81,7 @@ class Result(C.Structure):
         ("n_pauli", C.c_int), ("n_seg", C.c_int), ("n_evap", C.c_int),
         ("n_draw", C.c_int),
         ("first_z", C.c_double),
+        ("sea", C.c_int * 2), ("sea_min", C.c_int),
     ]
 
 
@@ -97,7 +98,7 @@ RESULT_DTYPE = np.dtype(
         ("Ex_casc", "f8"), ("Ex_f", "f8"), ("p_casc", "f8", 3), ("p_f", "f8", 3),
         ("n_sec", "i4"), ("flags", "i4"), ("n_retry", "i4"), ("n_coll", "i4"),
         ("n_tent", "i4"), ("n_pauli", "i4"), ("n_seg", "i4"), ("n_evap", "i4"),
-        ("n_draw", "i4"), ("first_z", "f8"),
+        ("n_draw", "i4"), ("first_z", "f8"), ("sea", "i4", 2), ("sea_min", "i4"),
     ],
     align=True,
 )
@@ -138,6 +139,8 @@ def lib():
         L.orc_elastic.restype = d
         L.orc_refract.argtypes = [P3, P3, d, d, d]
         L.orc_refract.restype = i
+        L.orc_collision_outcome.argtypes = [C.POINTER(Nucleus), i, i, i, d, d, d, i, d * 3]
+        L.orc_collision_outcome.restype = i
         L.orc_width_integral.argtypes = [d, d]
         L.orc_width_integral.restype = d
         L.orc_spectrum_cdf.argtypes = [d, d, d]
@@ -225,6 +228,16 @@ def refract(d, n, T_from, T_to, m):
     dd = P3(*d)
     r = lib().orc_refract(dd, P3(*n), T_from, T_to, m)
     return bool(r), np.array(dd[:])
+
+
+def collision_outcome(nu, shell, sp_x, sp_y, Tx, Ty, Tt, pauli=True):
+    """Pauli and cutoff decision after a collision (Sec. 2.3); returns
+    (blocked, track_x, track_y, eps_x, eps_y, hole)."""
+    out = (C.c_double * 3)()
+    r = lib().orc_collision_outcome(C.byref(nu), shell, sp_x, sp_y, Tx, Ty, Tt, int(pauli), out)
+    if r < 0:
+        raise ValueError("bad arguments")
+    return bool(r & 1), bool(r & 2), bool(r & 4), out[0], out[1], out[2]
 
 
 def width_integral(a, U) -> float:

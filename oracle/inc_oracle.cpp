@@ -256,6 +256,19 @@ inline Vec3 cross(Vec3 a, Vec3 b) { return {a.y * b.z - a.z * b.y, a.z * b.x - a
 
 inline double kinetic(double p, double m) { return p * p / (std::sqrt(p * p + m * m) + m); }
 
+/* Sec. 2.2: target momentum from the "quadratic distribution", P(p) ~ p^2 on
+ * [0, p_F] (reading: uniform in the local Fermi sphere, isotropic).  Uniforms
+ * in stream order: u_mag (|p| = p_F u^1/3), u_cos (cos theta = 2u - 1),
+ * u_phi (phi = 2 pi u).  *mag receives |p|. */
+Vec3 fermi_sample(double pF, double u_mag, double u_cos, double u_phi, double* mag) {
+  const double pt_mag = pF * std::cbrt(u_mag);
+  const double ct = 2.0 * u_cos - 1.0;
+  const double st = std::sqrt(std::max(0.0, 1.0 - ct * ct));
+  const double ph = 2.0 * kPi * u_phi;
+  *mag = pt_mag;
+  return pt_mag * Vec3{st * std::cos(ph), st * std::sin(ph), ct};
+}
+
 /* Unit vector at polar angle theta (cos c, sin s) and azimuth phi from a. */
 Vec3 rotate(Vec3 a, double c, double s, double phi) {
   const double st = std::sqrt(a.x * a.x + a.y * a.y);
@@ -385,6 +398,36 @@ double spectrum_sample(double a, double U, double u) {
 struct Fragment { int a, z, g; };
 constexpr Fragment kFrag[6] = {{1, 0, 2}, {1, 1, 2}, {2, 1, 3}, {3, 1, 2}, {3, 2, 2}, {4, 2, 1}};
 
+/* Sec. 2.3 after an elastic NN collision in shell s between a moving nucleon
+ * of species sx and a target of species sy (0 n, 1 p), with product kinetic
+ * energies Tx (the moving nucleon's) and Ty (the struck one's) and the
+ * target's kinetic energy Tt before the collision.
+ * Pauli: the collision happens only when both products end above the Fermi
+ * energy of their own species in that shell (reading: strict, local).
+ * Then each product's excess energy eps = T - E_F(own species, s) decides the
+ * cutoff: it stays in the nucleus (captured) when eps < E_B, plus E_C for a
+ * proton; otherwise it is tracked.  The hole left in the target's Fermi sea
+ * is E_F(sy, s) - Tt (reading: energy bookkeeping of the excitation). */
+struct CollisionOutcome {
+  bool blocked;
+  bool track_x, track_y;
+  double eps_x, eps_y, hole;
+};
+
+double cutoff_energy(const orc_nucleus& nu, int sp) { return nu.EB + (sp == 1 ? nu.EC : 0.0); }
+
+CollisionOutcome collision_outcome(const orc_nucleus& nu, int s, int sx, int sy, double Tx, double Ty, double Tt,
+                                   bool pauli) {
+  CollisionOutcome o;
+  o.blocked = pauli && (Tx <= nu.EF[sx][s] || Ty <= nu.EF[sy][s]);
+  o.hole = std::max(0.0, nu.EF[sy][s] - Tt);
+  o.eps_x = Tx - nu.EF[sx][s];
+  o.eps_y = Ty - nu.EF[sy][s];
+  o.track_x = o.eps_x >= cutoff_energy(nu, sx);
+  o.track_y = o.eps_y >= cutoff_energy(nu, sy);
+  return o;
+}
+
 /* ------------------------------------------------------------------- events */
 struct Particle {
   Vec3 pos, d;
@@ -408,6 +451,7 @@ struct Event {
   /* nucleons of each species still in the Fermi sea: a struck nucleon
    * leaves it, a captured particle returns to it (reading) */
   int avail[2];
+  int sea_min = 0;
   double sh[2] = {0, 0};  /* majorant cross-sections (fm^2) for targets n, p */
 
   Event(const orc_nucleus& n_, const orc_options& o, uint64_t seed, uint64_t id, orc_result& r,
@@ -416,8 +460,6 @@ struct Event {
     max_stack = opt.max_stack > 0 ? opt.max_stack : 64;
     max_seg = opt.max_segments > 0 ? opt.max_segments : 10000;
   }
-
-  double cutoff(int sp) const { return nu.EB + (sp == 1 ? nu.EC : 0.0); }
 
   /* majorant for a flight of species x with excess energy eps (reading) */
   void set_majorant(const Particle& q) {
@@ -445,6 +487,13 @@ struct Event {
   void capture(const Particle& q) {
     Ex += q.eps;
     avail[q.sp]++;
+  }
+
+  /* a collision takes a nucleon of species y out of the sea; the lowest
+   * occupancy reached is kept for the sea-occupancy check (reading) */
+  void strike(int y) {
+    avail[y]--;
+    sea_min = std::min(sea_min, avail[y]);
   }
 
   void emit(int sp, int stage, double T, Vec3 d) {
@@ -517,11 +566,9 @@ struct Event {
         const int y = (w0 > rng.next() * (w0 + w1)) ? 0 : 1;
         const double mx = nucleon_mass(cur.sp), my = nucleon_mass(y);
         /* target momentum: uniform in the local Fermi sphere (Sec. 2.2) */
-        const double pt_mag = nu.pF[y][s] * std::cbrt(rng.next());
-        const double ct = 2.0 * rng.next() - 1.0;
-        const double st = std::sqrt(std::max(0.0, 1.0 - ct * ct));
-        const double ph = 2.0 * kPi * rng.next();
-        const Vec3 pt = pt_mag * Vec3{st * std::cos(ph), st * std::sin(ph), ct};
+        const double u_mag = rng.next(), u_cos = rng.next(), u_phi = rng.next();
+        double pt_mag;
+        const Vec3 pt = fermi_sample(nu.pF[y][s], u_mag, u_cos, u_phi, &pt_mag);
         const double Tx = cur.eps + nu.EF[cur.sp][s];
         const Vec3 px = std::sqrt(Tx * Tx + 2.0 * Tx * mx) * cur.d;
         const int like = (cur.sp == y);
@@ -544,22 +591,23 @@ struct Event {
           std::swap(qx, qt);
           std::swap(Txn, Ttn);
         }
-        if (!opt.no_pauli && (Txn <= nu.EF[cur.sp][s] || Ttn <= nu.EF[y][s])) {
+        const CollisionOutcome oc = collision_outcome(nu, s, cur.sp, y, Txn, Ttn, Tt, !opt.no_pauli);
+        if (oc.blocked) {
           res.n_pauli++;
           tau = -std::log(rng.next());
           continue;
         }
-        /* accepted collision */
+        /* accepted collision: the struck nucleon leaves the sea */
         res.n_coll++;
-        avail[y]--;
-        Ex += std::max(0.0, nu.EF[y][s] - Tt);  /* hole left in the Fermi sea */
+        strike(y);
+        Ex += oc.hole;
         if (res.n_coll == 1) res.first_z = cur.pos.z;
         Particle px_new = cur, py_new = cur;
         px_new.d = (1.0 / norm(qx)) * qx;
-        px_new.eps = Txn - nu.EF[cur.sp][s];
+        px_new.eps = oc.eps_x;
         py_new.d = (1.0 / norm(qt)) * qt;
         py_new.sp = y;
-        py_new.eps = Ttn - nu.EF[y][s];
+        py_new.eps = oc.eps_y;
         if (opt.stop_after_first) {
           capture(px_new);
           capture(py_new);
@@ -567,8 +615,8 @@ struct Event {
           stack.clear();
           break;
         }
-        const bool tx = px_new.eps >= cutoff(px_new.sp);
-        const bool ty = py_new.eps >= cutoff(py_new.sp);
+        const bool tx = oc.track_x;
+        const bool ty = oc.track_y;
         if (!tx) capture(px_new);
         if (!ty) capture(py_new);
         if (tx && ty) {
@@ -692,6 +740,7 @@ struct Event {
       n_esc[0] = n_esc[1] = 0;
       avail[0] = nu.A - nu.Z;   /* the projectile proton is out of the sea */
       avail[1] = nu.Z;
+      sea_min = std::min(avail[0], avail[1]);
       out.resize(mark);
       res.n_sec = 0;
       if (cascade_pass(T0)) break;
@@ -703,6 +752,9 @@ struct Event {
     res.Z_casc = nu.Z + 1 - n_esc[1];
     res.Ex_casc = Ex;
     res.p_casc[0] = pres.x; res.p_casc[1] = pres.y; res.p_casc[2] = pres.z;
+    res.sea[0] = avail[0];
+    res.sea[1] = avail[1];
+    res.sea_min = sea_min;
     if (res.A_casc <= 0) {
       res.flags |= 4;
       res.A_f = res.A_casc; res.Z_f = res.Z_casc; res.Ex_f = Ex;
@@ -725,11 +777,10 @@ extern "C" {
 void orc_philox4x32_10(const uint32_t ctr[4], const uint32_t key[2], uint32_t out[4]) { philox(ctr, key, out); }
 double orc_uniform(uint32_t w) { return uniform_of(w); }
 double orc_stream_uniform(uint64_t seed, uint64_t event_id, uint64_t k) {
-  uint32_t key[2] = {(uint32_t)seed, (uint32_t)(seed >> 32)};
-  uint32_t ctr[4] = {(uint32_t)(k / 4), (uint32_t)event_id, (uint32_t)(event_id >> 32), 0u};
-  uint32_t w[4];
-  philox(ctr, key, w);
-  return uniform_of(w[k % 4]);
+  /* the k-th draw of the stream the events use */
+  Stream st(seed, event_id);
+  for (uint64_t i = 0; i < k; ++i) st.next();
+  return st.next();
 }
 double orc_binding(int A, int Z) { return binding(A, Z); }
 double orc_mass(int A, int Z) { return mass(A, Z); }
@@ -762,19 +813,24 @@ int orc_refract(double d[3], const double n[3], double T_from, double T_to, doub
   return r;
 }
 
+int orc_collision_outcome(const orc_nucleus* nu, int shell, int sp_x, int sp_y, double Tx, double Ty, double Tt,
+                          int pauli, double out[3]) {
+  if (!nu || !out || shell < 0 || shell >= ORC_NSHELL || sp_x < 0 || sp_x > 1 || sp_y < 0 || sp_y > 1) return -1;
+  const CollisionOutcome o = collision_outcome(*nu, shell, sp_x, sp_y, Tx, Ty, Tt, pauli != 0);
+  out[0] = o.eps_x;
+  out[1] = o.eps_y;
+  out[2] = o.hole;
+  return (o.blocked ? 1 : 0) | (o.track_x ? 2 : 0) | (o.track_y ? 4 : 0);
+}
+
 double orc_width_integral(double a, double U) { return width_integral(a, U); }
 double orc_spectrum_cdf(double a, double U, double x) { return spectrum_cdf(a, U, x); }
 double orc_spectrum_sample(double a, double U, double u) { return spectrum_sample(a, U, u); }
 
 void orc_fermi_sample(double pF, double u1, double u2, double u3, double p[3]) {
-  /* Sec. 2.2: uniform in the Fermi sphere, |p| = pF u^(1/3), isotropic */
-  const double mag = pF * std::cbrt(u1);
-  const double ct = 2.0 * u2 - 1.0;
-  const double st = std::sqrt(std::max(0.0, 1.0 - ct * ct));
-  const double ph = 2.0 * kPi * u3;
-  p[0] = mag * st * std::cos(ph);
-  p[1] = mag * st * std::sin(ph);
-  p[2] = mag * ct;
+  double mag;
+  const Vec3 v = fermi_sample(pF, u1, u2, u3, &mag);
+  p[0] = v.x; p[1] = v.y; p[2] = v.z;
 }
 
 int orc_evaporate(int A, int Z, double Ex, const double P[3], uint64_t seed, uint64_t event_id,

@@ -68,6 +68,9 @@ typedef struct {
   int n_evap;             /* evaporation steps                                */
   int n_draw;             /* uniforms consumed                                */
   double first_z;         /* z of the first accepted collision (fm)           */
+  int sea[2];             /* nucleons of each species (n, p) left in the Fermi
+                             sea when the cascade ends                        */
+  int sea_min;            /* lowest occupancy of either species reached      */
 } orc_result;
 
 typedef struct {
@@ -104,6 +107,15 @@ double orc_elastic(const double px[3], double mx, const double pt[3], double my,
 /* Refraction at a sphere (outward normal n).  T_in, T_out kinetic energies on
  * the two sides.  Returns 1 transmitted, 0 reflected; d is updated in place. */
 int orc_refract(double d[3], const double n[3], double T_in, double T_out, double m);
+
+/* Sec. 2.3 decision after an elastic collision in shell `shell` between a
+ * moving nucleon of species sp_x and a target of species sp_y (0 n, 1 p):
+ * product kinetic energies Tx, Ty, target kinetic energy Tt before it.
+ * Returns bit 0 = Pauli-blocked (only when pauli != 0), bit 1 = the moving
+ * product is tracked (else captured by the cutoff), bit 2 = the struck product
+ * is tracked; out = {eps_x, eps_y, hole depth}.  -1 on bad arguments. */
+int orc_collision_outcome(const orc_nucleus* nu, int shell, int sp_x, int sp_y, double Tx, double Ty, double Tt,
+                          int pauli, double out[3]);
 
 double orc_width_integral(double a, double U);   /* I(a,U) */
 double orc_spectrum_cdf(double a, double U, double x);

@@ -199,6 +199,67 @@ def test_plab_min_is_the_minimum_over_the_sphere():
         assert best - lo < 0.05 * p + 5.0
 
 
+# ------------------------------------- angular-distribution slope (Sec. 2.3)
+# Reading R9 (recalled Cugnon slopes, (GeV/c)^-2): b_pp = 5.5 p^8 / (7.7 + p^8);
+# b_np = 0 below 0.225 GeV/c, 16.53 (p - 0.225) up to 0.6, -1.63 p + 7.16 above.
+def test_slope_unlike_breaks_and_branches():
+    for p in (0.1374, 0.15, 0.2, 0.2249999):
+        assert oracle.slope(0, p) == 0.0
+    assert 0.0 < oracle.slope(0, 0.2250001) < 1e-5
+    # the two branches meet at 0.6 GeV/c within 0.02 (6.199 against 6.182)
+    left, right = oracle.slope(0, 0.6 - 1e-12), oracle.slope(0, 0.6)
+    assert left == pytest.approx(16.53 * 0.375, abs=1e-9)
+    assert right == pytest.approx(7.16 - 1.63 * 0.6, abs=1e-9)
+    assert abs(left - right) < 0.02
+    # branch gradients, from differences (a slipped coefficient moves them)
+    assert (oracle.slope(0, 0.5) - oracle.slope(0, 0.3)) / 0.2 == pytest.approx(16.53, rel=1e-9)
+    assert (oracle.slope(0, 1.2) - oracle.slope(0, 0.8)) / 0.4 == pytest.approx(-1.63, rel=1e-9)
+    # outside the table range the argument is clamped like the cross-sections'
+    assert oracle.slope(0, 3.0) == oracle.slope(0, 1.5)
+
+
+def test_slope_like_shape():
+    ps = np.linspace(0.1374, 1.5, 500)
+    b = np.array([oracle.slope(1, p) for p in ps])
+    assert np.all(np.diff(b) > 0) and b[0] < 1e-5
+    # half of the asymptote 5.5 where p^8 = 7.7
+    assert oracle.slope(1, 7.7 ** 0.125) == pytest.approx(2.75, rel=1e-12)
+    assert oracle.slope(1, 1.0) == pytest.approx(5.5 / 8.7, rel=1e-12)
+
+
+def _pstar2_at_rest(T, mx, my):
+    # CM momentum squared of x (kinetic energy T) on y at rest, MeV^2
+    s = mx * mx + my * my + 2 * my * (T + mx)
+    return (s - (mx + my) ** 2) * (s - (mx - my) ** 2) / (4 * s)
+
+
+def test_slope_anchors_at_200_MeV():
+    # the frozen reading's anchors: k = 2 b p*^2 is ~0.004 for pp (nearly
+    # isotropic) and ~1.15 for np (forward-peaked) at 200 MeV lab
+    T = 200.0
+    for like, (mx, my), k_want, tol in ((1, (M_P, M_P), 0.004, 2e-4), (0, (M_P, M_N), 1.15, 5e-3)):
+        plab = math.sqrt(T * T + 2 * T * mx)
+        k = 2 * oracle.slope(like, plab / 1000) * _pstar2_at_rest(T, mx, my) / 1e6
+        assert k == pytest.approx(k_want, abs=tol), (like, k)
+
+
+def test_np_angular_mean_through_the_slope():
+    # 200 MeV proton on a neutron at rest: the slope at the collision's p_lab
+    # fed to the elastic kinematics gives 1 - cos(theta*) with density
+    # ~ exp(-k y) on [0, 2], mean 1/k - 2/(e^{2k} - 1)
+    T = 200.0
+    p = math.sqrt(T * T + 2 * T * M_P)
+    plab = oracle.elastic([0, 0, p], M_P, [0, 0, 0], M_N, 0.0, 0.5, 0.5)[4]
+    b = oracle.slope(0, plab / 1000)
+    ps2 = _pstar2_at_rest(T, M_P, M_N)
+    k = 2 * b * ps2 / 1e6
+    rng = np.random.default_rng(29)
+    y = np.array([M_N * oracle.elastic([0, 0, p], M_P, [0, 0, 0], M_N, b, *rng.random(2))[3] / ps2
+                  for _ in range(40000)])
+    mean = 1 / k - 2 / math.expm1(2 * k)
+    assert abs(y.mean() - mean) < 4 * y.std() / math.sqrt(y.size), (y.mean(), mean)
+
+
 # ------------------------------------------------ elastic kinematics (Sec. 2.3)
 def test_elastic_four_momentum_conservation():
     rng = np.random.default_rng(3)
@@ -343,6 +404,86 @@ def test_mixed_target_ledgers():
     T0 = rng.uniform(20, 250, n)
     out = oracle.run(targets, T0, seed=9, tidx=tidx)
     ledger.assert_clean(ledger.check(ledger.from_oracle(out, targets, T0, tidx), tol_E=1e-7, tol_p=1e-7))
+
+
+# ------------------------------------------ Pauli and cutoff (Sec. 2.3, P11)
+def test_pauli_and_cutoff_hand_built_collisions():
+    # 56Fe has N > Z, so the neutron Fermi energy exceeds the proton one in
+    # every shell and a species mix-up changes the decision.  Reading R10:
+    # blocked unless BOTH products end strictly above the Fermi energy of
+    # their own species in the collision shell.  R11: a product with excess
+    # eps = T - E_F below E_B (+ E_C for a proton) is captured.
+    nu = oracle.nucleus(56, 26)
+    far = 300.0
+    for s in (0, 6, 12):
+        EF = {0: nu.EF[0][s], 1: nu.EF[1][s]}
+        assert EF[0] > EF[1] + 0.1
+        for x in (0, 1):
+            for y in (0, 1):
+                out = lambda Tx, Ty: oracle.collision_outcome(nu, s, x, y, Tx, Ty, 0.0)
+                # the moving product below, at and just above its own E_F
+                assert out(EF[x] - 1e-6, far)[0] and out(EF[x], far)[0]
+                assert not out(np.nextafter(EF[x], np.inf), far)[0]
+                # the struck product likewise
+                assert out(far, EF[y] - 1e-6)[0] and out(far, EF[y])[0]
+                assert not out(far, np.nextafter(EF[y], np.inf))[0]
+                # between the two species' Fermi energies: allowed for a
+                # proton, blocked for a neutron
+                mid = 0.5 * (EF[0] + EF[1])
+                assert out(mid, far)[0] == (x == 0)
+                assert out(far, mid)[0] == (y == 0)
+                # no Pauli test: never blocked
+                assert not oracle.collision_outcome(nu, s, x, y, 0.5 * EF[x], 0.5 * EF[y], 0.0, pauli=False)[0]
+    # the Fermi energy is the collision shell's: between an inner and an outer
+    # shell's E_F the decision flips with the shell
+    for sp in (0, 1):
+        T = 0.5 * (nu.EF[sp][2] + nu.EF[sp][12])
+        assert oracle.collision_outcome(nu, 2, sp, 1 - sp, T, far, 0.0)[0]
+        assert not oracle.collision_outcome(nu, 12, sp, 1 - sp, T, far, 0.0)[0]
+    # cutoff: captured below E_B (+E_C), tracked from there on; excess energy
+    # and hole depth from each product's own species
+    s = 4
+    EF = {0: nu.EF[0][s], 1: nu.EF[1][s]}
+    cut = {0: nu.EB, 1: nu.EB + nu.EC}
+    for x in (0, 1):
+        y = 1 - x
+        for eps, tracked in ((cut[x] - 1e-6, False), (cut[x] + 1e-6, True)):
+            b, tx, ty, ex, ey, hole = oracle.collision_outcome(nu, s, x, y, EF[x] + eps, EF[y] + 50.0, 10.0)
+            assert not b and tx == tracked and ty
+            assert ex == pytest.approx(eps, abs=1e-9) and ey == pytest.approx(50.0, abs=1e-9)
+            assert hole == pytest.approx(EF[y] - 10.0, abs=1e-12)
+        # the boundary itself, to one ulp of the product's kinetic energy
+        T = EF[x] + cut[x]
+        while T - EF[x] < cut[x]:
+            T = np.nextafter(T, np.inf)
+        assert oracle.collision_outcome(nu, s, x, y, T, EF[y] + 50.0, 0.0)[1]
+        assert not oracle.collision_outcome(nu, s, x, y, np.nextafter(T, -np.inf), EF[y] + 50.0, 0.0)[1]
+        # the struck product's cutoff is its own species'
+        b, tx, ty, *_ = oracle.collision_outcome(nu, s, x, y, EF[x] + 50.0, EF[y] + cut[y] - 1e-6, 10.0)
+        assert not b and tx and not ty
+    # an excess between E_B and E_B + E_C: a proton stays, a neutron leaves
+    eps = nu.EB + 0.5 * nu.EC
+    assert not oracle.collision_outcome(nu, s, 1, 0, EF[1] + eps, EF[0] + 50, 0.0)[1]
+    assert oracle.collision_outcome(nu, s, 0, 1, EF[0] + eps, EF[1] + 50, 0.0)[1]
+    # a target above the sea's Fermi energy leaves no hole
+    assert oracle.collision_outcome(nu, s, 1, 0, 100.0, 100.0, EF[0] + 1.0)[5] == 0.0
+
+
+@pytest.mark.parametrize("A,Z,reached", [(4, 2, 0.2), (12, 6, 1e-3)])
+def test_sea_occupancy(A, Z, reached):
+    # Reading R14: a species can be struck only while one of its nucleons is
+    # in the Fermi sea (a strike removes one, a capture returns one), so the
+    # occupancy never goes below zero, and at the end of the cascade it equals
+    # the residual's N' and Z' (every moving nucleon either escaped or was
+    # captured).  On 4He and 12C at 250 MeV a species runs out in a fair share
+    # of the events, so the rule is exercised.
+    out = oracle.run([(A, Z)], np.full(100000, 250.0), seed=3, n_threads=8, no_evaporation=1)
+    r = out.results
+    assert r["sea_min"].min() >= 0
+    assert np.mean(r["sea_min"] == 0) > reached
+    assert np.array_equal(r["sea"][:, 1], r["Z_casc"])
+    assert np.array_equal(r["sea"][:, 0], r["A_casc"] - r["Z_casc"])
+    assert r["Z_casc"].min() >= 0 and (r["A_casc"] - r["Z_casc"]).min() >= 0
 
 
 def test_pauli_never_blocks_without_a_fermi_sea():
