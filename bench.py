@@ -453,9 +453,8 @@ def _serving(n_req: int, loads, budget: int, slots: int):
     srv = inc.Server(ctx, hbm_budget=budget, max_slots=slots)
     # saturated throughput: every request arrives at once
     sat_reqs = _serving_requests(max(n_req // 4, 50), seed=100)
-    ev = sum(len(q["T0"]) for q in sat_reqs)
-    _, span = srv.replay(np.zeros(len(sat_reqs)), sat_reqs)
-    sat = ev / span
+    srv.replay(np.zeros(len(sat_reqs)), sat_reqs)
+    sat = srv.stats()["events_per_s"]
     out = {"requests_per_load": n_req, "hbm_budget_bytes": budget, "slots": slots,
            "saturated_events_per_s": sat, "loads": []}
     for k, f in enumerate(loads):
@@ -464,12 +463,12 @@ def _serving(n_req: int, loads, budget: int, slots: int):
         lam = f * sat / mean_n
         arrivals = np.cumsum(np.random.default_rng(300 + k).exponential(1.0 / lam, n_req))
         arrivals -= arrivals[0]
-        lat, span = srv.replay(arrivals, reqs)
-        events = sum(len(q["T0"]) for q in reqs)
+        srv.stats_reset()
+        srv.replay(arrivals, reqs)
+        st = srv.stats()  # the server's own latency statistics over this load's requests
         out["loads"].append({"load": f, "arrival_rate_per_s": lam, "mean_events_per_request": mean_n,
-                             "p50_ms": float(np.percentile(lat, 50) * 1e3),
-                             "p99_ms": float(np.percentile(lat, 99) * 1e3),
-                             "events_per_s": events / span})
+                             "p50_ms": st["latency_p50_s"] * 1e3, "p99_ms": st["latency_p99_s"] * 1e3,
+                             "events_per_s": st["events_per_s"], "launches": st["launches"]})
         print("bench: serving load %.1f done" % f, file=sys.stderr, flush=True)
     srv.close()
     ctx.close()

@@ -43,15 +43,21 @@ extern "C" {
 #define INC_ERR_DEVICE -6     /* a HIP call or kernel launch failed           */
 #define INC_ERR_BUSY -7       /* serving: no free slot or HBM budget now      */
 
+/* Text of an error code (static storage).  Library plumbing, no passage of
+ * the paper. */
 const char* inc_strerror(int code);
 
 /* ------------------------------------------------------------- targets */
+/* A target nucleus (Sec. 2.2: the nuclear model is built per (A, Z)). */
 typedef struct {
   int A; /* mass number, 4 <= A <= 250 */
   int Z; /* charge, 1 <= Z <= A - 1    */
 } inc_nucleus;
 
-/* Options.  Zero-initialised = the method as specified, default launch. */
+/* Options.  Zero-initialised = the method as specified, default launch.
+ * The hooks reduce the model of Sec. 2.2-2.3 to special cases with closed
+ * forms; fast_math is the compiler switch of Sec. 4.2; the launch policy is
+ * the scheduling of Sec. 3 (one event per thread) on this hardware. */
 typedef struct {
   /* test hooks (special cases with closed-form answers) */
   int uniform_density;   /* every shell at A / (4/3 pi R^3)                  */
@@ -97,7 +103,9 @@ typedef struct {
                          /* Results do not depend on it.                     */
 } inc_options;
 
-/* One residual nucleus per event, 32 bytes. */
+/* One residual nucleus per event, 32 bytes: the excited nucleus the cascade
+ * leaves (Sec. 2.3, excitation from energy conservation) after its
+ * evaporation (Sec. 2.4), the per-event output of Sec. 3.2. */
 typedef struct {
   uint16_t A_f, Z_f;     /* final residual                                   */
   uint16_t n_sec;        /* secondaries of this event                        */
@@ -109,7 +117,9 @@ typedef struct {
   uint16_t n_retry;      /* transparent passes before the event (Sec. 2.1)   */
 } inc_residual;
 
-/* Device-side output buffers, owned by the caller. */
+/* Device-side output buffers, owned by the caller: the escaping particles of
+ * the cascade (Sec. 3.2) and the evaporated particles (Sec. 3.3) as one SoA
+ * list of secondaries, and one residual per event. */
 typedef struct {
   inc_residual* res;      /* device, n entries (event order)                 */
   uint32_t* sec_event;    /* device, sec_capacity entries: index in batch    */
@@ -127,7 +137,9 @@ typedef struct {
                             heads.  Reset by the call.                      */
 } inc_output;
 
-/* A batch of incident protons, in device memory. */
+/* A batch of incident protons, in device memory (Sec. 3.2: the input array
+ * of incident protons; here kinetic energy and target per event, incidence
+ * along +z with the impact point sampled per event). */
 typedef struct {
   size_t n;                 /* events, 1 <= n < 2^32                         */
   const uint8_t* target_idx;/* device, n entries into the context's targets;
@@ -137,6 +149,9 @@ typedef struct {
   uint64_t first_event_id;
 } inc_batch;
 
+/* Resident state on one device: nucleus tables, NN table, binding and
+ * evaporation tables (Sec. 2.2-2.4; Sec. 3.1 keeps such tables in constant
+ * and texture memory). */
 typedef struct inc_ctx inc_ctx;
 
 /* Build a context on the current device: nucleus shell tables (Sec. 2.2),
@@ -145,9 +160,12 @@ typedef struct inc_ctx inc_ctx;
  * targets: host array of n_targets (1..16) nuclei.  opt: host, may be NULL.
  * The context is not thread-safe: calls on one context must be serialised. */
 int inc_ctx_create(const inc_nucleus* targets, int n_targets, const inc_options* opt, inc_ctx** out);
+/* Release a context and everything it owns (synchronises the device first
+ * through hipFree).  INC_ERR_ARG for NULL. */
 int inc_ctx_destroy(inc_ctx* ctx);
 
-/* Copy the context's shell tables to host memory: for target t, 15 shells x
+/* Copy the context's shell tables (Sec. 2.2, Eq. (1): the 15-shell Fermi
+ * density, per-shell Fermi momenta and energies, E_B, E_C) to host memory: for target t, 15 shells x
  * {r_outer, rho_n, rho_p, pF_n, pF_p, EF_n, EF_p} floats, then E_B, E_C, R
  * (108 floats per target).  host_out must hold 108 * n_targets floats. */
 int inc_ctx_tables(const inc_ctx* ctx, float* host_out);
@@ -165,7 +183,8 @@ int inc_ctx_tables(const inc_ctx* ctx, float* host_out);
  * Synchronous.  Returns INC_ERR_ARG for a NULL context or out-param. */
 int inc_ctx_xs_table(const inc_ctx* ctx, float* host_out, int* n_nodes, float* p_lo, float* p_hi);
 
-/* Launch modes */
+/* Launch modes (Sec. 3.1-3.3 organise the work as one cascade, then one
+ * de-excitation, per thread) */
 #define INC_MODE_PLAIN 0      /* one event per thread; cascade kernel then
                                  evaporation kernel (the paper's Sec. 3 shape) */
 #define INC_MODE_PERSISTENT 1 /* one fused persistent kernel: lanes refill
@@ -178,7 +197,9 @@ int inc_ctx_xs_table(const inc_ctx* ctx, float* host_out, int* n_nodes, float* p
                                  evaporation kernel takes any rest.  Same
                                  results as INC_MODE_PERSISTENT               */
 
-/* Generate batch->n non-elastic events asynchronously on `stream` (a
+/* Generate batch->n non-elastic events (Sec. 2.1: cascade, Sec. 2.3, then
+ * evaporation, Sec. 2.4; inputs and outputs as in Sec. 3.2 and 3.3)
+ * asynchronously on `stream` (a
  * hipStream_t; NULL = the default stream).  All batch and output pointers
  * are device pointers.  Incident energies are validated on the device:
  * out-of-range events are skipped and counted in counters[1] with
@@ -227,7 +248,8 @@ typedef struct {            /* all arrays are device memory                  */
  * INC_ERR_DEVICE if a buffer cannot be grown or a launch fails. */
 int inc_evaporate_dev(inc_ctx* ctx, const inc_excited* in, const inc_output* out, void* stream);
 
-/* Convenience form (the spec call shape): synchronous, host arrays.
+/* Convenience form: synchronous, host arrays; events of Sec. 2.1-2.4 on one
+ * target, inputs and outputs of Sec. 3.2-3.3.
  * energies_MeV: host, n_events floats.  Results are copied to host arrays
  * res (n_events) and the secondary arrays (sec_capacity each); *n_sec
  * receives the number of secondaries produced.  Returns INC_ERR_CAPACITY when
@@ -273,33 +295,70 @@ typedef struct {            /* host buffers receiving a request's results   */
   double* latency_s;        /* out: submit -> results on host, or NULL       */
 } inc_host_output;
 
+/* Counters and latency statistics over the requests completed since the
+ * server was created or its statistics were reset.  A request's latency runs
+ * from its arrival (its submission; for inc_server_replay, its scheduled
+ * arrival time) to its results being on the host. */
 typedef struct {
   unsigned long long submitted, completed, rejected_busy, events, secondaries;
-  unsigned long long in_flight;
-  size_t pool_free_largest;
+  unsigned long long in_flight;   /* admitted, not yet fetched               */
+  size_t pool_free_largest;       /* largest free block of the device pool   */
+  unsigned long long launches;    /* kernel launches started                 */
+  double latency_p50_s;           /* median latency of completed requests    */
+  double latency_p99_s;           /* 99th percentile (linear interpolation
+                                     between order statistics, position
+                                     0.99 (n - 1) of the sorted latencies)  */
+  double events_per_s;            /* events of completed requests / (last
+                                     completion - first arrival)            */
 } inc_server_stats;
 
-/* hbm_budget: bytes of device memory for requests in flight (>= 1 MiB; the
- * server also pins the same amount of host memory); max_slots 1..16. */
+/* The serving loop follows the paper's use case (Sec. 1): a transport code
+ * hands nuclear-interaction events to the GPU as its protons undergo them, so
+ * batches arrive while others run.
+ * hbm_budget: bytes of device memory for requests in flight (>= 1 MiB; the
+ * server also pins the same amount of host memory); max_slots 1..16.
+ * INC_ERR_ARG for bad sizes, INC_ERR_OOM if the pool cannot be allocated. */
 int inc_server_create(inc_ctx* ctx, size_t hbm_budget, int max_slots, inc_server** out);
+/* Wait for the server's launches, then free its pool, mirror and streams;
+ * results not fetched are lost.  INC_ERR_ARG for NULL. */
 int inc_server_destroy(inc_server* server);
 /* Admit a request (its arrays are copied) or return INC_ERR_BUSY (retry
  * after fetching finished requests); INC_ERR_ARG if it can never fit the
- * budget.  On success *ticket identifies it. */
+ * budget.  On success *ticket identifies it.  (Sec. 1: one batch of the
+ * transport code's nuclear events; Sec. 3.2 inputs.) */
 int inc_server_submit(inc_server* server, const inc_request* req, uint64_t* ticket);
-/* 1 = results ready on the host, 0 = still running, < 0 error. */
+/* 1 = results ready on the host, 0 = still running, < 0 error (INC_ERR_ARG:
+ * unknown ticket). */
 int inc_server_poll(inc_server* server, uint64_t ticket);
+/* Block until a request's results are on the host (returns 1).  Returns
+ * INC_ERR_BUSY instead of waiting forever when the request is queued and
+ * cannot start by itself: the queue is held (inc_server_hold), or nothing is
+ * running and the head of the queue does not fit the pool because finished
+ * requests have not been fetched.  INC_ERR_ARG: unknown ticket. */
 int inc_server_wait(inc_server* server, uint64_t ticket);
 /* Copy a ready request's results (out may be NULL to discard) and release
  * its memory; returns the request's status (INC_ERR_CAPACITY when its
- * secondary buffer overflowed, INC_ERR_BUSY if it is not ready yet). */
+ * secondary buffer overflowed, INC_ERR_BUSY if it is not ready yet).
+ * Output: Sec. 3.2-3.3 (residual per event, secondaries). */
 int inc_server_fetch(inc_server* server, uint64_t ticket, const inc_host_output* out);
+/* Fill *out (host) with the statistics above.  INC_ERR_ARG for NULL. */
 int inc_server_stats_get(inc_server* server, inc_server_stats* out);
+/* Start a new statistics window: counters, latencies and the rate restart
+ * from zero (requests in flight are not affected). */
+int inc_server_stats_reset(inc_server* server);
+/* hold = 1: keep admitting and queueing requests but start no launch; hold =
+ * 0: release the queue (it is launched at once, as slots free up).  For a
+ * caller that hands over a burst of batches, e.g. all nuclear events of one
+ * transport step (Sec. 1), and wants them batched into as few launches as
+ * possible.  A launch carries at most 65535 requests.  INC_ERR_ARG for a
+ * NULL server or hold outside {0, 1}. */
+int inc_server_hold(inc_server* server, int hold);
 /* Native request loop: request k arrives arrival_s[k] seconds (ascending)
  * after the call starts; requests are admitted first come first served as
  * memory frees up, batched into launches as slots free up, polled, fetched
  * and discarded.  latency_s[k] receives arrival -> results on host; *span_s
- * the time from the first arrival to the last completion. */
+ * the time from the first arrival to the last completion.  The server's
+ * statistics cover these requests too (latency from the scheduled arrival). */
 int inc_server_replay(inc_server* server, int n_req, const double* arrival_s, const inc_request* reqs,
                       double* latency_s, double* span_s);
 
@@ -310,6 +369,7 @@ int inc_server_replay(inc_server* server, int n_req, const double* arrival_s, co
  * arrays (in ring order) and hands the space back.  A full ring makes the
  * producing waves wait (up to ~3 s without consumer progress, then the call
  * fails with INC_ERR_DEVICE); no record is lost or duplicated. */
+/* (Sec. 3.2-3.3: the secondaries of the batch, streamed.) */
 typedef struct inc_ring inc_ring;
 
 typedef struct {
@@ -321,7 +381,11 @@ typedef struct {
   unsigned int producer_gave_up; /* 1 if a wave timed out waiting for room    */
 } inc_ring_stats;
 
+/* Ring of `slots` records (power of two, 1024..2^30) in pinned coherent host
+ * memory (7 x 4 bytes per slot) for batches of `ctx`.  INC_ERR_ARG for bad
+ * sizes, INC_ERR_OOM if the host memory cannot be pinned. */
 int inc_ring_create(inc_ctx* ctx, size_t slots, inc_ring** out);
+/* Free a ring (no call may be running on it).  INC_ERR_ARG for NULL. */
 int inc_ring_destroy(inc_ring* ring);
 /* Generate batch->n events (device inputs, as inc_simulate_dev) with their
  * residuals written to d_res (device, n entries) and their secondaries
@@ -393,8 +457,8 @@ int inc_ctx_tally_shape(const inc_ctx* ctx, int* n_targets, int* amax, int* zmax
 int inc_tally_residuals(inc_ctx* ctx, const inc_batch* batch, const inc_residual* res, int n_ebins,
                         unsigned long long* table, void* stream);
 
-/* Library version of the frozen physics readings (changes when any reading
- * that affects results changes). */
+/* Library version of the frozen physics readings of Sec. 2 (changes when any
+ * reading that affects results changes). */
 int inc_contract_version(void);
 
 #ifdef __cplusplus

@@ -367,7 +367,7 @@ class Server:
         if rc == _lib.INC_ERR_BUSY:
             return None
         _lib.check(rc, "inc_server_submit")
-        self._keep[t.value] = (int(r.n), int(capacity or (r.n * 12 + 4096)))
+        self._keep[t.value] = (int(r.n), int(capacity or self.ctx.default_capacity(r.n)))
         return t.value
 
     def poll(self, ticket: int) -> bool:
@@ -400,9 +400,20 @@ class Server:
                     sec_species=sp[:k], sec_stage=st[:k], sec_T=T[:k], sec_u=np.stack([ux[:k], uy[:k], uz[:k]], 1))
 
     def stats(self) -> dict:
+        """Counters and the native latency statistics (p50, p99, events/s)
+        over the requests completed since creation or stats_reset()."""
         s = _lib.ServerStats()
         _lib.check(_lib.load().inc_server_stats_get(self._h, C.byref(s)), "inc_server_stats_get")
         return {f: getattr(s, f) for f, _ in s._fields_}
+
+    def stats_reset(self):
+        _lib.check(_lib.load().inc_server_stats_reset(self._h), "inc_server_stats_reset")
+
+    def hold(self, on: bool = True):
+        """Queue admitted requests without launching them (on), or release
+        the queue (off): a burst submitted while held goes out in as few
+        launches as possible."""
+        _lib.check(_lib.load().inc_server_hold(self._h, int(bool(on))), "inc_server_hold")
 
     def replay(self, arrivals_s, requests):
         """Native request loop.  requests: list of dicts with T0, target_idx,

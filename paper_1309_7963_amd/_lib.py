@@ -26,7 +26,8 @@ SYMBOLS = (
     "inc_strerror", "inc_ctx_create", "inc_ctx_destroy", "inc_ctx_tables", "inc_ctx_xs_table",
     "inc_simulate_dev", "inc_evaporate_dev", "inc_simulate", "inc_server_create", "inc_server_destroy",
     "inc_server_submit", "inc_server_poll", "inc_server_wait", "inc_server_fetch",
-    "inc_server_stats_get", "inc_server_replay", "inc_ring_create", "inc_ring_destroy",
+    "inc_server_stats_get", "inc_server_stats_reset", "inc_server_hold", "inc_server_replay", "inc_ring_create",
+    "inc_ring_destroy",
     "inc_ring_simulate", "inc_ring_simulate_to", "inc_ctx_tally_shape", "inc_tally_residuals", "inc_contract_version",
 )
 
@@ -90,7 +91,8 @@ class ServerStats(C.Structure):
     _fields_ = [
         ("submitted", C.c_ulonglong), ("completed", C.c_ulonglong), ("rejected_busy", C.c_ulonglong),
         ("events", C.c_ulonglong), ("secondaries", C.c_ulonglong), ("in_flight", C.c_ulonglong),
-        ("pool_free_largest", C.c_size_t),
+        ("pool_free_largest", C.c_size_t), ("launches", C.c_ulonglong), ("latency_p50_s", C.c_double),
+        ("latency_p99_s", C.c_double), ("events_per_s", C.c_double),
     ]
 
 
@@ -181,6 +183,10 @@ def load():
         L.inc_server_fetch.restype = C.c_int
         L.inc_server_stats_get.argtypes = [vp, C.POINTER(ServerStats)]
         L.inc_server_stats_get.restype = C.c_int
+        L.inc_server_stats_reset.argtypes = [vp]
+        L.inc_server_stats_reset.restype = C.c_int
+        L.inc_server_hold.argtypes = [vp, C.c_int]
+        L.inc_server_hold.restype = C.c_int
         L.inc_server_replay.argtypes = [vp, C.c_int, C.c_void_p, C.c_void_p, C.c_void_p, C.POINTER(C.c_double)]
         L.inc_server_replay.restype = C.c_int
         L.inc_ring_create.argtypes = [vp, C.c_size_t, C.POINTER(vp)]

@@ -20,7 +20,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libinc.so")
 SOURCES = ["api.hip", "setup.hip", "kernels.hip", "kernels_fast.hip", "server.hip", "ring.hip", "tally.hip"]
-HEADERS = ["device.h", "event.h", "kernels.h", "ctx.h"]
+HEADERS = ["device.h", "event.h", "kernels.h", "ctx.h", "copy_pool.h"]
 
 HIPCC_FLAGS = [
     "--offload-arch=gfx950",

@@ -18,81 +18,14 @@
 #include <thread>
 #include <vector>
 
+#include "copy_pool.h"
 #include "ctx.h"
 
+using incdev::CopyPool;
 using incdev::RingDev;
 using incdev::Segment;
 
 namespace {
-
-// Host copy workers of a ring.  Copying the drained records into the
-// caller's arrays is memory-bound on one thread and bounds the drain, so a
-// large run of ready records is cut into chunks that the calling thread and
-// these workers copy together.
-class CopyPool {
- public:
-  explicit CopyPool(int workers) {
-    for (int i = 0; i < workers; ++i) th_.emplace_back([this] { loop(); });
-  }
-  ~CopyPool() {
-    {
-      std::lock_guard<std::mutex> g(m_);
-      stop_ = true;
-    }
-    cv_.notify_all();
-    for (auto& t : th_) t.join();
-  }
-  // Run fn(c) for every chunk c in [0, n) on the workers and the caller;
-  // returns when all chunks are done.
-  void run(int n, const std::function<void(int)>& fn) {
-    {
-      std::lock_guard<std::mutex> g(m_);
-      fn_ = &fn;
-      n_ = n;
-      left_ = n;
-      next_.store(0);
-      ++gen_;
-    }
-    cv_.notify_all();
-    work();
-    std::unique_lock<std::mutex> l(m_);
-    done_cv_.wait(l, [this] { return left_ == 0; });
-  }
-
- private:
-  void work() {
-    int done = 0;
-    for (int c; (c = next_.fetch_add(1)) < n_;) {
-      (*fn_)(c);
-      ++done;
-    }
-    if (done) {
-      std::lock_guard<std::mutex> g(m_);
-      left_ -= done;
-      if (left_ == 0) done_cv_.notify_all();
-    }
-  }
-  void loop() {
-    unsigned seen = 0;
-    std::unique_lock<std::mutex> l(m_);
-    for (;;) {
-      cv_.wait(l, [&] { return stop_ || gen_ != seen; });
-      if (stop_) return;
-      seen = gen_;
-      l.unlock();
-      work();
-      l.lock();
-    }
-  }
-  std::vector<std::thread> th_;
-  std::mutex m_;
-  std::condition_variable cv_, done_cv_;
-  const std::function<void(int)>* fn_ = nullptr;
-  int n_ = 0, left_ = 0;
-  std::atomic<int> next_{0};
-  unsigned gen_ = 0;
-  bool stop_ = false;
-};
 
 constexpr size_t kCopyChunk = 16384;  // records per chunk of a parallel copy
 

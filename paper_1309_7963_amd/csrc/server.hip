@@ -30,7 +30,16 @@ using incdev::Segment;
 namespace {
 
 constexpr size_t kAlign = 256;
-size_t align_up(size_t v) { return (v + kAlign - 1) & ~(kAlign - 1); }
+constexpr size_t align_up(size_t v) { return (v + kAlign - 1) & ~(kAlign - 1); }
+
+// Requests per launch: a secondary record names its request (segment of the
+// launch) in 16 bits of its kind word (species | stage << 8 | segment << 16).
+constexpr size_t kMaxLaunchSegments = 65535;
+// Pool bytes a launch needs beyond its requests' own (work-queue heads, and
+// alignment of the segment table and the hand-over buffer); admission keeps
+// this much free for every slot, so the queue head can always start once the
+// launches in flight have been fetched.
+constexpr size_t kLaunchFixed = 16 * 16 + 2 * kAlign;
 
 double now_s() {
   using namespace std::chrono;
@@ -121,6 +130,7 @@ struct Request {
   unsigned long long n_sec;
   int rc;
   double t_submit, t_done;
+  double t_arrival;   // latency origin: submit, or the arrival time a replay gives
 };
 
 struct Launch {
@@ -130,7 +140,7 @@ struct Launch {
   std::vector<uint64_t> tickets;
   size_t seg_off, queue_off;
   int phase;
-  hipEvent_t ev_kernel;  // after the cascade, evaporation and export kernels
+  hipEvent_t ev_kernel;  // after the cascade, evaporation and export kernels (NULL if not created)
   int pending_fetch;
 };
 
@@ -152,6 +162,9 @@ struct inc_server {
   int next_launch;
   uint64_t next_ticket;
   inc_server_stats st;
+  int hold;                      // 1: admit and queue, start no launch
+  std::vector<double> latencies; // arrival -> results on host, completed requests
+  double t_first_arrival, t_last_done;
 };
 
 namespace {
@@ -200,6 +213,9 @@ void complete_launch(inc_server* s, Launch& L, int rc) {
     s->st.completed += 1;
     s->st.events += r.n;
     s->st.secondaries += r.n_sec;
+    s->latencies.push_back(t - r.t_arrival);
+    if (s->latencies.size() == 1 || r.t_arrival < s->t_first_arrival) s->t_first_arrival = r.t_arrival;
+    s->t_last_done = t;
   }
   L.phase = kDone;
   s->slot_busy[L.slot] = 0;
@@ -207,7 +223,7 @@ void complete_launch(inc_server* s, Launch& L, int rc) {
 
 // Advance a launch without blocking.
 void advance_launch(inc_server* s, Launch& L) {
-  if (L.phase == kRunning) {
+  if (L.phase == kRunning && L.ev_kernel) {
     const hipError_t q = hipEventQuery(L.ev_kernel);
     if (q == hipErrorNotReady) return;
     if (q != hipSuccess) {
@@ -227,7 +243,7 @@ void advance_launch(inc_server* s, Launch& L) {
 
 // Launch the queued requests that share the head's key on a free slot.
 int start_launch(inc_server* s) {
-  if (s->queue.empty()) return INC_OK;
+  if (s->queue.empty() || s->hold) return INC_OK;
   int slot = -1;
   for (size_t i = 0; i < s->streams.size(); ++i)
     if (!s->slot_busy[i]) {
@@ -240,11 +256,13 @@ int start_launch(inc_server* s) {
   const uint64_t key = s->reqs[s->queue.front()].seed;
   const size_t room = s->pool.largest();
   const size_t fixed = align_up(2 * sizeof(unsigned long long)) + 2 * kAlign;
+  static_assert(align_up(2 * sizeof(unsigned long long)) + 2 * kAlign <= kLaunchFixed, "admission reserve");
   std::vector<uint64_t> take;
   size_t n = 0, bytes = fixed;
   for (uint64_t tk : s->queue) {
     const Request& r = s->reqs[tk];
-    if (r.seed != key || n + r.n >= (1ull << 31) || bytes + r.bytes > room) break;
+    if (r.seed != key || n + r.n >= (1ull << 31) || bytes + r.bytes > room || take.size() >= kMaxLaunchSegments)
+      break;
     take.push_back(tk);
     n += r.n;
     bytes += r.bytes;
@@ -259,7 +277,9 @@ int start_launch(inc_server* s) {
   L.tickets = take;
   L.phase = kRunning;
   L.pending_fetch = (int)take.size();
+  L.ev_kernel = nullptr;
   const int id = s->next_launch++;
+  s->st.launches += 1;
   // layout: [T0][tidx][segments][queues][hand-over][per request: counters res T ux uy uz ev sp st]
   size_t o = 0;
   const size_t T0_off = o;   o += align_up(4 * n);
@@ -313,6 +333,7 @@ int start_launch(inc_server* s) {
   hipStream_t st = s->streams[slot];
   const size_t in_bytes = L.queue_off;  // T0, tidx and segment table are contiguous at the front
   hipError_t e = hipEventCreateWithFlags(&L.ev_kernel, hipEventDisableTiming);
+  if (e != hipSuccess) L.ev_kernel = nullptr;
   if (e == hipSuccess) e = hipMemcpyAsync(d, h, in_bytes, hipMemcpyHostToDevice, st);
   int rc = inc_map_hip_error(e);
   if (rc == INC_OK) {
@@ -349,6 +370,20 @@ void pump(inc_server* s) {
   }
 }
 
+// Pool bytes admission keeps free beyond the requests' own: one launch's fixed
+// share per slot.
+size_t reserve(const inc_server* s) { return kLaunchFixed * s->streams.size(); }
+
+// True when queued work can make no progress by itself: nothing is running
+// and the queue head does not fit the pool (its memory is held by results not
+// yet fetched).
+bool stalled(inc_server* s) {
+  if (s->queue.empty() || s->hold) return false;
+  for (const auto& kv : s->launches)
+    if (kv.second.phase == kRunning) return false;
+  return true;
+}
+
 void release_request(inc_server* s, uint64_t ticket) {
   auto it = s->reqs.find(ticket);
   if (it == s->reqs.end()) return;
@@ -358,7 +393,7 @@ void release_request(inc_server* s, uint64_t ticket) {
     auto lt = s->launches.find(r.launch);
     if (lt != s->launches.end() && --lt->second.pending_fetch == 0) {
       Launch& L = lt->second;
-      (void)hipEventDestroy(L.ev_kernel);
+      if (L.ev_kernel) (void)hipEventDestroy(L.ev_kernel);
       s->pool.release(L.off, L.bytes);
       s->launches.erase(lt);
     }
@@ -387,6 +422,8 @@ int inc_server_create(inc_ctx* ctx, size_t hbm_budget, int max_slots, inc_server
   s->next_ticket = 1;
   s->next_launch = 1;
   memset(&s->st, 0, sizeof(s->st));
+  s->hold = 0;
+  s->t_first_arrival = s->t_last_done = 0.0;
   hipError_t e = hipMalloc(&s->d_pool, hbm_budget);
   if (e == hipSuccess) e = hipHostMalloc(&s->h_pool, hbm_budget, hipHostMallocMapped);
   if (e == hipSuccess) e = hipHostGetDevicePointer((void**)&s->h_pool_dev, s->h_pool, 0);
@@ -411,7 +448,7 @@ int inc_server_destroy(inc_server* s) {
   if (!s) return INC_ERR_ARG;
   for (hipStream_t st : s->streams) (void)hipStreamSynchronize(st);
   for (auto& kv : s->launches) {
-    (void)hipEventDestroy(kv.second.ev_kernel);
+    if (kv.second.ev_kernel) (void)hipEventDestroy(kv.second.ev_kernel);
   }
   for (hipStream_t st : s->streams) (void)hipStreamDestroy(st);
   if (s->d_pool) (void)hipFree(s->d_pool);
@@ -425,9 +462,9 @@ int inc_server_submit(inc_server* s, const inc_request* q, uint64_t* ticket) {
   const size_t cap = q->sec_capacity ? q->sec_capacity : default_cap(s->ctx, q->n);
   const size_t bytes = request_bytes(q->n, cap);
   // a launch of this request alone must fit the pool
-  if (bytes + 4 * kAlign > s->budget) return INC_ERR_ARG;
+  if (bytes + reserve(s) > s->budget) return INC_ERR_ARG;
   pump(s);
-  if (s->charged + bytes + 4 * kAlign > s->budget) {
+  if (s->charged + bytes + reserve(s) > s->budget) {
     s->st.rejected_busy += 1;
     return INC_ERR_BUSY;
   }
@@ -447,6 +484,7 @@ int inc_server_submit(inc_server* s, const inc_request* q, uint64_t* ticket) {
   r.n_sec = 0;
   r.rc = INC_OK;
   r.t_submit = now_s();
+  r.t_arrival = r.t_submit;
   r.t_done = 0.0;
   const uint64_t t = s->next_ticket++;
   s->reqs.emplace(t, std::move(r));
@@ -473,8 +511,18 @@ int inc_server_wait(inc_server* s, uint64_t ticket) {
   while (true) {
     pump(s);
     if (it->second.state == kReady) return 1;
+    // a queued request behind results nobody fetched, or held back: it
+    // cannot launch until the caller acts
+    if (it->second.state == kQueued && (s->hold || stalled(s))) return INC_ERR_BUSY;
     std::this_thread::sleep_for(std::chrono::microseconds(20));
   }
+}
+
+int inc_server_hold(inc_server* s, int hold) {
+  if (!s || hold < 0 || hold > 1) return INC_ERR_ARG;
+  s->hold = hold;
+  pump(s);
+  return INC_OK;
 }
 
 int inc_server_fetch(inc_server* s, uint64_t ticket, const inc_host_output* out) {
@@ -505,11 +553,36 @@ int inc_server_fetch(inc_server* s, uint64_t ticket, const inc_host_output* out)
   return rc;
 }
 
+// q-quantile of a sample by linear interpolation between order statistics
+// (position q (n - 1) in the sorted sample).
+double quantile(std::vector<double> v, double q) {
+  if (v.empty()) return 0.0;
+  const double pos = q * (double)(v.size() - 1);
+  const size_t lo = (size_t)pos;
+  std::nth_element(v.begin(), v.begin() + lo, v.end());
+  const double a = v[lo];
+  if (lo + 1 >= v.size()) return a;
+  const double b = *std::min_element(v.begin() + lo + 1, v.end());
+  return a + (pos - (double)lo) * (b - a);
+}
+
 int inc_server_stats_get(inc_server* s, inc_server_stats* out) {
   if (!s || !out) return INC_ERR_ARG;
   *out = s->st;
   out->in_flight = s->reqs.size();
   out->pool_free_largest = s->pool.largest();
+  out->latency_p50_s = quantile(s->latencies, 0.50);
+  out->latency_p99_s = quantile(s->latencies, 0.99);
+  const double span = s->t_last_done - s->t_first_arrival;
+  out->events_per_s = s->latencies.empty() || !(span > 0.0) ? 0.0 : (double)s->st.events / span;
+  return INC_OK;
+}
+
+int inc_server_stats_reset(inc_server* s) {
+  if (!s) return INC_ERR_ARG;
+  memset(&s->st, 0, sizeof(s->st));
+  s->latencies.clear();
+  s->t_first_arrival = s->t_last_done = 0.0;
   return INC_OK;
 }
 
@@ -519,7 +592,7 @@ int inc_server_replay(inc_server* s, int n_req, const double* arrival_s, const i
   for (int i = 0; i < n_req; ++i) {
     if (i && arrival_s[i] < arrival_s[i - 1]) return INC_ERR_ARG;
     const size_t cap = reqs[i].sec_capacity ? reqs[i].sec_capacity : default_cap(s->ctx, reqs[i].n);
-    if (request_bytes(reqs[i].n, cap) + 4 * kAlign > s->budget) return INC_ERR_ARG;
+    if (request_bytes(reqs[i].n, cap) + reserve(s) > s->budget) return INC_ERR_ARG;
   }
   std::vector<uint64_t> ticket(n_req, 0);
   std::vector<int> state(n_req, 0);  // 0 waiting, 1 admitted, 2 done
@@ -538,6 +611,7 @@ int inc_server_replay(inc_server* s, int n_req, const double* arrival_s, const i
       const int rc = inc_server_submit(s, &reqs[k], &ticket[k]);
       if (rc == INC_ERR_BUSY) break;
       if (rc != INC_OK) return rc;
+      s->reqs[ticket[k]].t_arrival = t0 + arrival_s[k];
       state[k] = 1;
       admitted.push_back(k);
       ++head;
@@ -548,7 +622,7 @@ int inc_server_replay(inc_server* s, int n_req, const double* arrival_s, const i
       const int k = admitted[a];
       Request& r = s->reqs[ticket[k]];
       if (r.state == kReady) {
-        latency_s[k] = r.t_done - t0 - arrival_s[k];
+        latency_s[k] = r.t_done - r.t_arrival;
         t_last = std::max(t_last, r.t_done);
         const int rc = inc_server_fetch(s, ticket[k], nullptr);
         if (rc != INC_OK && rc_all == INC_OK) rc_all = rc;

@@ -419,16 +419,109 @@ def test_serving_admission_by_budget():
 
 
 def test_serving_replay_latencies():
+    # the server's native statistics (p50, p99 by linear interpolation between
+    # order statistics, events/s) equal numpy's over the latencies the
+    # replay returns, for one statistics window and the next
     import paper_1309_7963_amd as inc
 
     ctx = inc.Context(TISSUE)
     srv = inc.Server(ctx, hbm_budget=512 << 20, max_slots=4)
-    reqs = _serving_requests(40, seed=8)
-    arrivals = np.cumsum(np.random.default_rng(2).exponential(0.002, len(reqs)))
-    lat, span = srv.replay(arrivals, reqs)
-    assert np.all(lat > 0) and np.isfinite(lat).all()
-    assert span > 0
-    assert srv.stats()["completed"] == len(reqs)
+    for rep in range(2):
+        reqs = _serving_requests(40, seed=8 + rep)
+        arrivals = np.cumsum(np.random.default_rng(2 + rep).exponential(0.002, len(reqs)))
+        arrivals -= arrivals[0]
+        if rep:
+            srv.stats_reset()
+        lat, span = srv.replay(arrivals, reqs)
+        assert np.all(lat > 0) and np.isfinite(lat).all()
+        assert span > 0
+        st = srv.stats()
+        assert st["completed"] == len(reqs) and st["launches"] >= 1
+        assert st["events"] == sum(len(q["T0"]) for q in reqs)
+        print("serving stats: p50 %.3f ms p99 %.3f ms, %.3g events/s, %d launches"
+              % (st["latency_p50_s"] * 1e3, st["latency_p99_s"] * 1e3, st["events_per_s"], st["launches"]))
+        assert st["latency_p50_s"] == pytest.approx(np.percentile(lat, 50), rel=1e-12, abs=1e-15)
+        assert st["latency_p99_s"] == pytest.approx(np.percentile(lat, 99), rel=1e-12, abs=1e-15)
+        assert st["events_per_s"] == pytest.approx(st["events"] / span, rel=1e-9)
+    srv.close()
+    ctx.close()
+
+
+def test_serving_launch_of_more_than_65536_requests():
+    # a held queue of 70000 one-event requests: a launch takes at most 65535
+    # of them (a record names its request in 16 bits), the rest go in a second
+    # launch, and every request's result equals the same event generated in
+    # one direct launch
+    import paper_1309_7963_amd as inc
+
+    n_req = 70000
+    rng = np.random.default_rng(41)
+    tidx = rng.choice(5, size=n_req, p=TISSUE_W).astype(np.uint8)
+    T0 = rng.uniform(20, 250, n_req).astype(np.float32)
+    ctx = inc.Context(TISSUE)
+    srv = inc.Server(ctx, hbm_budget=512 << 20, max_slots=1)
+    srv.hold(True)
+    tickets = []
+    for r in range(n_req):
+        t = srv.submit(T0[r:r + 1], seed=13, target_idx=tidx[r:r + 1], first_event_id=r, capacity=64)
+        assert t is not None, r
+        tickets.append(t)
+    assert not srv.poll(tickets[0])
+    with pytest.raises(inc.IncError) as e:
+        srv.wait(tickets[0])  # held: would wait forever
+    assert e.value.code == inc.INC_ERR_BUSY
+    srv.hold(False)
+    got = []
+    for t in tickets:
+        srv.wait(t)
+        got.append(srv.fetch(t))
+    st = srv.stats()
+    assert st["launches"] == 2 and st["completed"] == n_req
+    direct = run_gpu(TISSUE, T0, seed=13, tidx=tidx, ctx=ctx)
+    res = np.concatenate([g["res"] for g in got])
+    assert res.tobytes() == direct["res"].tobytes()
+    assert all(g["rc"] == 0 for g in got)
+    ev = np.concatenate([np.full(len(g["sec_T"]), r) for r, g in enumerate(got)])
+    T = np.concatenate([g["sec_T"] for g in got])
+    sp = np.concatenate([g["sec_species"] for g in got])
+    assert np.all(np.concatenate([g["sec_event"] for g in got]) == 0)
+    kd = np.lexsort((direct["sec_T"], direct["sec_species"], direct["sec_event"]))
+    km = np.lexsort((T, sp, ev))
+    assert np.array_equal(direct["sec_event"][kd], ev[km])
+    assert np.array_equal(direct["sec_T"][kd], T[km]) and np.array_equal(direct["sec_species"][kd], sp[km])
+    srv.close()
+    ctx.close()
+
+
+def test_serving_wait_returns_when_results_block_the_queue():
+    # results left unfetched hold the device pool: with the first and third
+    # of three finished requests fetched, the pool's free space is split in
+    # two; a larger request is admitted (the budget counts bytes, not
+    # blocks) but fits neither, and with nothing running wait() reports
+    # INC_ERR_BUSY instead of spinning; once the middle one is fetched it runs
+    import paper_1309_7963_amd as inc
+
+    ctx = inc.Context(TISSUE)
+    srv = inc.Server(ctx, hbm_budget=16 << 20, max_slots=1)
+    small = np.full(16000, 200.0, np.float32)
+    t = []
+    for k in range(3):
+        t.append(srv.submit(small, seed=1 + k))
+        assert t[-1] is not None
+        srv.wait(t[-1])
+    assert srv.fetch(t[0])["rc"] == 0 and srv.fetch(t[2])["rc"] == 0
+    big = np.full(30000, 200.0, np.float32)
+    t4 = srv.submit(big, seed=9)
+    assert t4 is not None
+    with pytest.raises(inc.IncError) as e:
+        srv.wait(t4)
+    assert e.value.code == inc.INC_ERR_BUSY
+    assert srv.fetch(t[1])["rc"] == 0
+    srv.wait(t4)
+    r = srv.fetch(t4)
+    assert r["rc"] == 0
+    alone = run_gpu(TISSUE, big, seed=9, ctx=ctx)
+    assert r["res"].tobytes() == alone["res"].tobytes()
     srv.close()
     ctx.close()
 

@@ -97,3 +97,48 @@ def test_argument_errors_before_device(lib):
     e = (C.c_float * 1)(10.0)
     rc = L.inc_simulate(16, 8, e, 1, 1, None, None, None, None, None, None, None, None, 0, C.byref(nsec))
     assert rc == inc.INC_ERR_ARG
+
+
+# struct name in include/inc.h -> ctypes mirror in the binding
+STRUCTS = {
+    "inc_nucleus": "Nucleus", "inc_options": "Options", "inc_output": "Output", "inc_batch": "Batch",
+    "inc_excited": "Excited", "inc_request": "Request", "inc_host_output": "HostOutput",
+    "inc_server_stats": "ServerStats", "inc_ring_stats": "RingStats", "inc_ring_chunk": "RingChunk",
+}
+
+
+def test_struct_layouts_match_header(tmp_path):
+    # sizes and field offsets of every struct of the header, as the C
+    # compiler lays them out, against the binding's ctypes mirrors (and the
+    # residual record against its numpy dtype)
+    import ctypes as C
+
+    from paper_1309_7963_amd import _lib
+
+    lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "inc.h"', "int main(void) {"]
+    for cname, pname in STRUCTS.items():
+        lines.append('printf("%s size %%zu\\n", sizeof(%s));' % (cname, cname))
+        for f, _ in getattr(_lib, pname)._fields_:
+            lines.append('printf("%s %s %%zu\\n", offsetof(%s, %s));' % (cname, f, cname, f))
+    lines.append('printf("inc_residual size %zu\\n", sizeof(inc_residual));')
+    for f in _lib.RESIDUAL_DTYPE.names:
+        lines.append('printf("inc_residual %s %%zu\\n", offsetof(inc_residual, %s));' % (f, f))
+    lines.append("return 0; }")
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines))
+    exe = tmp_path / "layout"
+    import subprocess
+
+    subprocess.check_call(["gcc", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)])
+    got = {}
+    for ln in subprocess.check_output([str(exe)], text=True).splitlines():
+        a, b, c = ln.split()
+        got[(a, b)] = int(c)
+    for cname, pname in STRUCTS.items():
+        S = getattr(_lib, pname)
+        assert got[(cname, "size")] == C.sizeof(S), cname
+        for f, _ in S._fields_:
+            assert got[(cname, f)] == getattr(S, f).offset, (cname, f)
+    assert got[("inc_residual", "size")] == _lib.RESIDUAL_DTYPE.itemsize
+    for f in _lib.RESIDUAL_DTYPE.names:
+        assert got[("inc_residual", f)] == _lib.RESIDUAL_DTYPE.fields[f][1], f
