@@ -42,6 +42,8 @@ extern "C" {
 #define INC_ERR_OOM -5        /* device allocation failed                     */
 #define INC_ERR_DEVICE -6     /* a HIP call or kernel launch failed           */
 #define INC_ERR_BUSY -7       /* serving: no free slot or HBM budget now      */
+#define INC_ERR_TOO_LARGE -8  /* batch larger than inc_simulate_dev_noalloc's
+                                 workspace (INC_NOALLOC_MAX_EVENTS events)   */
 
 /* Text of an error code (static storage).  Library plumbing, no passage of
  * the paper. */
@@ -211,6 +213,27 @@ int inc_ctx_xs_table(const inc_ctx* ctx, float* host_out, int* n_nodes, float* p
  * context must not overlap on the device (one stream, or synchronise
  * between streams). */
 int inc_simulate_dev(inc_ctx* ctx, const inc_batch* batch, const inc_output* out, void* stream, int mode);
+
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * launch as inc_simulate_dev, with the same kernels, arguments, results and
+ * errors, except that the hand-over records, the start order and its
+ * histogram live in a static device workspace of the library instead of
+ * buffers the context grows, so the call allocates nothing (no hipMalloc,
+ * hipFree or allocating library routine).  The workspace holds one launch of
+ * at most INC_NOALLOC_MAX_EVENTS events (about 37 MiB, reserved on every
+ * device the library is loaded on until the process ends); larger batches
+ * return INC_ERR_TOO_LARGE with nothing launched.  All calls on one device
+ * share that device's workspace: calls that overlap on the device race (use
+ * one stream, or synchronise between streams), also across contexts.
+ * Everything the kernels read from the workspace is written first in the
+ * same launch, so a call never sees the previous call's contents.  The
+ * caller still owns the batch and output buffers.  INC_ERR_ARG as for
+ * inc_simulate_dev; INC_ERR_DEVICE if the workspace could not be found on
+ * the context's device. */
+#define INC_NOALLOC_MAX_EVENTS 1048576
+int inc_simulate_dev_noalloc(inc_ctx* ctx, const inc_batch* batch, const inc_output* out, void* stream,
+                             int mode);
 
 /* ------------------------------------------------ evaporation alone
  * The de-excitation stage of Sec. 2.4 (Weisskopf-Ewing evaporation of n, p,

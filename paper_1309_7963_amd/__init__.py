@@ -22,7 +22,7 @@ import numpy as np
 from . import _lib
 from ._lib import (  # noqa: F401
     INC_ERR_ARG, INC_ERR_BUSY, INC_ERR_CAPACITY, INC_ERR_DEVICE, INC_ERR_NO_DEVICE, INC_ERR_OOM, INC_ERR_RANGE,
-    MODE_PERSISTENT, MODE_PLAIN, MODE_STAGED, RESIDUAL_DTYPE, IncError,
+    INC_ERR_TOO_LARGE, NOALLOC_MAX_EVENTS, MODE_PERSISTENT, MODE_PLAIN, MODE_STAGED, RESIDUAL_DTYPE, IncError,
 )
 
 FLAG_STACK, FLAG_SEGMENTS, FLAG_EMPTY, FLAG_RANGE = 1, 2, 4, 0x8000
@@ -174,6 +174,19 @@ class Context:
         """Generate len(T0) non-elastic events asynchronously on `stream`
         (default: torch's current stream).  T0: float32 cuda tensor (MeV);
         target_idx: uint8 cuda tensor or None."""
+        return self._simulate("inc_simulate_dev", T0, seed, target_idx, first_event_id, mode, out, capacity, stream)
+
+    def simulate_noalloc(self, T0, seed: int, out: DeviceOutput, target_idx=None, first_event_id: int = 0,
+                         mode: str = "staged", capacity: Optional[int] = None, stream=None) -> DeviceOutput:
+        """inc_simulate_dev_noalloc: as simulate(), into the caller's `out`,
+        with the library's static workspace (no device allocation; at most
+        NOALLOC_MAX_EVENTS events; calls on one device must not overlap)."""
+        if out is None:
+            raise TypeError("simulate_noalloc needs caller-allocated output buffers")
+        return self._simulate("inc_simulate_dev_noalloc", T0, seed, target_idx, first_event_id, mode, out, capacity,
+                              stream)
+
+    def _simulate(self, entry, T0, seed, target_idx, first_event_id, mode, out, capacity, stream):
         torch = _torch()
         if not (torch.is_tensor(T0) and T0.is_cuda and T0.dtype == torch.float32 and T0.is_contiguous()):
             raise TypeError("T0 must be a contiguous float32 CUDA tensor")
@@ -195,8 +208,7 @@ class Context:
         o = out.c_struct(capacity)
         s = stream if stream is not None else torch.cuda.current_stream()
         m = MODES[mode]
-        _lib.check(_lib.load().inc_simulate_dev(self._h, C.byref(b), C.byref(o), C.c_void_p(s.cuda_stream), m),
-                   "inc_simulate_dev")
+        _lib.check(getattr(_lib.load(), entry)(self._h, C.byref(b), C.byref(o), C.c_void_p(s.cuda_stream), m), entry)
         return out
 
     def evaporate(self, A, Z, Ex, seed: int, P=None, first_event_id: int = 0, out: Optional[DeviceOutput] = None,

@@ -17,6 +17,8 @@ INC_ERR_NO_DEVICE = -4
 INC_ERR_OOM = -5
 INC_ERR_DEVICE = -6
 INC_ERR_BUSY = -7
+INC_ERR_TOO_LARGE = -8
+NOALLOC_MAX_EVENTS = 1048576
 MODE_PLAIN = 0
 MODE_PERSISTENT = 1
 MODE_STAGED = 2
@@ -24,7 +26,7 @@ MODE_STAGED = 2
 # exported symbols, in the order include/inc.h declares them
 SYMBOLS = (
     "inc_strerror", "inc_ctx_create", "inc_ctx_destroy", "inc_ctx_tables", "inc_ctx_xs_table",
-    "inc_simulate_dev", "inc_evaporate_dev", "inc_simulate", "inc_server_create", "inc_server_destroy",
+    "inc_simulate_dev", "inc_simulate_dev_noalloc", "inc_evaporate_dev", "inc_simulate", "inc_server_create", "inc_server_destroy",
     "inc_server_submit", "inc_server_poll", "inc_server_wait", "inc_server_fetch",
     "inc_server_stats_get", "inc_server_stats_reset", "inc_server_hold", "inc_server_replay", "inc_ring_create",
     "inc_ring_destroy",
@@ -160,6 +162,8 @@ def load():
         L.inc_ctx_xs_table.restype = C.c_int
         L.inc_simulate_dev.argtypes = [C.c_void_p, C.POINTER(Batch), C.POINTER(Output), C.c_void_p, C.c_int]
         L.inc_simulate_dev.restype = C.c_int
+        L.inc_simulate_dev_noalloc.argtypes = [C.c_void_p, C.POINTER(Batch), C.POINTER(Output), C.c_void_p, C.c_int]
+        L.inc_simulate_dev_noalloc.restype = C.c_int
         L.inc_evaporate_dev.argtypes = [C.c_void_p, C.POINTER(Excited), C.POINTER(Output), C.c_void_p]
         L.inc_evaporate_dev.restype = C.c_int
         L.inc_simulate.argtypes = [

@@ -3,13 +3,63 @@
 // convenience call.
 #include <string.h>
 
+#include <mutex>
 #include <new>
 
 #include "ctx.h"
 
 using namespace incdev;
 
+// Workspace of inc_simulate_dev_noalloc: the hand-over records (plain and
+// staged modes), the start order and its counting-sort histogram of one
+// launch of at most INC_NOALLOC_MAX_EVENTS events, in static device memory
+// (each device holds its own copy from the library's load to the process's
+// end).  Host code never passes this name to a kernel: it holds a host-side
+// stand-in, not a device address.  Every use goes through the address that
+// hipGetSymbolAddress returns for the current device (noalloc_ws).
 namespace {
+constexpr size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+constexpr size_t kWsMidBytes = align256(mid_bytes(INC_NOALLOC_MAX_EVENTS));
+constexpr size_t kWsPermBytes = align256(sizeof(uint32_t) * INC_NOALLOC_MAX_EVENTS);
+constexpr size_t kWsHistBytes = align256(sizeof(uint32_t) * kOrderHist);
+constexpr size_t kWsBytes = kWsMidBytes + kWsPermBytes + kWsHistBytes;
+constexpr int kWsMaxDevices = 64;
+}  // namespace
+static __device__ __align__(256) unsigned char scratch[kWsBytes];
+
+namespace {
+
+std::mutex ws_mu;
+unsigned char* ws_ptr[kWsMaxDevices];  // device address of `scratch`, per device
+
+// Resolve the workspace's address on device `dev` (current) once.
+hipError_t noalloc_resolve(int dev) {
+  if (dev < 0 || dev >= kWsMaxDevices) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> g(ws_mu);
+  if (ws_ptr[dev]) return hipSuccess;
+  void* p = nullptr;
+  const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+  if (e != hipSuccess) return e;
+  if (!p) return hipErrorInvalidSymbol;
+  ws_ptr[dev] = (unsigned char*)p;
+  return hipSuccess;
+}
+
+// The workspace of device `dev` as launch buffers (resolved by
+// inc_ctx_create on that device).
+bool noalloc_ws(int dev, Workspace* ws) {
+  if (dev < 0 || dev >= kWsMaxDevices) return false;
+  unsigned char* p;
+  {
+    std::lock_guard<std::mutex> g(ws_mu);
+    p = ws_ptr[dev];
+  }
+  if (!p) return false;
+  ws->mid = (MidState*)p;
+  ws->perm = (uint32_t*)(p + kWsMidBytes);
+  ws->hist = (uint32_t*)(p + kWsMidBytes + kWsPermBytes);
+  return true;
+}
 
 int map_err(hipError_t e) {
   if (e == hipSuccess) return INC_OK;
@@ -116,28 +166,36 @@ bool valid_output(const inc_output* out) {
 
 int inc_launch_segments(inc_ctx* ctx, size_t n, const uint8_t* tidx, const float* T0, const Segment* d_segs,
                         int n_seg, uint64_t seed, unsigned long long* queue, hipStream_t s, int mode, int max_blocks,
-                        const RingDev* ring, MidState* mid) {
+                        const RingDev* ring, MidState* mid, const Workspace* ws) {
+  // a launch of the context's own (no hand-over buffer brought by the caller)
+  const bool own = !mid;
+  if (ws) mid = ws->mid;
   if (!mid && (mode == INC_MODE_PLAIN || mode == INC_MODE_STAGED)) {
     const hipError_t e = ensure_mid(ctx, n);
     if (e != hipSuccess) return map_err(e);
   }
   // the context's own persistent launches start their costliest events first
   const uint32_t* perm = nullptr;
-  if (!mid && (mode == INC_MODE_PERSISTENT || mode == INC_MODE_STAGED) && n >= kOrderMin && !ctx->opt.input_order) {
+  if (own && (mode == INC_MODE_PERSISTENT || mode == INC_MODE_STAGED) && n >= kOrderMin && !ctx->opt.input_order) {
     hipError_t e = hipSuccess;
-    if (!ctx->d_order_hist) e = hipMalloc(&ctx->d_order_hist, sizeof(uint32_t) * kOrderHist);
-    if (e == hipSuccess && ctx->perm_cap < n) {
-      if (ctx->d_perm) (void)hipFree(ctx->d_perm);
-      ctx->d_perm = nullptr;
-      ctx->perm_cap = 0;
-      e = hipMalloc(&ctx->d_perm, sizeof(uint32_t) * n);
-      if (e == hipSuccess) ctx->perm_cap = n;
+    uint32_t* hist = ws ? ws->hist : ctx->d_order_hist;
+    uint32_t* order = ws ? ws->perm : ctx->d_perm;
+    if (!ws) {
+      if (!ctx->d_order_hist) e = hipMalloc(&ctx->d_order_hist, sizeof(uint32_t) * kOrderHist);
+      if (e == hipSuccess && ctx->perm_cap < n) {
+        if (ctx->d_perm) (void)hipFree(ctx->d_perm);
+        ctx->d_perm = nullptr;
+        ctx->perm_cap = 0;
+        e = hipMalloc(&ctx->d_perm, sizeof(uint32_t) * n);
+        if (e == hipSuccess) ctx->perm_cap = n;
+      }
+      hist = ctx->d_order_hist;
+      order = ctx->d_perm;
     }
     if (e == hipSuccess)
-      e = inc_launch_order(T0, tidx, n, ctx->d_nuc, ctx->n_targets, ctx->order_inv_cmax, ctx->d_order_hist,
-                           ctx->d_perm, s);
+      e = inc_launch_order(T0, tidx, n, ctx->d_nuc, ctx->n_targets, ctx->order_inv_cmax, hist, order, s);
     if (e != hipSuccess) return map_err(e);
-    perm = ctx->d_perm;
+    perm = order;
   }
   LaunchDesc L = launch_desc(ctx, n, mode, max_blocks);
   L.perm = perm;
@@ -152,7 +210,8 @@ int inc_launch_segments(inc_ctx* ctx, size_t n, const uint8_t* tidx, const float
   return map_err(ctx->opt.fast_math ? fast::launch_events(L, s) : precise::launch_events(L, s));
 }
 
-int inc_launch_batch(inc_ctx* ctx, const inc_batch* b, const inc_output* out, hipStream_t s, int mode, int max_blocks) {
+int inc_launch_batch(inc_ctx* ctx, const inc_batch* b, const inc_output* out, hipStream_t s, int mode, int max_blocks,
+                     const Workspace* ws) {
   if (!ctx || !b || !valid_output(out)) return INC_ERR_ARG;
   if (mode != INC_MODE_PLAIN && mode != INC_MODE_PERSISTENT && mode != INC_MODE_STAGED) return INC_ERR_ARG;
   if (b->n < 1 || b->n >= (1ull << 32) || !b->T0) return INC_ERR_ARG;
@@ -161,7 +220,7 @@ int inc_launch_batch(inc_ctx* ctx, const inc_batch* b, const inc_output* out, hi
   const int rc = map_err(inc_upload_segment(seg, slot, s));
   if (rc) return rc;
   return inc_launch_segments(ctx, b->n, b->target_idx, b->T0, slot, 1, b->seed, out->counters + 2, s, mode,
-                             max_blocks);
+                             max_blocks, nullptr, nullptr, ws);
 }
 
 int inc_map_hip_error(hipError_t e) { return map_err(e); }
@@ -178,6 +237,7 @@ const char* inc_strerror(int code) {
     case INC_ERR_OOM: return "device out of memory";
     case INC_ERR_DEVICE: return "HIP error";
     case INC_ERR_BUSY: return "no free slot or memory now";
+    case INC_ERR_TOO_LARGE: return "batch larger than the allocation-free entry point's workspace";
     default: return "unknown error";
   }
 }
@@ -205,6 +265,8 @@ int inc_ctx_create(const inc_nucleus* targets, int n_targets, const inc_options*
   int dev = 0, n_cu = 0;
   int rc = current_gfx950(&dev, &n_cu);
   if (rc) return rc;
+  // the allocation-free entry point's workspace on this device
+  if (noalloc_resolve(dev) != hipSuccess) return INC_ERR_DEVICE;
 
   inc_ctx* c = new (std::nothrow) inc_ctx;
   if (!c) return INC_ERR_OOM;
@@ -313,7 +375,15 @@ int inc_ctx_xs_table(const inc_ctx* ctx, float* host_out, int* n_nodes, float* p
 }
 
 int inc_simulate_dev(inc_ctx* ctx, const inc_batch* b, const inc_output* out, void* stream, int mode) {
-  return inc_launch_batch(ctx, b, out, (hipStream_t)stream, mode, 0);
+  return inc_launch_batch(ctx, b, out, (hipStream_t)stream, mode, 0, nullptr);
+}
+
+int inc_simulate_dev_noalloc(inc_ctx* ctx, const inc_batch* b, const inc_output* out, void* stream, int mode) {
+  if (!ctx || !b) return INC_ERR_ARG;
+  if (b->n > INC_NOALLOC_MAX_EVENTS) return INC_ERR_TOO_LARGE;
+  Workspace ws;
+  if (!noalloc_ws(ctx->device, &ws)) return INC_ERR_DEVICE;
+  return inc_launch_batch(ctx, b, out, (hipStream_t)stream, mode, 0, &ws);
 }
 
 int inc_evaporate_dev(inc_ctx* ctx, const inc_excited* in, const inc_output* out, void* stream) {

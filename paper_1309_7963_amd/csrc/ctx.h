@@ -34,6 +34,15 @@ struct inc_ctx {
 
 constexpr int kSegSlots = 64;  // inc_simulate_dev calls that may be in flight per context
 
+// Launch buffers that a caller brings instead of the context's own (grown on
+// demand): hand-over records for n events (plain and staged modes), the start
+// order (n entries) and its kOrderHist-count histogram.
+struct Workspace {
+  incdev::MidState* mid;
+  uint32_t* perm;
+  uint32_t* hist;
+};
+
 // Launch n events described by n_seg device segments (sorted by start, each
 // with its own ids and outputs) that share the random-stream key `seed`;
 // queue: two device work-queue counters.
@@ -41,17 +50,21 @@ constexpr int kSegSlots = 64;  // inc_simulate_dev calls that may be in flight p
 // mid: plain/staged hand-over buffer of n records (NULL: the context's own,
 // grown on demand; launches that overlap on different streams must each
 // bring their own).
+// ws: every launch buffer comes from ws and nothing is allocated (mid must be
+// NULL; the start order is used as for the context's own launches).
 __attribute__((visibility("hidden"))) int inc_launch_segments(inc_ctx* ctx, size_t n, const uint8_t* tidx,
                                                               const float* T0, const incdev::Segment* d_segs,
                                                               int n_seg, uint64_t seed, unsigned long long* queue,
                                                               hipStream_t s,
                                                               int mode, int max_blocks,
                                                               const incdev::RingDev* ring = nullptr,
-                                                              incdev::MidState* mid = nullptr);
+                                                              incdev::MidState* mid = nullptr,
+                                                              const Workspace* ws = nullptr);
 
 // Launch one batch (validated like inc_simulate_dev); max_blocks > 0 caps the
-// persistent grid (small batches use fewer blocks).  Internal to the library.
+// persistent grid (small batches use fewer blocks); ws as for
+// inc_launch_segments.  Internal to the library.
 __attribute__((visibility("hidden"))) int inc_launch_batch(inc_ctx* ctx, const inc_batch* b,
                                                            const inc_output* out, hipStream_t s, int mode,
-                                                           int max_blocks);
+                                                           int max_blocks, const Workspace* ws = nullptr);
 __attribute__((visibility("hidden"))) int inc_map_hip_error(hipError_t e);

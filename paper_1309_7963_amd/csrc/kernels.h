@@ -28,7 +28,7 @@ constexpr int kChunkEvents = 64;
 // evaporation kernel: [0] chunks listed, [1] chunks claimed by the
 // evaporation kernel, [2], [3] unused, then the first event of each listed
 // chunk.
-inline size_t mid_bytes(size_t n) {
+constexpr size_t mid_bytes(size_t n) {
   return sizeof(MidState) * n + sizeof(uint32_t) * (4 + (n + kChunkEvents - 1) / kChunkEvents);
 }
 

@@ -43,8 +43,8 @@ def test_binding_knows_every_symbol():
 
 def test_error_strings(lib):
     lib.inc_strerror.restype = C.c_char_p
-    for code in range(0, -7, -1):
-        assert lib.inc_strerror(code)
+    for code in range(0, -9, -1):
+        assert lib.inc_strerror(code) != b"unknown error"
     lib.inc_contract_version.restype = C.c_int
     assert lib.inc_contract_version() >= 1
 
