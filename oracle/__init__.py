@@ -67,6 +67,7 @@ class Options(C.Structure):
         ("fixed_b", C.c_double),
         ("max_stack", C.c_int),
         ("max_segments", C.c_int),
+        ("photon_evaporation", C.c_int),
     ]
 
 
@@ -148,7 +149,16 @@ def lib():
         L.orc_spectrum_sample.argtypes = [d, d, d]
         L.orc_spectrum_sample.restype = d
         L.orc_fermi_sample.argtypes = [d, d, d, d, d * 3]
-        L.orc_evaporate.argtypes = [i, i, d, d * 3, u64, u64, C.c_void_p, C.c_void_p, i]
+        for name in ("orc_photon_integral", "orc_photon_cdf", "orc_photon_sample"):
+            getattr(L, name).argtypes = [d, d] + ([d] if name != "orc_photon_integral" else [])
+            getattr(L, name).restype = d
+        L.orc_gdr_energy.argtypes = [i]
+        L.orc_gdr_energy.restype = d
+        L.orc_photon_s0.argtypes = [i, i]
+        L.orc_photon_s0.restype = d
+        L.orc_photon_width.argtypes = [i, i, d]
+        L.orc_photon_width.restype = d
+        L.orc_evaporate.argtypes = [i, i, d, d * 3, u64, u64, C.POINTER(Options), C.c_void_p, C.c_void_p, i]
         L.orc_evaporate.restype = i
         L.orc_run.argtypes = [
             C.POINTER(C.c_int), i, C.POINTER(Options), C.c_size_t,
@@ -258,15 +268,44 @@ def fermi_sample(pF, u1, u2, u3):
     return np.array(p[:])
 
 
-def evaporate(A, Z, Ex, P=(0.0, 0.0, 0.0), seed=1, event_id=0):
+def evaporate(A, Z, Ex, P=(0.0, 0.0, 0.0), seed=1, event_id=0, photon_evaporation=0):
     """Evaporate one excited nucleus; returns (result record, secondaries)."""
     res = np.zeros(1, dtype=RESULT_DTYPE)
+    opt = options(photon_evaporation=photon_evaporation)
     cap = A + 1
-    sec = np.zeros(cap, dtype=SECONDARY_DTYPE)
-    n = lib().orc_evaporate(A, Z, Ex, (C.c_double * 3)(*P), seed, event_id, res.ctypes.data, sec.ctypes.data, cap)
-    if n < 0:
-        raise ValueError("invalid nucleus")
-    return res[0], sec[:n].copy()
+    while True:
+        sec = np.zeros(cap, dtype=SECONDARY_DTYPE)
+        n = lib().orc_evaporate(A, Z, Ex, (C.c_double * 3)(*P), seed, event_id, C.byref(opt), res.ctypes.data,
+                                sec.ctypes.data, cap)
+        if n < 0:
+            raise ValueError("invalid nucleus")
+        if n <= cap:
+            return res[0], sec[:n].copy()
+        cap = n  # photons do not use up nucleons: run again with room for all
+
+
+def gdr_energy(A: int) -> float:
+    return lib().orc_gdr_energy(A)
+
+
+def photon_s0(A: int, Z: int) -> float:
+    return lib().orc_photon_s0(A, Z)
+
+
+def photon_integral(a, U) -> float:
+    return lib().orc_photon_integral(a, U)
+
+
+def photon_cdf(a, U, x) -> float:
+    return lib().orc_photon_cdf(a, U, x)
+
+
+def photon_sample(a, U, u) -> float:
+    return lib().orc_photon_sample(a, U, u)
+
+
+def photon_width(A: int, Z: int, E: float) -> float:
+    return lib().orc_photon_width(A, Z, E)
 
 
 @dataclass
@@ -290,15 +329,16 @@ def run(targets, T0, seed, tidx=None, first_id=0, n_threads=None, sec_per_event=
         sec_per_event = int(AZ[:, 0].max()) + 1
     res = np.zeros(n, dtype=RESULT_DTYPE)
     cap = max(1, n * sec_per_event)
-    sec = np.zeros(cap, dtype=SECONDARY_DTYPE)
     opt = options(**hooks)
-    total = lib().orc_run(
-        AZ.ctypes.data_as(C.POINTER(C.c_int)), AZ.shape[0], C.byref(opt), n,
-        tidx.ctypes.data if tidx is not None else None, T0.ctypes.data,
-        seed, first_id, res.ctypes.data, sec.ctypes.data, cap, n_threads,
-    )
-    if total < 0:
-        raise ValueError("oracle rejected the arguments")
-    if total > cap:
-        raise RuntimeError("secondary capacity exceeded")
-    return RunOutput(res, sec[:total].copy(), int(total))
+    while True:
+        sec = np.zeros(cap, dtype=SECONDARY_DTYPE)
+        total = lib().orc_run(
+            AZ.ctypes.data_as(C.POINTER(C.c_int)), AZ.shape[0], C.byref(opt), n,
+            tidx.ctypes.data if tidx is not None else None, T0.ctypes.data,
+            seed, first_id, res.ctypes.data, sec.ctypes.data, cap, n_threads,
+        )
+        if total < 0:
+            raise ValueError("oracle rejected the arguments")
+        if total <= cap:
+            return RunOutput(res, sec[:total].copy(), int(total))
+        cap = int(total)  # (photons add records beyond A + 1 per event) run again

@@ -398,6 +398,101 @@ double spectrum_sample(double a, double U, double u) {
 struct Fragment { int a, z, g; };
 constexpr Fragment kFrag[6] = {{1, 0, 2}, {1, 1, 2}, {2, 1, 3}, {3, 1, 2}, {3, 2, 2}, {4, 2, 1}};
 
+/* ------------------------------------------------ photon emission (option)
+ * Reading R19.  Sec. 2 has an excited nucleus shed its energy by particle
+ * emission first, then by photons; Sec. 2.4 leaves photon evaporation out,
+ * so it is an option, off by default.  The photon channel competes with the
+ * six particle channels at every step.  Detailed balance with two photon
+ * polarisations gives, in the units of the particle widths above (which are
+ * Gamma_j pi (hbar c)^2 rho(E)),
+ *   w_gamma = (1/pi) int_0^E eps^2 sigma_g(eps) rho(E - eps) d eps,
+ * with the same level density rho(U) = exp(2 sqrt(a U)), a = A/8 of the
+ * nucleus itself (a photon leaves A and Z unchanged).  The photoabsorption
+ * cross-section rises linearly, sigma_g = s0 eps, up to the giant-dipole
+ * energy E_G = 31.2 A^-1/3 + 20.6 A^-1/6 MeV so that the ramp holds the
+ * classical dipole sum 60 N Z / A mb MeV: s0 = 12 N Z / (A E_G^2) fm^2/MeV
+ * (1 mb = 0.1 fm^2).  Then w_gamma = (s0/pi) J(a, E), J(a, U) =
+ * int_0^U eps^3 exp(2 sqrt(a (U - eps))) d eps.  The channel is open while
+ * E > 0.1 MeV; below that the rest of E stays with the nucleus.  A nucleus
+ * with N = 0 or Z = 0 has no dipole strength (s0 = 0): no photons. */
+constexpr double kPhotonMin = 0.1;
+
+double gdr_energy(int A) { return 31.2 / std::cbrt((double)A) + 20.6 / std::pow((double)A, 1.0 / 6.0); }
+
+double photon_s0(int A, int Z) {
+  const double EG = gdr_energy(A);
+  return 12.0 * (double)(A - Z) * (double)Z / ((double)A * EG * EG);
+}
+
+/* L(y, Y) = int_0^y (Y^2 - t^2)^3 t e^t dt.  The polynomial is
+ * Y^6 t - 3 Y^4 t^3 + 3 Y^2 t^5 - t^7.  Small Y: the series of e^t, term
+ * by term; otherwise the antiderivative e^t sum_j (-1)^j P^(j)(t). */
+double photon_L(double y, double Y) {
+  double c[8] = {0.0, std::pow(Y, 6), 0.0, -3.0 * std::pow(Y, 4), 0.0, 3.0 * Y * Y, 0.0, -1.0};
+  if (Y < 10.0) {
+    double sum = 0.0, fact = 1.0;
+    for (int n = 0; n < 90; ++n) {
+      double inner = 0.0;  /* int_0^y P(t) t^n dt */
+      for (int k = 1; k < 8; k += 2) inner += c[k] * std::pow(y, k + n + 1) / (k + n + 1);
+      sum += inner / fact;
+      fact *= (n + 1);
+    }
+    return sum;
+  }
+  auto G = [&](double t) {
+    /* e^t sum_j (-1)^j P^(j)(t), derivatives of the coefficient array */
+    double d[8];
+    std::memcpy(d, c, sizeof(d));
+    double acc = 0.0, sign = 1.0;
+    for (int j = 0; j < 8; ++j) {
+      double v = 0.0;
+      for (int k = 7; k >= 0; --k) v = v * t + d[k];
+      acc += sign * v;
+      sign = -sign;
+      for (int k = 0; k < 7; ++k) d[k] = (k + 1) * d[k + 1];
+      d[7] = 0.0;
+    }
+    return std::exp(t) * acc;
+  };
+  return G(y) - G(0.0);
+}
+
+/* J(a, U) = int_0^U eps^3 exp(2 sqrt(a (U - eps))) d eps: with
+ * y = 2 sqrt(a (U - eps)), J = L(Y, Y) / (128 a^4), Y = 2 sqrt(a U); a -> 0
+ * gives U^4 / 4. */
+double photon_J(double a, double U) {
+  if (U <= 0.0) return 0.0;
+  if (a <= 0.0) return U * U * U * U / 4.0;
+  const double Y = 2.0 * std::sqrt(a * U);
+  return photon_L(Y, Y) / (128.0 * a * a * a * a);
+}
+
+/* CDF of the photon's energy share eps in [0, U]: density ~ eps^3 rho(U - eps). */
+double photon_cdf(double a, double U, double x) {
+  if (x <= 0.0) return 0.0;
+  if (x >= U) return 1.0;
+  if (a <= 0.0) return std::pow(x / U, 4);
+  const double Y = 2.0 * std::sqrt(a * U);
+  const double y = 2.0 * std::sqrt(a * (U - x));
+  const double LY = photon_L(Y, Y);
+  return (LY - photon_L(y, Y)) / LY;
+}
+
+double photon_sample(double a, double U, double u) {
+  double lo = 0.0, hi = U;
+  for (int it = 0; it < 200 && hi - lo > 1e-15 * U; ++it) {
+    const double mid = 0.5 * (lo + hi);
+    if (photon_cdf(a, U, mid) < u) lo = mid; else hi = mid;
+  }
+  return 0.5 * (lo + hi);
+}
+
+/* photon channel weight of nucleus (A, Z) at excitation E (0: closed) */
+double photon_width(int A, int Z, double E) {
+  if (!(E > kPhotonMin)) return 0.0;
+  return photon_s0(A, Z) / kPi * photon_J(A / 8.0, E);
+}
+
 /* Sec. 2.3 after an elastic NN collision in shell s between a moving nucleon
  * of species sx and a target of species sy (0 n, 1 p), with product kinetic
  * energies Tx (the moving nucleon's) and Ty (the struck one's) and the
@@ -670,7 +765,8 @@ struct Event {
 
   void evaporate(int A, int Z, double E, Vec3 P) {
     while (true) {
-      double w[6], U[6], V[6], a[6];
+      /* channels 0-5: the particles of kFrag; 6: a photon (option, R19) */
+      double w[7], U[6], V[6], a[6];
       int Ad[6], Zd[6];
       double total = 0.0;
       for (int j = 0; j < 6; ++j) {
@@ -689,16 +785,41 @@ struct Event {
         w[j] = kFrag[j].g * mass(kFrag[j].a, kFrag[j].z) * Rj * Rj * width_integral(a[j], U[j]);
         total += w[j];
       }
+      w[6] = opt.photon_evaporation ? photon_width(A, Z, E) : 0.0;
+      total += w[6];
       if (!(total > 0.0)) break;
       const double uc = rng.next() * total;
       int j = 0;
       double cum = 0.0;
-      for (j = 0; j < 6; ++j) {
+      for (j = 0; j < 7; ++j) {
         cum += w[j];
         if (w[j] > 0.0 && cum > uc) break;
       }
-      if (j == 6) {  /* rounding at the top: take the last open channel */
-        for (j = 5; j >= 0 && !(w[j] > 0.0); --j) {}
+      if (j == 7) {  /* rounding at the top: take the last open channel */
+        for (j = 6; j >= 0 && !(w[j] > 0.0); --j) {}
+      }
+      if (j == 6) {
+        /* photon: eps from its spectrum, A and Z unchanged; in the nucleus's
+         * rest frame the photon carries (Mp^2 - Md^2) / (2 Mp) */
+        const double x = photon_sample(A / 8.0, E, rng.next());
+        const double Ed = E - x;
+        const double Mp = mass(A, Z) + E;
+        const double Md = mass(A, Z) + Ed;
+        const double Eg = x * (Mp + Md) / (2.0 * Mp);
+        const double ct = 2.0 * rng.next() - 1.0;
+        const double st = std::sqrt(std::max(0.0, 1.0 - ct * ct));
+        const double ph = 2.0 * kPi * rng.next();
+        const Vec3 q = Eg * Vec3{st * std::cos(ph), st * std::sin(ph), ct};
+        const Vec3 u = (1.0 / Mp) * P;
+        const double g = std::sqrt(1.0 + dot(u, u));
+        Vec3 pf;
+        double Tf;
+        boost(q, 0.0, u, g, pf, Tf);
+        res.n_evap++;
+        emit(6, 1, Tf, (1.0 / norm(pf)) * pf);
+        P = P - pf;
+        E = Ed;
+        continue;
       }
       const double x = spectrum_sample(a[j], U[j], rng.next());
       const double Ed = U[j] - x;
@@ -826,6 +947,12 @@ int orc_collision_outcome(const orc_nucleus* nu, int shell, int sp_x, int sp_y, 
 double orc_width_integral(double a, double U) { return width_integral(a, U); }
 double orc_spectrum_cdf(double a, double U, double x) { return spectrum_cdf(a, U, x); }
 double orc_spectrum_sample(double a, double U, double u) { return spectrum_sample(a, U, u); }
+double orc_gdr_energy(int A) { return gdr_energy(A); }
+double orc_photon_s0(int A, int Z) { return photon_s0(A, Z); }
+double orc_photon_integral(double a, double U) { return photon_J(a, U); }
+double orc_photon_cdf(double a, double U, double x) { return photon_cdf(a, U, x); }
+double orc_photon_sample(double a, double U, double u) { return photon_sample(a, U, u); }
+double orc_photon_width(int A, int Z, double E) { return photon_width(A, Z, E); }
 
 void orc_fermi_sample(double pF, double u1, double u2, double u3, double p[3]) {
   double mag;
@@ -834,13 +961,14 @@ void orc_fermi_sample(double pF, double u1, double u2, double u3, double p[3]) {
 }
 
 int orc_evaporate(int A, int Z, double Ex, const double P[3], uint64_t seed, uint64_t event_id,
-                  orc_result* res, orc_secondary* sec, int sec_cap) {
+                  const orc_options* opt_in, orc_result* res, orc_secondary* sec, int sec_cap) {
   if (A < 1 || Z < 0 || Z > A || !(Ex >= 0.0) || !res) return -1;
   orc_nucleus nu;
   std::memset(&nu, 0, sizeof(nu));
   orc_options opt;
   std::memset(&opt, 0, sizeof(opt));
   opt.fixed_b = -1.0;
+  if (opt_in) opt.photon_evaporation = opt_in->photon_evaporation;
   std::vector<orc_secondary> out;
   std::memset(res, 0, sizeof(*res));
   Event ev(nu, opt, seed, event_id, *res, out, 0);

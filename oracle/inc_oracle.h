@@ -47,6 +47,8 @@ typedef struct {
   double fixed_b;         /* >= 0: fixed impact parameter (fm); < 0: sampled  */
   int max_stack;          /* 0 = default 64                                   */
   int max_segments;       /* 0 = default 10000                                */
+  int photon_evaporation; /* 1: photons compete with the particle channels of
+                             the evaporation (reading R19; off by default)    */
 } orc_options;
 
 /* Per-event result.  Stage-0 (cascade) and stage-1 (evaporation) secondaries
@@ -75,7 +77,7 @@ typedef struct {
 
 typedef struct {
   uint32_t event;         /* event index within the batch                     */
-  int species;            /* 0 n, 1 p, 2 d, 3 t, 4 3He, 5 alpha               */
+  int species;            /* 0 n, 1 p, 2 d, 3 t, 4 3He, 5 alpha, 6 photon     */
   int stage;              /* 0 cascade, 1 evaporation                         */
   double T;               /* kinetic energy (MeV)                             */
   double u[3];            /* direction (lab)                                  */
@@ -120,15 +122,23 @@ int orc_collision_outcome(const orc_nucleus* nu, int shell, int sp_x, int sp_y, 
 double orc_width_integral(double a, double U);   /* I(a,U) */
 double orc_spectrum_cdf(double a, double U, double x);
 double orc_spectrum_sample(double a, double U, double u);
+/* photon channel (option, reading R19) */
+double orc_gdr_energy(int A);                    /* E_G (MeV)                 */
+double orc_photon_s0(int A, int Z);              /* sigma_g / eps (fm^2/MeV)  */
+double orc_photon_integral(double a, double U);  /* J(a,U)                    */
+double orc_photon_cdf(double a, double U, double x);
+double orc_photon_sample(double a, double U, double u);
+double orc_photon_width(int A, int Z, double E); /* channel weight, 0 closed  */
 
 /* Sample a target momentum uniform in a Fermi sphere of radius pF. */
 void orc_fermi_sample(double pF, double u1, double u2, double u3, double p[3]);
 
 /* Evaporation (Sec. 2.4) of an excited nucleus (A, Z, Ex, momentum P) with the
- * stream of (seed, event_id).  Fills res->A_f, Z_f, Ex_f, p_f, n_evap, n_draw
+ * stream of (seed, event_id).  Of opt (NULL: defaults) only
+ * photon_evaporation applies.  Fills res->A_f, Z_f, Ex_f, p_f, n_evap, n_draw
  * and up to sec_cap secondaries; returns the number emitted or -1. */
 int orc_evaporate(int A, int Z, double Ex, const double P[3], uint64_t seed, uint64_t event_id,
-                  orc_result* res, orc_secondary* sec, int sec_cap);
+                  const orc_options* opt, orc_result* res, orc_secondary* sec, int sec_cap);
 
 /* --- event generation ----------------------------------------------------
  * targets: n_targets (A,Z) pairs.  tidx: per-event target index (NULL = 0).

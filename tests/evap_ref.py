@@ -24,9 +24,24 @@ def threshold(A: int, Z: int, j: int) -> float:
     return Q + V
 
 
-def branching(A: int, Z: int, E: float) -> np.ndarray:
+def photon_weight(A: int, Z: int, E: float) -> float:
+    """The photon channel's weight in the particle widths' units (reading
+    R19): (s0 / pi) int_0^E e^3 exp(2 sqrt(a (E - e))) de, a = A / 8,
+    s0 = 12 N Z / (A E_G^2) fm^2/MeV, E_G = 31.2 A^-1/3 + 20.6 A^-1/6 MeV;
+    0 at or below 0.1 MeV."""
+    if not E > ledger.PHOTON_MIN_EXCITATION:
+        return 0.0
+    EG = 31.2 * A ** (-1 / 3) + 20.6 * A ** (-1 / 6)
+    s0 = 12.0 * (A - Z) * Z / (A * EG * EG)
+    a = A / 8.0
+    J = integrate.quad(lambda x: x ** 3 * math.exp(2 * math.sqrt(a * max(E - x, 0))), 0, E, epsrel=1e-12)[0]
+    return s0 / math.pi * J
+
+
+def branching(A: int, Z: int, E: float, photons: bool = False) -> np.ndarray:
     """Gamma_j / sum Gamma at excitation E: Gamma_j = g_j m_j R_j^2 I(a_d, U_j),
-    I(a, U) = int_0^U x exp(2 sqrt(a (U - x))) dx, a_d = A_d / 8 MeV^-1."""
+    I(a, U) = int_0^U x exp(2 sqrt(a (U - x))) dx, a_d = A_d / 8 MeV^-1; with
+    photons, a seventh entry for the photon channel."""
     w = []
     for j in range(6):
         a = int(ledger.FRAG_A[j])
@@ -39,5 +54,7 @@ def branching(A: int, Z: int, E: float) -> np.ndarray:
         aa = Ad / 8.0
         I = integrate.quad(lambda x: x * math.exp(2 * math.sqrt(aa * max(U - x, 0))), 0, U, epsrel=1e-12)[0]
         w.append(ledger.FRAG_G[j] * oracle.mass(a, int(ledger.FRAG_Z[j])) * Rj * Rj * I)
+    if photons:
+        w.append(photon_weight(A, Z, E))
     w = np.array(w)
     return w / w.sum()

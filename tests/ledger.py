@@ -20,9 +20,13 @@ import numpy as np
 
 import oracle
 
-FRAG_A = np.array([1, 1, 2, 3, 3, 4])
-FRAG_Z = np.array([0, 1, 1, 1, 2, 2])
-FRAG_G = np.array([2, 2, 3, 2, 2, 1])
+# species 0-5: n, p, d, t, 3He, alpha; 6: photon (massless, no nucleons; the
+# optional photon channel)
+FRAG_A = np.array([1, 1, 2, 3, 3, 4, 0])
+FRAG_Z = np.array([0, 1, 1, 1, 2, 2, 0])
+FRAG_G = np.array([2, 2, 3, 2, 2, 1, 2])
+PHOTON = 6
+PHOTON_MIN_EXCITATION = 0.1  # MeV: the photon channel is open above this
 E2_COULOMB = 1.44
 M_PROTON = 938.272088
 
@@ -83,14 +87,17 @@ def from_oracle(out, targets, T0, tidx=None) -> Events:
     )
 
 
-def evaporate_oracle(A, Z, Ex, P=None, seed: int = 1, first_id: int = 0) -> Events:
+def evaporate_oracle(A, Z, Ex, P=None, seed: int = 1, first_id: int = 0, with_results: bool = False,
+                     photon_evaporation: int = 0):
     """Evaporation alone of nuclei (A[i], Z[i], Ex[i], P[i]) by the oracle, nucleus
-    i on the stream of (seed, first_id + i), as an Events batch (T0 = 0)."""
+    i on the stream of (seed, first_id + i), as an Events batch (T0 = 0); with
+    with_results, also the oracle's result records (draw counts included)."""
     n = len(A)
     P = np.zeros((n, 3)) if P is None else np.asarray(P, dtype=np.float64).reshape(n, 3)
     rows, secs = [], []
     for i in range(n):
-        r, s = oracle.evaporate(int(A[i]), int(Z[i]), float(Ex[i]), tuple(P[i]), seed=seed, event_id=first_id + i)
+        r, s = oracle.evaporate(int(A[i]), int(Z[i]), float(Ex[i]), tuple(P[i]), seed=seed, event_id=first_id + i,
+                                photon_evaporation=photon_evaporation)
         r = r.copy()
         r["n_sec"] = len(s)
         rows.append(r)
@@ -99,7 +106,7 @@ def evaporate_oracle(A, Z, Ex, P=None, seed: int = 1, first_id: int = 0) -> Even
         secs.append(s)
     r = np.array(rows)
     s = np.concatenate(secs) if secs else np.zeros(0, dtype=oracle.SECONDARY_DTYPE)
-    return Events(
+    ev = Events(
         A=np.asarray(A, dtype=np.int64), Z=np.asarray(Z, dtype=np.int64), T0=np.zeros(n),
         A_f=r["A_f"].astype(np.int64), Z_f=r["Z_f"].astype(np.int64),
         Ex_casc=np.asarray(Ex, dtype=np.float64), Ex_f=r["Ex_f"].astype(np.float64),
@@ -109,14 +116,18 @@ def evaporate_oracle(A, Z, Ex, P=None, seed: int = 1, first_id: int = 0) -> Even
         sec_stage=s["stage"].astype(np.int64), sec_T=s["T"].astype(np.float64),
         sec_u=np.asarray(s["u"], dtype=np.float64),
     )
+    return (ev, r) if with_results else ev
+
 
 
 def _sum_by_event(idx, w, n):
     return np.bincount(idx, weights=w, minlength=n)
 
 
-def check(ev: Events, tol_E: float = 1e-3, tol_p: float = 1e-3, tol_u: float = 1e-5) -> dict:
-    """Return violation counts and worst residuals for every per-event check."""
+def check(ev: Events, tol_E: float = 1e-3, tol_p: float = 1e-3, tol_u: float = 1e-5, photons: bool = False) -> dict:
+    """Return violation counts and worst residuals for every per-event check
+    (photons: the photon channel was on, so no event may end above its
+    threshold either)."""
     M, B = mass_table()
     n = ev.n
     e = ev.sec_event
@@ -174,13 +185,13 @@ def check(ev: Events, tol_E: float = 1e-3, tol_p: float = 1e-3, tol_u: float = 1
     out["bad_T"] = int(np.sum(T < 0))
     un = np.sqrt(np.sum(ev.sec_u ** 2, axis=1))
     out["bad_u"] = int(np.sum(np.abs(un - 1.0) > tol_u))
-    out["bad_threshold"] = _open_channel_left(ev, B)
+    out["bad_threshold"] = _open_channel_left(ev, B, photons)
     out["n_events"] = n
     out["n_secondaries"] = int(e.shape[0])
     return out
 
 
-def _open_channel_left(ev: Events, B) -> int:
+def _open_channel_left(ev: Events, B, photons: bool = False) -> int:
     """Events whose final nucleus still has an open channel: E*_f >= S_j + V_j
     for some valid channel j (beyond 1e-4 MeV of FP32 slack)."""
     bad_thr = np.zeros(ev.n, dtype=bool)
@@ -197,10 +208,18 @@ def _open_channel_left(ev: Events, B) -> int:
             0.0,
         )
         bad_thr |= valid & (ev.Ex_f - S - V > 1e-4) & (ev.flags & 4 == 0)
+    if photons:
+        # the photon channel is open above 0.1 MeV wherever there is dipole
+        # strength (N Z > 0)
+        has_dipole = (Af - Zf) * Zf > 0
+        bad_thr |= (ev.Ex_f > PHOTON_MIN_EXCITATION + 1e-4) & has_dipole & (ev.flags & 4 == 0)
+    else:
+        bad_thr |= np.bincount(ev.sec_event[ev.sec_species == PHOTON], minlength=ev.n) > 0
     return int(np.sum(bad_thr))
 
 
-def check_evaporation(ev: Events, P_in, tol_E: float = 1e-3, tol_p: float = 1e-3, tol_u: float = 1e-5) -> dict:
+def check_evaporation(ev: Events, P_in, tol_E: float = 1e-3, tol_p: float = 1e-3, tol_u: float = 1e-5,
+                      photons: bool = False) -> dict:
     """Per-nucleus checks of an evaporation-only batch (Sec. 2.4): nucleus i,
     (A, Z) with excitation Ex_casc and lab momentum P_in[i], decays into its
     records (all stage 1) and the final nucleus.
@@ -242,7 +261,7 @@ def check_evaporation(ev: Events, P_in, tol_E: float = 1e-3, tol_p: float = 1e-3
     out["bad_T"] = int(np.sum(T < 0))
     un = np.sqrt(np.sum(ev.sec_u ** 2, axis=1))
     out["bad_u"] = int(np.sum(np.abs(un - 1.0) > tol_u))
-    out["bad_threshold"] = _open_channel_left(ev, B)
+    out["bad_threshold"] = _open_channel_left(ev, B, photons)
     out["n_events"] = n
     out["n_secondaries"] = int(e.shape[0])
     return out
