@@ -103,6 +103,17 @@ typedef struct {
                          /* (A^1/3 (T0 + 50 MeV), a counting sort on the     */
                          /* device); 1: start them in input order instead.   */
                          /* Results do not depend on it.                     */
+  /* model extension (Sec. 2, 2.4) */
+  int photon_evaporation; /* 1: photons compete with the six particle       */
+                         /* channels at every evaporation step (species 6,   */
+                         /* stage 1, T = photon energy): detailed-balance    */
+                         /* width with a photoabsorption cross-section      */
+                         /* rising linearly to the giant-dipole energy and  */
+                         /* holding the classical dipole sum, open while     */
+                         /* E* > 0.1 MeV and N Z > 0.  Sec. 2 has excited    */
+                         /* nuclei shed energy by particles, then photons;  */
+                         /* Sec. 2.4 leaves photons out, so 0 (the default) */
+                         /* is the paper's model                             */
 } inc_options;
 
 /* One residual nucleus per event, 32 bytes: the excited nucleus the cascade
@@ -125,7 +136,8 @@ typedef struct {
 typedef struct {
   inc_residual* res;      /* device, n entries (event order)                 */
   uint32_t* sec_event;    /* device, sec_capacity entries: index in batch    */
-  uint8_t* sec_species;   /* device, sec_capacity                            */
+  uint8_t* sec_species;   /* device, sec_capacity: 0 n, 1 p, 2 d, 3 t, 4 3He,
+                             5 alpha, 6 photon (photon_evaporation)        */
   uint8_t* sec_stage;     /* device, sec_capacity                            */
   float* sec_T;           /* device, sec_capacity: kinetic energy (MeV)      */
   float* sec_ux;          /* device, sec_capacity: direction cosines         */
@@ -137,6 +149,18 @@ typedef struct {
                                 only the first sec_capacity are stored),
                             [1] flagged events, [2] and [3] work-queue
                             heads.  Reset by the call.                      */
+  uint32_t* history;      /* device, 3 n entries, or NULL (not written):
+                            per event [0] the uniforms drawn from its
+                            Philox stream (Sec. 3.1), cascade and
+                            evaporation together, [1] its cascade's flight
+                            segments (Sec. 2.3: one per shell crossing or
+                            tentative collision point), [2] where its
+                            tentative collisions happened: h = 3 h +
+                            shell + 1 over them in order from h = 0, mod
+                            2^32 (shells 0..14 from the centre).  All 0
+                            for a flagged out-of-range event.  A
+                            diagnostic of the event's path, e.g. for
+                            comparing replays of one stream               */
 } inc_output;
 
 /* A batch of incident protons, in device memory (Sec. 3.2: the input array

@@ -82,7 +82,7 @@ class Result(C.Structure):
         ("n_pauli", C.c_int), ("n_seg", C.c_int), ("n_evap", C.c_int),
         ("n_draw", C.c_int),
         ("first_z", C.c_double),
-        ("sea", C.c_int * 2), ("sea_min", C.c_int),
+        ("sea", C.c_int * 2), ("sea_min", C.c_int), ("tent_shells", C.c_uint32),
     ]
 
 
@@ -99,7 +99,7 @@ RESULT_DTYPE = np.dtype(
         ("Ex_casc", "f8"), ("Ex_f", "f8"), ("p_casc", "f8", 3), ("p_f", "f8", 3),
         ("n_sec", "i4"), ("flags", "i4"), ("n_retry", "i4"), ("n_coll", "i4"),
         ("n_tent", "i4"), ("n_pauli", "i4"), ("n_seg", "i4"), ("n_evap", "i4"),
-        ("n_draw", "i4"), ("first_z", "f8"), ("sea", "i4", 2), ("sea_min", "i4"),
+        ("n_draw", "i4"), ("first_z", "f8"), ("sea", "i4", 2), ("sea_min", "i4"), ("tent_shells", "u4"),
     ],
     align=True,
 )

@@ -657,6 +657,7 @@ struct Event {
         /* tentative collision (null-collision flight, reading) */
         cur.pos = cur.pos + (tau / lam) * cur.d;
         res.n_tent++;
+        res.tent_shells = res.tent_shells * 3u + (uint32_t)(s + 1);
         const double w0 = weight(0, s), w1 = weight(1, s);
         const int y = (w0 > rng.next() * (w0 + w1)) ? 0 : 1;
         const double mx = nucleon_mass(cur.sp), my = nucleon_mass(y);

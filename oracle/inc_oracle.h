@@ -73,6 +73,9 @@ typedef struct {
   int sea[2];             /* nucleons of each species (n, p) left in the Fermi
                              sea when the cascade ends                        */
   int sea_min;            /* lowest occupancy of either species reached      */
+  uint32_t tent_shells;   /* h = 3 h + shell + 1 over the tentative collisions
+                             in order, from h = 0 (mod 2^32): where they
+                             happened, a fingerprint of the event's path      */
 } orc_result;
 
 typedef struct {

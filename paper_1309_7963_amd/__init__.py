@@ -48,13 +48,16 @@ class DeviceOutput:
     sec_uy: "object"
     sec_uz: "object"
     counters: "object"     # int64 [4]
+    history: "object" = None  # int32 [3 n] (uint32 values) or None: per event the
+    #                           uniforms drawn, the cascade's flight segments and
+    #                           the shell fingerprint of its tentative collisions
 
     @property
     def capacity(self) -> int:
         return int(self.sec_T.shape[0])
 
     @classmethod
-    def allocate(cls, n: int, capacity: int, device="cuda"):
+    def allocate(cls, n: int, capacity: int, device="cuda", history: bool = False):
         torch = _torch()
         cap = max(int(capacity), 1)
         e = lambda dt: torch.empty(cap, dtype=dt, device=device)
@@ -64,6 +67,7 @@ class DeviceOutput:
             sec_event=e(torch.int32), sec_species=e(torch.uint8), sec_stage=e(torch.uint8),
             sec_T=e(torch.float32), sec_ux=e(torch.float32), sec_uy=e(torch.float32), sec_uz=e(torch.float32),
             counters=torch.zeros(4, dtype=torch.int64, device=device),
+            history=torch.empty(3 * n, dtype=torch.int32, device=device) if history else None,
         )
 
     def c_struct(self, capacity: Optional[int] = None) -> _lib.Output:
@@ -78,6 +82,7 @@ class DeviceOutput:
         o.sec_uz = self.sec_uz.data_ptr()
         o.sec_capacity = self.capacity if capacity is None else int(capacity)
         o.counters = self.counters.data_ptr()
+        o.history = self.history.data_ptr() if self.history is not None else None
         return o
 
     def n_sec(self) -> int:
@@ -91,7 +96,11 @@ class DeviceOutput:
         """Copy everything to host numpy arrays (synchronising)."""
         k = min(self.n_sec(), self.capacity)
         res = self.res.cpu().numpy().view(RESIDUAL_DTYPE)
+        extra = {}
+        if self.history is not None:
+            extra["history"] = self.history.cpu().numpy().view(np.uint32).reshape(self.n, 3)
         return dict(
+            **extra,
             res=res,
             n_sec_total=self.n_sec(),
             sec_event=self.sec_event[:k].cpu().numpy().view(np.uint32),
@@ -167,6 +176,8 @@ class Context:
         needs more reports the required total (counters[0]); allocate that and
         run again."""
         per_event = min(self.max_A + 1, 6 + self.max_A // 10)
+        if self.options.get("photon_evaporation"):
+            per_event += 12  # photons leave A and Z: a few per event on top
         return int(n * per_event) + 4096
 
     def simulate(self, T0, seed: int, target_idx=None, first_event_id: int = 0, mode: str = "staged",
@@ -231,7 +242,8 @@ class Context:
                                   and tuple(P.shape) == (n, 3)):
             raise TypeError("P must be a contiguous float32 CUDA tensor of shape (len(Ex), 3)")
         if out is None:
-            cap = min(self.max_A + 1, 4 + self.max_A // 4) * n + 4096 if capacity is None else capacity
+            per = min(self.max_A + 1, 4 + self.max_A // 4) + (12 if self.options.get("photon_evaporation") else 0)
+            cap = per * n + 4096 if capacity is None else capacity
             out = DeviceOutput.allocate(n, cap, Ex.device)
         elif out.n < n:
             raise ValueError("output buffers hold %d nuclei, batch has %d" % (out.n, n))

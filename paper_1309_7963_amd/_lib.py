@@ -47,6 +47,7 @@ class Options(C.Structure):
         ("kin_threshold", C.c_int), ("waves_per_cu", C.c_int), ("stack_levels", C.c_int),
         ("same_stream", C.c_int), ("fast_math", C.c_int), ("start_threshold", C.c_int),
         ("input_order", C.c_int),
+        ("photon_evaporation", C.c_int),
     ]
 
 
@@ -55,7 +56,7 @@ class Output(C.Structure):
         ("res", C.c_void_p), ("sec_event", C.c_void_p), ("sec_species", C.c_void_p),
         ("sec_stage", C.c_void_p), ("sec_T", C.c_void_p), ("sec_ux", C.c_void_p),
         ("sec_uy", C.c_void_p), ("sec_uz", C.c_void_p), ("sec_capacity", C.c_size_t),
-        ("counters", C.c_void_p),
+        ("counters", C.c_void_p), ("history", C.c_void_p),
     ]
 
 

@@ -153,6 +153,7 @@ Segment batch_segment(const inc_output* out, size_t n, uint64_t first_event_id) 
   seg.uz = out->sec_uz;
   seg.cap = out->sec_capacity;
   seg.counters = out->counters;
+  seg.hist = out->history;
   return seg;
 }
 
@@ -258,7 +259,7 @@ int inc_ctx_create(const inc_nucleus* targets, int n_targets, const inc_options*
       o.kin_threshold < 0 || o.kin_threshold > 64 || o.waves_per_cu < 0 || o.waves_per_cu > 32 ||
       o.stack_levels < -1 || o.stack_levels > incdev::kStackLdsMax || o.fast_math < 0 || o.fast_math > 1 ||
       o.start_threshold < 0 || o.start_threshold > 64 || o.input_order < 0 || o.input_order > 1 ||
-      o.same_stream < 0 || o.same_stream > 1)
+      o.same_stream < 0 || o.same_stream > 1 || o.photon_evaporation < 0 || o.photon_evaporation > 1)
     return INC_ERR_ARG;
   if (!(o.const_sigma_mb >= 0.0f) || o.const_sigma_mb > 1e5f) return INC_ERR_ARG;
   if (o.fixed_b_on && !(o.fixed_b >= 0.0f && o.fixed_b < 20.0f)) return INC_ERR_ARG;
@@ -315,6 +316,7 @@ int inc_ctx_create(const inc_nucleus* targets, int n_targets, const inc_options*
       break;
     if ((e = hipDeviceSynchronize()) != hipSuccess) break;
     e = hipMemcpy(&c->evap, d_evap, sizeof(EvapTab), hipMemcpyDeviceToHost);
+    c->evap.photon = o.photon_evaporation;
     for (int m = 0; m < 2; ++m) {
       const int mode = m == 0 ? INC_MODE_PLAIN : INC_MODE_PERSISTENT;
       int lv = o.fast_math ? fast::stack_levels(mode, n_targets, c->block, c->waves_per_cu)
@@ -443,6 +445,7 @@ int inc_simulate(int target_A, int target_Z, const float* energies, size_t n, ui
     o.sec_stage = o.sec_species + dcap;
     o.sec_capacity = cap;
     o.counters = d_cnt;
+    o.history = nullptr;
     inc_batch bt = {n, nullptr, d_T0, seed, 0};
     rc = inc_simulate_dev(ctx, &bt, &o, nullptr, INC_MODE_STAGED);
     if (rc) break;

@@ -5,6 +5,8 @@
 // nuclear total energy is ever formed in FP32.
 #pragma once
 
+#include <stddef.h>
+
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
@@ -55,6 +57,18 @@ struct XsTab {
   float hat[2][kXsNodes];
   float slope[2][kXsNodes];
 };
+// The part of XsTab the event kernels stage in LDS: the cross-sections and
+// their majorant.  The kernels take the slope b from its closed form
+// (slope_b): linear interpolation across the unlike-pair breaks of b (0.225
+// and 0.6 GeV/c, where 200 MeV collisions sit) errs by up to ~1e-3 and moves
+// the sampled scattering angle; the closed form costs a few instructions per
+// collision and frees 4 KB of LDS per block.  The slope columns stay in the
+// device table for read-back.
+struct XsLds {
+  float sig[2][kXsNodes];
+  float hat[2][kXsNodes];
+};
+static_assert(offsetof(XsTab, slope) == sizeof(XsLds), "XsLds is the head of XsTab");
 
 // Evaporation constants (Sec. 2.4): fragment masses, mass numbers, charges,
 // spin factors, a^(1/3), binding energies.
@@ -63,6 +77,7 @@ struct EvapTab {
   float a13[6];
   float lngm[6];   // ln(g_j m_j)
   double B[6];
+  int photon;      // the photon channel competes (option; set by the host)
 };
 
 // Per mass number A = 0..kMaxA: A^(1/3) and ln A (evaporation geometry).
@@ -84,10 +99,12 @@ struct Opts {
 // Evaporation constants of one nucleus (A, Z) (Sec. 2.4), computed once per
 // context from the binding table: per channel j the separation energy S_j
 // (+inf when the daughter does not exist), the Coulomb barrier V_j and
-// ln(g_j m_j) + ln R_j^2; and the nuclear mass M(A, Z).
+// ln(g_j m_j) + ln R_j^2; the nuclear mass M(A, Z); and for the optional
+// photon channel ln(s0 / pi), s0 the slope of the photoabsorption
+// cross-section (-inf: no dipole strength, N Z = 0).
 struct ChanRow {
   float S[6], V[6], P[6];
-  float M, pad;
+  float M, lg;
 };
 static_assert(sizeof(ChanRow) == 80, "ChanRow layout");
 
@@ -286,6 +303,17 @@ __device__ __forceinline__ void xs_coord(float p_GeV, int& k, float& f) {
   k = min((int)x, kXsNodes - 2);
   f = x - (float)k;
 }
+// Slope b ((GeV/c)^-2) of the CM angular distribution exp(b t) (Sec. 2.3,
+// reading R9) at p_lab (GeV/c, clamped to the table's range like the
+// cross-sections): like pairs 5.5 p^8 / (7.7 + p^8); unlike pairs 0 below
+// 0.225, 16.53 (p - 0.225) below 0.6, -1.63 p + 7.16 above.
+__device__ __forceinline__ float slope_b(int like, float p_GeV) {
+  const float p = fminf(fmaxf(p_GeV, kPlo), kPhi);
+  const float p2 = p * p, p4 = p2 * p2, p8 = p4 * p4;
+  const float bl = 5.5f * p8 / (7.7f + p8);
+  const float bu = p < 0.225f ? 0.0f : (p < 0.6f ? 16.53f * (p - 0.225f) : 7.16f - 1.63f * p);
+  return like ? bl : bu;
+}
 __device__ __forceinline__ float xs_lerp(const float* col, int k, float f) {
   const float a = col[k], b = col[k + 1];
   return a + f * (b - a);
@@ -294,7 +322,7 @@ __device__ __forceinline__ float xs_lerp(const float* col, int k, float f) {
 // Majorant flight cross-sections (fm^2) for a particle of species sp with
 // excess energy eps: smallest own momentum (at the smallest E_F) against the
 // largest Fermi momentum of each target species.
-__device__ __forceinline__ void majorant(const NucTab& nt, const XsTab& xs, const Opts& o, int sp, float eps,
+__device__ __forceinline__ void majorant(const NucTab& nt, const XsLds& xs, const Opts& o, int sp, float eps,
                                          float& sh0, float& sh1) {
   const float mx = nucleon_mass(sp);
   const float T = eps + nt.EFmin[sp];
@@ -364,29 +392,44 @@ __device__ __forceinline__ float log_width_integral(float Y, float lnAd) {
 // Kinetic-energy excess x in [0, U] with density ~ x exp(2 sqrt(a (U - x))).
 // With Y = 2 sqrt(a U), t = Y - 2 sqrt(a (U - x)) and s = t / Y in [0, 1]:
 // x = U s (2 - s), U - x = U (1 - s)^2, and the CDF in s is K(s) / K(1) with
-// dK/ds ~ s (2 - s) (1 - s) e^{-Y s}.  K is integrated in closed form
-// (large Y) or by its series in s (small Y); the root of K(s) = u K(1) is found
-// by bracketed Newton iteration, stopped once the CDF residual is below 1e-6
-// (a quantile error far below what any sample of this size resolves).  For
-// large Y the start is the quantile of the Gamma(2) limit, x = Y s with
-// 1 - u = (1 + x) e^{-x}, from one fixed-point step.  Returns s.
-__device__ __forceinline__ float spectrum_K(float Y, float s) {
-  if (Y < 1.0f) {
-    // sum_m (-Y)^m / m! [2 s^{m+2}/(m+2) - 3 s^{m+3}/(m+3) + s^{m+4}/(m+4)]
-    float c = 1.0f, sm = s * s, sum = 0.0f;
+// dK/ds = k(s) = s (2 - s) (1 - s) e^{-Y s} (times Y^4 for Y >= 1, the scale
+// of the closed form).  The sampler solves on the lower half of the CDF
+// (u <= 1/2) with K(s) and on the upper half with the tail mass K(1) - K(s),
+// each from a form without cancellation: K by its series in s while Y s < 1
+// (or Y < 1), else closed form; the tail in closed form (Y >= 1).  The root
+// is found by bracketed Newton iteration to a residual of 1e-6 of the target
+// mass or a relative step of 1e-7, so tail samples keep their relative
+// accuracy.  For large Y the start is the quantile of the Gamma(2) limit,
+// x = Y s with 1 - u = (1 + x) e^{-x}, from one fixed-point step.
+__device__ __forceinline__ float spectrum_series(float Y, float s) {
+  // sum_m (-Y)^m / m! [2 s^{m+2}/(m+2) - 3 s^{m+3}/(m+3) + s^{m+4}/(m+4)]
+  float c = 1.0f, sm = s * s, sum = 0.0f;
 #pragma unroll
-    for (int m = 0; m < 12; ++m) {
-      // unrolled: the coefficients are constant reciprocals, no division
-      sum += c * sm * (2.0f / (float)(m + 2) - s * (3.0f / (float)(m + 3)) + s * s * (1.0f / (float)(m + 4)));
-      c *= -Y * (1.0f / (float)(m + 1));
-      sm *= s;
-    }
-    return sum;
+  for (int m = 0; m < 12; ++m) {
+    // unrolled: the coefficients are constant reciprocals, no division
+    sum += c * sm * (2.0f / (float)(m + 2) - s * (3.0f / (float)(m + 3)) + s * s * (1.0f / (float)(m + 4)));
+    c *= -Y * (1.0f / (float)(m + 1));
+    sm *= s;
   }
-  const float t = Y * s;
-  const float C = (2.0f * Y - 6.0f) * Y + 6.0f;
+  return sum;
+}
+// e^{-t} Q(t) with t = Y s: the closed form K(s) = Q(0) - e^{-t} Q(t) (Y >= 1)
+__device__ __forceinline__ float spectrum_eQ(float Y, float t) {
   const float Q = 2.0f * Y * Y * (1.0f + t) - 3.0f * Y * ((t + 2.0f) * t + 2.0f) + ((t + 3.0f) * t + 6.0f) * t + 6.0f;
-  return C - expf(-t) * Q;
+  return expf(-t) * Q;
+}
+__device__ __forceinline__ float spectrum_K(float Y, float s) {
+  if (Y < 1.0f) return spectrum_series(Y, s);
+  if (Y * s < 1.0f) {
+    const float Y2 = Y * Y;
+    return Y2 * Y2 * spectrum_series(Y, s);
+  }
+  return ((2.0f * Y - 6.0f) * Y + 6.0f) - spectrum_eQ(Y, Y * s);
+}
+// K(1) - K(s), the CDF's upper tail mass
+__device__ __forceinline__ float spectrum_Kc(float Y, float s, float K1) {
+  if (Y < 1.0f) return K1 - spectrum_series(Y, s);
+  return spectrum_eQ(Y, Y * s) - spectrum_eQ(Y, Y);
 }
 __device__ __forceinline__ float spectrum_dK(float Y, float s) {
   const float core = s * (2.0f - s) * (1.0f - s) * expf(-Y * s);
@@ -396,8 +439,10 @@ __device__ __forceinline__ float spectrum_dK(float Y, float s) {
 }
 __device__ __forceinline__ float spectrum_sample_s(float Y, float u) {
   const float K1 = spectrum_K(Y, 1.0f);
-  const float target = u * K1;
-  const float ftol = 1e-6f * K1;
+  const bool upper = u > 0.5f;
+  // lower half: K(s) = u K1, increasing in s; upper half: K1 - K(s) = (1 - u) K1
+  const float target = (upper ? 1.0f - u : u) * K1;
+  const float ftol = 1e-6f * target;
   float lo = 0.0f, hi = 1.0f;
   float s = 0.5f;
   if (Y > 4.0f) {
@@ -405,7 +450,8 @@ __device__ __forceinline__ float spectrum_sample_s(float Y, float u) {
     s = fminf(fmaxf((x0 + log1p_acc(x0)) / Y, 1e-4f), 0.95f);
   }
   for (int it = 0; it < 40; ++it) {
-    const float F = spectrum_K(Y, s) - target;
+    // F increases with s on both halves
+    const float F = upper ? target - spectrum_Kc(Y, s, K1) : spectrum_K(Y, s) - target;
     if (F < 0.0f) lo = s; else hi = s;
     if (fabsf(F) <= ftol) break;
     const float dF = spectrum_dK(Y, s);
@@ -413,7 +459,93 @@ __device__ __forceinline__ float spectrum_sample_s(float Y, float u) {
     if (!(sn > lo && sn < hi)) sn = 0.5f * (lo + hi);
     const float step = fabsf(sn - s);
     s = sn;
-    if (step <= 2e-7f || hi - lo <= 2e-7f) break;
+    if (step <= 1e-7f * s || hi - lo <= 1e-7f * hi) break;
+  }
+  return fminf(fmaxf(s, 0.0f), 1.0f);
+}
+
+// ------------------------------------------------------------ photon channel
+// Optional (off by default; Sec. 2 has de-excitation by particles, then
+// photons, and Sec. 2.4 leaves photons out).  Width from detailed balance
+// with a photoabsorption cross-section s0 eps (rising to the giant-dipole
+// energy, holding the classical dipole sum), in the particle widths' units:
+// w = (s0/pi) J, J = int_0^E eps^3 exp(2 sqrt(a (E - eps))) d eps, a = A/8.
+// With Y = 2 sqrt(a E) and eps = E s (2 - s): J = 2 E^4 e^Y Kg(Y, 1),
+// Kg(Y, s) = int_0^s q(t) e^{-Y t} dt, q(t) = t^3 (2 - t)^3 (1 - t)
+// = 8 t^3 - 20 t^4 + 18 t^5 - 7 t^6 + t^7; the CDF of s is Kg(Y, s) / Kg(Y, 1).
+constexpr float kPhotonMin = 0.1f;  // MeV: the channel is open above this
+__device__ __forceinline__ float photon_q(float t) {
+  return t * t * t * ((((t - 7.0f) * t + 18.0f) * t - 20.0f) * t + 8.0f);
+}
+__device__ __forceinline__ float photon_series(float Y, float s) {
+  // sum_m (-Y)^m / m! int_0^s q(t) t^m dt (converges for Y s < 4 in 21 terms)
+  float c = 1.0f, sm = s * s * s * s, sum = 0.0f;
+#pragma unroll
+  for (int m = 0; m < 21; ++m) {
+    sum += c * sm *
+           (8.0f / (float)(m + 4) -
+            s * (20.0f / (float)(m + 5) -
+                 s * (18.0f / (float)(m + 6) - s * (7.0f / (float)(m + 7) - s * (1.0f / (float)(m + 8))))));
+    c *= -Y * (1.0f / (float)(m + 1));
+    sm *= s;
+  }
+  return sum;
+}
+// S(t) = sum_j q^(j)(t) / Y^(j+1) as a polynomial in t (c7 = 1/Y,
+// c_n = (q_n + (n + 1) c_{n+1}) / Y), so that int q e^{-Y t} = -e^{-Y t} S(t);
+// returns S(t) and S(0) = c0
+__device__ __forceinline__ float photon_S(float Y, float t, float& c0) {
+  const float iy = 1.0f / Y;
+  const float c7 = iy;
+  const float c6 = (-7.0f + 7.0f * c7) * iy;
+  const float c5 = (18.0f + 6.0f * c6) * iy;
+  const float c4 = (-20.0f + 5.0f * c5) * iy;
+  const float c3 = (8.0f + 4.0f * c4) * iy;
+  const float c2 = 3.0f * c3 * iy;
+  const float c1 = 2.0f * c2 * iy;
+  c0 = c1 * iy;
+  return ((((((c7 * t + c6) * t + c5) * t + c4) * t + c3) * t + c2) * t + c1) * t + c0;
+}
+__device__ __forceinline__ float photon_K(float Y, float s) {
+  if (Y < 4.0f || Y * s < 4.0f) return photon_series(Y, s);
+  float c0;
+  const float S = photon_S(Y, s, c0);
+  return c0 - expf(-Y * s) * S;
+}
+// Kg(1) - Kg(s), the CDF's upper tail mass
+__device__ __forceinline__ float photon_Kc(float Y, float s, float K1) {
+  if (Y < 4.0f) return K1 - photon_series(Y, s);
+  float c0;
+  const float Ss = photon_S(Y, s, c0);
+  const float S1 = photon_S(Y, 1.0f, c0);
+  return expf(-Y * s) * Ss - expf(-Y) * S1;
+}
+// ln J(a, E) - ln 2: Y + 4 ln E + ln Kg(Y, 1)
+__device__ __forceinline__ float log_photon_integral(float Y, float E) {
+  return Y + 4.0f * logf(E) + logf(photon_K(Y, 1.0f)) + 0.6931472f;
+}
+// s of the photon's share eps = E s (2 - s) for a uniform u: on the lower
+// half of the CDF the root of Kg(Y, s) = u Kg(Y, 1), on the upper half of
+// Kg(Y, 1) - Kg(Y, s) = (1 - u) Kg(Y, 1), by bracketed Newton iteration (as
+// the particles').
+__device__ __forceinline__ float photon_sample_s(float Y, float u) {
+  const float K1 = photon_K(Y, 1.0f);
+  const bool upper = u > 0.5f;
+  const float target = (upper ? 1.0f - u : u) * K1;
+  const float ftol = 1e-6f * target;
+  float lo = 0.0f, hi = 1.0f;
+  // start near the median of the large-Y limit t^3 e^{-Y t} (Gamma(4))
+  float s = fminf(0.5f, 3.672f / Y);
+  for (int it = 0; it < 40; ++it) {
+    const float F = upper ? target - photon_Kc(Y, s, K1) : photon_K(Y, s) - target;
+    if (F < 0.0f) lo = s; else hi = s;
+    if (fabsf(F) <= ftol) break;
+    const float dF = photon_q(s) * expf(-Y * s);
+    float sn = (dF > 0.0f) ? s - F / dF : 0.5f * (lo + hi);
+    if (!(sn > lo && sn < hi)) sn = 0.5f * (lo + hi);
+    const float step = fabsf(sn - s);
+    s = sn;
+    if (step <= 1e-7f * s || hi - lo <= 1e-7f * hi) break;
   }
   return fminf(fmaxf(s, 0.0f), 1.0f);
 }
@@ -447,6 +579,7 @@ struct Segment {
   float* uz;
   unsigned long long cap;
   unsigned long long* counters;
+  uint32_t* hist;  // optional history words, 2 per event (NULL: not written)
 };
 
 __device__ __forceinline__ int lane_id() { return __lane_id(); }

@@ -43,13 +43,13 @@ struct KernelArgs {
 
 __device__ __forceinline__ bool energy_ok(float T0) { return T0 >= 20.0f && T0 <= 250.0f; }
 
-// LDS layout of the event kernels: [n_targets NucTab][XsTab][MassTab][writer
+// LDS layout of the event kernels: [n_targets NucTab][XsLds][MassTab][writer
 // buffers of the block's waves][LIFO levels: per wave stack_lds x 2 x 64
 // float4].  The evaporation kernels stage only the MassTab (n_targets = 0,
-// no XsTab: with_xs = false), have no stack and larger writer buffers
+// no XsLds: with_xs = false), have no stack and larger writer buffers
 // (kWriterCapEvap records per wave: nearly every lane emits every step).
 __device__ __forceinline__ size_t lds_mass_offset(int n_targets, bool with_xs) {
-  return (size_t)n_targets * sizeof(NucTab) + (with_xs ? sizeof(XsTab) : 0);
+  return (size_t)n_targets * sizeof(NucTab) + (with_xs ? sizeof(XsLds) : 0);
 }
 // First float4 of this lane's column in the LDS stack area (each wave owns
 // levels x 2 x 64 consecutive float4).
@@ -66,7 +66,7 @@ __device__ __forceinline__ void stage_tables(char* lds, const KernelArgs& a, int
   if (with_xs) {
     uint32_t* dx = (uint32_t*)(lds + n_targets * sizeof(NucTab));
     const uint32_t* sx = (const uint32_t*)a.xs;
-    for (int i = threadIdx.x; i < (int)(sizeof(XsTab) / 4); i += blockDim.x) dx[i] = sx[i];
+    for (int i = threadIdx.x; i < (int)(sizeof(XsLds) / 4); i += blockDim.x) dx[i] = sx[i];
   }
   uint32_t* dm = (uint32_t*)(lds + lds_mass_offset(n_targets, with_xs));
   const uint32_t* sm = (const uint32_t*)a.mass;
@@ -106,6 +106,22 @@ __device__ __forceinline__ void init_stream(Rng& rng, const KernelArgs& a, Event
   rng.init(a.segs[e.seg].first_id + (a.opt.same_stream ? 0 : e.local));
 }
 __device__ __forceinline__ uint32_t kind_of(uint32_t k, EventRef e) { return k | ((uint32_t)e.seg << 16); }
+// Optional history words of an event (inc_output.history): word 0 = uniforms
+// drawn from its stream, word 1 = flight segments of its cascade, word 2 =
+// the fingerprint of the shells of its tentative collisions.
+constexpr int kHistDraws = 0, kHistSegments = 1, kHistShells = 2, kHistWords = 3;
+__device__ __forceinline__ void put_hist(const KernelArgs& a, EventRef e, int word, uint32_t v) {
+  uint32_t* h = a.segs[e.seg].hist;
+  if (h) h[kHistWords * (size_t)e.local + word] = v;
+}
+// The cascade's words (segments and shell fingerprint) of a finished cascade.
+__device__ __forceinline__ void put_hist_cascade(const KernelArgs& a, EventRef e, const Cascade& c) {
+  uint32_t* h = a.segs[e.seg].hist;
+  if (h) {
+    h[kHistWords * (size_t)e.local + kHistSegments] = (uint32_t)c.nseg;
+    h[kHistWords * (size_t)e.local + kHistShells] = c.hsh;
+  }
+}
 
 // Plain cascade kernel: one event per thread (Sec. 3.2).  Each iteration of
 // the wave loop advances every live lane by one flight segment together with
@@ -115,7 +131,7 @@ __global__ void __launch_bounds__(256) k_cascade_plain(KernelArgs a) {
   extern __shared__ __align__(16) char lds[];
   stage_tables(lds, a, a.n_targets, true);
   const NucTab* snt = (const NucTab*)lds;
-  const XsTab& sxs = *(const XsTab*)(lds + a.n_targets * sizeof(NucTab));
+  const XsLds& sxs = *(const XsLds*)(lds + a.n_targets * sizeof(NucTab));
   uint32_t* wbuf = (uint32_t*)(lds + lds_mass_offset(a.n_targets, true) + sizeof(MassTab)) +
                    (threadIdx.x / 64) * (kWriterCap * kRecWords);
   int fill = 0;
@@ -157,6 +173,7 @@ __global__ void __launch_bounds__(256) k_cascade_plain(KernelArgs a) {
       if (st == kStKin) st = kin_step(c, stk, rng, nt, sxs, a.opt);
       if (st == kStDone) {
         const Nucleus r = cascade_residual(c, nt, T0);
+        put_hist_cascade(a, er, c);
         MidState m;
         m.A = (int16_t)r.A;
         m.Z = (int16_t)r.Z;
@@ -201,6 +218,9 @@ __global__ void __launch_bounds__(256) k_evap_plain(KernelArgs a) {
     flags = m.flags;
     if (flags & kFlagRange) {
       write_residual(res, nu, 0.0f, 0, flags, 0, 0);
+      put_hist(a, er, kHistDraws, 0u);
+      put_hist(a, er, kHistSegments, 0u);
+      put_hist(a, er, kHistShells, 0u);
       live = false;
     } else {
       nu.A = m.A;
@@ -214,6 +234,7 @@ __global__ void __launch_bounds__(256) k_evap_plain(KernelArgs a) {
       if (flags) atomicAdd(&a.segs[er.seg].counters[1], 1ull);
       if (nu.A <= 0 || a.opt.no_evaporation) {
         write_residual(res, nu, m.E, nsec, flags, m.ncoll, m.nretry);
+        put_hist(a, er, kHistDraws, m.drawn);
         live = false;
       }
     }
@@ -224,6 +245,7 @@ __global__ void __launch_bounds__(256) k_evap_plain(KernelArgs a) {
     if (live) {
       if (evap_step(nu, rng, a.bind, a.evap, smt, em)) {
         write_residual(a.segs[er.seg].res + er.local, nu, m.E, nsec, flags, m.ncoll, m.nretry);
+        put_hist(a, er, kHistDraws, rng.drawn());
         live = false;
       } else {
         ++nsec;
@@ -337,6 +359,7 @@ __device__ __forceinline__ void evap_events(const KernelArgs& a, const MassTab& 
     if (busy) {
       if (evap_step(nu, rng, a.bind, a.evap, smt, em)) {
         write_residual(a.segs[er.seg].res + er.local, nu, Ex_casc, nsec, flags, ncoll, nretry);
+        put_hist(a, er, kHistDraws, rng.drawn());
         if (flags) atomicAdd(&a.segs[er.seg].counters[1], 1ull);
         busy = false;
       } else {
@@ -358,7 +381,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) k
   extern __shared__ __align__(16) char lds[];
   stage_tables(lds, a, a.n_targets, true);
   const NucTab* snt = (const NucTab*)lds;
-  const XsTab& sxs = *(const XsTab*)(lds + a.n_targets * sizeof(NucTab));
+  const XsLds& sxs = *(const XsLds*)(lds + a.n_targets * sizeof(NucTab));
   const MassTab& smt = *(const MassTab*)(lds + lds_mass_offset(a.n_targets, true));
   uint32_t* wbuf = (uint32_t*)(lds + lds_mass_offset(a.n_targets, true) + sizeof(MassTab)) +
                    (threadIdx.x / 64) * (kWriterCap * kRecWords);
@@ -421,6 +444,9 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) k
           tgt = 0;
           const Nucleus z = {0, 0, 0.0f, {0.0f, 0.0f, 0.0f}};
           write_residual(a.segs[er.seg].res + er.local, z, 0.0f, 0, kFlagRange, 0, 0);
+          put_hist(a, er, kHistDraws, 0u);
+          put_hist(a, er, kHistSegments, 0u);
+          put_hist(a, er, kHistShells, 0u);
           atomicAdd(&a.segs[er.seg].counters[1], 1ull);
           if (!kFused) {
             MidState m = {};
@@ -473,6 +499,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) k
       if (st == kStEvap) {
         if (evap_step(nu, rng, a.bind, a.evap, smt, em)) {
           write_residual(a.segs[er.seg].res + er.local, nu, Ex_casc, nsec, c.flags, c.ncoll, c.nretry);
+          put_hist(a, er, kHistDraws, rng.drawn());
           if (c.flags) atomicAdd(&a.segs[er.seg].counters[1], 1ull);
           st = kStDone;
         } else {
@@ -492,8 +519,10 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) k
         Ex_casc = nu.E;
         if (nu.A <= 0) c.flags |= kFlagEmpty;
         const bool final = nu.A <= 0 || a.opt.no_evaporation;
+        put_hist_cascade(a, er, c);
         if (final) {
           write_residual(a.segs[er.seg].res + er.local, nu, Ex_casc, nsec, c.flags, c.ncoll, c.nretry);
+          put_hist(a, er, kHistDraws, rng.drawn());
           if (c.flags) atomicAdd(&a.segs[er.seg].counters[1], 1ull);
         }
         if (!kFused) {
@@ -579,6 +608,9 @@ __global__ void k_excited_setup(KernelArgs a, ExcitedDesc x) {
   const bool ok = A >= 1 && A <= a.bind.amax && Z <= A && Z <= a.bind.zmax && E >= 0.0f && E <= kMaxExcitation &&
                   isfinite(P[0]) && isfinite(P[1]) && isfinite(P[2]);
   MidState m = {};
+  const EventRef er = event_ref(a, i);
+  put_hist(a, er, kHistSegments, 0u);
+  put_hist(a, er, kHistShells, 0u);
   if (ok) {
     m.A = (int16_t)A;
     m.Z = (int16_t)Z;
@@ -588,9 +620,9 @@ __global__ void k_excited_setup(KernelArgs a, ExcitedDesc x) {
     m.P[2] = P[2];
   } else {
     m.flags = kFlagRange | kMidFinal;
-    const EventRef er = event_ref(a, i);
     const Nucleus z = {0, 0, 0.0f, {0.0f, 0.0f, 0.0f}};
     write_residual(a.segs[er.seg].res + er.local, z, 0.0f, 0, kFlagRange, 0, 0);
+    put_hist(a, er, kHistDraws, 0u);
     atomicAdd(&a.segs[er.seg].counters[1], 1ull);
   }
   a.mid[i] = m;
@@ -614,7 +646,7 @@ __global__ void k_zero_counters(const Segment* segs, int n_seg, unsigned long lo
 
 // ================================================================ launchers
 size_t lds_bytes(int n_targets, int block, bool with_xs, int stack_levels) {
-  return (size_t)n_targets * sizeof(NucTab) + (with_xs ? sizeof(XsTab) : 0) + sizeof(MassTab) +
+  return (size_t)n_targets * sizeof(NucTab) + (with_xs ? sizeof(XsLds) : 0) + sizeof(MassTab) +
          (size_t)(block / 64) * (with_xs ? kWriterCap : kWriterCapEvap) * kRecWords * sizeof(uint32_t) +
          (size_t)stack_levels * 2 * block * sizeof(float4);
 }

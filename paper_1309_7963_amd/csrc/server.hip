@@ -327,6 +327,7 @@ int start_launch(inc_server* s) {
     g.uz = (float*)(d + r.o.uz);
     g.cap = r.cap;
     g.counters = (unsigned long long*)(d + r.o.cnt);
+    g.hist = nullptr;
     start += r.n;
   }
   memcpy(h + L.seg_off, segs.data(), sizeof(Segment) * segs.size());

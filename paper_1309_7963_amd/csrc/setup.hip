@@ -63,7 +63,15 @@ __global__ void k_chan_table(const double* B, int amax, int zmax, const EvapTab*
   const double BAZ = B[idx];
   ChanRow r;
   r.M = (float)((double)Z * kMassP + (double)(A - Z) * kMassN - BAZ);
-  r.pad = 0.0f;
+  // photon channel (option): s0 = 12 N Z / (A E_G^2) fm^2/MeV, the linear
+  // photoabsorption ramp up to E_G = 31.2 A^-1/3 + 20.6 A^-1/6 MeV that
+  // holds the classical dipole sum 60 N Z / A mb MeV
+  if (A >= 2 && Z >= 1 && Z < A) {
+    const double EG = 31.2 / cbrt((double)A) + 20.6 / pow((double)A, 1.0 / 6.0);
+    r.lg = (float)log(12.0 * (double)(A - Z) * (double)Z / ((double)A * EG * EG) / 3.14159265358979323846);
+  } else {
+    r.lg = -INFINITY;
+  }
   for (int j = 0; j < 6; ++j) {
     const int Ad = A - fa[j], Zd = Z - fz[j];
     if (Z <= A && Ad >= 1 && Zd >= 0 && Zd <= Ad) {

@@ -8,7 +8,9 @@ import ledger
 
 
 def run_gpu(targets, T0, seed, tidx=None, mode="persistent", first_id=0, capacity=None, ctx=None,
-            allow_overflow=False, **opts):
+            allow_overflow=False, history=False, **opts):
+    """history: also return the per-event history words (uniforms drawn,
+    flight segments) as h["history"] (n x 2)."""
     import torch
     import paper_1309_7963_amd as inc
 
@@ -17,7 +19,13 @@ def run_gpu(targets, T0, seed, tidx=None, mode="persistent", first_id=0, capacit
         ctx = inc.Context(targets, **opts)
     T0_d = torch.as_tensor(np.asarray(T0, dtype=np.float32), device="cuda")
     ti_d = None if tidx is None else torch.as_tensor(np.asarray(tidx, dtype=np.uint8), device="cuda")
-    out = ctx.simulate(T0_d, seed=seed, target_idx=ti_d, first_event_id=first_id, mode=mode, capacity=capacity)
+    out = None
+    if history:
+        n = len(T0)
+        out = inc.DeviceOutput.allocate(n, ctx.default_capacity(n) if capacity is None else capacity, "cuda",
+                                        history=True)
+    out = ctx.simulate(T0_d, seed=seed, target_idx=ti_d, first_event_id=first_id, mode=mode, capacity=capacity,
+                       out=out)
     torch.cuda.synchronize()
     if out.n_sec() > out.capacity and not allow_overflow:
         raise RuntimeError("secondary buffer too small: %d records for capacity %d" % (out.n_sec(), out.capacity))

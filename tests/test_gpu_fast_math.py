@@ -47,8 +47,8 @@ def test_fast_replay_agreement_reported():
 def _chi2_gate(g, o, T_max, label):
     res = stats.compare_samples(g, o, T_max)
     print(label, {k: (round(v[0], 1), v[1], round(v[2], 4)) for k, v in res.items()})
-    for k, (chi2, dof, p) in res.items():
-        assert p > 0.01, (label, k, chi2, dof, p)
+    bad = stats.gate(res)
+    assert not bad, (label, bad)
 
 
 def test_fast_chi2_o16_paper_scale():
