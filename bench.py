@@ -547,6 +547,11 @@ def main(argv=None):
         from paper_1309_7963_amd import autotune
 
         rate = lambda e: e["n"] / (float(np.median(e["launch_ms"])) / 1000.0)
+
+        def tuner_table(tuned):
+            # each swept candidate: its dimension, the options it set, ms per launch
+            return [[r["dimension"], r["options"], round(r["ms"], 3)] for r in tuned["table"]]
+
         for key in ("o16_200", "ca40_200", "tissue_mix", "implant_mix"):
             e = _time_gpu(wl[key], args.mode, 5, 1)
             extra[key] = dict(label=wl[key]["label"], events=e["n"], events_per_s=rate(e))
@@ -557,8 +562,16 @@ def main(argv=None):
                 e = _time_gpu(w, args.mode, 5, 1, **tuned["options"])
                 p = _time_gpu(w, "plain", 3, 1)
                 extra[key].update(tuned_options=tuned["options"] or "library default", tuned_events_per_s=rate(e),
-                                  plain_events_per_s=rate(p), autotune_sweep_s=tuned["sweep_s"])
+                                  plain_events_per_s=rate(p), autotune_sweep_s=tuned["sweep_s"],
+                                  autotune=dict(swept_options=tuned["swept_options"], swept_ms=tuned["swept_ms"],
+                                                default_ms=tuned["default_ms"], table=tuner_table(tuned)))
             print("bench: %s done" % key, file=sys.stderr, flush=True)
+        # the tuner on the main workload itself
+        tuned = autotune.tune(main_w["targets"], main_w["T0"], main_w["tidx"], use_cache=False)
+        extra["main_autotune"] = dict(options=tuned["options"] or "library default", ms=tuned["ms"],
+                                      default_ms=tuned["default_ms"], swept_options=tuned["swept_options"],
+                                      swept_ms=tuned["swept_ms"], table=tuner_table(tuned))
+        print("bench: main-workload autotune done", file=sys.stderr, flush=True)
         e = _time_gpu(main_w, "plain", 3, 1)
         extra["plain_two_kernel"] = dict(events_per_s=rate(e))
         e = _time_gpu(main_w, "persistent", 3, 1)

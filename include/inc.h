@@ -114,6 +114,17 @@ typedef struct {
                          /* nuclei shed energy by particles, then photons;  */
                          /* Sec. 2.4 leaves photons out, so 0 (the default) */
                          /* is the paper's model                             */
+  /* launch policy, continued */
+  int table_layout;      /* persistent and staged kernels: the NN table in   */
+                         /* LDS as columns (0, default: two 4-byte reads per */
+                         /* interpolation) or as node pairs (1: entry k of a */
+                         /* column holds values k and k+1, one 8-byte read,  */
+                         /* twice the LDS, so fewer LIFO levels may fit).    */
+                         /* Results do not depend on it.                     */
+  int chunk_events;      /* persistent and staged kernels: events a wave     */
+                         /* claims from the work queue at once (16..1024, a  */
+                         /* multiple of 16; 0 = 64).  Results do not depend  */
+                         /* on it.                                           */
 } inc_options;
 
 /* One residual nucleus per event, 32 bytes: the excited nucleus the cascade

@@ -48,6 +48,8 @@ class Options(C.Structure):
         ("same_stream", C.c_int), ("fast_math", C.c_int), ("start_threshold", C.c_int),
         ("input_order", C.c_int),
         ("photon_evaporation", C.c_int),
+        ("table_layout", C.c_int),
+        ("chunk_events", C.c_int),
     ]
 
 

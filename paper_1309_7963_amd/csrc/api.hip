@@ -122,6 +122,9 @@ LaunchDesc launch_desc(const inc_ctx* ctx, size_t n, int mode, int max_blocks) {
   L.kin_threshold = ctx->kin_threshold;
   L.start_threshold = ctx->start_threshold;
   L.stack_lds = ctx->stack_lds[mode == INC_MODE_PLAIN ? 0 : 1];
+  L.chunk = ctx->opt.chunk_events ? ctx->opt.chunk_events : kChunkEvents;
+  L.xs_pairs = ctx->opt.table_layout;
+  L.photon = ctx->opt.photon_evaporation;
   L.nuc = ctx->d_nuc;
   L.n_targets = ctx->n_targets;
   L.xs = ctx->d_xs;
@@ -259,7 +262,9 @@ int inc_ctx_create(const inc_nucleus* targets, int n_targets, const inc_options*
       o.kin_threshold < 0 || o.kin_threshold > 64 || o.waves_per_cu < 0 || o.waves_per_cu > 32 ||
       o.stack_levels < -1 || o.stack_levels > incdev::kStackLdsMax || o.fast_math < 0 || o.fast_math > 1 ||
       o.start_threshold < 0 || o.start_threshold > 64 || o.input_order < 0 || o.input_order > 1 ||
-      o.same_stream < 0 || o.same_stream > 1 || o.photon_evaporation < 0 || o.photon_evaporation > 1)
+      o.same_stream < 0 || o.same_stream > 1 || o.photon_evaporation < 0 || o.photon_evaporation > 1 ||
+      o.table_layout < 0 || o.table_layout > 1 ||
+      (o.chunk_events && (o.chunk_events < kChunkMin || o.chunk_events > kChunkMax || o.chunk_events % kChunkMin)))
     return INC_ERR_ARG;
   if (!(o.const_sigma_mb >= 0.0f) || o.const_sigma_mb > 1e5f) return INC_ERR_ARG;
   if (o.fixed_b_on && !(o.fixed_b >= 0.0f && o.fixed_b < 20.0f)) return INC_ERR_ARG;
@@ -316,11 +321,11 @@ int inc_ctx_create(const inc_nucleus* targets, int n_targets, const inc_options*
       break;
     if ((e = hipDeviceSynchronize()) != hipSuccess) break;
     e = hipMemcpy(&c->evap, d_evap, sizeof(EvapTab), hipMemcpyDeviceToHost);
-    c->evap.photon = o.photon_evaporation;
     for (int m = 0; m < 2; ++m) {
       const int mode = m == 0 ? INC_MODE_PLAIN : INC_MODE_PERSISTENT;
-      int lv = o.fast_math ? fast::stack_levels(mode, n_targets, c->block, c->waves_per_cu)
-                           : precise::stack_levels(mode, n_targets, c->block, c->waves_per_cu);
+      const int layout = o.table_layout ? kXsPairs : kXsColumns;
+      int lv = o.fast_math ? fast::stack_levels(mode, n_targets, c->block, c->waves_per_cu, layout)
+                           : precise::stack_levels(mode, n_targets, c->block, c->waves_per_cu, layout);
       if (o.stack_levels < 0) lv = 0;
       else if (o.stack_levels > 0 && o.stack_levels < lv) lv = o.stack_levels;
       c->stack_lds[m] = lv;

@@ -69,6 +69,13 @@ struct XsLds {
   float hat[2][kXsNodes];
 };
 static_assert(offsetof(XsTab, slope) == sizeof(XsLds), "XsLds is the head of XsTab");
+// The same columns as node pairs: entry k of a column holds (v[k], v[k+1]),
+// so an interpolation takes one 8-byte LDS read instead of two 4-byte ones,
+// for twice the LDS (the launch-policy option table_layout = 1).
+struct XsPairs {
+  float2 sig[2][kXsNodes];
+  float2 hat[2][kXsNodes];
+};
 
 // Evaporation constants (Sec. 2.4): fragment masses, mass numbers, charges,
 // spin factors, a^(1/3), binding energies.
@@ -77,7 +84,6 @@ struct EvapTab {
   float a13[6];
   float lngm[6];   // ln(g_j m_j)
   double B[6];
-  int photon;      // the photon channel competes (option; set by the host)
 };
 
 // Per mass number A = 0..kMaxA: A^(1/3) and ln A (evaporation geometry).
@@ -314,6 +320,19 @@ __device__ __forceinline__ float slope_b(int like, float p_GeV) {
   const float bu = p < 0.225f ? 0.0f : (p < 0.6f ? 16.53f * (p - 0.225f) : 7.16f - 1.63f * p);
   return like ? bl : bu;
 }
+__device__ __forceinline__ float xs_lerp(const float* col, int k, float f);
+// sigma and its majorant of like (1) / unlike (0) pairs at table coordinate
+// (k, f), from either LDS layout (the same arithmetic, the same result)
+__device__ __forceinline__ float xs_sig(const XsLds& xs, int like, int k, float f) { return xs_lerp(xs.sig[like], k, f); }
+__device__ __forceinline__ float xs_hat(const XsLds& xs, int like, int k, float f) { return xs_lerp(xs.hat[like], k, f); }
+__device__ __forceinline__ float xs_sig(const XsPairs& xs, int like, int k, float f) {
+  const float2 v = xs.sig[like][k];
+  return v.x + f * (v.y - v.x);
+}
+__device__ __forceinline__ float xs_hat(const XsPairs& xs, int like, int k, float f) {
+  const float2 v = xs.hat[like][k];
+  return v.x + f * (v.y - v.x);
+}
 __device__ __forceinline__ float xs_lerp(const float* col, int k, float f) {
   const float a = col[k], b = col[k + 1];
   return a + f * (b - a);
@@ -322,7 +341,8 @@ __device__ __forceinline__ float xs_lerp(const float* col, int k, float f) {
 // Majorant flight cross-sections (fm^2) for a particle of species sp with
 // excess energy eps: smallest own momentum (at the smallest E_F) against the
 // largest Fermi momentum of each target species.
-__device__ __forceinline__ void majorant(const NucTab& nt, const XsLds& xs, const Opts& o, int sp, float eps,
+template <class XS>
+__device__ __forceinline__ void majorant(const NucTab& nt, const XS& xs, const Opts& o, int sp, float eps,
                                          float& sh0, float& sh1) {
   const float mx = nucleon_mass(sp);
   const float T = eps + nt.EFmin[sp];
@@ -340,7 +360,7 @@ __device__ __forceinline__ void majorant(const NucTab& nt, const XsLds& xs, cons
       int k;
       float f;
       xs_coord(pmin, k, f);
-      s = xs_lerp(xs.hat[sp == y], k, f);
+      s = xs_hat(xs, sp == y, k, f);
     }
     sh[y] = s * kMbToFm2;
   }
@@ -396,10 +416,10 @@ __device__ __forceinline__ float log_width_integral(float Y, float lnAd) {
 // of the closed form).  The sampler solves on the lower half of the CDF
 // (u <= 1/2) with K(s) and on the upper half with the tail mass K(1) - K(s),
 // each from a form without cancellation: K by its series in s while Y s < 1
-// (or Y < 1), else closed form; the tail in closed form (Y >= 1).  The root
-// is found by bracketed Newton iteration to a residual of 1e-6 of the target
-// mass or a relative step of 1e-7, so tail samples keep their relative
-// accuracy.  For large Y the start is the quantile of the Gamma(2) limit,
+// for lower-tail targets (u < 0.01; always for Y < 1), else closed form; the
+// tail mass in closed form (Y >= 1).  The root is found by bracketed Newton
+// iteration to a residual of 1e-5 of the target mass or a relative step of
+// 1e-6, so tail samples keep their relative accuracy.  For large Y the start is the quantile of the Gamma(2) limit,
 // x = Y s with 1 - u = (1 + x) e^{-x}, from one fixed-point step.
 __device__ __forceinline__ float spectrum_series(float Y, float s) {
   // sum_m (-Y)^m / m! [2 s^{m+2}/(m+2) - 3 s^{m+3}/(m+3) + s^{m+4}/(m+4)]
@@ -418,9 +438,11 @@ __device__ __forceinline__ float spectrum_eQ(float Y, float t) {
   const float Q = 2.0f * Y * Y * (1.0f + t) - 3.0f * Y * ((t + 2.0f) * t + 2.0f) + ((t + 3.0f) * t + 6.0f) * t + 6.0f;
   return expf(-t) * Q;
 }
-__device__ __forceinline__ float spectrum_K(float Y, float s) {
+// K(s); `deep`: a lower-tail target (u < 0.01), where the closed form's
+// cancellation would show, so the series is taken while Y s < 1
+__device__ __forceinline__ float spectrum_K(float Y, float s, bool deep = false) {
   if (Y < 1.0f) return spectrum_series(Y, s);
-  if (Y * s < 1.0f) {
+  if (deep && Y * s < 1.0f) {
     const float Y2 = Y * Y;
     return Y2 * Y2 * spectrum_series(Y, s);
   }
@@ -442,7 +464,8 @@ __device__ __forceinline__ float spectrum_sample_s(float Y, float u) {
   const bool upper = u > 0.5f;
   // lower half: K(s) = u K1, increasing in s; upper half: K1 - K(s) = (1 - u) K1
   const float target = (upper ? 1.0f - u : u) * K1;
-  const float ftol = 1e-6f * target;
+  const float ftol = 1e-5f * target;
+  const bool deep = u < 0.01f;
   float lo = 0.0f, hi = 1.0f;
   float s = 0.5f;
   if (Y > 4.0f) {
@@ -451,7 +474,7 @@ __device__ __forceinline__ float spectrum_sample_s(float Y, float u) {
   }
   for (int it = 0; it < 40; ++it) {
     // F increases with s on both halves
-    const float F = upper ? target - spectrum_Kc(Y, s, K1) : spectrum_K(Y, s) - target;
+    const float F = upper ? target - spectrum_Kc(Y, s, K1) : spectrum_K(Y, s, deep) - target;
     if (F < 0.0f) lo = s; else hi = s;
     if (fabsf(F) <= ftol) break;
     const float dF = spectrum_dK(Y, s);
@@ -459,7 +482,7 @@ __device__ __forceinline__ float spectrum_sample_s(float Y, float u) {
     if (!(sn > lo && sn < hi)) sn = 0.5f * (lo + hi);
     const float step = fabsf(sn - s);
     s = sn;
-    if (step <= 1e-7f * s || hi - lo <= 1e-7f * hi) break;
+    if (step <= 1e-6f * s || hi - lo <= 1e-6f * hi) break;
   }
   return fminf(fmaxf(s, 0.0f), 1.0f);
 }
@@ -532,7 +555,7 @@ __device__ __forceinline__ float photon_sample_s(float Y, float u) {
   const float K1 = photon_K(Y, 1.0f);
   const bool upper = u > 0.5f;
   const float target = (upper ? 1.0f - u : u) * K1;
-  const float ftol = 1e-6f * target;
+  const float ftol = 1e-5f * target;
   float lo = 0.0f, hi = 1.0f;
   // start near the median of the large-Y limit t^3 e^{-Y t} (Gamma(4))
   float s = fminf(0.5f, 3.672f / Y);
@@ -545,7 +568,7 @@ __device__ __forceinline__ float photon_sample_s(float Y, float u) {
     if (!(sn > lo && sn < hi)) sn = 0.5f * (lo + hi);
     const float step = fabsf(sn - s);
     s = sn;
-    if (step <= 1e-7f * s || hi - lo <= 1e-7f * hi) break;
+    if (step <= 1e-6f * s || hi - lo <= 1e-6f * hi) break;
   }
   return fminf(fmaxf(s, 0.0f), 1.0f);
 }

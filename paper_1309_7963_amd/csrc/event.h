@@ -113,7 +113,8 @@ __device__ __forceinline__ void cascade_init(Cascade& c, const NucTab& nt) {
 
 // Entry (reading): impact parameter uniform over the disc of radius R,
 // incidence along +z, inward refraction at R; then the first optical depth.
-__device__ __forceinline__ void cascade_entry(Cascade& c, Rng& rng, const NucTab& nt, const XsLds& xs,
+template <class XS>
+__device__ __forceinline__ void cascade_entry(Cascade& c, Rng& rng, const NucTab& nt, const XS& xs,
                                               const Opts& o, float T0) {
   const float ub = rng.next();
   const float uphi = rng.next();
@@ -149,8 +150,9 @@ __device__ __forceinline__ void capture(Cascade& c, float eps, int sp) {
 
 // Take the next particle from the stack or end the cascade.  Returns false
 // when the cascade is over.
+template <class XS>
 __device__ __forceinline__ bool next_particle(Cascade& c, StackEntry* stk, Rng& rng, const NucTab& nt,
-                                              const XsLds& xs, const Opts& o) {
+                                              const XS& xs, const Opts& o) {
   if (c.top == 0) return false;
   pop(stk, c);
   majorant(nt, xs, o, c.sp, c.eps, c.sh0, c.sh1);
@@ -173,7 +175,8 @@ __device__ __forceinline__ float flight_weight(const Cascade& c, const NucTab& n
 // nucleus (impact parameter, refraction, majorant, first optical depth);
 // otherwise the particle in hand has escaped and the next one comes from the
 // stack (kStDone when it is empty).  Draws at most 3 uniforms.
-__device__ __forceinline__ int start_step(Cascade& c, StackEntry* stk, Rng& rng, const NucTab& nt, const XsLds& xs,
+template <class XS>
+__device__ __forceinline__ int start_step(Cascade& c, StackEntry* stk, Rng& rng, const NucTab& nt, const XS& xs,
                                           const Opts& o, float T0) {
   rng.ensure(3);
   if (!c.started) {
@@ -254,7 +257,8 @@ __device__ __forceinline__ int flight_core(Cascade& c, StackEntry* stk, const Nu
 // not started, one segment, and after an escape the next particle.  Returns
 // kStFlight, kStTent or kStDone; a transparent pass returns kStFlight with the
 // entry left for the next call.
-__device__ __forceinline__ int flight_step(Cascade& c, StackEntry* stk, Rng& rng, const NucTab& nt, const XsLds& xs,
+template <class XS>
+__device__ __forceinline__ int flight_step(Cascade& c, StackEntry* stk, Rng& rng, const NucTab& nt, const XS& xs,
                                            const Opts& o, float T0, Emit& em) {
   if (!c.started) start_step(c, stk, rng, nt, xs, o, T0);
   int st = flight_core(c, stk, nt, em);
@@ -289,7 +293,8 @@ __device__ __forceinline__ Pair pair_of(const Cascade& c, const NucTab& nt, int 
 // (Sec. 2.2), accept with sigma(p_lab) / sigma_hat.  A rejected (null)
 // collision draws a fresh optical depth and the flight goes on (-> FLIGHT);
 // an accepted one goes to KIN.  Draws at most 6 uniforms.
-__device__ __forceinline__ int tent_step(Cascade& c, Rng& rng, const NucTab& nt, const XsLds& xs, const Opts& o) {
+template <class XS>
+__device__ __forceinline__ int tent_step(Cascade& c, Rng& rng, const NucTab& nt, const XS& xs, const Opts& o) {
   rng.ensure(6);
   const int s = c.shell;
   c.hsh = c.hsh * 3u + (uint32_t)(s + 1);
@@ -308,7 +313,7 @@ __device__ __forceinline__ int tent_step(Cascade& c, Rng& rng, const NucTab& nt,
   float f;
   xs_coord(q.plab * 1e-3f, k, f);
   const int like = (c.sp == y);
-  const float sig = (o.const_sigma_mb > 0.0f ? o.const_sigma_mb : xs_lerp(xs.sig[like], k, f)) * kMbToFm2;
+  const float sig = (o.const_sigma_mb > 0.0f ? o.const_sigma_mb : xs_sig(xs, like, k, f)) * kMbToFm2;
   const float shy = y ? c.sh1 : c.sh0;
   if (!(rng.next() * shy < sig)) {  // u < sigma / sigma_hat
     c.tau = -logf(rng.next());
@@ -321,7 +326,8 @@ __device__ __forceinline__ int tent_step(Cascade& c, Rng& rng, const NucTab& nt,
 // boosts to the lab, Pauli test on both products, hole energy, cutoff
 // capture, LIFO push of the struck nucleon.  Returns the next state (kStDone
 // when the cascade is over).  Draws at most 4 uniforms.
-__device__ __forceinline__ int kin_step(Cascade& c, StackEntry* stk, Rng& rng, const NucTab& nt, const XsLds& xs,
+template <class XS>
+__device__ __forceinline__ int kin_step(Cascade& c, StackEntry* stk, Rng& rng, const NucTab& nt, const XS& xs,
                                         const Opts& o) {
   rng.ensure(4);
   const int s = c.shell;
@@ -420,6 +426,9 @@ __device__ __forceinline__ Nucleus cascade_residual(const Cascade& c, const NucT
 
 // EVAP: one evaporation step (Sec. 2.4, Weisskopf-Ewing reading).  Returns true
 // when no channel is open (the nucleus is final).  Draws at most 4 uniforms.
+// kPhoton: the optional photon channel competes (a separate instantiation,
+// so that the paper's model compiles without any of its code).
+template <bool kPhoton>
 __device__ __forceinline__ bool evap_step(Nucleus& nu, Rng& rng, const BindTab& bt, const EvapTab& et,
                                           const MassTab& mt, Emit& em) {
   em.on = false;
@@ -447,10 +456,12 @@ __device__ __forceinline__ bool evap_step(Nucleus& nu, Rng& rng, const BindTab& 
   // the optional photon channel (channel 6, after the particles): A and Z
   // stay, the level density is the nucleus's own (a = A/8)
   float lwg = -INFINITY, Yg = 0.0f;
-  if (et.photon && nu.E > kPhotonMin && row.lg > -INFINITY) {
-    Yg = 2.0f * sqrtf((float)nu.A * 0.125f * nu.E);
-    lwg = row.lg + log_photon_integral(Yg, nu.E);
-    lmax = fmaxf(lmax, lwg);
+  if constexpr (kPhoton) {
+    if (nu.E > kPhotonMin && row.lg > -INFINITY) {
+      Yg = 2.0f * sqrtf((float)nu.A * 0.125f * nu.E);
+      lwg = row.lg + log_photon_integral(Yg, nu.E);
+      lmax = fmaxf(lmax, lwg);
+    }
   }
   if (lmax == -INFINITY) return true;
   float w[6], total = 0.0f;
@@ -459,8 +470,11 @@ __device__ __forceinline__ bool evap_step(Nucleus& nu, Rng& rng, const BindTab& 
     w[j] = lw[j] == -INFINITY ? 0.0f : expf(lw[j] - lmax);
     total += w[j];
   }
-  const float wg = lwg == -INFINITY ? 0.0f : expf(lwg - lmax);
-  if (et.photon) total += wg;
+  float wg = 0.0f;
+  if constexpr (kPhoton) {
+    wg = lwg == -INFINITY ? 0.0f : expf(lwg - lmax);
+    total += wg;
+  }
   const float uc = rng.next() * total;
   int j = -1;
   float cum = 0.0f;
@@ -469,7 +483,7 @@ __device__ __forceinline__ bool evap_step(Nucleus& nu, Rng& rng, const BindTab& 
     cum += w[i];
     if (j < 0 && w[i] > 0.0f && cum > uc) j = i;
   }
-  if (et.photon) {
+  if constexpr (kPhoton) {
     cum += wg;
     if (j < 0 && wg > 0.0f && cum > uc) j = 6;
   }
@@ -477,36 +491,38 @@ __device__ __forceinline__ bool evap_step(Nucleus& nu, Rng& rng, const BindTab& 
 #pragma unroll
     for (int i = 0; i < 6; ++i)
       if (w[i] > 0.0f) j = i;
-    if (wg > 0.0f) j = 6;
+    if (kPhoton && wg > 0.0f) j = 6;
   }
-  if (j == 6) {
-    // photon: its share of the excitation from the spectrum, energy
-    // (Mp^2 - Md^2) / (2 Mp) = eps (1 - eps / (2 Mp)) in the nucleus's rest
-    // frame, isotropic, boosted to the lab
-    const float sg = photon_sample_s(Yg, rng.next());
-    const float eg = nu.E * sg * (2.0f - sg);
-    const float Ed = nu.E * (1.0f - sg) * (1.0f - sg);
-    const float Mp = row.M + nu.E;
-    const float Eg = eg * (1.0f - 0.5f * eg / Mp);
-    const float ct = 2.0f * rng.next() - 1.0f;
-    const float st = sqrtf(fmaxf(0.0f, 1.0f - ct * ct));
-    float sph, cph;
-    sincospif(2.0f * rng.next(), &sph, &cph);
-    const V3 qv = {Eg * st * cph, Eg * st * sph, Eg * ct};
-    const V3 u = scale(1.0f / Mp, nu.P);
-    const float uu = dot3(u, u);
-    const float g = sqrtf(1.0f + uu);
-    const float ig1 = 1.0f / (g + 1.0f);
-    V3 pf;
-    float Tf;
-    boost_out(qv, 0.0f, u, g, ig1, uu * ig1, pf, Tf);
-    em.on = true;
-    em.kind = 6u | (1u << 8);
-    em.T = sqrtf(dot3(pf, pf));
-    em.u = unit(pf);
-    nu.P = {nu.P.x - pf.x, nu.P.y - pf.y, nu.P.z - pf.z};
-    nu.E = Ed;
-    return false;
+  if constexpr (kPhoton) {
+    if (j == 6) {
+      // photon: its share of the excitation from the spectrum, energy
+      // (Mp^2 - Md^2) / (2 Mp) = eps (1 - eps / (2 Mp)) in the nucleus's rest
+      // frame, isotropic, boosted to the lab
+      const float sg = photon_sample_s(Yg, rng.next());
+      const float eg = nu.E * sg * (2.0f - sg);
+      const float Ed = nu.E * (1.0f - sg) * (1.0f - sg);
+      const float Mp = row.M + nu.E;
+      const float Eg = eg * (1.0f - 0.5f * eg / Mp);
+      const float ct = 2.0f * rng.next() - 1.0f;
+      const float st = sqrtf(fmaxf(0.0f, 1.0f - ct * ct));
+      float sph, cph;
+      sincospif(2.0f * rng.next(), &sph, &cph);
+      const V3 qv = {Eg * st * cph, Eg * st * sph, Eg * ct};
+      const V3 u = scale(1.0f / Mp, nu.P);
+      const float uu = dot3(u, u);
+      const float g = sqrtf(1.0f + uu);
+      const float ig1 = 1.0f / (g + 1.0f);
+      V3 pf;
+      float Tf;
+      boost_out(qv, 0.0f, u, g, ig1, uu * ig1, pf, Tf);
+      em.on = true;
+      em.kind = 6u | (1u << 8);
+      em.T = sqrtf(dot3(pf, pf));
+      em.u = unit(pf);
+      nu.P = {nu.P.x - pf.x, nu.P.y - pf.y, nu.P.z - pf.z};
+      nu.E = Ed;
+      return false;
+    }
   }
   float Uj = 0.0f, Vj = 0.0f, Yj = 0.0f, mj = 0.0f;
   int aj = 0, zj = 0;

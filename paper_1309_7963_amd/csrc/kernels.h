@@ -20,16 +20,26 @@ struct MidState {
 };
 static_assert(sizeof(MidState) == 32, "MidState layout");
 
-// Events per work-queue chunk of the persistent kernels.
+// Events per work-queue chunk of the persistent kernels: the default, and
+// the range of the chunk_events option (multiples of kChunkMin).
 constexpr int kChunkEvents = 64;
+constexpr int kChunkMin = 16;
+constexpr int kChunkMax = 1024;
+
+// LDS layouts of the NN table in the event kernels: none (evaporation
+// kernels), columns (XsLds) or node pairs (XsPairs).
+constexpr int kXsNone = -1, kXsColumns = 0, kXsPairs = 1;
+__host__ __device__ constexpr size_t xs_lds_bytes(int layout) {
+  return layout == kXsPairs ? sizeof(XsPairs) : layout == kXsColumns ? sizeof(XsLds) : 0;
+}
 
 // Hand-over buffer of a plain or staged launch of n events: n MidState
 // records, then (staged) the chunks whose evaporation is left to the
 // evaporation kernel: [0] chunks listed, [1] chunks claimed by the
 // evaporation kernel, [2], [3] unused, then the first event of each listed
-// chunk.
+// chunk (room for chunks as small as kChunkMin).
 constexpr size_t mid_bytes(size_t n) {
-  return sizeof(MidState) * n + sizeof(uint32_t) * (4 + (n + kChunkEvents - 1) / kChunkEvents);
+  return sizeof(MidState) * n + sizeof(uint32_t) * (4 + (n + kChunkMin - 1) / kChunkMin);
 }
 
 struct LaunchDesc {
@@ -39,6 +49,9 @@ struct LaunchDesc {
   int evap_blocks;       // staged mode: grid of the evaporation kernel
   int evap_threshold, tent_threshold, kin_threshold, start_threshold;
   int stack_lds;         // stack entries per lane held in LDS (stack_levels)
+  int chunk;             // events per work-queue claim (0: kChunkEvents)
+  int xs_pairs;          // persistent kernels: NN table in LDS as node pairs
+  int photon;            // the evaporation has the photon channel (instantiation)
   const NucTab* nuc;
   int n_targets;
   const XsTab* xs;
@@ -74,26 +87,28 @@ constexpr float kMaxExcitation = 500.0f;  // MeV
 // The event kernels exist in two builds of one source (kernels.hip): IEEE
 // arithmetic and precise transcendentals (precise, the default) and the
 // fast-math build (fast, Sec. 4.2).  Each namespace provides:
-//   lds_bytes     dynamic LDS of an event kernel launch;
+//   lds_bytes     dynamic LDS of an event kernel launch (xs_layout: kXsNone for
+//                 the evaporation kernels, else the NN table's layout);
 //   stack_levels  LIFO entries per lane that fit in LDS for the event kernel of
 //                 `mode` at this block size when `waves_per_cu` waves are meant
-//                 to share a CU (the kernel's own occupancy limit applies too);
-//                 0 when none fit;
+//                 to share a CU, with the NN table in xs_layout (the plain
+//                 kernel always uses columns; the kernel's own occupancy limit
+//                 applies too); 0 when none fit;
 //   evap_blocks_per_cu  resident blocks per CU of the staged evaporation
 //                 kernel (its own occupancy: it needs fewer registers);
 //   launch_events zero the counters, then launch the event kernel(s) of L.mode.
 //   launch_evaporation  evaporation alone of L.n given excited nuclei
 //                 (L.mid: the hand-over buffer; L.T0, L.tidx unused).
 namespace precise {
-size_t lds_bytes(int n_targets, int block, bool with_xs, int stack_levels);
-int stack_levels(int mode, int n_targets, int block, int waves_per_cu);
+size_t lds_bytes(int n_targets, int block, int xs_layout, int stack_levels);
+int stack_levels(int mode, int n_targets, int block, int waves_per_cu, int xs_layout);
 int evap_blocks_per_cu(int block);
 hipError_t launch_events(const LaunchDesc& L, hipStream_t s);
 hipError_t launch_evaporation(const LaunchDesc& L, const ExcitedDesc& x, hipStream_t s);
 }  // namespace precise
 namespace fast {
-size_t lds_bytes(int n_targets, int block, bool with_xs, int stack_levels);
-int stack_levels(int mode, int n_targets, int block, int waves_per_cu);
+size_t lds_bytes(int n_targets, int block, int xs_layout, int stack_levels);
+int stack_levels(int mode, int n_targets, int block, int waves_per_cu, int xs_layout);
 int evap_blocks_per_cu(int block);
 hipError_t launch_events(const LaunchDesc& L, hipStream_t s);
 hipError_t launch_evaporation(const LaunchDesc& L, const ExcitedDesc& x, hipStream_t s);

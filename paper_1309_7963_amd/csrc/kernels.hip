@@ -11,6 +11,8 @@
 // transcendentals, reciprocal division, flushed denormals, Sec. 4.2).
 #include "kernels.h"
 
+#include <type_traits>
+
 #include "event.h"
 
 #ifndef INC_KERNEL_NS
@@ -39,36 +41,48 @@ struct KernelArgs {
   MidState* mid;             // plain kernels: cascade -> evaporation hand-over
   RingDev ring;              // streaming output (rec == NULL: segment arrays)
   int stack_lds;             // stack entries per lane held in LDS
+  int chunk;                 // events per work-queue claim
 };
 
 __device__ __forceinline__ bool energy_ok(float T0) { return T0 >= 20.0f && T0 <= 250.0f; }
 
-// LDS layout of the event kernels: [n_targets NucTab][XsLds][MassTab][writer
-// buffers of the block's waves][LIFO levels: per wave stack_lds x 2 x 64
-// float4].  The evaporation kernels stage only the MassTab (n_targets = 0,
-// no XsLds: with_xs = false), have no stack and larger writer buffers
+// LDS layout of the event kernels: [n_targets NucTab][NN table][MassTab]
+// [writer buffers of the block's waves][LIFO levels: per wave stack_lds x 2 x
+// 64 float4].  The NN table is XsLds (columns) or XsPairs (node pairs), see
+// xs_lds_bytes.  The evaporation kernels stage only the MassTab (n_targets =
+// 0, no NN table: kXsNone), have no stack and larger writer buffers
 // (kWriterCapEvap records per wave: nearly every lane emits every step).
-__device__ __forceinline__ size_t lds_mass_offset(int n_targets, bool with_xs) {
-  return (size_t)n_targets * sizeof(NucTab) + (with_xs ? sizeof(XsLds) : 0);
+__device__ __forceinline__ size_t lds_mass_offset(int n_targets, int xs_layout) {
+  return (size_t)n_targets * sizeof(NucTab) + xs_lds_bytes(xs_layout);
 }
 // First float4 of this lane's column in the LDS stack area (each wave owns
 // levels x 2 x 64 consecutive float4).
-__device__ __forceinline__ int lds_stack_base(int n_targets, int levels) {
-  return (int)((lds_mass_offset(n_targets, true) + sizeof(MassTab) +
+__device__ __forceinline__ int lds_stack_base(int n_targets, int xs_layout, int levels) {
+  return (int)((lds_mass_offset(n_targets, xs_layout) + sizeof(MassTab) +
                 (blockDim.x / 64) * (kWriterCap * kRecWords * sizeof(uint32_t))) /
                sizeof(float4)) +
          (int)(threadIdx.x / 64) * levels * 128 + (int)(threadIdx.x % 64);
 }
-__device__ __forceinline__ void stage_tables(char* lds, const KernelArgs& a, int n_targets, bool with_xs) {
+__device__ __forceinline__ void stage_tables(char* lds, const KernelArgs& a, int n_targets, int xs_layout) {
   uint32_t* dst = (uint32_t*)lds;
   const uint32_t* src = (const uint32_t*)a.nuc;
   for (int i = threadIdx.x; i < n_targets * (int)(sizeof(NucTab) / 4); i += blockDim.x) dst[i] = src[i];
-  if (with_xs) {
+  if (xs_layout == kXsColumns) {
     uint32_t* dx = (uint32_t*)(lds + n_targets * sizeof(NucTab));
     const uint32_t* sx = (const uint32_t*)a.xs;
     for (int i = threadIdx.x; i < (int)(sizeof(XsLds) / 4); i += blockDim.x) dx[i] = sx[i];
+  } else if (xs_layout == kXsPairs) {
+    // the four columns (sigma and majorant of unlike and like pairs) as
+    // (v[k], v[k+1]); the last node repeats itself (never read: the table
+    // coordinate stays below the last node)
+    float2* dx = (float2*)(lds + n_targets * sizeof(NucTab));
+    const float* sx = (const float*)a.xs;
+    for (int i = threadIdx.x; i < 4 * kXsNodes; i += blockDim.x) {
+      const int k = i % kXsNodes;
+      dx[i] = make_float2(sx[i], sx[i - k + min(k + 1, kXsNodes - 1)]);
+    }
   }
-  uint32_t* dm = (uint32_t*)(lds + lds_mass_offset(n_targets, with_xs));
+  uint32_t* dm = (uint32_t*)(lds + lds_mass_offset(n_targets, xs_layout));
   const uint32_t* sm = (const uint32_t*)a.mass;
   for (int i = threadIdx.x; i < (int)(sizeof(MassTab) / 4); i += blockDim.x) dm[i] = sm[i];
   __syncthreads();
@@ -129,10 +143,10 @@ __device__ __forceinline__ void put_hist_cascade(const KernelArgs& a, EventRef e
 // the escaping particles through the compacted writer.
 __global__ void __launch_bounds__(256) k_cascade_plain(KernelArgs a) {
   extern __shared__ __align__(16) char lds[];
-  stage_tables(lds, a, a.n_targets, true);
+  stage_tables(lds, a, a.n_targets, kXsColumns);
   const NucTab* snt = (const NucTab*)lds;
   const XsLds& sxs = *(const XsLds*)(lds + a.n_targets * sizeof(NucTab));
-  uint32_t* wbuf = (uint32_t*)(lds + lds_mass_offset(a.n_targets, true) + sizeof(MassTab)) +
+  uint32_t* wbuf = (uint32_t*)(lds + lds_mass_offset(a.n_targets, kXsColumns) + sizeof(MassTab)) +
                    (threadIdx.x / 64) * (kWriterCap * kRecWords);
   int fill = 0;
 
@@ -161,7 +175,7 @@ __global__ void __launch_bounds__(256) k_cascade_plain(KernelArgs a) {
   Cascade c;
   cascade_init(c, nt);
   StackEntry stk[kStackDepth];
-  c.stk_base = lds_stack_base(a.n_targets, a.stack_lds);
+  c.stk_base = lds_stack_base(a.n_targets, kXsColumns, a.stack_lds);
   c.stk_levels = a.stack_lds;
 
   while (__any(live)) {
@@ -197,9 +211,10 @@ __global__ void __launch_bounds__(256) k_cascade_plain(KernelArgs a) {
 
 // Plain evaporation kernel: one de-excitation per thread (Sec. 3.3), same
 // random stream continued after the cascade's draws.
+template <bool kPhoton>
 __global__ void __launch_bounds__(256) k_evap_plain(KernelArgs a) {
   extern __shared__ __align__(16) char lds[];
-  stage_tables(lds, a, 0, false);
+  stage_tables(lds, a, 0, kXsNone);
   const MassTab& smt = *(const MassTab*)lds;
   uint32_t* wbuf = (uint32_t*)(lds + sizeof(MassTab)) + (threadIdx.x / 64) * (kWriterCapEvap * kRecWords);
   int fill = 0;
@@ -243,7 +258,7 @@ __global__ void __launch_bounds__(256) k_evap_plain(KernelArgs a) {
     Emit em;
     em.on = false;
     if (live) {
-      if (evap_step(nu, rng, a.bind, a.evap, smt, em)) {
+      if (evap_step<kPhoton>(nu, rng, a.bind, a.evap, smt, em)) {
         write_residual(a.segs[er.seg].res + er.local, nu, m.E, nsec, flags, m.ncoll, m.nretry);
         put_hist(a, er, kHistDraws, rng.drawn());
         live = false;
@@ -266,9 +281,7 @@ __global__ void __launch_bounds__(256) k_evap_plain(KernelArgs a) {
 // states wait, so every step runs with many lanes together; each lane still
 // consumes its own random stream in order, so results do not depend on the
 // schedule.
-constexpr int kChunk = kChunkEvents;
-
-// Sources of evaporation work: chunks of kChunk consecutive launch events.
+// Sources of evaporation work: chunks of a.chunk consecutive launch events.
 // The evaporation kernel takes the chunks listed after the hand-over records
 // (mid_bytes): those of waves that took more chunks than they keep.
 struct LeftChunks {
@@ -301,7 +314,7 @@ struct OwnChunks {
 // current chunk, records whose cascade already ended the event (kMidFinal)
 // are skipped.  The random stream resumes after the cascade's draws, so the
 // results equal the fused kernel's whichever kernel runs this.
-template <int kCap, class Src>
+template <int kCap, bool kPhoton, class Src>
 __device__ __forceinline__ void evap_events(const KernelArgs& a, const MassTab& smt, uint32_t* wbuf, int& fill,
                                             Src& src) {
   unsigned long long chunk_next = 0, chunk_end = 0;
@@ -319,7 +332,7 @@ __device__ __forceinline__ void evap_events(const KernelArgs& a, const MassTab& 
         unsigned long long base = 0;
         if (src.claim(base)) {
           chunk_next = base;
-          chunk_end = base + kChunk < a.n ? base + kChunk : a.n;
+          chunk_end = base + a.chunk < a.n ? base + a.chunk : a.n;
         } else {
           exhausted = true;
           chunk_next = chunk_end = 0;
@@ -357,7 +370,7 @@ __device__ __forceinline__ void evap_events(const KernelArgs& a, const MassTab& 
     Emit em;
     em.on = false;
     if (busy) {
-      if (evap_step(nu, rng, a.bind, a.evap, smt, em)) {
+      if (evap_step<kPhoton>(nu, rng, a.bind, a.evap, smt, em)) {
         write_residual(a.segs[er.seg].res + er.local, nu, Ex_casc, nsec, flags, ncoll, nretry);
         put_hist(a, er, kHistDraws, rng.drawn());
         if (flags) atomicAdd(&a.segs[er.seg].counters[1], 1ull);
@@ -376,14 +389,18 @@ __device__ __forceinline__ void evap_events(const KernelArgs& a, const MassTab& 
 // otherwise (staged mode) the loop hands each finished cascade over and has
 // no evaporation state, which leaves it fewer live registers; the wave
 // evaporates its hand-overs in a second loop once its cascades are over.
-template <bool kFused>
+// kPairs: the NN table in LDS as node pairs (XsPairs) instead of columns.
+// kPhoton: the evaporation has the optional photon channel.
+template <bool kFused, bool kPairs, bool kPhoton>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) k_persistent(KernelArgs a) {
+  using XS = typename std::conditional<kPairs, XsPairs, XsLds>::type;
+  constexpr int kLayout = kPairs ? kXsPairs : kXsColumns;
   extern __shared__ __align__(16) char lds[];
-  stage_tables(lds, a, a.n_targets, true);
+  stage_tables(lds, a, a.n_targets, kLayout);
   const NucTab* snt = (const NucTab*)lds;
-  const XsLds& sxs = *(const XsLds*)(lds + a.n_targets * sizeof(NucTab));
-  const MassTab& smt = *(const MassTab*)(lds + lds_mass_offset(a.n_targets, true));
-  uint32_t* wbuf = (uint32_t*)(lds + lds_mass_offset(a.n_targets, true) + sizeof(MassTab)) +
+  const XS& sxs = *(const XS*)(lds + a.n_targets * sizeof(NucTab));
+  const MassTab& smt = *(const MassTab*)(lds + lds_mass_offset(a.n_targets, kLayout));
+  uint32_t* wbuf = (uint32_t*)(lds + lds_mass_offset(a.n_targets, kLayout) + sizeof(MassTab)) +
                    (threadIdx.x / 64) * (kWriterCap * kRecWords);
   int fill = 0;
 
@@ -402,7 +419,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) k
   Cascade c;
   Nucleus nu = {0, 0, 0.0f, {0.0f, 0.0f, 0.0f}};
   StackEntry stk[kStackDepth];
-  c.stk_base = lds_stack_base(a.n_targets, a.stack_lds);
+  c.stk_base = lds_stack_base(a.n_targets, kLayout, a.stack_lds);
   c.stk_levels = a.stack_lds;
 
   for (;;) {
@@ -411,10 +428,10 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) k
     if (need && !exhausted) {
       if (chunk_next == chunk_end) {
         unsigned long long base = 0;
-        if (lane_id() == 0) base = atomicAdd(a.queue, (unsigned long long)kChunk);
+        if (lane_id() == 0) base = atomicAdd(a.queue, (unsigned long long)a.chunk);
         base = __shfl(base, 0);
         chunk_next = base;
-        chunk_end = base + kChunk < a.n ? base + kChunk : a.n;
+        chunk_end = base + a.chunk < a.n ? base + a.chunk : a.n;
         if (base >= a.n) {
           exhausted = true;
           chunk_next = chunk_end = a.n;
@@ -497,7 +514,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) k
     em.on = false;
     if (kFused && run == kStEvap) {
       if (st == kStEvap) {
-        if (evap_step(nu, rng, a.bind, a.evap, smt, em)) {
+        if (evap_step<kPhoton>(nu, rng, a.bind, a.evap, smt, em)) {
           write_residual(a.segs[er.seg].res + er.local, nu, Ex_casc, nsec, c.flags, c.ncoll, c.nretry);
           put_hist(a, er, kHistDraws, rng.drawn());
           if (c.flags) atomicAdd(&a.segs[er.seg].counters[1], 1ull);
@@ -559,7 +576,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) k
     __builtin_amdgcn_s_setprio(0);
     __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
     OwnChunks src = {own_list, own_count, 0};
-    evap_events<kWriterCap>(a, smt, wbuf, fill, src);
+    evap_events<kWriterCap, kPhoton>(a, smt, wbuf, fill, src);
   }
   writer_flush(wbuf, fill, a.segs, a.ring);
 }
@@ -567,18 +584,19 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) k
 // Staged mode, second kernel: the evaporation of the handed-over events the
 // cascade kernel's waves did not evaporate themselves (the chunks listed
 // after the hand-over records), as a persistent work-queue kernel.
+template <bool kPhoton>
 __global__ void __launch_bounds__(256) k_evap_persistent(KernelArgs a) {
   // usually nothing is left: the cascade waves evaporated what they handed over
   uint32_t* left = (uint32_t*)(a.mid + a.n);
   const uint32_t count = __hip_atomic_load(&left[0], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   if (count == 0) return;
   extern __shared__ __align__(16) char lds[];
-  stage_tables(lds, a, 0, false);
+  stage_tables(lds, a, 0, kXsNone);
   const MassTab& smt = *(const MassTab*)lds;
   uint32_t* wbuf = (uint32_t*)(lds + sizeof(MassTab)) + (threadIdx.x / 64) * (kWriterCapEvap * kRecWords);
   int fill = 0;
   LeftChunks src = {left, count};
-  evap_events<kWriterCapEvap>(a, smt, wbuf, fill, src);
+  evap_events<kWriterCapEvap, kPhoton>(a, smt, wbuf, fill, src);
   writer_flush(wbuf, fill, a.segs, a.ring);
 }
 
@@ -592,11 +610,11 @@ __global__ void k_excited_setup(KernelArgs a, ExcitedDesc x) {
   const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
   uint32_t* left = (uint32_t*)(a.mid + a.n);
   if (i == 0) {
-    left[0] = (uint32_t)((a.n + kChunk - 1) / kChunk);
+    left[0] = (uint32_t)((a.n + a.chunk - 1) / a.chunk);
     left[1] = 0u;
   }
   if (i >= a.n) return;
-  if (i % kChunk == 0) left[4 + i / kChunk] = (uint32_t)i;
+  if (i % a.chunk == 0) left[4 + i / a.chunk] = (uint32_t)i;
   const int A = x.A[i], Z = x.Z[i];
   const float E = x.Ex[i];
   float P[3] = {0.0f, 0.0f, 0.0f};
@@ -645,23 +663,28 @@ __global__ void k_zero_counters(const Segment* segs, int n_seg, unsigned long lo
 }
 
 // ================================================================ launchers
-size_t lds_bytes(int n_targets, int block, bool with_xs, int stack_levels) {
-  return (size_t)n_targets * sizeof(NucTab) + (with_xs ? sizeof(XsLds) : 0) + sizeof(MassTab) +
-         (size_t)(block / 64) * (with_xs ? kWriterCap : kWriterCapEvap) * kRecWords * sizeof(uint32_t) +
+size_t lds_bytes(int n_targets, int block, int xs_layout, int stack_levels) {
+  const bool events = xs_layout != kXsNone;
+  return (size_t)n_targets * sizeof(NucTab) + xs_lds_bytes(xs_layout) + sizeof(MassTab) +
+         (size_t)(block / 64) * (events ? kWriterCap : kWriterCapEvap) * kRecWords * sizeof(uint32_t) +
          (size_t)stack_levels * 2 * block * sizeof(float4);
 }
 
-int stack_levels(int mode, int n_targets, int block, int waves_per_cu) {
+int stack_levels(int mode, int n_targets, int block, int waves_per_cu, int xs_layout) {
   int dev = 0, lds_cu = 0;
   if (hipGetDevice(&dev) != hipSuccess ||
       hipDeviceGetAttribute(&lds_cu, hipDeviceAttributeMaxSharedMemoryPerMultiprocessor, dev) != hipSuccess ||
       lds_cu <= 0)
     return 0;
-  const size_t base = lds_bytes(n_targets, block, true, 0);
+  if (mode == INC_MODE_PLAIN) xs_layout = kXsColumns;
+  const size_t base = lds_bytes(n_targets, block, xs_layout, 0);
   int occ = 0;
+  const bool pairs = xs_layout == kXsPairs;
   const void* fn = mode == INC_MODE_PLAIN        ? (const void*)k_cascade_plain
-                   : mode == INC_MODE_PERSISTENT ? (const void*)k_persistent<true>
-                                                 : (const void*)k_persistent<false>;
+                   : mode == INC_MODE_PERSISTENT ? (pairs ? (const void*)k_persistent<true, true, false>
+                                                          : (const void*)k_persistent<true, false, false>)
+                                                 : (pairs ? (const void*)k_persistent<false, true, false>
+                                                          : (const void*)k_persistent<false, false, false>);
   if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, fn, block, base) != hipSuccess || occ < 1) return 0;
   int blocks = occ;
   if (mode != INC_MODE_PLAIN) {
@@ -677,8 +700,8 @@ int stack_levels(int mode, int n_targets, int block, int waves_per_cu) {
 
 int evap_blocks_per_cu(int block) {
   int occ = 0;
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, (const void*)k_evap_persistent, block,
-                                                   lds_bytes(0, block, false, 0)) != hipSuccess ||
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, (const void*)k_evap_persistent<false>, block,
+                                                   lds_bytes(0, block, kXsNone, 0)) != hipSuccess ||
       occ < 1)
     return 1;
   return occ;
@@ -713,6 +736,7 @@ static KernelArgs kernel_args(const LaunchDesc& L) {
   a.mid = L.mid;
   a.ring = L.ring;
   a.stack_lds = L.stack_lds;
+  a.chunk = L.chunk > 0 ? L.chunk : kChunkEvents;
   return a;
 }
 
@@ -723,18 +747,39 @@ hipError_t launch_events(const LaunchDesc& L, hipStream_t s) {
   const int block = L.block;
   if (L.mode == INC_MODE_PLAIN) {
     const unsigned grid = (unsigned)((L.n + block - 1) / block);
-    hipLaunchKernelGGL(k_cascade_plain, dim3(grid), dim3(block), lds_bytes(L.n_targets, block, true, L.stack_lds),
-                       s, a);
-    hipLaunchKernelGGL(k_evap_plain, dim3(grid), dim3(block), lds_bytes(0, block, false, 0), s, a);
-  } else {
-    if (L.mode == INC_MODE_STAGED)
-      hipLaunchKernelGGL(k_persistent<false>, dim3(L.persistent_blocks), dim3(block),
-                         lds_bytes(L.n_targets, block, true, L.stack_lds), s, a);
+    hipLaunchKernelGGL(k_cascade_plain, dim3(grid), dim3(block),
+                       lds_bytes(L.n_targets, block, kXsColumns, L.stack_lds), s, a);
+    if (L.photon)
+      hipLaunchKernelGGL(k_evap_plain<true>, dim3(grid), dim3(block), lds_bytes(0, block, kXsNone, 0), s, a);
     else
-      hipLaunchKernelGGL(k_persistent<true>, dim3(L.persistent_blocks), dim3(block),
-                         lds_bytes(L.n_targets, block, true, L.stack_lds), s, a);
-    if (L.mode == INC_MODE_STAGED)
-      hipLaunchKernelGGL(k_evap_persistent, dim3(L.evap_blocks), dim3(block), lds_bytes(0, block, false, 0), s, a);
+      hipLaunchKernelGGL(k_evap_plain<false>, dim3(grid), dim3(block), lds_bytes(0, block, kXsNone, 0), s, a);
+  } else {
+    const int layout = L.xs_pairs ? kXsPairs : kXsColumns;
+    const size_t lds = lds_bytes(L.n_targets, block, layout, L.stack_lds);
+    const dim3 grid(L.persistent_blocks);
+    // the photon channel's instantiations take the columns layout
+    if (L.photon) {
+      if (L.mode == INC_MODE_STAGED)
+        hipLaunchKernelGGL((k_persistent<false, false, true>), grid, dim3(block),
+                           lds_bytes(L.n_targets, block, kXsColumns, L.stack_lds), s, a);
+      else
+        hipLaunchKernelGGL((k_persistent<true, false, true>), grid, dim3(block),
+                           lds_bytes(L.n_targets, block, kXsColumns, L.stack_lds), s, a);
+    } else if (L.mode == INC_MODE_STAGED) {
+      if (L.xs_pairs) hipLaunchKernelGGL((k_persistent<false, true, false>), grid, dim3(block), lds, s, a);
+      else hipLaunchKernelGGL((k_persistent<false, false, false>), grid, dim3(block), lds, s, a);
+    } else {
+      if (L.xs_pairs) hipLaunchKernelGGL((k_persistent<true, true, false>), grid, dim3(block), lds, s, a);
+      else hipLaunchKernelGGL((k_persistent<true, false, false>), grid, dim3(block), lds, s, a);
+    }
+    if (L.mode == INC_MODE_STAGED) {
+      if (L.photon)
+        hipLaunchKernelGGL(k_evap_persistent<true>, dim3(L.evap_blocks), dim3(block), lds_bytes(0, block, kXsNone, 0),
+                           s, a);
+      else
+        hipLaunchKernelGGL(k_evap_persistent<false>, dim3(L.evap_blocks), dim3(block),
+                           lds_bytes(0, block, kXsNone, 0), s, a);
+    }
   }
   return hipGetLastError();
 }
@@ -744,7 +789,12 @@ hipError_t launch_evaporation(const LaunchDesc& L, const ExcitedDesc& x, hipStre
   hipLaunchKernelGGL(k_zero_counters, dim3((L.n_seg + 63) / 64), dim3(64), 0, s, L.segs, L.n_seg, L.queue,
                      (uint32_t*)nullptr);
   hipLaunchKernelGGL(k_excited_setup, dim3((unsigned)((L.n + 255) / 256)), dim3(256), 0, s, a, x);
-  hipLaunchKernelGGL(k_evap_persistent, dim3(L.evap_blocks), dim3(L.block), lds_bytes(0, L.block, false, 0), s, a);
+  if (L.photon)
+    hipLaunchKernelGGL(k_evap_persistent<true>, dim3(L.evap_blocks), dim3(L.block), lds_bytes(0, L.block, kXsNone, 0),
+                       s, a);
+  else
+    hipLaunchKernelGGL(k_evap_persistent<false>, dim3(L.evap_blocks), dim3(L.block), lds_bytes(0, L.block, kXsNone, 0),
+                       s, a);
   return hipGetLastError();
 }
 

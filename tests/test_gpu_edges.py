@@ -91,28 +91,38 @@ def test_sixteen_targets_in_one_context():
 
 
 def test_autotuned_policy_changes_speed_not_results():
-    """The autotuner picks among launch policies (block size, waves per CU,
-    scheduler thresholds); every candidate must produce the same events."""
+    """The autotuner picks among launch policies (block size and waves per
+    CU, scheduler thresholds, LIFO levels in LDS, events per queue claim, the
+    NN table's LDS layout); every candidate must produce the same events, in
+    staged and in fused persistent mode."""
     from paper_1309_7963_amd import autotune
 
-    targets = [(12, 6), (16, 8)]
+    targets = [(12, 6), (16, 8), (208, 82)]
     rng = np.random.default_rng(11)
     n = 20000
-    tidx = rng.integers(0, 2, n).astype(np.uint8)
+    tidx = rng.choice(3, n, p=[0.45, 0.45, 0.1]).astype(np.uint8)
     T0 = rng.uniform(20, 250, n).astype(np.float32)
-    grid = {"block_size": (128, 256), "waves_per_cu": (8, 12), "thresholds": ((24, 24, 8), (16, 8, 8))}
-    best = autotune.tune(targets, T0, tidx, grid=grid, repeats=2, use_cache=False)
-    opts = best["options"]
-    if opts:  # else the library default was kept (no candidate was clearly faster)
-        assert opts["block_size"] in grid["block_size"] and opts["waves_per_cu"] in grid["waves_per_cu"]
-        assert (opts["kin_threshold"], opts["tent_threshold"], opts["start_threshold"]) in grid["thresholds"]
-        assert best["ms"] < best["default_ms"]
-    assert len(best["table"]) == 8 and best["ms"] > 0 and best["default_ms"] > 0
-    ref = run_gpu(targets, T0, seed=4, tidx=tidx, mode="staged")
-    for cand in best["table"]:
-        h = run_gpu(targets, T0, seed=4, tidx=tidx, mode="staged", **cand["options"])
-        assert h["res"].tobytes() == ref["res"].tobytes(), cand["options"]
-        assert h["n_sec_total"] == ref["n_sec_total"], cand["options"]
+    dims = {
+        "launch": (dict(block_size=128, waves_per_cu=8), dict(block_size=256, waves_per_cu=12)),
+        "thresholds": (dict(kin_threshold=24, tent_threshold=24, start_threshold=8),
+                       dict(kin_threshold=16, tent_threshold=8, start_threshold=8)),
+        "stack_levels": (dict(stack_levels=-1), dict(stack_levels=1), dict(stack_levels=0)),
+        "chunk_events": (dict(chunk_events=16), dict(chunk_events=128), dict(chunk_events=1024)),
+        "table_layout": (dict(table_layout=0), dict(table_layout=1)),
+    }
+    best = autotune.tune(targets, T0, tidx, dimensions=dims, repeats=2, use_cache=False)
+    assert len(best["table"]) == 12 and best["ms"] > 0 and best["default_ms"] > 0
+    swept = best["swept_options"]
+    for name, cands in dims.items():
+        assert any(all(swept[k] == v for k, v in c.items()) for c in cands), name
+    if best["options"]:  # else the library default was kept (not clearly faster)
+        assert best["options"] == swept and best["ms"] < best["default_ms"]
+    for mode in ("staged", "persistent"):
+        ref = run_gpu(targets, T0, seed=4, tidx=tidx, mode=mode)
+        for cand in best["table"]:
+            h = run_gpu(targets, T0, seed=4, tidx=tidx, mode=mode, **cand["options"])
+            assert h["res"].tobytes() == ref["res"].tobytes(), (mode, cand["options"])
+            assert h["n_sec_total"] == ref["n_sec_total"], (mode, cand["options"])
 
 
 def test_staged_evaporation_overflow_pass():
