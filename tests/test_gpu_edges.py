@@ -156,3 +156,33 @@ def test_costliest_first_start_order_changes_nothing(mode):
     inorder = run_gpu(targets, T0, seed=6, tidx=tidx, mode=mode, input_order=1)
     assert ordered["res"].tobytes() == inorder["res"].tobytes()
     assert ordered["n_sec_total"] == inorder["n_sec_total"]
+
+
+def test_batches_in_flight_on_two_streams_equal_one_at_a_time():
+    """Consecutive batches with two on the device at once (each with its own
+    context, buffers and stream, as the benchmark runs them) give the same
+    events as the same batches run one after another."""
+    import torch
+    import paper_1309_7963_amd as inc
+
+    targets = [(16, 8), (40, 20)]
+    n = 200_000
+    rng = np.random.default_rng(31)
+    tidx = rng.integers(0, 2, n).astype(np.uint8)
+    T0 = np.full(n, 200.0, np.float32)
+    T0_d = torch.as_tensor(T0, device="cuda")
+    ti_d = torch.as_tensor(tidx, device="cuda")
+    ctxs = [inc.Context(targets) for _ in range(2)]
+    streams = [torch.cuda.Stream() for _ in range(2)]
+    outs = [[inc.DeviceOutput.allocate(n, ctxs[0].default_capacity(n)) for _ in range(2)] for _ in range(2)]
+    for k in range(4):
+        i = k % 2
+        ctxs[i].simulate(T0_d, seed=3, target_idx=ti_d, out=outs[i][k // 2], first_event_id=k * n, stream=streams[i])
+    torch.cuda.synchronize()
+    for k in range(4):
+        ref = run_gpu(targets, T0, seed=3, tidx=tidx, mode="staged", first_id=k * n)
+        got = outs[k % 2][k // 2].to_numpy()
+        assert got["res"].tobytes() == ref["res"].tobytes(), k
+        assert got["n_sec_total"] == ref["n_sec_total"], k
+    for c in ctxs:
+        c.close()
