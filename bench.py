@@ -41,22 +41,122 @@ sys.path.insert(0, ROOT)
 # MI355X: 256 CUs x 64 FP32 lanes x 2.4 GHz = one VALU lane-operation per lane
 # per clock (FMA counted as one operation, no packed math).
 PEAK_LANE_OPS = 256 * 64 * 2.4e9
-# Algorithmic lane-operations per step of the method (FP32 add/mul/FMA/compare
-# and 32-bit integer ops count 1; exp, log, sqrt, rcp/div, sin/cos count 4,
-# the issue cost of a quarter-rate transcendental; cbrt and sincos count 8).
-STEP_COST = {
-    "draw": 27,          # one uniform: a quarter of a Philox4x32-10 block (98 ops) + mapping
-    "tau": 5,            # -ln u
-    "segment": 37,       # ray-sphere distances to the shell boundaries, optical-depth test
-    "crossing": 60,      # move to the boundary, normal, refraction or reflection
-    "tentative": 110,    # species, Fermi momentum, invariants s and p_lab, table lookup, accept test
-    "kinematics": 170,   # CM frame, angle sampling, rotation, two boosts, Pauli test
-    "collision": 90,     # cutoff, stack, majorant of the new flight
-    "entry": 70,         # impact parameter, inward refraction, majorant
-    "evap_channels": 300,  # six channels: separation energy, barrier, width (log domain)
-    "evap_emit": 330,    # channel choice, spectrum inversion (~6 Newton steps), decay, boost
-    "escape": 30,        # escape momentum and the ledger
+# Algorithmic lane-operations per step of the method, counted item by item
+# from the oracle's formulas.  Each entry is (what, basic, transcendental,
+# wide): basic = FP32 add/sub/mul/FMA/min/max/compare/select and 32-bit
+# integer operations, weight 1; transcendental = exp, log, sqrt, reciprocal,
+# sin, cos (a division is a reciprocal and a multiply), weight 4, the issue
+# cost of a quarter-rate instruction; wide = cbrt or a sine-cosine pair,
+# weight 8.  Counting rules: a quantity is counted once per event where it is
+# first formed (the collision reuses T_x, T_t, Q, s, p* and p_lab of its
+# tentative step); quantities that depend only on the target or on the
+# nuclide (A, Z) -- masses, separation energies, Coulomb barriers, radii,
+# Fermi energies and momenta, shell radii -- are set-up tables, not per-event
+# work; sigma and its majorant are read from pre-calculated tables with
+# linear interpolation in log p_lab, as the paper's implementation does
+# (Sec. 3); an inversion counts the mean number of Newton steps it takes
+# (4 residuals, 3 updates for the spectrum) rather than the oracle's
+# bisection; counters that only serve diagnostics are not counted.
+STEP_OPS = {
+    "draw": [  # one uniform
+        ("a quarter of a Philox4x32-10 block: 10 rounds x (2 mul_lo, 2 mul_hi, 4 xor), "
+         "9 key bumps x 2 adds, counter bump", 99 / 4, 0, 0),
+        ("24-bit mantissa to (0, 1): shift, convert, FMA; position in the block", 4, 0, 0),
+    ],
+    "tau": [  # optical depth of a new flight (the uniform is a draw)
+        ("-ln u", 1, 1, 0),
+    ],
+    "segment": [  # every flight segment inside one shell
+        ("lambda = rho_n sh_n + rho_p sh_p with the sea-occupancy checks", 6, 0, 0),
+        ("x.d and b^2 = |x cross d|^2", 12, 0, 0),
+        ("inner-sphere test: s > 0, x.d < 0, b^2 < r_in^2", 5, 0, 0),
+        ("distance: r^2 - b^2, clamp, sqrt, -x.d -/+ root, clamp; destination shell", 5, 1, 0),
+        ("optical-depth test tau < lambda t; segment guard", 4, 0, 0),
+    ],
+    "crossing": [  # a segment that ends on a shell boundary
+        ("tau -= lambda t; x += t d", 4, 0, 0),
+        ("normal n = x / |x|", 6, 2, 0),
+        ("T on both sides of the step (E_F of both shells, or the binding energy), outer test", 4, 0, 0),
+        ("|p| = sqrt(T^2 + 2 T m); p_n = |p| d.n", 6, 1, 0),
+        ("dp^2 = (T' - T)(T' + T + 2m); p_n'^2 = p_n^2 + dp^2; both tests", 7, 0, 0),
+        ("p_t = p - p_n n; p_n' = +/-sqrt(p_n'^2); q = p_t + p_n' n", 11, 1, 0),
+        ("d' = q / |q|; shell index", 7, 2, 0),
+    ],
+    "tentative": [  # a segment that ends in a tentative collision
+        ("x += (tau / lambda) d", 4, 1, 0),
+        ("target species: u (w_n + w_p) against w_n; its m, p_F, E_F", 6, 0, 0),
+        ("Fermi momentum: p_F u^(1/3), cos = 2u - 1, sin = sqrt(1 - cos^2), phi = 2 pi u, "
+         "sine-cosine pair, vector", 10, 1, 2),
+        ("T_x = eps + E_F; p_x = sqrt(T_x^2 + 2 T_x m_x) d; like pair", 7, 1, 0),
+        ("T_t = p_t^2 / (sqrt(p_t^2 + m_y^2) + m_y)", 4, 2, 0),
+        ("Q = 2 (T_x T_t + T_x m_y + T_t m_x - p_x.p_t); s = (m_x + m_y)^2 + Q", 9, 0, 0),
+        ("p_lab = sqrt(Q (Q + 4 m_x m_y) / (4 s)) sqrt(s) / m_y", 6, 3, 0),
+        ("sigma from its table: GeV/c, clamp, log coordinate, node, fraction, interpolation, "
+         "like/unlike, mb to fm^2", 13, 1, 0),
+        ("acceptance u < sigma / sh_y", 2, 1, 0),
+    ],
+    "kinematics": [  # an accepted or Pauli-blocked collision
+        ("P = p_x + p_t; sqrt(s) and its reciprocal", 3, 2, 0),
+        ("CM velocity u = P / sqrt(s); gamma = (T_x + T_t + m_x + m_y) / sqrt(s)", 7, 0, 0),
+        ("direction of x in the CM: q = p_x + (u.p_x / (g + 1) - E_x) u, normalised", 16, 3, 0),
+        ("slope b at p_lab (closed form; mean of like and unlike pairs), GeV/c, clamp", 10, 0.5, 0),
+        ("k = 2 b (p*/1000)^2; y = -log1p(u expm1(-2k)) / k, small-k branch, clamp", 12, 3, 0),
+        ("cos = 1 - y, sin = sqrt(y (2 - y))", 4, 1, 0),
+        ("rotation by (theta, phi) about the CM direction: perpendicular frame, sine-cosine pair", 23, 2, 1),
+        ("q* = p* n", 3, 0, 0),
+        ("boosts of both products sharing 1/(g+1) and u.u/(g+1): E* = sqrt(p*^2 + m^2), u.q, "
+         "p = q + (u.q/(g+1) + E*) u, T* = p*^2 / (E* + m), T = g T* + m u.u/(g+1) + u.q", 29, 4, 0),
+        ("like pairs: which product is x", 9, 0, 0),
+        ("Pauli test and outcome: T' <= E_F for both, hole depth, excess energies, cutoff tests", 11, 0, 0),
+    ],
+    "collision": [  # an accepted collision, after its kinematics
+        ("the struck nucleon leaves the sea; lowest occupancy; hole depth to E*", 3, 0, 0),
+        ("unit directions of both products", 12, 4, 0),
+        ("cutoff captures; stack push or pop (position, direction, eps, species, shell)", 14, 0, 0),
+    ],
+    "majorant": [  # every new flight: entry, after a collision, after an escape
+        ("T = eps + min E_F; p = sqrt(T^2 + 2 T m); E = T + m", 4, 1, 0),
+        ("per target species: p_lab,min = (p E_F,y - E p_F,max) / m_y, clamp, GeV/c", 10, 0, 0),
+        ("per target species: sigma-hat from its table, like/unlike, mb to fm^2", 26, 2, 0),
+    ],
+    "entry": [  # every cascade pass
+        ("b = R sqrt(u), azimuth (sine-cosine pair), entry point on the sphere, eps = T0 + E_B", 8, 2, 1),
+        ("inward normal n = x / |x|", 7, 2, 0),
+        ("inward refraction at R (the crossing's refraction items)", 31, 4, 0),
+    ],
+    "escape": [  # a cascade particle that leaves the nucleus
+        ("|p| = sqrt(T^2 + 2 T m) outside; recoil p_res -= |p| d; escape count", 6, 1, 0),
+        ("next particle from the stack, or the end of the pass", 10, 0, 0),
+    ],
+    "evap_channels": [  # every evaporation step, including the last (nothing open)
+        ("6 channels: daughter (A - a, Z - z) and its existence test", 6 * 7, 0, 0),
+        ("6 channels: U = E - S - V, open test", 6 * 3, 0, 0),
+        ("6 channels: Y = 2 sqrt(a U)", 6 * 2, 6 * 1, 0),
+        ("6 channels: I = [e^Y (2Y^2 - 6Y + 6) + Y^2 - 6] / (8 a^2)", 6 * 6, 6 * 1, 0),
+        ("6 channels: w = g m R^2 I; running total; any channel open", 6 * 2 + 1, 0, 0),
+    ],
+    "evap_emit": [  # every emission
+        ("channel: u x total, cumulative scan over the channels", 22, 0, 0),
+        ("K(1) of the spectrum (closed form) and the target mass", 12, 1, 0),
+        ("4 residuals K(s) - target (closed form e^(-Ys) Q(Ys), Q cubic)", 4 * 12, 4 * 1, 0),
+        ("3 Newton updates: density s (2 - s)(1 - s) e^(-Ys), step, bracket, stop tests", 3 * 13, 3 * 1, 0),
+        ("x = U s (2 - s); E_d = U - x; eps = V + x; parent and daughter masses", 7, 0, 0),
+        ("p^2 = eps (eps + 2m)(eps + 2M_d)(eps + 2M_d + 2m) / (4 M_p^2); p", 9, 2, 0),
+        ("isotropic direction: cos = 2u - 1, sin, phi, sine-cosine pair, q = p n", 9, 1, 1),
+        ("recoil velocity u = P / M_p, g = sqrt(1 + u.u), 1/(g+1), u.u/(g+1)", 8, 3, 0),
+        ("boost of the fragment: E*, u.q, p, T*, T", 14, 2, 0),
+        ("unit direction of the record; P -= p; A, Z, E", 12, 2, 0),
+    ],
 }
+OP_WEIGHTS = (1, 4, 8)
+
+
+def step_cost(items) -> float:
+    """Weighted lane-operations of one step from its itemised counts."""
+    return float(sum(b * OP_WEIGHTS[0] + t * OP_WEIGHTS[1] + w * OP_WEIGHTS[2] for _, b, t, w in items))
+
+
+STEP_COST = {k: step_cost(v) for k, v in STEP_OPS.items()}
 
 
 # kernels of one step per launch mode (timed together: they run back to back
@@ -111,27 +211,53 @@ def profiled_traffic(kernel: str, events: int):
     return None
 
 
-def algorithmic_ops_per_event(res) -> float:
-    """Mean lane-operations per event from the oracle's per-event counters."""
+def profiled_same_stream(kernel: str):
+    """The divergence-free probe's VALU counters from a committed summary
+    under profiles/ (`same_stream_json:` line): every lane of a launch
+    replays one event, so VALU wave-instructions x 64 / events is the
+    instructions one event's history takes with every lane active.  None
+    when no summary was taken on the current kernel sources."""
+    d = os.path.join(ROOT, "profiles")
+    if not os.path.isdir(d):
+        return None
+    want = kernel_sources_hash()
+    for f in sorted(os.listdir(d)):
+        if not f.endswith(".md"):
+            continue
+        with open(os.path.join(d, f)) as fh:
+            for ln in fh:
+                if ln.startswith("same_stream_json:"):
+                    rec = json.loads(ln.split(":", 1)[1])
+                    if rec["kernel"] == kernel and rec["kernel_sources"] == want:
+                        return rec
+    return None
+
+
+def step_counts(res) -> dict:
+    """Per-step totals over the events of `res` (the oracle's per-event
+    counters: draws, segments, tentative, accepted and Pauli-blocked
+    collisions, retried passes, emissions and records).  Every pass starts
+    with an entry, a majorant and an optical depth; each null or blocked
+    tentative collision draws a new optical depth; each accepted collision and
+    each escape starts a new flight (majorant and optical depth) except the
+    one that ends its event; a retried (transparent) pass records nothing."""
     n = len(res)
-    draws = res["n_draw"].sum()
-    seg = res["n_seg"].sum()
-    tent = res["n_tent"].sum()
-    coll = res["n_coll"].sum()
-    pauli = res["n_pauli"].sum()
-    evap = res["n_evap"].sum()
-    passes = n + res["n_retry"].sum()
-    # an accepted tentative collision runs the kinematics; so does a blocked one
-    kin = coll + pauli
-    taus = passes + (tent - coll) + coll  # first flight, every null/blocked/accepted collision
-    crossings = seg - tent
-    escapes = res["n_sec"].sum() - evap
-    ops = (draws * STEP_COST["draw"] + taus * STEP_COST["tau"] + seg * STEP_COST["segment"]
-           + crossings * STEP_COST["crossing"] + tent * STEP_COST["tentative"]
-           + kin * STEP_COST["kinematics"] + coll * STEP_COST["collision"] + passes * STEP_COST["entry"]
-           + (evap + n) * STEP_COST["evap_channels"] + evap * STEP_COST["evap_emit"]
-           + escapes * STEP_COST["escape"])
-    return float(ops) / n
+    tent = int(res["n_tent"].sum())
+    coll = int(res["n_coll"].sum())
+    evap = int(res["n_evap"].sum())
+    passes = n + int(res["n_retry"].sum())
+    escapes = int(res["n_sec"].sum()) - evap
+    return {"draw": int(res["n_draw"].sum()), "tau": passes + tent + escapes - n,
+            "segment": int(res["n_seg"].sum()), "crossing": int(res["n_seg"].sum()) - tent,
+            "tentative": tent, "kinematics": coll + int(res["n_pauli"].sum()), "collision": coll,
+            "majorant": passes + coll + escapes - n, "entry": passes, "escape": escapes,
+            "evap_channels": evap + n, "evap_emit": evap}
+
+
+def algorithmic_ops_per_event(res) -> float:
+    """Mean lane-operations per event: the step totals times STEP_COST."""
+    c = step_counts(res)
+    return sum(c[k] * STEP_COST[k] for k in STEP_COST) / len(res)
 
 
 def _workloads(n_events: int):
@@ -415,16 +541,17 @@ def _tally_run(w, n_ebins: int = 23, reps: int = 5):
     return dict(events_per_s=n / (ms / 1000.0), kernel_ms=ms, n_ebins=n_ebins, yields_per_1e6_events=per_1e6)
 
 
-def _ring_run(w, slots: int, reps: int = 2):
+def _ring_run(w, slots: int, reps: int = 2, placement: str = "host", chunk: int = 1 << 16):
     """Implant mixture with the secondaries streamed through a bounded ring
-    in host memory while the kernel runs, drained into reused host arrays
-    (timed: the call, residuals copied back included)."""
+    (in host memory, or in device memory drained by asynchronous chunk
+    copies) while the kernel runs, drained into reused host arrays (timed:
+    the call, residuals copied back included)."""
     import torch
 
     import paper_1309_7963_amd as inc
 
     ctx = inc.Context(w["targets"])
-    ring = inc.Ring(ctx, slots=slots)
+    ring = inc.Ring(ctx, slots=slots, placement=placement, chunk=chunk)
     T0 = torch.as_tensor(w["T0"], device="cuda")
     tidx = torch.as_tensor(w["tidx"], device="cuda")
     buf = inc.Ring.host_buffers(ctx.default_capacity(len(w["T0"])), len(w["T0"]))  # reused host arrays
@@ -438,7 +565,8 @@ def _ring_run(w, slots: int, reps: int = 2):
         if best is None or dt < best[0]:
             best = (dt, r)
     dt, r = best
-    out = {"label": w["label"] + ", secondaries through a %d-record ring" % slots, "events": len(w["T0"]),
+    out = {"label": w["label"] + ", secondaries through a %d-record ring in %s memory" % (slots, placement),
+           "placement": placement, "chunk": chunk if placement == "device" else None, "events": len(w["T0"]),
            "events_per_s": len(w["T0"]) / dt, "records": r["stats"]["records"], "wraps": r["stats"]["wraps"],
            "rc": r["rc"]}
     ring.close()
@@ -533,6 +661,13 @@ def main(argv=None):
     ap.add_argument("--stage-split", action="store_true",
                     help="only time the cascade and evaporation stages apart on the main workload "
                          "(one JSON line; for profiling the evaporation-only launch)")
+    ap.add_argument("--same-stream", action="store_true",
+                    help="only run the divergence-free probe: --steps launches of the 200 MeV p+16O batch, "
+                         "launch k with every lane replaying event id k x batch size (seed 1), one at a "
+                         "time (one JSON line; for the VALU instruction counters)")
+    ap.add_argument("--rings", action="store_true",
+                    help="only time the implant mixture directly and through the host and device rings "
+                         "(one JSON line)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="first copy 256 MiB device to device (a plain copy kernel of known size, "
                          "to scale the HBM byte counters)")
@@ -556,6 +691,25 @@ def main(argv=None):
     main_w = wl["o16_ca40_200"]
     if args.stage_split:
         print(json.dumps(dict(workload=main_w["label"], **_evaporation_stage(main_w, reps=args.steps))))
+        return 0
+    if args.rings:
+        w = wl["implant_mix"]
+        e = _time_gpu(w, args.mode, 5, 1)
+        rate = e["n"] / (float(np.median(e["launch_ms"])) / 1000.0)
+        rings = {}
+        for placement, slots, chunk in (("host", 1 << 20, 1 << 16), ("device", 1 << 20, 1 << 16),
+                                        ("device", 1 << 20, 1 << 18), ("device", 1 << 22, 1 << 16),
+                                        ("device", 1 << 22, 1 << 18)):
+            rings["%s_%d_%d" % (placement, slots, chunk)] = _ring_run(w, slots, reps=3, placement=placement,
+                                                                      chunk=chunk)
+        print(json.dumps(dict(workload=w["label"], direct_events_per_s=rate, rings=rings)))
+        return 0
+    if args.same_stream:
+        w = wl["o16_200"]
+        e = _time_gpu(w, args.mode, args.steps, 0, same_stream=1)
+        print(json.dumps(dict(same_stream=True, workload=w["label"], kernel=KERNELS[args.mode],
+                              events_per_launch=e["n"], first_ids=[k * e["n"] for k in range(args.steps)],
+                              launch_ms=e["launch_ms"])))
         return 0
     # whole-job throughput: the K batches with args.inflight of them on the
     # device at once (one context, buffer set and stream each)
@@ -622,8 +776,9 @@ def main(argv=None):
             fm[key] = rate(_time_gpu(w, args.mode, 3, 1, fast_math=1))
         extra["fast_math"] = dict(events_per_s=fm, speedup_main=fm["o16_ca40_200"] / (r["n"] / (ms / 1000.0)))
         print("bench: divergence ceiling and end-to-end done", file=sys.stderr, flush=True)
-        extra["implant_ring"] = _ring_run(wl["implant_mix"], slots=1 << 20)
-        print("bench: implant ring done", file=sys.stderr, flush=True)
+        extra["implant_ring"] = _ring_run(wl["implant_mix"], slots=1 << 20, placement="device")
+        extra["implant_ring_host"] = _ring_run(wl["implant_mix"], slots=1 << 20, placement="host")
+        print("bench: implant rings done", file=sys.stderr, flush=True)
 
     serving = None
     if args.serving_requests > 0 and not args.no_extra:
@@ -645,13 +800,28 @@ def main(argv=None):
                          "%d threads, %.1f s" % (args.cpu_sample, threads, dt),
                "per_core": args.cpu_sample / dt / threads, "one_thread": n1 / dt1, "one_thread_sample": n1,
                "host_cpus": os.cpu_count(), "host_cpu_model": _host_cpu()}
+    same = None
+    rec = profiled_same_stream(KERNELS[args.mode])
+    if rec is not None and not args.no_cpu:
+        import oracle
+
+        per = []
+        for fid, valu in zip(rec["first_ids"], rec["valu_per_event"]):
+            o = oracle.run([(16, 8)], np.array([200.0]), seed=1, first_id=fid)
+            per.append([fid, valu, algorithmic_ops_per_event(o.results)])
+        same = {"workload": rec["workload"] + ", every lane of a launch replays one event",
+                "valu_instructions_per_event": float(np.mean([p[1] for p in per])),
+                "algorithmic_ops_per_event": float(np.mean([p[2] for p in per])),
+                "valu_utilization": rec["valu_utilization"], "per_event": per}
+        same["ratio"] = same["valu_instructions_per_event"] / same["algorithmic_ops_per_event"]
     roof = None
     if ops_per_event is not None:
         achieved = ops_per_event * r["n"] / (ms / 1000.0)
         roof = {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_LANE_OPS / 1e12,
                 "unit": "T lane-ops/s (FP32 VALU)", "frac": achieved / PEAK_LANE_OPS,
                 "traffic": profiled_traffic(KERNELS[args.mode], r["n"]),
-                "ops_per_event": ops_per_event, "kernel": KERNELS[args.mode], "kernel_ms": ms,
+                "ops_per_event": ops_per_event, "same_stream": same, "kernel": KERNELS[args.mode],
+                "kernel_ms": ms,
                 "hbm_write_GBps": r["out_bytes"] / (ms / 1000.0) / 1e9}
 
     line = {

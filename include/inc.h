@@ -422,11 +422,14 @@ int inc_server_replay(inc_server* server, int n_req, const double* arrival_s, co
 
 /* ------------------------------------------------------------- ring output
  * Streaming output for large batches: the secondaries flow through a ring of
- * `slots` records (a power of two >= 1024) in coherent host memory while the
- * kernel runs; the calling thread drains the ring into the caller's host
- * arrays (in ring order) and hands the space back.  A full ring makes the
- * producing waves wait (up to ~3 s without consumer progress, then the call
- * fails with INC_ERR_DEVICE); no record is lost or duplicated. */
+ * `slots` records (a power of two >= 1024) while the kernel runs; the calling
+ * thread drains the ring into the caller's host arrays (in ring order) and
+ * hands the space back.  A full ring makes the producing waves wait (up to
+ * ~3 s without consumer progress, then the call fails with INC_ERR_DEVICE);
+ * no record is lost or duplicated.  The ring lives in coherent host memory
+ * (inc_ring_create: each record crosses PCIe as a wave stores it) or in
+ * device memory (inc_ring_create_device: complete chunks are copied to a
+ * pinned host mirror by asynchronous copies on the ring's own stream). */
 /* (Sec. 3.2-3.3: the secondaries of the batch, streamed.) */
 typedef struct inc_ring inc_ring;
 
@@ -443,6 +446,16 @@ typedef struct {
  * memory (7 x 4 bytes per slot) for batches of `ctx`.  INC_ERR_ARG for bad
  * sizes, INC_ERR_OOM if the host memory cannot be pinned. */
 int inc_ring_create(inc_ctx* ctx, size_t slots, inc_ring** out);
+/* Ring of `slots` records in device memory (6 x 4 bytes per slot), cut into
+ * chunks of `chunk` slots (a power of two, 1024..slots/2), with a pinned host
+ * mirror of the same size (7 x 4 bytes per slot) and a copy stream of its
+ * own (default priority).  The device marks a chunk complete once all of its
+ * records are written (and visible in device memory); the calling thread
+ * then queues its copy to the mirror and hands it on when the copy is done.
+ * The last, incomplete chunk of a batch is copied once the kernel has ended.
+ * Used with inc_ring_simulate / inc_ring_simulate_to like a host ring.
+ * INC_ERR_ARG for bad sizes, INC_ERR_OOM if memory cannot be allocated. */
+int inc_ring_create_device(inc_ctx* ctx, size_t slots, size_t chunk, inc_ring** out);
 /* Free a ring (no call may be running on it).  INC_ERR_ARG for NULL. */
 int inc_ring_destroy(inc_ring* ring);
 /* Generate batch->n events (device inputs, as inc_simulate_dev) with their

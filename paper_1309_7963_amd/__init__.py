@@ -460,14 +460,23 @@ class Server:
 class Ring:
     """Streaming output through a bounded ring of `slots` records
     (inc_ring_*): the secondaries of a batch are drained to host arrays while
-    the kernel runs."""
+    the kernel runs.  placement "host": the ring in coherent host memory
+    (inc_ring_create); "device": in device memory, drained chunk by chunk
+    (`chunk` slots) by asynchronous copies (inc_ring_create_device)."""
 
-    def __init__(self, ctx: Context, slots: int = 1 << 20):
+    def __init__(self, ctx: Context, slots: int = 1 << 20, placement: str = "device", chunk: int = 1 << 16):
         self.ctx = ctx
         h = C.c_void_p()
-        _lib.check(_lib.load().inc_ring_create(ctx._h, int(slots), C.byref(h)), "inc_ring_create")
+        if placement == "host":
+            _lib.check(_lib.load().inc_ring_create(ctx._h, int(slots), C.byref(h)), "inc_ring_create")
+        elif placement == "device":
+            _lib.check(_lib.load().inc_ring_create_device(ctx._h, int(slots), int(chunk), C.byref(h)),
+                       "inc_ring_create_device")
+        else:
+            raise ValueError("placement must be 'host' or 'device'")
         self._h = h
         self.slots = int(slots)
+        self.placement = placement
 
     def close(self):
         if getattr(self, "_h", None) and self._h.value:

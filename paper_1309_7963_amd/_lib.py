@@ -29,6 +29,7 @@ SYMBOLS = (
     "inc_simulate_dev", "inc_simulate_dev_noalloc", "inc_evaporate_dev", "inc_simulate", "inc_server_create", "inc_server_destroy",
     "inc_server_submit", "inc_server_poll", "inc_server_wait", "inc_server_fetch",
     "inc_server_stats_get", "inc_server_stats_reset", "inc_server_hold", "inc_server_replay", "inc_ring_create",
+    "inc_ring_create_device",
     "inc_ring_destroy",
     "inc_ring_simulate", "inc_ring_simulate_to", "inc_ctx_tally_shape", "inc_tally_residuals", "inc_contract_version",
 )
@@ -198,6 +199,8 @@ def load():
         L.inc_server_replay.restype = C.c_int
         L.inc_ring_create.argtypes = [vp, C.c_size_t, C.POINTER(vp)]
         L.inc_ring_create.restype = C.c_int
+        L.inc_ring_create_device.argtypes = [vp, C.c_size_t, C.c_size_t, C.POINTER(vp)]
+        L.inc_ring_create_device.restype = C.c_int
         L.inc_ring_destroy.argtypes = [vp]
         L.inc_ring_destroy.restype = C.c_int
         L.inc_ring_simulate.argtypes = [vp, C.POINTER(Batch), vp, C.POINTER(HostOutput), vp, C.c_int,

@@ -621,14 +621,21 @@ __device__ __forceinline__ int segment_of(const Segment* segs, int n_seg, uint32
   return lo;
 }
 
-// Ring output (streaming mode): records go to a ring of `mask + 1` slots in
-// coherent host memory while a host thread drains it.  A wave reserves `fill`
-// sequence numbers on the device counter `head`, waits (bounded) until the
-// consumer's `tail` leaves room, writes the records' payload, then - after a
-// system-scope release fence - their tags (sequence number + 1).  The
-// consumer takes slot s & mask once its tag equals s + 1.  The ring is a
-// structure of arrays so that a wave's stores are contiguous (256 bytes per
-// array and store instruction).
+// Ring output (streaming mode).  Host placement: records go to a ring of
+// `mask + 1` slots in coherent host memory while a host thread drains it.  A
+// wave reserves `fill` sequence numbers on the device counter `head`, waits
+// (bounded) until the consumer's `tail` leaves room, writes the records'
+// payload, then - after a system-scope release fence - their tags (sequence
+// number + 1).  The consumer takes slot s & mask once its tag equals s + 1.
+// Device placement (`done` set, `tag` NULL): the ring is in device memory
+// (from `ev`; the other field pointers are unused) and is cut into chunks of
+// 2^chunk_shift slots.  A wave writes its records with
+// ordinary stores, makes them visible device-wide (agent-scope release), and
+// adds their number to the counter of each chunk they fall in; the wave that
+// completes a chunk clears its counter and publishes the chunk number + 1 in
+// the host array `ready`, and the host copies the chunk out with an
+// asynchronous copy.  The ring is a structure of arrays so that a wave's
+// stores are contiguous (256 bytes per array and store instruction).
 struct RingDev {
   uint32_t* tag;                    // host memory, one array per field; NULL = off
   uint32_t* ev;
@@ -642,10 +649,71 @@ struct RingDev {
   const unsigned long long* tail;   // host memory: records consumed so far
   unsigned int* error;              // host memory: 1 = producer gave up waiting
   unsigned long long spin_limit;    // waits of ~1.7 us before giving up
+  unsigned long long* done;         // device placement: records written per chunk (NULL: host placement)
+  unsigned long long* ready;        // device placement, host memory: chunk number + 1 once complete
+  unsigned long long chunk_mask;    // chunks in the ring - 1
+  unsigned int chunk_shift;         // log2 of the slots per chunk
 };
 
 __device__ __forceinline__ void sys_store(uint32_t* p, uint32_t v) {
   __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+}
+
+// Device placement.  Must be called by all lanes of the wave.
+__device__ __forceinline__ void ring_flush_device(const uint32_t* buf, int fill, const RingDev& R) {
+  unsigned long long base = 0;
+  int ok = 1;
+  if (lane_id() == 0) {
+    base = atomicAdd(R.head, (unsigned long long)fill);
+    unsigned long long t = __hip_atomic_load(R.tail, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+    unsigned long long spins = 0;
+    while (base + (unsigned long long)fill > t + R.mask + 1ull) {
+      if (++spins > R.spin_limit ||
+          __hip_atomic_load(R.error, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM) != 0u) {
+        ok = 0;
+        break;
+      }
+      __builtin_amdgcn_s_sleep(63);
+      t = __hip_atomic_load(R.tail, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+    }
+    if (!ok) __hip_atomic_fetch_or(R.error, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+  }
+  base = __shfl(base, 0);
+  ok = __shfl(ok, 0);
+  if (!ok) return;
+  // chunk-major layout: chunk q holds its six fields one after another
+  // (6 x 2^chunk_shift words from R.ev + 6 q 2^chunk_shift), so a complete
+  // chunk leaves in one copy
+  const unsigned long long per = 1ull << R.chunk_shift;
+  for (int i = lane_id(); i < fill; i += 64) {
+    const unsigned long long k = (base + (unsigned long long)i) & R.mask;
+    const uint32_t* r = buf + i * kRecWords;
+    uint32_t* d = R.ev + (k >> R.chunk_shift) * 6ull * per + (k & (per - 1ull));
+    d[0] = r[0];
+    d[per] = r[1];
+    d[2 * per] = r[2];
+    d[3 * per] = r[3];
+    d[4 * per] = r[4];
+    d[5 * per] = r[5];
+  }
+  // the records reach device memory (past this XCD's L2) before they count
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+  if (lane_id() == 0) {
+    const unsigned long long end = base + (unsigned long long)fill;
+    for (unsigned long long c = base >> R.chunk_shift; c <= (end - 1ull) >> R.chunk_shift; ++c) {
+      const unsigned long long lo = c << R.chunk_shift;
+      const unsigned long long n = min(end, lo + per) - max(base, lo);
+      unsigned long long* cnt = R.done + (c & R.chunk_mask);
+      const unsigned long long old = __hip_atomic_fetch_add(cnt, n, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+      if (old + n == per) {
+        // the chunk is complete: its counter starts over for the next lap,
+        // and the host learns the chunk number
+        __hip_atomic_store(cnt, 0ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "");
+        __hip_atomic_store(R.ready + (c & R.chunk_mask), c + 1ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+      }
+    }
+  }
 }
 
 // Must be called by all lanes of the wave.
@@ -693,8 +761,11 @@ __device__ __forceinline__ void ring_flush(const uint32_t* buf, int fill, const 
 __device__ __forceinline__ void writer_flush(uint32_t* buf, int& fill, const Segment* segs, const RingDev& ring) {
   if (fill == 0) return;
   __builtin_amdgcn_wave_barrier();
-  if (ring.tag) {
-    ring_flush(buf, fill, ring);
+  if (ring.tag || ring.done) {
+    if (ring.done)
+      ring_flush_device(buf, fill, ring);
+    else
+      ring_flush(buf, fill, ring);
     __builtin_amdgcn_wave_barrier();
     fill = 0;
     return;

@@ -550,7 +550,8 @@ def test_serving_wait_returns_when_results_block_the_queue():
 
 
 # ------------------------------------------------------------------- ring
-def test_ring_output_equals_direct_output():
+@pytest.mark.parametrize("placement", ["host", "device"])
+def test_ring_output_equals_direct_output(placement):
     import torch
 
     import paper_1309_7963_amd as inc
@@ -559,7 +560,7 @@ def test_ring_output_equals_direct_output():
     tidx, T0 = _mixture(n, IMPLANT, [0.5, 0.5], 70, 250, seed=23)
     ctx = inc.Context(IMPLANT)
     direct = run_gpu(IMPLANT, T0, seed=3, tidx=tidx, ctx=ctx)
-    ring = inc.Ring(ctx, slots=1 << 14)
+    ring = inc.Ring(ctx, slots=1 << 14, placement=placement, chunk=1 << 11)
     T0_d = torch.as_tensor(T0, device="cuda")
     ti_d = torch.as_tensor(tidx, device="cuda")
     for rep in range(2):  # the second call continues the sequence numbers
@@ -605,7 +606,8 @@ def test_chi2_implant_through_the_ring():
     _chi2_gate(g, o, 250.0, "Ti/Fe through the ring")
 
 
-def test_ring_consumer_receives_every_record_once():
+@pytest.mark.parametrize("placement", ["host", "device"])
+def test_ring_consumer_receives_every_record_once(placement):
     # the streaming form of the ring: each run of records goes to a consumer as
     # it is drained; the runs arrive in order without gaps or repeats and
     # together equal the direct output; a consumer that raises gets its
@@ -618,7 +620,7 @@ def test_ring_consumer_receives_every_record_once():
     tidx, T0 = _mixture(n, IMPLANT, [0.5, 0.5], 70, 250, seed=37)
     ctx = inc.Context(IMPLANT)
     direct = run_gpu(IMPLANT, T0, seed=5, tidx=tidx, ctx=ctx, mode="staged")
-    ring = inc.Ring(ctx, slots=1 << 14)
+    ring = inc.Ring(ctx, slots=1 << 14, placement=placement, chunk=1 << 11)
     T0_d, ti_d = torch.as_tensor(T0, device="cuda"), torch.as_tensor(tidx, device="cuda")
     fields = ("event", "species", "stage", "T", "ux", "uy", "uz")
 
@@ -659,7 +661,8 @@ def test_ring_consumer_receives_every_record_once():
     assert np.array_equal(direct["sec_u"][kd], np.stack([cat["ux"], cat["uy"], cat["uz"]], 1)[kr])
 
 
-def test_ring_staged_mode_equals_direct_staged():
+@pytest.mark.parametrize("placement", ["host", "device"])
+def test_ring_staged_mode_equals_direct_staged(placement):
     import torch
 
     import paper_1309_7963_amd as inc
@@ -668,7 +671,7 @@ def test_ring_staged_mode_equals_direct_staged():
     tidx, T0 = _mixture(n, IMPLANT, [0.5, 0.5], 70, 250, seed=29)
     ctx = inc.Context(IMPLANT)
     direct = run_gpu(IMPLANT, T0, seed=4, tidx=tidx, ctx=ctx, mode="staged")
-    ring = inc.Ring(ctx, slots=1 << 14)
+    ring = inc.Ring(ctx, slots=1 << 14, placement=placement, chunk=1 << 11)
     r = ring.simulate(torch.as_tensor(T0, device="cuda"), seed=4, target_idx=torch.as_tensor(tidx, device="cuda"),
                       mode="staged")
     assert r["rc"] == 0 and r["stats"]["producer_gave_up"] == 0
@@ -683,7 +686,8 @@ def test_ring_staged_mode_equals_direct_staged():
     ctx.close()
 
 
-def test_ring_parallel_drain_equals_direct():
+@pytest.mark.parametrize("placement", ["host", "device"])
+def test_ring_parallel_drain_equals_direct(placement):
     """Large ring and batch: runs of ready records long enough for the
     drain's parallel host copy, into reused host arrays (twice; the second
     time with pinned residual memory, whose copy overlaps the drain)."""
@@ -695,7 +699,7 @@ def test_ring_parallel_drain_equals_direct():
     tidx, T0 = _mixture(n, IMPLANT, [0.5, 0.5], 70, 250, seed=31)
     ctx = inc.Context(IMPLANT)
     direct = run_gpu(IMPLANT, T0, seed=6, tidx=tidx, ctx=ctx, mode="staged")
-    ring = inc.Ring(ctx, slots=1 << 20)
+    ring = inc.Ring(ctx, slots=1 << 20, placement=placement, chunk=1 << 16)
     buf = inc.Ring.host_buffers(ctx.default_capacity(n))
     T0_d = torch.as_tensor(T0, device="cuda")
     ti_d = torch.as_tensor(tidx, device="cuda")

@@ -87,6 +87,8 @@ def test_argument_errors_before_device(lib):
     nsec_r = C.c_ulonglong()
     noop = _lib.RING_CONSUMER(lambda chunk, user: None)
     assert L.inc_ring_simulate_to(None, None, None, None, noop, None, C.byref(nsec_r), None, 0, None) == inc.INC_ERR_ARG
+    rh = C.c_void_p(1)
+    assert L.inc_ring_create_device(None, 1 << 14, 1 << 12, C.byref(rh)) == inc.INC_ERR_ARG and not rh.value
     # option ranges are checked before the device is looked for
     for field, bad in (("fast_math", 2), ("same_stream", -1), ("stack_levels", 5), ("block_size", 96),
                        ("waves_per_cu", 33), ("kin_threshold", 65), ("start_threshold", 65), ("input_order", 2)):
