@@ -68,6 +68,7 @@ class Options(C.Structure):
         ("max_stack", C.c_int),
         ("max_segments", C.c_int),
         ("photon_evaporation", C.c_int),
+        ("heavy_fragments", C.c_int),
     ]
 
 
@@ -158,6 +159,8 @@ def lib():
         L.orc_photon_s0.restype = d
         L.orc_photon_width.argtypes = [i, i, d]
         L.orc_photon_width.restype = d
+        L.orc_fragment.argtypes = [i, C.POINTER(i), C.POINTER(i), C.POINTER(i)]
+        L.orc_fragment.restype = i
         L.orc_evaporate.argtypes = [i, i, d, d * 3, u64, u64, C.POINTER(Options), C.c_void_p, C.c_void_p, i]
         L.orc_evaporate.restype = i
         L.orc_run.argtypes = [
@@ -268,10 +271,10 @@ def fermi_sample(pF, u1, u2, u3):
     return np.array(p[:])
 
 
-def evaporate(A, Z, Ex, P=(0.0, 0.0, 0.0), seed=1, event_id=0, photon_evaporation=0):
+def evaporate(A, Z, Ex, P=(0.0, 0.0, 0.0), seed=1, event_id=0, photon_evaporation=0, heavy_fragments=0):
     """Evaporate one excited nucleus; returns (result record, secondaries)."""
     res = np.zeros(1, dtype=RESULT_DTYPE)
-    opt = options(photon_evaporation=photon_evaporation)
+    opt = options(photon_evaporation=photon_evaporation, heavy_fragments=heavy_fragments)
     cap = A + 1
     while True:
         sec = np.zeros(cap, dtype=SECONDARY_DTYPE)
@@ -282,6 +285,15 @@ def evaporate(A, Z, Ex, P=(0.0, 0.0, 0.0), seed=1, event_id=0, photon_evaporatio
         if n <= cap:
             return res[0], sec[:n].copy()
         cap = n  # photons do not use up nucleons: run again with room for all
+
+
+def fragment(j: int):
+    """(a, z, g) of emitted species j (0-5 particles, 7-26 heavier fragments,
+    reading R20); None for the photon (6) or out of range."""
+    a, z, g = C.c_int(), C.c_int(), C.c_int()
+    if not lib().orc_fragment(j, C.byref(a), C.byref(z), C.byref(g)):
+        return None
+    return a.value, z.value, g.value
 
 
 def gdr_energy(A: int) -> float:

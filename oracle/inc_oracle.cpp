@@ -398,6 +398,29 @@ double spectrum_sample(double a, double U, double u) {
 struct Fragment { int a, z, g; };
 constexpr Fragment kFrag[6] = {{1, 0, 2}, {1, 1, 2}, {2, 1, 3}, {3, 1, 2}, {3, 2, 2}, {4, 2, 1}};
 
+/* Reading R20 (option heavy_fragments): GEM's ejectiles reach Mg (Sec. 2.4);
+ * the heavier ones emitted here are the stable isotopes of Li to Mg with
+ * their measured ground-state spins (g = 2s + 1), as channels 7-26, with the
+ * particles' width and spectrum (R15) and masses from the same mass formula. */
+constexpr Fragment kHeavy[20] = {{6, 3, 3},   {7, 3, 4},   {9, 4, 4},   {10, 5, 7},  {11, 5, 4},
+                                 {12, 6, 1},  {13, 6, 2},  {14, 7, 3},  {15, 7, 2},  {16, 8, 1},
+                                 {17, 8, 6},  {18, 8, 1},  {19, 9, 2},  {20, 10, 1}, {21, 10, 4},
+                                 {22, 10, 1}, {23, 11, 4}, {24, 12, 1}, {25, 12, 6}, {26, 12, 1}};
+constexpr int kNumChan = 27;  /* 0-5 particles, 6 photon, 7-26 heavier fragments */
+
+/* Fragment of channel j; false for the photon (6) and out of range. */
+bool fragment_of(int j, Fragment& f) {
+  if (j >= 0 && j < 6) {
+    f = kFrag[j];
+    return true;
+  }
+  if (j >= 7 && j < kNumChan) {
+    f = kHeavy[j - 7];
+    return true;
+  }
+  return false;
+}
+
 /* ------------------------------------------------ photon emission (option)
  * Reading R19.  Sec. 2 has an excited nucleus shed its energy by particle
  * emission first, then by photons; Sec. 2.4 leaves photon evaporation out,
@@ -766,24 +789,27 @@ struct Event {
 
   void evaporate(int A, int Z, double E, Vec3 P) {
     while (true) {
-      /* channels 0-5: the particles of kFrag; 6: a photon (option, R19) */
-      double w[7], U[6], V[6], a[6];
-      int Ad[6], Zd[6];
+      /* channels 0-5: the particles of kFrag; 6: a photon (option, R19);
+       * 7-26: the heavier fragments of kHeavy (option, R20) */
+      double w[kNumChan], U[kNumChan], V[kNumChan], a[kNumChan];
+      int Ad[kNumChan], Zd[kNumChan];
       double total = 0.0;
-      for (int j = 0; j < 6; ++j) {
+      for (int j = 0; j < kNumChan; ++j) {
         w[j] = 0.0;
-        Ad[j] = A - kFrag[j].a;
-        Zd[j] = Z - kFrag[j].z;
+        Fragment f;
+        if (!fragment_of(j, f) || (j >= 7 && !opt.heavy_fragments)) continue;
+        Ad[j] = A - f.a;
+        Zd[j] = Z - f.z;
         if (Ad[j] < 1 || Zd[j] < 0 || Zd[j] > Ad[j]) continue;
-        const double S = binding(A, Z) - binding(Ad[j], Zd[j]) - binding(kFrag[j].a, kFrag[j].z);
+        const double S = binding(A, Z) - binding(Ad[j], Zd[j]) - binding(f.a, f.z);
         const double ad13 = std::cbrt((double)Ad[j]);
-        const double aj13 = std::cbrt((double)kFrag[j].a);
-        V[j] = kFrag[j].z > 0 ? kE2 * kFrag[j].z * Zd[j] / (1.5 * (ad13 + aj13)) : 0.0;
+        const double aj13 = std::cbrt((double)f.a);
+        V[j] = f.z > 0 ? kE2 * f.z * Zd[j] / (1.5 * (ad13 + aj13)) : 0.0;
         U[j] = E - S - V[j];
         if (!(U[j] > 0.0)) continue;
         a[j] = Ad[j] / 8.0;
         const double Rj = j <= 1 ? 1.5 * ad13 : 1.5 * (ad13 + aj13);
-        w[j] = kFrag[j].g * mass(kFrag[j].a, kFrag[j].z) * Rj * Rj * width_integral(a[j], U[j]);
+        w[j] = f.g * mass(f.a, f.z) * Rj * Rj * width_integral(a[j], U[j]);
         total += w[j];
       }
       w[6] = opt.photon_evaporation ? photon_width(A, Z, E) : 0.0;
@@ -792,12 +818,12 @@ struct Event {
       const double uc = rng.next() * total;
       int j = 0;
       double cum = 0.0;
-      for (j = 0; j < 7; ++j) {
+      for (j = 0; j < kNumChan; ++j) {
         cum += w[j];
         if (w[j] > 0.0 && cum > uc) break;
       }
-      if (j == 7) {  /* rounding at the top: take the last open channel */
-        for (j = 6; j >= 0 && !(w[j] > 0.0); --j) {}
+      if (j == kNumChan) {  /* rounding at the top: take the last open channel */
+        for (j = kNumChan - 1; j >= 0 && !(w[j] > 0.0); --j) {}
       }
       if (j == 6) {
         /* photon: eps from its spectrum, A and Z unchanged; in the nucleus's
@@ -822,12 +848,14 @@ struct Event {
         E = Ed;
         continue;
       }
+      Fragment f;
+      fragment_of(j, f);
       const double x = spectrum_sample(a[j], U[j], rng.next());
       const double Ed = U[j] - x;
       const double eps = V[j] + x;
       const double Mp = mass(A, Z) + E;
       const double Mb = mass(Ad[j], Zd[j]) + Ed;
-      const double mc = mass(kFrag[j].a, kFrag[j].z);
+      const double mc = mass(f.a, f.z);
       const double p2 = eps * (eps + 2.0 * mc) * (eps + 2.0 * Mb) * (eps + 2.0 * Mb + 2.0 * mc) / (4.0 * Mp * Mp);
       const double ps = std::sqrt(p2);
       const double ct = 2.0 * rng.next() - 1.0;
@@ -954,6 +982,14 @@ double orc_photon_integral(double a, double U) { return photon_J(a, U); }
 double orc_photon_cdf(double a, double U, double x) { return photon_cdf(a, U, x); }
 double orc_photon_sample(double a, double U, double u) { return photon_sample(a, U, u); }
 double orc_photon_width(int A, int Z, double E) { return photon_width(A, Z, E); }
+int orc_fragment(int j, int* a, int* z, int* g) {
+  Fragment f;
+  if (!fragment_of(j, f)) return 0;
+  if (a) *a = f.a;
+  if (z) *z = f.z;
+  if (g) *g = f.g;
+  return 1;
+}
 
 void orc_fermi_sample(double pF, double u1, double u2, double u3, double p[3]) {
   double mag;
@@ -970,6 +1006,7 @@ int orc_evaporate(int A, int Z, double Ex, const double P[3], uint64_t seed, uin
   std::memset(&opt, 0, sizeof(opt));
   opt.fixed_b = -1.0;
   if (opt_in) opt.photon_evaporation = opt_in->photon_evaporation;
+  if (opt_in) opt.heavy_fragments = opt_in->heavy_fragments;
   std::vector<orc_secondary> out;
   std::memset(res, 0, sizeof(*res));
   Event ev(nu, opt, seed, event_id, *res, out, 0);

@@ -49,6 +49,8 @@ typedef struct {
   int max_segments;       /* 0 = default 10000                                */
   int photon_evaporation; /* 1: photons compete with the particle channels of
                              the evaporation (reading R19; off by default)    */
+  int heavy_fragments;    /* 1: the stable isotopes of Li to Mg are emitted
+                             too, channels 7-26 (reading R20; off by default) */
 } orc_options;
 
 /* Per-event result.  Stage-0 (cascade) and stage-1 (evaporation) secondaries
@@ -80,7 +82,8 @@ typedef struct {
 
 typedef struct {
   uint32_t event;         /* event index within the batch                     */
-  int species;            /* 0 n, 1 p, 2 d, 3 t, 4 3He, 5 alpha, 6 photon     */
+  int species;            /* 0 n, 1 p, 2 d, 3 t, 4 3He, 5 alpha, 6 photon,
+                             7-26 the heavier fragments (orc_fragment)        */
   int stage;              /* 0 cascade, 1 evaporation                         */
   double T;               /* kinetic energy (MeV)                             */
   double u[3];            /* direction (lab)                                  */
@@ -131,6 +134,10 @@ double orc_photon_s0(int A, int Z);              /* sigma_g / eps (fm^2/MeV)  */
 double orc_photon_integral(double a, double U);  /* J(a,U)                    */
 double orc_photon_cdf(double a, double U, double x);
 double orc_photon_sample(double a, double U, double u);
+/* Emitted species j (0-5 particles, 7-26 heavier fragments; 6 the photon):
+ * mass number, charge and ground-state spin multiplicity 2s + 1.  Returns 0
+ * for j outside 0..26 or j = 6. */
+int orc_fragment(int j, int* a, int* z, int* g);
 double orc_photon_width(int A, int Z, double E); /* channel weight, 0 closed  */
 
 /* Sample a target momentum uniform in a Fermi sphere of radius pF. */

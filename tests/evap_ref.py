@@ -38,23 +38,24 @@ def photon_weight(A: int, Z: int, E: float) -> float:
     return s0 / math.pi * J
 
 
-def branching(A: int, Z: int, E: float, photons: bool = False) -> np.ndarray:
+def branching(A: int, Z: int, E: float, photons: bool = False, heavy: bool = False) -> np.ndarray:
     """Gamma_j / sum Gamma at excitation E: Gamma_j = g_j m_j R_j^2 I(a_d, U_j),
     I(a, U) = int_0^U x exp(2 sqrt(a (U - x))) dx, a_d = A_d / 8 MeV^-1; with
-    photons, a seventh entry for the photon channel."""
-    w = []
-    for j in range(6):
+    photons, the photon channel's weight at index 6; with heavy, the heavier
+    fragments' channels 7-26 (the same width form).  Length 6, 7 with
+    photons, 27 with heavy."""
+    chans = list(range(6)) + (list(ledger.HEAVY) if heavy else [])
+    w = np.zeros(27 if heavy else (7 if photons else 6))
+    for j in chans:
         a = int(ledger.FRAG_A[j])
         Ad = A - a
         U = E - threshold(A, Z, j)
         if not U > 0:
-            w.append(0.0)
             continue
         Rj = 1.5 * Ad ** (1 / 3) if j <= 1 else 1.5 * (Ad ** (1 / 3) + a ** (1 / 3))
         aa = Ad / 8.0
         I = integrate.quad(lambda x: x * math.exp(2 * math.sqrt(aa * max(U - x, 0))), 0, U, epsrel=1e-12)[0]
-        w.append(ledger.FRAG_G[j] * oracle.mass(a, int(ledger.FRAG_Z[j])) * Rj * Rj * I)
+        w[j] = ledger.FRAG_G[j] * oracle.mass(a, int(ledger.FRAG_Z[j])) * Rj * Rj * I
     if photons:
-        w.append(photon_weight(A, Z, E))
-    w = np.array(w)
+        w[6] = photon_weight(A, Z, E)
     return w / w.sum()

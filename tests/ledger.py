@@ -21,11 +21,17 @@ import numpy as np
 import oracle
 
 # species 0-5: n, p, d, t, 3He, alpha; 6: photon (massless, no nucleons; the
-# optional photon channel)
-FRAG_A = np.array([1, 1, 2, 3, 3, 4, 0])
-FRAG_Z = np.array([0, 1, 1, 1, 2, 2, 0])
-FRAG_G = np.array([2, 2, 3, 2, 2, 1, 2])
+# optional photon channel); 7-26: the optional heavier fragments, the stable
+# isotopes of Li to Mg (6Li 7Li 9Be 10B 11B 12C 13C 14N 15N 16O 17O 18O 19F
+# 20Ne 21Ne 22Ne 23Na 24Mg 25Mg 26Mg) with their ground-state 2s + 1
+FRAG_A = np.array([1, 1, 2, 3, 3, 4, 0,
+                   6, 7, 9, 10, 11, 12, 13, 14, 15, 16, 17, 18, 19, 20, 21, 22, 23, 24, 25, 26])
+FRAG_Z = np.array([0, 1, 1, 1, 2, 2, 0,
+                   3, 3, 4, 5, 5, 6, 6, 7, 7, 8, 8, 8, 9, 10, 10, 10, 11, 12, 12, 12])
+FRAG_G = np.array([2, 2, 3, 2, 2, 1, 2,
+                   3, 4, 4, 7, 4, 1, 2, 3, 2, 1, 6, 1, 2, 1, 4, 1, 4, 1, 6, 1])
 PHOTON = 6
+HEAVY = np.arange(7, 27)
 PHOTON_MIN_EXCITATION = 0.1  # MeV: the photon channel is open above this
 E2_COULOMB = 1.44
 M_PROTON = 938.272088
@@ -124,10 +130,12 @@ def _sum_by_event(idx, w, n):
     return np.bincount(idx, weights=w, minlength=n)
 
 
-def check(ev: Events, tol_E: float = 1e-3, tol_p: float = 1e-3, tol_u: float = 1e-5, photons: bool = False) -> dict:
+def check(ev: Events, tol_E: float = 1e-3, tol_p: float = 1e-3, tol_u: float = 1e-5, photons: bool = False,
+          heavy: bool = False) -> dict:
     """Return violation counts and worst residuals for every per-event check
     (photons: the photon channel was on, so no event may end above its
-    threshold either)."""
+    threshold either; heavy: the heavier fragments' channels were on, so
+    none of them may be left open, and records of them are allowed)."""
     M, B = mass_table()
     n = ev.n
     e = ev.sec_event
@@ -185,18 +193,19 @@ def check(ev: Events, tol_E: float = 1e-3, tol_p: float = 1e-3, tol_u: float = 1
     out["bad_T"] = int(np.sum(T < 0))
     un = np.sqrt(np.sum(ev.sec_u ** 2, axis=1))
     out["bad_u"] = int(np.sum(np.abs(un - 1.0) > tol_u))
-    out["bad_threshold"] = _open_channel_left(ev, B, photons)
+    out["bad_threshold"] = _open_channel_left(ev, B, photons, heavy)
     out["n_events"] = n
     out["n_secondaries"] = int(e.shape[0])
     return out
 
 
-def _open_channel_left(ev: Events, B, photons: bool = False) -> int:
+def _open_channel_left(ev: Events, B, photons: bool = False, heavy: bool = False) -> int:
     """Events whose final nucleus still has an open channel: E*_f >= S_j + V_j
-    for some valid channel j (beyond 1e-4 MeV of FP32 slack)."""
+    for some valid channel j (beyond 1e-4 MeV of FP32 slack); with the
+    channels off, any record of a photon or heavier fragment counts too."""
     bad_thr = np.zeros(ev.n, dtype=bool)
     Af, Zf = ev.A_f, ev.Z_f
-    for j in range(6):
+    for j in list(range(6)) + (list(HEAVY) if heavy else []):
         Ad = Af - FRAG_A[j]
         Zd = Zf - FRAG_Z[j]
         valid = (Ad >= 1) & (Zd >= 0) & (Zd <= Ad)
@@ -215,11 +224,13 @@ def _open_channel_left(ev: Events, B, photons: bool = False) -> int:
         bad_thr |= (ev.Ex_f > PHOTON_MIN_EXCITATION + 1e-4) & has_dipole & (ev.flags & 4 == 0)
     else:
         bad_thr |= np.bincount(ev.sec_event[ev.sec_species == PHOTON], minlength=ev.n) > 0
+    if not heavy:
+        bad_thr |= np.bincount(ev.sec_event[ev.sec_species >= 7], minlength=ev.n) > 0
     return int(np.sum(bad_thr))
 
 
 def check_evaporation(ev: Events, P_in, tol_E: float = 1e-3, tol_p: float = 1e-3, tol_u: float = 1e-5,
-                      photons: bool = False) -> dict:
+                      photons: bool = False, heavy: bool = False) -> dict:
     """Per-nucleus checks of an evaporation-only batch (Sec. 2.4): nucleus i,
     (A, Z) with excitation Ex_casc and lab momentum P_in[i], decays into its
     records (all stage 1) and the final nucleus.
@@ -261,7 +272,7 @@ def check_evaporation(ev: Events, P_in, tol_E: float = 1e-3, tol_p: float = 1e-3
     out["bad_T"] = int(np.sum(T < 0))
     un = np.sqrt(np.sum(ev.sec_u ** 2, axis=1))
     out["bad_u"] = int(np.sum(np.abs(un - 1.0) > tol_u))
-    out["bad_threshold"] = _open_channel_left(ev, B, photons)
+    out["bad_threshold"] = _open_channel_left(ev, B, photons, heavy)
     out["n_events"] = n
     out["n_secondaries"] = int(e.shape[0])
     return out
