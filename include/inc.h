@@ -13,7 +13,8 @@
  * Conventions
  *   Units: MeV, MeV/c, fm.  Incident protons move along +z.  Directions are
  *   unit vectors in the target rest frame; T is the asymptotic kinetic energy.
- *   Species codes: 0 n, 1 p, 2 d, 3 t, 4 3He, 5 alpha.  Stage 0 = cascade,
+ *   Species codes: 0 n, 1 p, 2 d, 3 t, 4 3He, 5 alpha (options: 6 photon,
+ *   7-26 heavier fragments, see inc_options).  Stage 0 = cascade,
  *   1 = evaporation.
  *   Event identity: event i of a batch uses the Philox4x32-10 stream with
  *   key = seed and counter = (block, id lo, id hi, 0), id = first_event_id + i,
@@ -125,6 +126,15 @@ typedef struct {
                          /* claims from the work queue at once (16..1024, a  */
                          /* multiple of 16; 0 = 64).  Results do not depend  */
                          /* on it.                                           */
+  /* model extension (Sec. 2.4), continued */
+  int heavy_fragments;   /* 1: the stable isotopes of Li to Mg (6Li 7Li 9Be */
+                         /* 10B 11B 12C 13C 14N 15N 16O 17O 18O 19F 20Ne    */
+                         /* 21Ne 22Ne 23Na 24Mg 25Mg 26Mg: species 7-26 in  */
+                         /* that order) are evaporated too, with the light   */
+                         /* particles' width and spectrum and their ground-  */
+                         /* state spins.  Sec. 2.4 keeps He and lighter      */
+                         /* ejectiles of a model that reaches Mg, so 0 (the */
+                         /* default) is the paper's model                    */
 } inc_options;
 
 /* One residual nucleus per event, 32 bytes: the excited nucleus the cascade
@@ -148,7 +158,8 @@ typedef struct {
   inc_residual* res;      /* device, n entries (event order)                 */
   uint32_t* sec_event;    /* device, sec_capacity entries: index in batch    */
   uint8_t* sec_species;   /* device, sec_capacity: 0 n, 1 p, 2 d, 3 t, 4 3He,
-                             5 alpha, 6 photon (photon_evaporation)        */
+                             5 alpha, 6 photon (photon_evaporation), 7-26
+                             heavier fragments (heavy_fragments)           */
   uint8_t* sec_stage;     /* device, sec_capacity                            */
   float* sec_T;           /* device, sec_capacity: kinetic energy (MeV)      */
   float* sec_ux;          /* device, sec_capacity: direction cosines         */

@@ -51,6 +51,7 @@ class Options(C.Structure):
         ("photon_evaporation", C.c_int),
         ("table_layout", C.c_int),
         ("chunk_events", C.c_int),
+        ("heavy_fragments", C.c_int),
     ]
 
 

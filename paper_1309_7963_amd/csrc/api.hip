@@ -88,6 +88,8 @@ void release(inc_ctx* c) {
   if (c->d_mass) (void)hipFree(c->d_mass);
   if (c->d_B) (void)hipFree(c->d_B);
   if (c->d_chan) (void)hipFree(c->d_chan);
+  if (c->d_heavy) (void)hipFree(c->d_heavy);
+  if (c->d_hmass) (void)hipFree(c->d_hmass);
   if (c->d_mid) (void)hipFree(c->d_mid);
   if (c->d_perm) (void)hipFree(c->d_perm);
   if (c->d_order_hist) (void)hipFree(c->d_order_hist);
@@ -125,6 +127,9 @@ LaunchDesc launch_desc(const inc_ctx* ctx, size_t n, int mode, int max_blocks) {
   L.chunk = ctx->opt.chunk_events ? ctx->opt.chunk_events : kChunkEvents;
   L.xs_pairs = ctx->opt.table_layout;
   L.photon = ctx->opt.photon_evaporation;
+  L.heavy = ctx->opt.heavy_fragments;
+  L.heavy_rows = ctx->d_heavy;
+  L.heavy_mass = ctx->d_hmass;
   L.nuc = ctx->d_nuc;
   L.n_targets = ctx->n_targets;
   L.xs = ctx->d_xs;
@@ -263,7 +268,7 @@ int inc_ctx_create(const inc_nucleus* targets, int n_targets, const inc_options*
       o.stack_levels < -1 || o.stack_levels > incdev::kStackLdsMax || o.fast_math < 0 || o.fast_math > 1 ||
       o.start_threshold < 0 || o.start_threshold > 64 || o.input_order < 0 || o.input_order > 1 ||
       o.same_stream < 0 || o.same_stream > 1 || o.photon_evaporation < 0 || o.photon_evaporation > 1 ||
-      o.table_layout < 0 || o.table_layout > 1 ||
+      o.table_layout < 0 || o.table_layout > 1 || o.heavy_fragments < 0 || o.heavy_fragments > 1 ||
       (o.chunk_events && (o.chunk_events < kChunkMin || o.chunk_events > kChunkMax || o.chunk_events % kChunkMin)))
     return INC_ERR_ARG;
   if (!(o.const_sigma_mb >= 0.0f) || o.const_sigma_mb > 1e5f) return INC_ERR_ARG;
@@ -319,6 +324,12 @@ int inc_ctx_create(const inc_nucleus* targets, int n_targets, const inc_options*
                               nullptr)) !=
         hipSuccess)
       break;
+    if (o.heavy_fragments) {
+      if ((e = hipMalloc(&c->d_heavy, sizeof(HeavyRow) * (amax + 1) * (zmax + 1))) != hipSuccess) break;
+      if ((e = hipMalloc(&c->d_hmass, sizeof(float) * kHeavy)) != hipSuccess) break;
+      if ((e = inc_launch_heavy_setup(c->d_B, amax, zmax, c->d_mass, c->d_heavy, c->d_hmass, nullptr)) != hipSuccess)
+        break;
+    }
     if ((e = hipDeviceSynchronize()) != hipSuccess) break;
     e = hipMemcpy(&c->evap, d_evap, sizeof(EvapTab), hipMemcpyDeviceToHost);
     for (int m = 0; m < 2; ++m) {

@@ -15,6 +15,8 @@ struct inc_ctx {
   incdev::MassTab* d_mass;
   double* d_B;
   incdev::ChanRow* d_chan;  // evaporation rows of every (A, Z) of d_B
+  incdev::HeavyRow* d_heavy;  // option heavy_fragments: the heavier fragments' rows (NULL when off)
+  float* d_hmass;             // and their masses
   int amax, zmax;
   incdev::EvapTab evap;
   incdev::MidState* d_mid;

@@ -114,6 +114,18 @@ struct ChanRow {
 };
 static_assert(sizeof(ChanRow) == 80, "ChanRow layout");
 
+// Heavier evaporation fragments (option, reading R20): the stable isotopes of
+// Li to Mg, species 7 .. 6 + kHeavy, with ground-state multiplicities 2s + 1.
+constexpr int kHeavy = 20;
+#define INC_HEAVY_A {6, 7, 9, 10, 11, 12, 13, 14, 15, 16, 17, 18, 19, 20, 21, 22, 23, 24, 25, 26}
+#define INC_HEAVY_Z {3, 3, 4, 5, 5, 6, 6, 7, 7, 8, 8, 8, 9, 10, 10, 10, 11, 12, 12, 12}
+#define INC_HEAVY_G {3, 4, 4, 7, 4, 1, 2, 3, 2, 1, 6, 1, 2, 1, 4, 1, 4, 1, 6, 1}
+// Per (A, Z): the heavier channels' S_j (+inf for a missing daughter), V_j and
+// ln(g_j m_j R_j^2), as ChanRow holds them for the particles.
+struct HeavyRow {
+  float S[kHeavy], V[kHeavy], P[kHeavy];
+};
+
 // Binding energies B(A, Z) in double and the evaporation rows, for A <= amax,
 // Z <= zmax (row of (A, Z) at A * zstride + Z).
 struct BindTab {
@@ -121,6 +133,8 @@ struct BindTab {
   int zstride;  // zmax + 1
   int amax, zmax;
   const ChanRow* chan;
+  const HeavyRow* heavy;  // option heavy_fragments (NULL when off)
+  const float* hmass;     // the heavier fragments' masses (kHeavy)
 };
 
 // --------------------------------------------------------------- Philox

@@ -424,13 +424,20 @@ __device__ __forceinline__ Nucleus cascade_residual(const Cascade& c, const NucT
 }
 
 
+// Evaporation options compiled into a kernel instantiation (bits).
+constexpr int kExtPhoton = 1;  // the photon channel (R19)
+constexpr int kExtHeavy = 2;   // the heavier fragments (R20)
+
 // EVAP: one evaporation step (Sec. 2.4, Weisskopf-Ewing reading).  Returns true
 // when no channel is open (the nucleus is final).  Draws at most 4 uniforms.
-// kPhoton: the optional photon channel competes (a separate instantiation,
-// so that the paper's model compiles without any of its code).
-template <bool kPhoton>
+// kExt: the optional channels that compete (the photon, channel 6; the
+// heavier fragments, channels 7-26), each a separate instantiation, so that
+// the paper's model compiles without any of their code.
+template <int kExt>
 __device__ __forceinline__ bool evap_step(Nucleus& nu, Rng& rng, const BindTab& bt, const EvapTab& et,
                                           const MassTab& mt, Emit& em) {
+  constexpr bool kPhoton = (kExt & kExtPhoton) != 0;
+  constexpr bool kHvy = (kExt & kExtHeavy) != 0;
   em.on = false;
   rng.ensure(4);
   constexpr int fa[6] = {1, 1, 2, 3, 3, 4};
@@ -463,6 +470,23 @@ __device__ __forceinline__ bool evap_step(Nucleus& nu, Rng& rng, const BindTab& 
       lmax = fmaxf(lmax, lwg);
     }
   }
+  // the optional heavier fragments (channels 7-26), the particles' width form
+  constexpr int ha[kHeavy] = INC_HEAVY_A;
+  constexpr int hz[kHeavy] = INC_HEAVY_Z;
+  float wh[kHvy ? kHeavy : 1];
+  if constexpr (kHvy) {
+    const HeavyRow& hrow = bt.heavy[nu.A * bt.zstride + nu.Z];
+#pragma unroll
+    for (int i = 0; i < kHeavy; ++i) {
+      wh[i] = -INFINITY;
+      const float Uh = nu.E - hrow.S[i] - hrow.V[i];
+      if (Uh > 0.0f) {
+        const int Ad = nu.A - ha[i];
+        wh[i] = hrow.P[i] + log_width_integral(2.0f * sqrtf((float)Ad * 0.125f * Uh), mt.lnA[Ad]);
+        lmax = fmaxf(lmax, wh[i]);
+      }
+    }
+  }
   if (lmax == -INFINITY) return true;
   float w[6], total = 0.0f;
 #pragma unroll
@@ -474,6 +498,13 @@ __device__ __forceinline__ bool evap_step(Nucleus& nu, Rng& rng, const BindTab& 
   if constexpr (kPhoton) {
     wg = lwg == -INFINITY ? 0.0f : expf(lwg - lmax);
     total += wg;
+  }
+  if constexpr (kHvy) {
+#pragma unroll
+    for (int i = 0; i < kHeavy; ++i) {
+      wh[i] = wh[i] == -INFINITY ? 0.0f : expf(wh[i] - lmax);
+      total += wh[i];
+    }
   }
   const float uc = rng.next() * total;
   int j = -1;
@@ -487,11 +518,24 @@ __device__ __forceinline__ bool evap_step(Nucleus& nu, Rng& rng, const BindTab& 
     cum += wg;
     if (j < 0 && wg > 0.0f && cum > uc) j = 6;
   }
+  if constexpr (kHvy) {
+#pragma unroll
+    for (int i = 0; i < kHeavy; ++i) {
+      cum += wh[i];
+      if (j < 0 && wh[i] > 0.0f && cum > uc) j = 7 + i;
+    }
+  }
   if (j < 0) {
+    // rounding at the top: the last open channel
 #pragma unroll
     for (int i = 0; i < 6; ++i)
       if (w[i] > 0.0f) j = i;
     if (kPhoton && wg > 0.0f) j = 6;
+    if constexpr (kHvy) {
+#pragma unroll
+      for (int i = 0; i < kHeavy; ++i)
+        if (wh[i] > 0.0f) j = 7 + i;
+    }
   }
   if constexpr (kPhoton) {
     if (j == 6) {
@@ -536,6 +580,22 @@ __device__ __forceinline__ bool evap_step(Nucleus& nu, Rng& rng, const BindTab& 
       aj = fa[i];
       zj = fz[i];
     }
+  if constexpr (kHvy) {
+    if (j >= 7) {
+      // the chosen heavier fragment's U, V and Y as its width had them
+      const HeavyRow& hrow = bt.heavy[nu.A * bt.zstride + nu.Z];
+#pragma unroll
+      for (int i = 0; i < kHeavy; ++i)
+        if (7 + i == j) {
+          Vj = hrow.V[i];
+          Uj = nu.E - hrow.S[i] - Vj;
+          aj = ha[i];
+          zj = hz[i];
+          Yj = 2.0f * sqrtf((float)(nu.A - aj) * 0.125f * Uj);
+          mj = bt.hmass[i];
+        }
+    }
+  }
   const float s = spectrum_sample_s(Yj, rng.next());
   const float x = Uj * s * (2.0f - s);
   const float Ed = Uj * (1.0f - s) * (1.0f - s);

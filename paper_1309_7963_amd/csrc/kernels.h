@@ -52,12 +52,15 @@ struct LaunchDesc {
   int chunk;             // events per work-queue claim (0: kChunkEvents)
   int xs_pairs;          // persistent kernels: NN table in LDS as node pairs
   int photon;            // the evaporation has the photon channel (instantiation)
+  int heavy;             // the evaporation has the heavier fragments (instantiation)
   const NucTab* nuc;
   int n_targets;
   const XsTab* xs;
   const MassTab* mass;
   const double* bind;
   const ChanRow* chan;
+  const HeavyRow* heavy_rows;  // option heavy_fragments (NULL when off)
+  const float* heavy_mass;
   int amax, zmax;
   EvapTab evap;
   inc_options opt;
@@ -119,6 +122,10 @@ hipError_t launch_evaporation(const LaunchDesc& L, const ExcitedDesc& x, hipStre
 hipError_t inc_launch_setup(const int* d_AZ, int n_targets, incdev::NucTab* d_nuc, incdev::XsTab* d_xs, double* d_B,
                             incdev::ChanRow* d_chan, int amax, int zmax, incdev::EvapTab* d_evap,
                             incdev::MassTab* d_mass, const inc_options& o, hipStream_t s);
+// The heavier fragments' rows (option heavy_fragments) after inc_launch_setup
+// has filled the binding and mass tables.
+hipError_t inc_launch_heavy_setup(const double* d_B, int amax, int zmax, const incdev::MassTab* d_mass,
+                                  incdev::HeavyRow* d_rows, float* d_hmass, hipStream_t s);
 hipError_t inc_upload_segment(const incdev::Segment& seg, incdev::Segment* d_slot, hipStream_t s);
 
 // Longest-expected-first start order of a launch's n events: perm (device, n

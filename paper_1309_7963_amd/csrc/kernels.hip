@@ -211,7 +211,7 @@ __global__ void __launch_bounds__(256) k_cascade_plain(KernelArgs a) {
 
 // Plain evaporation kernel: one de-excitation per thread (Sec. 3.3), same
 // random stream continued after the cascade's draws.
-template <bool kPhoton>
+template <int kExt>
 __global__ void __launch_bounds__(256) k_evap_plain(KernelArgs a) {
   extern __shared__ __align__(16) char lds[];
   stage_tables(lds, a, 0, kXsNone);
@@ -258,7 +258,7 @@ __global__ void __launch_bounds__(256) k_evap_plain(KernelArgs a) {
     Emit em;
     em.on = false;
     if (live) {
-      if (evap_step<kPhoton>(nu, rng, a.bind, a.evap, smt, em)) {
+      if (evap_step<kExt>(nu, rng, a.bind, a.evap, smt, em)) {
         write_residual(a.segs[er.seg].res + er.local, nu, m.E, nsec, flags, m.ncoll, m.nretry);
         put_hist(a, er, kHistDraws, rng.drawn());
         live = false;
@@ -314,7 +314,7 @@ struct OwnChunks {
 // current chunk, records whose cascade already ended the event (kMidFinal)
 // are skipped.  The random stream resumes after the cascade's draws, so the
 // results equal the fused kernel's whichever kernel runs this.
-template <int kCap, bool kPhoton, class Src>
+template <int kCap, int kExt, class Src>
 __device__ __forceinline__ void evap_events(const KernelArgs& a, const MassTab& smt, uint32_t* wbuf, int& fill,
                                             Src& src) {
   unsigned long long chunk_next = 0, chunk_end = 0;
@@ -370,7 +370,7 @@ __device__ __forceinline__ void evap_events(const KernelArgs& a, const MassTab& 
     Emit em;
     em.on = false;
     if (busy) {
-      if (evap_step<kPhoton>(nu, rng, a.bind, a.evap, smt, em)) {
+      if (evap_step<kExt>(nu, rng, a.bind, a.evap, smt, em)) {
         write_residual(a.segs[er.seg].res + er.local, nu, Ex_casc, nsec, flags, ncoll, nretry);
         put_hist(a, er, kHistDraws, rng.drawn());
         if (flags) atomicAdd(&a.segs[er.seg].counters[1], 1ull);
@@ -390,8 +390,8 @@ __device__ __forceinline__ void evap_events(const KernelArgs& a, const MassTab& 
 // no evaporation state, which leaves it fewer live registers; the wave
 // evaporates its hand-overs in a second loop once its cascades are over.
 // kPairs: the NN table in LDS as node pairs (XsPairs) instead of columns.
-// kPhoton: the evaporation has the optional photon channel.
-template <bool kFused, bool kPairs, bool kPhoton>
+// kExt: the evaporation's optional channels (kExtPhoton, kExtHeavy bits).
+template <bool kFused, bool kPairs, int kExt>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) k_persistent(KernelArgs a) {
   using XS = typename std::conditional<kPairs, XsPairs, XsLds>::type;
   constexpr int kLayout = kPairs ? kXsPairs : kXsColumns;
@@ -514,7 +514,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) k
     em.on = false;
     if (kFused && run == kStEvap) {
       if (st == kStEvap) {
-        if (evap_step<kPhoton>(nu, rng, a.bind, a.evap, smt, em)) {
+        if (evap_step<kExt>(nu, rng, a.bind, a.evap, smt, em)) {
           write_residual(a.segs[er.seg].res + er.local, nu, Ex_casc, nsec, c.flags, c.ncoll, c.nretry);
           put_hist(a, er, kHistDraws, rng.drawn());
           if (c.flags) atomicAdd(&a.segs[er.seg].counters[1], 1ull);
@@ -576,7 +576,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) k
     __builtin_amdgcn_s_setprio(0);
     __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
     OwnChunks src = {own_list, own_count, 0};
-    evap_events<kWriterCap, kPhoton>(a, smt, wbuf, fill, src);
+    evap_events<kWriterCap, kExt>(a, smt, wbuf, fill, src);
   }
   writer_flush(wbuf, fill, a.segs, a.ring);
 }
@@ -584,7 +584,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) k
 // Staged mode, second kernel: the evaporation of the handed-over events the
 // cascade kernel's waves did not evaporate themselves (the chunks listed
 // after the hand-over records), as a persistent work-queue kernel.
-template <bool kPhoton>
+template <int kExt>
 __global__ void __launch_bounds__(256) k_evap_persistent(KernelArgs a) {
   // usually nothing is left: the cascade waves evaporated what they handed over
   uint32_t* left = (uint32_t*)(a.mid + a.n);
@@ -596,7 +596,7 @@ __global__ void __launch_bounds__(256) k_evap_persistent(KernelArgs a) {
   uint32_t* wbuf = (uint32_t*)(lds + sizeof(MassTab)) + (threadIdx.x / 64) * (kWriterCapEvap * kRecWords);
   int fill = 0;
   LeftChunks src = {left, count};
-  evap_events<kWriterCapEvap, kPhoton>(a, smt, wbuf, fill, src);
+  evap_events<kWriterCapEvap, kExt>(a, smt, wbuf, fill, src);
   writer_flush(wbuf, fill, a.segs, a.ring);
 }
 
@@ -700,7 +700,7 @@ int stack_levels(int mode, int n_targets, int block, int waves_per_cu, int xs_la
 
 int evap_blocks_per_cu(int block) {
   int occ = 0;
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, (const void*)k_evap_persistent<false>, block,
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, (const void*)k_evap_persistent<0>, block,
                                                    lds_bytes(0, block, kXsNone, 0)) != hipSuccess ||
       occ < 1)
     return 1;
@@ -713,7 +713,7 @@ static KernelArgs kernel_args(const LaunchDesc& L) {
   a.n_targets = L.n_targets;
   a.xs = L.xs;
   a.mass = L.mass;
-  a.bind = {L.bind, L.zmax + 1, L.amax, L.zmax, L.chan};
+  a.bind = {L.bind, L.zmax + 1, L.amax, L.zmax, L.chan, L.heavy_rows, L.heavy_mass};
   a.evap = L.evap;
   a.opt.no_pauli = L.opt.no_pauli;
   a.opt.no_evaporation = L.opt.no_evaporation;
@@ -740,46 +740,41 @@ static KernelArgs kernel_args(const LaunchDesc& L) {
   return a;
 }
 
-hipError_t launch_events(const LaunchDesc& L, hipStream_t s) {
-  const KernelArgs a = kernel_args(L);
-  hipLaunchKernelGGL(k_zero_counters, dim3((L.n_seg + 63) / 64), dim3(64), 0, s, L.segs, L.n_seg, L.queue,
-                     L.mode == INC_MODE_STAGED ? (uint32_t*)(L.mid + L.n) : nullptr);
+// The evaporation options' instantiations (kExt != 0) take the columns layout.
+template <int kExt>
+static void launch_ext(const LaunchDesc& L, const KernelArgs& a, hipStream_t s) {
   const int block = L.block;
   if (L.mode == INC_MODE_PLAIN) {
     const unsigned grid = (unsigned)((L.n + block - 1) / block);
     hipLaunchKernelGGL(k_cascade_plain, dim3(grid), dim3(block),
                        lds_bytes(L.n_targets, block, kXsColumns, L.stack_lds), s, a);
-    if (L.photon)
-      hipLaunchKernelGGL(k_evap_plain<true>, dim3(grid), dim3(block), lds_bytes(0, block, kXsNone, 0), s, a);
-    else
-      hipLaunchKernelGGL(k_evap_plain<false>, dim3(grid), dim3(block), lds_bytes(0, block, kXsNone, 0), s, a);
+    hipLaunchKernelGGL(k_evap_plain<kExt>, dim3(grid), dim3(block), lds_bytes(0, block, kXsNone, 0), s, a);
+    return;
+  }
+  const dim3 grid(L.persistent_blocks);
+  const size_t lds = lds_bytes(L.n_targets, block, L.xs_pairs && kExt == 0 ? kXsPairs : kXsColumns, L.stack_lds);
+  if (L.mode == INC_MODE_STAGED) {
+    if (kExt == 0 && L.xs_pairs) hipLaunchKernelGGL((k_persistent<false, true, 0>), grid, dim3(block), lds, s, a);
+    else hipLaunchKernelGGL((k_persistent<false, false, kExt>), grid, dim3(block), lds, s, a);
+    hipLaunchKernelGGL(k_evap_persistent<kExt>, dim3(L.evap_blocks), dim3(block), lds_bytes(0, block, kXsNone, 0), s,
+                       a);
   } else {
-    const int layout = L.xs_pairs ? kXsPairs : kXsColumns;
-    const size_t lds = lds_bytes(L.n_targets, block, layout, L.stack_lds);
-    const dim3 grid(L.persistent_blocks);
-    // the photon channel's instantiations take the columns layout
-    if (L.photon) {
-      if (L.mode == INC_MODE_STAGED)
-        hipLaunchKernelGGL((k_persistent<false, false, true>), grid, dim3(block),
-                           lds_bytes(L.n_targets, block, kXsColumns, L.stack_lds), s, a);
-      else
-        hipLaunchKernelGGL((k_persistent<true, false, true>), grid, dim3(block),
-                           lds_bytes(L.n_targets, block, kXsColumns, L.stack_lds), s, a);
-    } else if (L.mode == INC_MODE_STAGED) {
-      if (L.xs_pairs) hipLaunchKernelGGL((k_persistent<false, true, false>), grid, dim3(block), lds, s, a);
-      else hipLaunchKernelGGL((k_persistent<false, false, false>), grid, dim3(block), lds, s, a);
-    } else {
-      if (L.xs_pairs) hipLaunchKernelGGL((k_persistent<true, true, false>), grid, dim3(block), lds, s, a);
-      else hipLaunchKernelGGL((k_persistent<true, false, false>), grid, dim3(block), lds, s, a);
-    }
-    if (L.mode == INC_MODE_STAGED) {
-      if (L.photon)
-        hipLaunchKernelGGL(k_evap_persistent<true>, dim3(L.evap_blocks), dim3(block), lds_bytes(0, block, kXsNone, 0),
-                           s, a);
-      else
-        hipLaunchKernelGGL(k_evap_persistent<false>, dim3(L.evap_blocks), dim3(block),
-                           lds_bytes(0, block, kXsNone, 0), s, a);
-    }
+    if (kExt == 0 && L.xs_pairs) hipLaunchKernelGGL((k_persistent<true, true, 0>), grid, dim3(block), lds, s, a);
+    else hipLaunchKernelGGL((k_persistent<true, false, kExt>), grid, dim3(block), lds, s, a);
+  }
+}
+
+static int ext_of(const LaunchDesc& L) { return (L.photon ? kExtPhoton : 0) | (L.heavy ? kExtHeavy : 0); }
+
+hipError_t launch_events(const LaunchDesc& L, hipStream_t s) {
+  const KernelArgs a = kernel_args(L);
+  hipLaunchKernelGGL(k_zero_counters, dim3((L.n_seg + 63) / 64), dim3(64), 0, s, L.segs, L.n_seg, L.queue,
+                     L.mode == INC_MODE_STAGED ? (uint32_t*)(L.mid + L.n) : nullptr);
+  switch (ext_of(L)) {
+    case 0: launch_ext<0>(L, a, s); break;
+    case kExtPhoton: launch_ext<kExtPhoton>(L, a, s); break;
+    case kExtHeavy: launch_ext<kExtHeavy>(L, a, s); break;
+    default: launch_ext<kExtPhoton | kExtHeavy>(L, a, s); break;
   }
   return hipGetLastError();
 }
@@ -789,12 +784,14 @@ hipError_t launch_evaporation(const LaunchDesc& L, const ExcitedDesc& x, hipStre
   hipLaunchKernelGGL(k_zero_counters, dim3((L.n_seg + 63) / 64), dim3(64), 0, s, L.segs, L.n_seg, L.queue,
                      (uint32_t*)nullptr);
   hipLaunchKernelGGL(k_excited_setup, dim3((unsigned)((L.n + 255) / 256)), dim3(256), 0, s, a, x);
-  if (L.photon)
-    hipLaunchKernelGGL(k_evap_persistent<true>, dim3(L.evap_blocks), dim3(L.block), lds_bytes(0, L.block, kXsNone, 0),
-                       s, a);
-  else
-    hipLaunchKernelGGL(k_evap_persistent<false>, dim3(L.evap_blocks), dim3(L.block), lds_bytes(0, L.block, kXsNone, 0),
-                       s, a);
+  const dim3 grid(L.evap_blocks), block(L.block);
+  const size_t lds = lds_bytes(0, L.block, kXsNone, 0);
+  switch (ext_of(L)) {
+    case 0: hipLaunchKernelGGL(k_evap_persistent<0>, grid, block, lds, s, a); break;
+    case kExtPhoton: hipLaunchKernelGGL(k_evap_persistent<kExtPhoton>, grid, block, lds, s, a); break;
+    case kExtHeavy: hipLaunchKernelGGL(k_evap_persistent<kExtHeavy>, grid, block, lds, s, a); break;
+    default: hipLaunchKernelGGL(k_evap_persistent<kExtPhoton | kExtHeavy>, grid, block, lds, s, a); break;
+  }
   return hipGetLastError();
 }
 

@@ -91,6 +91,41 @@ __global__ void k_chan_table(const double* B, int amax, int zmax, const EvapTab*
   chan[idx] = r;
 }
 
+// The heavier fragments' rows (option heavy_fragments, reading R20) for every
+// (A, Z) of the binding table, as k_chan_table makes the particles' rows:
+// S_j = B(A, Z) - B(A_d, Z_d) - B_j, V_j = e^2 z_j Z_d / (1.5 (A_d^1/3 +
+// a_j^1/3)), ln(g_j m_j R_j^2) with R_j = 1.5 (A_d^1/3 + a_j^1/3); and the
+// fragments' masses.
+__global__ void k_heavy_table(const double* B, int amax, int zmax, const MassTab* mt, HeavyRow* rows,
+                              float* hmass) {
+  const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+  const int zs = zmax + 1;
+  if (idx >= (amax + 1) * zs) return;
+  const int A = idx / zs, Z = idx % zs;
+  constexpr int ha[kHeavy] = INC_HEAVY_A;
+  constexpr int hz[kHeavy] = INC_HEAVY_Z;
+  constexpr int hg[kHeavy] = INC_HEAVY_G;
+  const double BAZ = B[idx];
+  HeavyRow r;
+  for (int i = 0; i < kHeavy; ++i) {
+    const double bj = semf_binding(ha[i], hz[i]);
+    const double mj = (double)hz[i] * kMassP + (double)(ha[i] - hz[i]) * kMassN - bj;
+    if (idx == 0) hmass[i] = (float)mj;
+    const int Ad = A - ha[i], Zd = Z - hz[i];
+    if (Z <= A && Ad >= 1 && Zd >= 0 && Zd <= Ad) {
+      r.S[i] = (float)(BAZ - B[Ad * zs + Zd] - bj);
+      const float R = 1.5f * (mt->a13[Ad] + mt->a13[ha[i]]);
+      r.V[i] = kE2 * (float)(hz[i] * Zd) / R;
+      r.P[i] = (float)log((double)hg[i] * mj) + 2.0f * logf(R);
+    } else {
+      r.S[i] = INFINITY;
+      r.V[i] = 0.0f;
+      r.P[i] = -INFINITY;
+    }
+  }
+  rows[idx] = r;
+}
+
 // Fermi density of Eq. (1), c = 1.07 A^1/3, delta = 0.545, R = c + 2.5 fm,
 // 15 equal shells; each shell's density is its share of the A nucleons over
 // its volume (integrals by 64-panel 5-point Gauss-Legendre, double).
@@ -356,6 +391,14 @@ hipError_t inc_launch_setup(const int* d_AZ, int n_targets, NucTab* d_nuc, XsTab
   const int rows = (amax + 1) * (zmax + 1);
   hipLaunchKernelGGL(k_chan_table, dim3((rows + 255) / 256), dim3(256), 0, s, d_B, amax, zmax, d_evap, d_mass,
                      d_chan);
+  return hipGetLastError();
+}
+
+hipError_t inc_launch_heavy_setup(const double* d_B, int amax, int zmax, const MassTab* d_mass, HeavyRow* d_rows,
+                                  float* d_hmass, hipStream_t s) {
+  const int rows = (amax + 1) * (zmax + 1);
+  hipLaunchKernelGGL(k_heavy_table, dim3((rows + 255) / 256), dim3(256), 0, s, d_B, amax, zmax, d_mass, d_rows,
+                     d_hmass);
   return hipGetLastError();
 }
 

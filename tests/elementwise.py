@@ -38,8 +38,8 @@ def same_history(g, o, g_counts=None, o_counts=None):
     m = (g.A_f == o.A_f) & (g.Z_f == o.Z_f) & (ng == no)
     if g_counts is not None:
         m &= np.all(np.asarray(g_counts) == np.asarray(o_counts), axis=1)
-    code_g = (g.sec_stage[og] * 8 + g.sec_species[og]).astype(np.int64)
-    code_o = (o.sec_stage[oo] * 8 + o.sec_species[oo]).astype(np.int64)
+    code_g = (g.sec_stage[og] * 32 + g.sec_species[og]).astype(np.int64)
+    code_o = (o.sec_stage[oo] * 32 + o.sec_species[oo]).astype(np.int64)
     for i in np.flatnonzero(m):
         if not np.array_equal(code_g[bg[i]:bg[i + 1]], code_o[bo[i]:bo[i + 1]]):
             m[i] = False

@@ -61,7 +61,7 @@ def outcome_keys(ev: ledger.Events):
     """Per-event integer outcome: (A_f, Z_f, sorted (stage, species) list)."""
     order = np.lexsort((ev.sec_species, ev.sec_stage, ev.sec_event))
     e = ev.sec_event[order]
-    code = (ev.sec_stage[order] * 8 + ev.sec_species[order]).astype(np.int64)
+    code = (ev.sec_stage[order] * 32 + ev.sec_species[order]).astype(np.int64)
     bounds = np.searchsorted(e, np.arange(ev.n + 1))
     keys = []
     for i in range(ev.n):

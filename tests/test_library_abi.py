@@ -91,7 +91,8 @@ def test_argument_errors_before_device(lib):
     assert L.inc_ring_create_device(None, 1 << 14, 1 << 12, C.byref(rh)) == inc.INC_ERR_ARG and not rh.value
     # option ranges are checked before the device is looked for
     for field, bad in (("fast_math", 2), ("same_stream", -1), ("stack_levels", 5), ("block_size", 96),
-                       ("waves_per_cu", 33), ("kin_threshold", 65), ("start_threshold", 65), ("input_order", 2)):
+                       ("waves_per_cu", 33), ("kin_threshold", 65), ("start_threshold", 65), ("input_order", 2),
+                       ("heavy_fragments", 2), ("photon_evaporation", 2)):
         o = _lib.Options()
         setattr(o, field, bad)
         assert L.inc_ctx_create(arr, 1, C.byref(o), C.byref(h)) == inc.INC_ERR_ARG, field
