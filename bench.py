@@ -541,6 +541,25 @@ def _tally_run(w, n_ebins: int = 23, reps: int = 5):
     return dict(events_per_s=n / (ms / 1000.0), kernel_ms=ms, n_ebins=n_ebins, yields_per_1e6_events=per_1e6)
 
 
+def _vertex_run(w, steps: int = 3, windows=(16, 18, 20), plain_launches: bool = True):
+    """The event-based vertex pipeline (mode vertex: in-flight window in
+    device memory, one kernel per vertex type over compacted queues) on
+    workload w, one batch at a time, against the staged kernels: mean ms per
+    batch (HIP events on the stream) for in-flight windows of 2^16, 2^18 and
+    2^20 events."""
+    staged = _time_gpu(w, "staged", steps, 1)
+    out = {"staged_ms": float(np.mean(staged["launch_ms"])), "vertex_ms": {}, "vertex_ms_plain_launches": {}}
+    for log2w in windows:
+        e = _time_gpu(w, "vertex", steps, 1, vertex_window=1 << log2w)
+        out["vertex_ms"]["2^%d" % log2w] = float(np.mean(e["launch_ms"]))
+        if plain_launches:
+            e = _time_gpu(w, "vertex", steps, 1, vertex_window=1 << log2w, vertex_launch=1)
+            out["vertex_ms_plain_launches"]["2^%d" % log2w] = float(np.mean(e["launch_ms"]))
+    best = min(out["vertex_ms"].values())
+    out["vertex_over_staged"] = best / out["staged_ms"]
+    return out
+
+
 def _ring_run(w, slots: int, reps: int = 2, placement: str = "host", chunk: int = 1 << 16):
     """Implant mixture with the secondaries streamed through a bounded ring
     (in host memory, or in device memory drained by asynchronous chunk
@@ -665,6 +684,11 @@ def main(argv=None):
                     help="only run the divergence-free probe: --steps launches of the 200 MeV p+16O batch, "
                          "launch k with every lane replaying event id k x batch size (seed 1), one at a "
                          "time (one JSON line; for the VALU instruction counters)")
+    ap.add_argument("--vertex", action="store_true",
+                    help="only time the vertex pipeline (mode vertex, three window sizes) against the staged "
+                         "kernels on the main workload (one JSON line)")
+    ap.add_argument("--vertex-window", type=int, default=0,
+                    help="with --vertex: only this in-flight window (log2), graph replay only")
     ap.add_argument("--rings", action="store_true",
                     help="only time the implant mixture directly and through the host and device rings "
                          "(one JSON line)")
@@ -691,6 +715,10 @@ def main(argv=None):
     main_w = wl["o16_ca40_200"]
     if args.stage_split:
         print(json.dumps(dict(workload=main_w["label"], **_evaporation_stage(main_w, reps=args.steps))))
+        return 0
+    if args.vertex:
+        kw = dict(windows=(args.vertex_window,), plain_launches=False) if args.vertex_window else {}
+        print(json.dumps(dict(workload=main_w["label"], **_vertex_run(main_w, args.steps, **kw))))
         return 0
     if args.rings:
         w = wl["implant_mix"]
@@ -754,6 +782,7 @@ def main(argv=None):
         print("bench: main-workload autotune done", file=sys.stderr, flush=True)
         e = _time_gpu(main_w, "plain", 3, 1)
         extra["plain_two_kernel"] = dict(events_per_s=rate(e))
+        extra["vertex_pipeline"] = _vertex_run(main_w, 2)
         e = _time_gpu(main_w, "persistent", 3, 1)
         extra["fused_persistent"] = dict(events_per_s=rate(e))
         # divergence ceiling: every lane on the same event stream (one history)

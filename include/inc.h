@@ -135,6 +135,15 @@ typedef struct {
                          /* state spins.  Sec. 2.4 keeps He and lighter      */
                          /* ejectiles of a model that reaches Mg, so 0 (the */
                          /* default) is the paper's model                    */
+  /* launch policy, continued */
+  int vertex_window;     /* INC_MODE_VERTEX: events in flight (a power of    */
+                         /* two, 1024..2^20; 0 = 2^18).  Each takes about    */
+                         /* 2.4 KB of device memory (state and LIFO).        */
+                         /* Results do not depend on it.                     */
+  int vertex_launch;     /* INC_MODE_VERTEX: each group of 8 cycles goes as  */
+                         /* one replay of a graph captured for the call (0, */
+                         /* default) or as separate kernel launches (1).     */
+                         /* Results do not depend on it.                     */
 } inc_options;
 
 /* One residual nucleus per event, 32 bytes: the excited nucleus the cascade
@@ -244,6 +253,18 @@ int inc_ctx_xs_table(const inc_ctx* ctx, float* host_out, int* n_nodes, float* p
                                  events it handed over; a persistent
                                  evaporation kernel takes any rest.  Same
                                  results as INC_MODE_PERSISTENT               */
+#define INC_MODE_VERTEX 3     /* event-based pipeline (the restructuring Sec.
+                                 4.2 suggests): a window of in-flight events
+                                 whose state stays in device memory, one
+                                 kernel per vertex type (flight segments,
+                                 tentative collisions, collision kinematics,
+                                 evaporation, refill) over compacted queues,
+                                 in cycles; the host checks for the end every
+                                 few cycles, so the call returns only when the
+                                 batch is done.  Same results as
+                                 INC_MODE_PERSISTENT; not with a workspace
+                                 (inc_simulate_dev_noalloc), the ring or the
+                                 server                                       */
 
 /* Generate batch->n non-elastic events (Sec. 2.1: cascade, Sec. 2.3, then
  * evaporation, Sec. 2.4; inputs and outputs as in Sec. 3.2 and 3.3)

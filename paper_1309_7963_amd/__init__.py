@@ -22,7 +22,8 @@ import numpy as np
 from . import _lib
 from ._lib import (  # noqa: F401
     INC_ERR_ARG, INC_ERR_BUSY, INC_ERR_CAPACITY, INC_ERR_DEVICE, INC_ERR_NO_DEVICE, INC_ERR_OOM, INC_ERR_RANGE,
-    INC_ERR_TOO_LARGE, NOALLOC_MAX_EVENTS, MODE_PERSISTENT, MODE_PLAIN, MODE_STAGED, RESIDUAL_DTYPE, IncError,
+    INC_ERR_TOO_LARGE, NOALLOC_MAX_EVENTS, MODE_PERSISTENT, MODE_PLAIN, MODE_STAGED, MODE_VERTEX, RESIDUAL_DTYPE,
+    IncError,
 )
 
 FLAG_STACK, FLAG_SEGMENTS, FLAG_EMPTY, FLAG_RANGE = 1, 2, 4, 0x8000
@@ -290,7 +291,7 @@ class Context:
         return table
 
 
-MODES = {"plain": MODE_PLAIN, "persistent": MODE_PERSISTENT, "staged": MODE_STAGED}
+MODES = {"plain": MODE_PLAIN, "persistent": MODE_PERSISTENT, "staged": MODE_STAGED, "vertex": MODE_VERTEX}
 
 
 # Positron emitters reachable from tissue nuclei (C, N, O, P, Ca) by

@@ -22,6 +22,7 @@ NOALLOC_MAX_EVENTS = 1048576
 MODE_PLAIN = 0
 MODE_PERSISTENT = 1
 MODE_STAGED = 2
+MODE_VERTEX = 3
 
 # exported symbols, in the order include/inc.h declares them
 SYMBOLS = (
@@ -52,6 +53,8 @@ class Options(C.Structure):
         ("table_layout", C.c_int),
         ("chunk_events", C.c_int),
         ("heavy_fragments", C.c_int),
+        ("vertex_window", C.c_int),
+        ("vertex_launch", C.c_int),
     ]
 
 

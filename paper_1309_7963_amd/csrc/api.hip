@@ -94,7 +94,50 @@ void release(inc_ctx* c) {
   if (c->d_perm) (void)hipFree(c->d_perm);
   if (c->d_order_hist) (void)hipFree(c->d_order_hist);
   if (c->d_segs) (void)hipFree(c->d_segs);
+  if (c->vtx.slots) (void)hipFree(c->vtx.slots);
+  if (c->vtx.stacks) (void)hipFree(c->vtx.stacks);
+  if (c->vtx.queues) (void)hipFree(c->vtx.queues);
+  if (c->vtx.ctl) (void)hipFree(c->vtx.ctl);
+  if (c->vtx.h_done) (void)hipHostFree(c->vtx.h_done);
+  for (int k = 0; k < 2; ++k)
+    if (c->vtx.ev[k]) (void)hipEventDestroy(c->vtx.ev[k]);
+  if (c->vtx.capture) (void)hipStreamDestroy(c->vtx.capture);
   delete c;
+}
+
+// The vertex pipeline's buffers for a window of the context's vertex_window
+// slots (allocated once).
+hipError_t ensure_vertex(inc_ctx* ctx) {
+  VertexBuf& v = ctx->vtx;
+  if (v.slots) return hipSuccess;
+  const size_t w = ctx->opt.vertex_window ? (size_t)ctx->opt.vertex_window : (size_t)1 << 18;
+  const size_t slot = ctx->opt.fast_math ? fast::vertex_slot_bytes() : precise::vertex_slot_bytes();
+  hipError_t e = hipMalloc(&v.slots, slot * w);
+  const size_t stack = ctx->opt.fast_math ? fast::vertex_stack_bytes() : precise::vertex_stack_bytes();
+  if (e == hipSuccess) e = hipMalloc(&v.stacks, stack * w);
+  const size_t qw = ctx->opt.fast_math ? fast::vertex_queue_words(w) : precise::vertex_queue_words(w);
+  if (e == hipSuccess) e = hipMalloc(&v.queues, sizeof(uint32_t) * qw);
+  if (e == hipSuccess) e = hipMalloc(&v.ctl, sizeof(uint32_t) * kVertexCtlWords);
+  if (e == hipSuccess) e = hipStreamCreateWithFlags(&v.capture, hipStreamNonBlocking);
+  if (e == hipSuccess) e = hipHostMalloc(&v.h_done, sizeof(uint32_t) * 2, hipHostMallocDefault);
+  for (int k = 0; k < 2 && e == hipSuccess; ++k) e = hipEventCreateWithFlags(&v.ev[k], hipEventDisableTiming);
+  if (e != hipSuccess) {
+    if (v.slots) (void)hipFree(v.slots);
+    if (v.stacks) (void)hipFree(v.stacks);
+    if (v.queues) (void)hipFree(v.queues);
+    if (v.ctl) (void)hipFree(v.ctl);
+    if (v.h_done) (void)hipHostFree(v.h_done);
+    for (int k = 0; k < 2; ++k)
+      if (v.ev[k]) (void)hipEventDestroy(v.ev[k]);
+    if (v.capture) (void)hipStreamDestroy(v.capture);
+    memset(&v, 0, sizeof(v));
+    return e;
+  }
+  v.window = w;
+  v.use_graph = ctx->opt.vertex_launch == 0;
+  v.cycles_per_group = 8;
+  v.max_cycles = 200000;
+  return hipSuccess;
 }
 
 // The context's hand-over buffer, grown to n events.
@@ -185,7 +228,8 @@ int inc_launch_segments(inc_ctx* ctx, size_t n, const uint8_t* tidx, const float
   }
   // the context's own persistent launches start their costliest events first
   const uint32_t* perm = nullptr;
-  if (own && (mode == INC_MODE_PERSISTENT || mode == INC_MODE_STAGED) && n >= kOrderMin && !ctx->opt.input_order) {
+  if (own && (mode == INC_MODE_PERSISTENT || mode == INC_MODE_STAGED || mode == INC_MODE_VERTEX) && n >= kOrderMin &&
+      !ctx->opt.input_order) {
     hipError_t e = hipSuccess;
     uint32_t* hist = ws ? ws->hist : ctx->d_order_hist;
     uint32_t* order = ws ? ws->perm : ctx->d_perm;
@@ -216,13 +260,20 @@ int inc_launch_segments(inc_ctx* ctx, size_t n, const uint8_t* tidx, const float
   L.queue = queue;
   L.mid = mid ? mid : ctx->d_mid;
   if (ring) L.ring = *ring;
+  if (mode == INC_MODE_VERTEX) {
+    const hipError_t e = ensure_vertex(ctx);
+    if (e != hipSuccess) return map_err(e);
+    return map_err(ctx->opt.fast_math ? fast::launch_vertex(L, ctx->vtx, s) : precise::launch_vertex(L, ctx->vtx, s));
+  }
   return map_err(ctx->opt.fast_math ? fast::launch_events(L, s) : precise::launch_events(L, s));
 }
 
 int inc_launch_batch(inc_ctx* ctx, const inc_batch* b, const inc_output* out, hipStream_t s, int mode, int max_blocks,
                      const Workspace* ws) {
   if (!ctx || !b || !valid_output(out)) return INC_ERR_ARG;
-  if (mode != INC_MODE_PLAIN && mode != INC_MODE_PERSISTENT && mode != INC_MODE_STAGED) return INC_ERR_ARG;
+  if (mode != INC_MODE_PLAIN && mode != INC_MODE_PERSISTENT && mode != INC_MODE_STAGED && mode != INC_MODE_VERTEX)
+    return INC_ERR_ARG;
+  if (mode == INC_MODE_VERTEX && ws) return INC_ERR_ARG;
   if (b->n < 1 || b->n >= (1ull << 32) || !b->T0) return INC_ERR_ARG;
   const Segment seg = batch_segment(out, b->n, b->first_event_id);
   Segment* slot = ctx->d_segs + (ctx->seg_next++ % kSegSlots);
@@ -269,6 +320,9 @@ int inc_ctx_create(const inc_nucleus* targets, int n_targets, const inc_options*
       o.start_threshold < 0 || o.start_threshold > 64 || o.input_order < 0 || o.input_order > 1 ||
       o.same_stream < 0 || o.same_stream > 1 || o.photon_evaporation < 0 || o.photon_evaporation > 1 ||
       o.table_layout < 0 || o.table_layout > 1 || o.heavy_fragments < 0 || o.heavy_fragments > 1 ||
+      (o.vertex_window && (o.vertex_window < 1024 || o.vertex_window > (1 << 20) ||
+                           (o.vertex_window & (o.vertex_window - 1)))) ||
+      o.vertex_launch < 0 || o.vertex_launch > 1 ||
       (o.chunk_events && (o.chunk_events < kChunkMin || o.chunk_events > kChunkMax || o.chunk_events % kChunkMin)))
     return INC_ERR_ARG;
   if (!(o.const_sigma_mb >= 0.0f) || o.const_sigma_mb > 1e5f) return INC_ERR_ARG;

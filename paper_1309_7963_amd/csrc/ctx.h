@@ -31,6 +31,7 @@ struct inc_ctx {
   int block, evap_threshold, tent_threshold, kin_threshold, start_threshold, waves_per_cu;
   int stack_lds[2];  // LIFO entries per lane in LDS: [plain, persistent]
   int evap_blocks;   // staged mode: evaporation kernel grid (full occupancy)
+  incdev::VertexBuf vtx;  // INC_MODE_VERTEX buffers (allocated on first use; slots NULL until then)
 };
 
 

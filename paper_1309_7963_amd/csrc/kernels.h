@@ -102,7 +102,31 @@ constexpr float kMaxExcitation = 500.0f;  // MeV
 //   launch_events zero the counters, then launch the event kernel(s) of L.mode.
 //   launch_evaporation  evaporation alone of L.n given excited nuclei
 //                 (L.mid: the hand-over buffer; L.T0, L.tidx unused).
+// Device and host buffers of the vertex pipeline (INC_MODE_VERTEX): a window
+// of in-flight event slots (vertex_slot_bytes() each), their LIFOs
+// (vertex_stack_bytes() each), the stage queues (vertex_queue_words(window))
+// and the control words; two pinned done flags and two events for the host's
+// checks; a stream to capture a group of cycles as a graph on.
+constexpr int kVertexCtlWords = 40;
+struct VertexBuf {
+  void* slots;
+  void* stacks;
+  uint32_t* queues;
+  uint32_t* ctl;
+  size_t window;
+  uint32_t* h_done;
+  hipEvent_t ev[2];
+  hipStream_t capture;
+  int use_graph;
+  int cycles_per_group;
+  long max_cycles;
+};
+
 namespace precise {
+size_t vertex_slot_bytes();
+size_t vertex_stack_bytes();  // one slot's LIFO
+size_t vertex_queue_words(size_t window);
+hipError_t launch_vertex(const LaunchDesc& L, const VertexBuf& vb, hipStream_t s);
 size_t lds_bytes(int n_targets, int block, int xs_layout, int stack_levels);
 int stack_levels(int mode, int n_targets, int block, int waves_per_cu, int xs_layout);
 int evap_blocks_per_cu(int block);
@@ -110,6 +134,10 @@ hipError_t launch_events(const LaunchDesc& L, hipStream_t s);
 hipError_t launch_evaporation(const LaunchDesc& L, const ExcitedDesc& x, hipStream_t s);
 }  // namespace precise
 namespace fast {
+size_t vertex_slot_bytes();
+size_t vertex_stack_bytes();  // one slot's LIFO
+size_t vertex_queue_words(size_t window);
+hipError_t launch_vertex(const LaunchDesc& L, const VertexBuf& vb, hipStream_t s);
 size_t lds_bytes(int n_targets, int block, int xs_layout, int stack_levels);
 int stack_levels(int mode, int n_targets, int block, int waves_per_cu, int xs_layout);
 int evap_blocks_per_cu(int block);

@@ -662,6 +662,302 @@ __global__ void k_zero_counters(const Segment* segs, int n_seg, unsigned long lo
   }
 }
 
+// ================================================================== vertex
+// Event-based pipeline (the restructuring Sec. 4.2 suggests: separate kernels
+// for the vertex types, over compacted queues), kept as a measured rival of
+// the persistent kernel.  A window of W in-flight events keeps its state in
+// device memory (VSlot, with a LIFO of kStackDepth entries per slot); one
+// kernel per vertex type runs the events that stand at that vertex, every
+// lane busy with one of them.  One cycle runs kVPairs pairs of stages FLIGHT
+// (flight segments until a tentative collision or the end of the cascade; an
+// escape or a transparent pass starts the next flight at once) and TENT
+// (tentative collisions; a null collision goes on in the next FLIGHT stage),
+// then KIN (accepted or blocked collisions), EVAP (the whole evaporation of a
+// finished cascade), REFILL (slots whose event ended take the next events of
+// the launch, in start order, and enter them) and SWAP.  A slot handed to a
+// vertex type joins the queue of the next stage of that type in the cycle, or
+// of its first stage in the next cycle.  Each event runs the same steps on its
+// own stream as in the other modes, so the results are the same.
+enum { kVFlight = 0, kVTent = 1, kVKin = 2, kVEvap = 3, kVFree = 4, kVTypes = 5 };
+constexpr int kVPairs = 3;
+constexpr int kVStages = 2 * kVPairs + 3;
+constexpr int kVRefill = kVStages - 1;
+__host__ __device__ constexpr int vstage_type(int k) {
+  return k < 2 * kVPairs ? (k & 1) : (k == 2 * kVPairs ? kVKin : (k == 2 * kVPairs + 1 ? kVEvap : kVFree));
+}
+// Destination stage of a slot handed to type t by stage k: bit 8 set for the
+// next cycle.
+__host__ __device__ constexpr int vdest(int k, int t) {
+  for (int j = k + 1; j < kVStages; ++j)
+    if (vstage_type(j) == t) return j;
+  for (int j = 0; j < kVStages; ++j)
+    if (vstage_type(j) == t) return j | 256;
+  return 0;
+}
+static_assert(vdest(kVRefill, kVFlight) == 256 && vdest(1, kVFlight) == 2 && vdest(2 * kVPairs - 1, kVFlight) == 256,
+              "stage order");
+
+struct __align__(16) VSlot {
+  Cascade c;
+  Rng rng;
+  Nucleus nu;
+  EventRef er;
+  float T0, Ex_casc;
+  int tgt, nsec;
+};
+
+struct VertexArgs {
+  VSlot* slots;
+  StackEntry* stacks;  // kStackDepth per slot
+  uint32_t* queues;    // [2 parities][kVStages][window]
+  uint32_t* ctl;       // [0] parity of this cycle, [1] slots holding an event, [2] done, [4 + 16 p + k] counts
+  uint32_t window;
+};
+static_assert(4 + 16 + kVStages <= kVertexCtlWords && kVStages <= 16, "control words");
+
+__device__ __forceinline__ uint32_t* vq(const VertexArgs& v, int p, int k) {
+  return v.queues + ((size_t)p * kVStages + k) * v.window;
+}
+__device__ __forceinline__ uint32_t* vcnt(const VertexArgs& v, int p, int k) { return v.ctl + 4 + 16 * p + k; }
+
+// Hand `slot` to type t (lanes with `on`; every lane of the wave calls) from
+// stage kFrom.  One atomic per wave and destination queue.
+template <int kFrom>
+__device__ __forceinline__ void vpush(const VertexArgs& v, bool on, int t, int cur, uint32_t slot) {
+#pragma unroll
+  for (int q = 0; q < kVTypes; ++q) {
+    const uint64_t m = __ballot(on && t == q);
+    if (!m) continue;
+    constexpr int kD[kVTypes] = {vdest(kFrom, 0), vdest(kFrom, 1), vdest(kFrom, 2), vdest(kFrom, 3), vdest(kFrom, 4)};
+    const int p = (kD[q] & 256) ? 1 - cur : cur;
+    const int k = kD[q] & 255;
+    const int leader = __ffsll((unsigned long long)m) - 1;
+    uint32_t base = 0;
+    if (lane_id() == leader) base = atomicAdd(vcnt(v, p, k), (uint32_t)__popcll(m));
+    base = (uint32_t)__shfl((int)base, leader);
+    if (on && t == q) vq(v, p, k)[base + rank_in(m)] = slot;
+  }
+}
+
+// A slot's state to and from separate locals (as the persistent kernel keeps
+// them), so that every field can stay in registers.
+__device__ __forceinline__ void vload(const VSlot& g, Cascade& c, Rng& rng, Nucleus& nu, EventRef& er, float& T0,
+                                      float& Ex_casc, int& tgt, int& nsec) {
+  c = g.c;
+  rng = g.rng;
+  nu = g.nu;
+  er = g.er;
+  T0 = g.T0;
+  Ex_casc = g.Ex_casc;
+  tgt = g.tgt;
+  nsec = g.nsec;
+}
+__device__ __forceinline__ void vstore(VSlot& g, const Cascade& c, const Rng& rng, const Nucleus& nu, EventRef er,
+                                       float T0, float Ex_casc, int tgt, int nsec) {
+  g.c = c;
+  g.rng = rng;
+  g.nu = nu;
+  g.er = er;
+  g.T0 = T0;
+  g.Ex_casc = Ex_casc;
+  g.tgt = tgt;
+  g.nsec = nsec;
+}
+
+// End of a cascade, as in the fused persistent kernel: the residual nucleus;
+// a final one (empty, or evaporation off) is written out and frees its slot.
+__device__ __forceinline__ int vtx_cascade_end(const KernelArgs& a, Cascade& c, const Rng& rng, Nucleus& nu,
+                                               EventRef er, float T0, float& Ex_casc, int nsec, const NucTab& nt) {
+  nu = cascade_residual(c, nt, T0);
+  Ex_casc = nu.E;
+  if (nu.A <= 0) c.flags |= kFlagEmpty;
+  put_hist_cascade(a, er, c);
+  if (nu.A <= 0 || a.opt.no_evaporation) {
+    write_residual(a.segs[er.seg].res + er.local, nu, Ex_casc, nsec, c.flags, c.ncoll, c.nretry);
+    put_hist(a, er, kHistDraws, rng.drawn());
+    if (c.flags) atomicAdd(&a.segs[er.seg].counters[1], 1ull);
+    return kVFree;
+  }
+  return kVEvap;
+}
+
+__global__ void k_vertex_init(VertexArgs v, uint32_t w) {
+  const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < w) vq(v, 0, kVRefill)[i] = i;
+  if (i < kVertexCtlWords) v.ctl[i] = 0u;
+  __syncthreads();  // (block 0 only writes ctl)
+  if (i == 0) {
+    v.ctl[1] = w;
+    *vcnt(v, 0, kVRefill) = w;
+  }
+}
+
+// One stage (FLIGHT, TENT, KIN or EVAP) over this cycle's queue of the stage,
+// grid-stride.
+template <int kStage, int kExt>
+__global__ void __launch_bounds__(256) k_vertex(KernelArgs a, VertexArgs v) {
+  constexpr int kType = vstage_type(kStage);
+  const int cur = (int)v.ctl[0];
+  const uint32_t n = *vcnt(v, cur, kStage);
+  if ((uint32_t)(blockIdx.x * blockDim.x) >= n) return;
+  constexpr bool kEvap = kType == kVEvap;
+  constexpr int kLayout = kEvap ? kXsNone : kXsColumns;
+  extern __shared__ __align__(16) char lds[];
+  const int ntab = kEvap ? 0 : a.n_targets;
+  stage_tables(lds, a, ntab, kLayout);
+  const NucTab* snt = (const NucTab*)lds;
+  const XsLds& sxs = *(const XsLds*)(lds + ntab * sizeof(NucTab));
+  const MassTab& smt = *(const MassTab*)(lds + lds_mass_offset(ntab, kLayout));
+  constexpr int kCap = kEvap ? kWriterCapEvap : kWriterCap;
+  uint32_t* wbuf = (uint32_t*)(lds + lds_mass_offset(ntab, kLayout) + sizeof(MassTab)) +
+                   (threadIdx.x / 64) * (kCap * kRecWords);
+  int fill = 0;
+  for (uint32_t base = blockIdx.x * blockDim.x; base < n; base += gridDim.x * blockDim.x) {
+    const uint32_t i = base + threadIdx.x;
+    const bool live = i < n;
+    const uint32_t slot = live ? vq(v, cur, kStage)[i] : 0u;
+    Cascade c;
+    Rng rng;
+    Nucleus nu;
+    EventRef er;
+    float T0, Ex_casc;
+    int tgt, nsec;
+    // (slot 0 for idle lanes: read, never written)
+    vload(v.slots[slot], c, rng, nu, er, T0, Ex_casc, tgt, nsec);
+    StackEntry* stk = v.stacks + (size_t)slot * kStackDepth;
+    int next = kVFree;
+    if constexpr (kEvap) {
+      bool act = live;
+      while (__any(act)) {
+        Emit em;
+        em.on = false;
+        if (act) {
+          if (evap_step<kExt>(nu, rng, a.bind, a.evap, smt, em)) {
+            write_residual(a.segs[er.seg].res + er.local, nu, Ex_casc, nsec, c.flags, c.ncoll, c.nretry);
+            put_hist(a, er, kHistDraws, rng.drawn());
+            if (c.flags) atomicAdd(&a.segs[er.seg].counters[1], 1ull);
+            act = false;
+          } else {
+            ++nsec;
+          }
+        }
+        writer_append<kCap>(wbuf, fill, a.segs, a.ring, em.on, er.local, kind_of(em.kind, er), em.T, em.u);
+      }
+    } else {
+      const NucTab& nt = snt[live ? tgt : 0];
+      if constexpr (kType == kVFlight) {
+        bool act = live;
+        while (__any(act)) {
+          Emit em;
+          em.on = false;
+          if (act) {
+            int ns = flight_core(c, stk, nt, em);
+            if (em.on) ++nsec;
+            if (ns == kStStart) ns = start_step(c, stk, rng, nt, sxs, a.opt, T0);
+            if (ns == kStTent) {
+              next = kVTent;
+              act = false;
+            } else if (ns == kStDone) {
+              next = vtx_cascade_end(a, c, rng, nu, er, T0, Ex_casc, nsec, nt);
+              act = false;
+            }
+          }
+          writer_append(wbuf, fill, a.segs, a.ring, em.on, er.local, kind_of(em.kind, er), em.T, em.u);
+        }
+      } else if constexpr (kType == kVTent) {
+        if (live) next = tent_step(c, rng, nt, sxs, a.opt) == kStKin ? kVKin : kVFlight;
+      } else {
+        if (live) {
+          const int ns = kin_step(c, stk, rng, nt, sxs, a.opt);
+          next = ns == kStDone ? vtx_cascade_end(a, c, rng, nu, er, T0, Ex_casc, nsec, nt) : kVFlight;
+        }
+      }
+    }
+    if (live && next != kVFree) vstore(v.slots[slot], c, rng, nu, er, T0, Ex_casc, tgt, nsec);
+    vpush<kStage>(v, live, next, cur, slot);
+  }
+  writer_flush(wbuf, fill, a.segs, a.ring);
+}
+
+// REFILL: every freed slot takes the next event of the launch (in start
+// order; out-of-range inputs are written out flagged and skipped) and enters
+// the nucleus; a slot that finds none is retired.  Grid-stride.
+__global__ void __launch_bounds__(256) k_vertex_refill(KernelArgs a, VertexArgs v) {
+  const int cur = (int)v.ctl[0];
+  const uint32_t n = *vcnt(v, cur, kVRefill);
+  if ((uint32_t)(blockIdx.x * blockDim.x) >= n) return;
+  extern __shared__ __align__(16) char lds[];
+  stage_tables(lds, a, a.n_targets, kXsColumns);
+  const NucTab* snt = (const NucTab*)lds;
+  const XsLds& sxs = *(const XsLds*)(lds + a.n_targets * sizeof(NucTab));
+  for (uint32_t base = blockIdx.x * blockDim.x; base < n; base += gridDim.x * blockDim.x) {
+    const uint32_t i = base + threadIdx.x;
+    const bool live = i < n;
+    const uint32_t slot = live ? vq(v, cur, kVRefill)[i] : 0u;
+    EventRef er = {0, 0};
+    float T0 = 0.0f;
+    int tgt = 0;
+    bool need = live, got = false;
+    while (__any(need)) {
+      const uint64_t m = __ballot(need);
+      const int leader = __ffsll((unsigned long long)m) - 1;
+      unsigned long long first = 0;
+      if (lane_id() == leader) first = atomicAdd(a.queue, (unsigned long long)__popcll(m));
+      first = __shfl(first, leader);
+      if (need) {
+        const unsigned long long pos = first + rank_in(m);
+        if (pos >= a.n) {
+          need = false;
+        } else {
+          const size_t ev = a.perm ? (size_t)a.perm[pos] : (size_t)pos;
+          er = event_ref(a, ev);
+          T0 = a.T0[ev];
+          tgt = a.tidx ? (int)a.tidx[ev] : 0;
+          if (!energy_ok(T0) || tgt >= a.n_targets) {
+            tgt = 0;
+            const Nucleus z = {0, 0, 0.0f, {0.0f, 0.0f, 0.0f}};
+            write_residual(a.segs[er.seg].res + er.local, z, 0.0f, 0, kFlagRange, 0, 0);
+            put_hist(a, er, kHistDraws, 0u);
+            put_hist(a, er, kHistSegments, 0u);
+            put_hist(a, er, kHistShells, 0u);
+            atomicAdd(&a.segs[er.seg].counters[1], 1ull);
+          } else {
+            need = false;
+            got = true;
+          }
+        }
+      }
+    }
+    if (got) {
+      StackEntry* stk = v.stacks + (size_t)slot * kStackDepth;
+      Rng rng;
+      rng.set_key(a.seed);
+      init_stream(rng, a, er);
+      const NucTab& nt = snt[tgt];
+      Cascade c;
+      cascade_init(c, nt);
+      c.stk_base = 0;
+      c.stk_levels = 0;  // the whole LIFO in the slot's device memory
+      (void)start_step(c, stk, rng, nt, sxs, a.opt, T0);  // the entry: always a flight
+      const Nucleus nu = {0, 0, 0.0f, {0.0f, 0.0f, 0.0f}};
+      vstore(v.slots[slot], c, rng, nu, er, T0, 0.0f, tgt, 0);
+    }
+    vpush<kVRefill>(v, got, kVFlight, cur, slot);
+    const uint64_t retired = __ballot(live && !got);
+    if (retired && lane_id() == __ffsll((unsigned long long)retired) - 1)
+      atomicSub(&v.ctl[1], (uint32_t)__popcll(retired));
+  }
+}
+
+// SWAP: this cycle's queues are spent; the next cycle's become current.
+__global__ void k_vertex_swap(VertexArgs v) {
+  if (threadIdx.x != 0) return;
+  const int cur = (int)v.ctl[0];
+  for (int k = 0; k < kVStages; ++k) *vcnt(v, cur, k) = 0u;
+  v.ctl[0] = (uint32_t)(1 - cur);
+  v.ctl[2] = v.ctl[1] == 0u ? 1u : 0u;
+}
+
 // ================================================================ launchers
 size_t lds_bytes(int n_targets, int block, int xs_layout, int stack_levels) {
   const bool events = xs_layout != kXsNone;
@@ -793,6 +1089,95 @@ hipError_t launch_evaporation(const LaunchDesc& L, const ExcitedDesc& x, hipStre
     default: hipLaunchKernelGGL(k_evap_persistent<kExtPhoton | kExtHeavy>, grid, block, lds, s, a); break;
   }
   return hipGetLastError();
+}
+
+size_t vertex_slot_bytes() { return sizeof(VSlot); }
+size_t vertex_stack_bytes() { return sizeof(StackEntry) * kStackDepth; }
+size_t vertex_queue_words(size_t window) { return 2 * (size_t)kVStages * window; }
+
+template <int kExt, int kStage>
+static void launch_vertex_stage(const LaunchDesc& L, const KernelArgs& a, const VertexArgs& v, unsigned grid,
+                                hipStream_t s) {
+  if constexpr (kStage < kVRefill) {
+    const size_t lds = vstage_type(kStage) == kVEvap ? lds_bytes(0, L.block, kXsNone, 0)
+                                                     : lds_bytes(L.n_targets, L.block, kXsColumns, 0);
+    hipLaunchKernelGGL((k_vertex<kStage, kExt>), dim3(grid), dim3(L.block), lds, s, a, v);
+    launch_vertex_stage<kExt, kStage + 1>(L, a, v, grid, s);
+  } else {
+    hipLaunchKernelGGL(k_vertex_refill, dim3(grid), dim3(L.block), lds_bytes(L.n_targets, L.block, kXsColumns, 0), s,
+                       a, v);
+    hipLaunchKernelGGL(k_vertex_swap, dim3(1), dim3(64), 0, s, v);
+  }
+}
+
+static void launch_vertex_group(const LaunchDesc& L, const KernelArgs& a, const VertexArgs& v, unsigned grid,
+                                int cycles, hipStream_t s) {
+  for (int k = 0; k < cycles; ++k) {
+    switch (ext_of(L)) {
+      case 0: launch_vertex_stage<0, 0>(L, a, v, grid, s); break;
+      case kExtPhoton: launch_vertex_stage<kExtPhoton, 0>(L, a, v, grid, s); break;
+      case kExtHeavy: launch_vertex_stage<kExtHeavy, 0>(L, a, v, grid, s); break;
+      default: launch_vertex_stage<kExtPhoton | kExtHeavy, 0>(L, a, v, grid, s); break;
+    }
+  }
+}
+
+hipError_t launch_vertex(const LaunchDesc& L, const VertexBuf& vb, hipStream_t s) {
+  const KernelArgs a = kernel_args(L);
+  const uint32_t w = (uint32_t)(L.n < vb.window ? L.n : vb.window);
+  VertexArgs v;
+  v.slots = (VSlot*)vb.slots;
+  v.stacks = (StackEntry*)vb.stacks;
+  v.queues = vb.queues;
+  v.ctl = vb.ctl;
+  v.window = (uint32_t)vb.window;
+  hipLaunchKernelGGL(k_zero_counters, dim3((L.n_seg + 63) / 64), dim3(64), 0, s, L.segs, L.n_seg, L.queue,
+                     (uint32_t*)nullptr);
+  hipLaunchKernelGGL(k_vertex_init, dim3((w + 255) / 256), dim3(256), 0, s, v, w);
+  // grid-stride stages on at most two resident waves' worth of blocks
+  const unsigned need = (w + L.block - 1) / L.block, cap = (unsigned)(2 * L.persistent_blocks);
+  const unsigned grid = need < cap ? need : cap;
+  hipError_t e = hipSuccess;
+  // a group of cycles as one graph (kernel nodes only), built for this call's
+  // arguments, replayed group after group
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  if (vb.use_graph) {
+    e = hipStreamBeginCapture(vb.capture, hipStreamCaptureModeThreadLocal);
+    if (e == hipSuccess) {
+      launch_vertex_group(L, a, v, grid, vb.cycles_per_group, vb.capture);
+      e = hipStreamEndCapture(vb.capture, &graph);
+    }
+    if (e == hipSuccess) e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+    if (e != hipSuccess) {
+      if (graph) (void)hipGraphDestroy(graph);
+      return e;
+    }
+  }
+  // the host reads the done flag of a group while the next group runs (two
+  // flags, two events), so it waits at most one group of (then empty) cycles
+  // past the end
+  for (long g = 0;; ++g) {
+    if (exec) e = hipGraphLaunch(exec, s);
+    else launch_vertex_group(L, a, v, grid, vb.cycles_per_group, s);
+    if (e == hipSuccess) e = hipMemcpyAsync(vb.h_done + (g & 1), vb.ctl + 2, sizeof(uint32_t), hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipEventRecord(vb.ev[g & 1], s);
+    if (e != hipSuccess) break;
+    if (g == 0) continue;
+    if ((e = hipEventSynchronize(vb.ev[(g - 1) & 1])) != hipSuccess) break;
+    if (vb.h_done[(g - 1) & 1]) break;
+    if (g * vb.cycles_per_group > vb.max_cycles) {
+      e = hipErrorLaunchTimeOut;
+      break;
+    }
+  }
+  if (exec) {
+    // the last replay may still run: the executable graph goes once it is done
+    (void)hipStreamSynchronize(s);
+    (void)hipGraphExecDestroy(exec);
+    (void)hipGraphDestroy(graph);
+  }
+  return e != hipSuccess ? e : hipGetLastError();
 }
 
 }  // namespace INC_KERNEL_NS
