@@ -771,11 +771,14 @@ __device__ __forceinline__ void ring_flush(const uint32_t* buf, int fill, const 
 
 // Must be called by all lanes of the wave.  The wave's records are copied out
 // 64 at a time; within a group of 64 the lanes of each distinct segment
-// reserve their slots with one atomic and store contiguously.
+// reserve their slots with one atomic and store contiguously.  kRing: the
+// records go to the ring of `ring` instead (a separate instantiation of the
+// kernels, so that the others hold none of the ring's code and registers).
+template <bool kRing>
 __device__ __forceinline__ void writer_flush(uint32_t* buf, int& fill, const Segment* segs, const RingDev& ring) {
   if (fill == 0) return;
   __builtin_amdgcn_wave_barrier();
-  if (ring.tag || ring.done) {
+  if constexpr (kRing) {
     if (ring.done)
       ring_flush_device(buf, fill, ring);
     else
@@ -847,13 +850,13 @@ __device__ __forceinline__ void writer_flush(uint32_t* buf, int& fill, const Seg
 // Must be called by all lanes of the wave.  ev: index of the event in its
 // segment; kind: species | stage << 8 | segment << 16.  kCap: records the
 // wave's buffer holds.
-template <int kCap = kWriterCap>
+template <bool kRing, int kCap = kWriterCap>
 __device__ __forceinline__ void writer_append(uint32_t* buf, int& fill, const Segment* segs, const RingDev& ring,
                                               bool emit, uint32_t ev, uint32_t kind, float T, V3 u) {
   const uint64_t m = __ballot(emit);
   if (m == 0) return;
   const int cnt = __popcll(m);
-  if (fill + cnt > kCap) writer_flush(buf, fill, segs, ring);
+  if (fill + cnt > kCap) writer_flush<kRing>(buf, fill, segs, ring);
   if (emit) {
     uint32_t* r = buf + (fill + (int)rank_in(m)) * kRecWords;
     r[0] = ev;

@@ -141,6 +141,7 @@ __device__ __forceinline__ void put_hist_cascade(const KernelArgs& a, EventRef e
 // the wave loop advances every live lane by one flight segment together with
 // the tentative collision and kinematics it may end in, then the wave writes
 // the escaping particles through the compacted writer.
+template <bool kRing>
 __global__ void __launch_bounds__(256) k_cascade_plain(KernelArgs a) {
   extern __shared__ __align__(16) char lds[];
   stage_tables(lds, a, a.n_targets, kXsColumns);
@@ -204,14 +205,14 @@ __global__ void __launch_bounds__(256) k_cascade_plain(KernelArgs a) {
         live = false;
       }
     }
-    writer_append(wbuf, fill, a.segs, a.ring, em.on, er.local, kind_of(em.kind, er), em.T, em.u);
+    writer_append<kRing>(wbuf, fill, a.segs, a.ring, em.on, er.local, kind_of(em.kind, er), em.T, em.u);
   }
-  writer_flush(wbuf, fill, a.segs, a.ring);
+  writer_flush<kRing>(wbuf, fill, a.segs, a.ring);
 }
 
 // Plain evaporation kernel: one de-excitation per thread (Sec. 3.3), same
 // random stream continued after the cascade's draws.
-template <int kExt>
+template <int kExt, bool kRing>
 __global__ void __launch_bounds__(256) k_evap_plain(KernelArgs a) {
   extern __shared__ __align__(16) char lds[];
   stage_tables(lds, a, 0, kXsNone);
@@ -266,9 +267,9 @@ __global__ void __launch_bounds__(256) k_evap_plain(KernelArgs a) {
         ++nsec;
       }
     }
-    writer_append<kWriterCapEvap>(wbuf, fill, a.segs, a.ring, em.on, er.local, kind_of(em.kind, er), em.T, em.u);
+    writer_append<kRing, kWriterCapEvap>(wbuf, fill, a.segs, a.ring, em.on, er.local, kind_of(em.kind, er), em.T, em.u);
   }
-  writer_flush(wbuf, fill, a.segs, a.ring);
+  writer_flush<kRing>(wbuf, fill, a.segs, a.ring);
 }
 
 // Persistent kernels.  Every wave keeps 64 events in flight; finished lanes
@@ -314,7 +315,7 @@ struct OwnChunks {
 // current chunk, records whose cascade already ended the event (kMidFinal)
 // are skipped.  The random stream resumes after the cascade's draws, so the
 // results equal the fused kernel's whichever kernel runs this.
-template <int kCap, int kExt, class Src>
+template <int kCap, int kExt, bool kRing, class Src>
 __device__ __forceinline__ void evap_events(const KernelArgs& a, const MassTab& smt, uint32_t* wbuf, int& fill,
                                             Src& src) {
   unsigned long long chunk_next = 0, chunk_end = 0;
@@ -379,7 +380,7 @@ __device__ __forceinline__ void evap_events(const KernelArgs& a, const MassTab& 
         ++nsec;
       }
     }
-    writer_append<kCap>(wbuf, fill, a.segs, a.ring, em.on, er.local, kind_of(em.kind, er), em.T, em.u);
+    writer_append<kRing, kCap>(wbuf, fill, a.segs, a.ring, em.on, er.local, kind_of(em.kind, er), em.T, em.u);
   }
 }
 
@@ -391,7 +392,7 @@ __device__ __forceinline__ void evap_events(const KernelArgs& a, const MassTab& 
 // evaporates its hand-overs in a second loop once its cascades are over.
 // kPairs: the NN table in LDS as node pairs (XsPairs) instead of columns.
 // kExt: the evaporation's optional channels (kExtPhoton, kExtHeavy bits).
-template <bool kFused, bool kPairs, int kExt>
+template <bool kFused, bool kPairs, int kExt, bool kRing>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) k_persistent(KernelArgs a) {
   using XS = typename std::conditional<kPairs, XsPairs, XsLds>::type;
   constexpr int kLayout = kPairs ? kXsPairs : kXsColumns;
@@ -565,7 +566,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) k
         st = ns;
       }
     }
-    writer_append(wbuf, fill, a.segs, a.ring, em.on, er.local, kind_of(em.kind, er), em.T, em.u);
+    writer_append<kRing>(wbuf, fill, a.segs, a.ring, em.on, er.local, kind_of(em.kind, er), em.T, em.u);
   }
   if (!kFused) {
     // Staged mode: this wave's cascades are over and no event is left to
@@ -576,15 +577,15 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) k
     __builtin_amdgcn_s_setprio(0);
     __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
     OwnChunks src = {own_list, own_count, 0};
-    evap_events<kWriterCap, kExt>(a, smt, wbuf, fill, src);
+    evap_events<kWriterCap, kExt, kRing>(a, smt, wbuf, fill, src);
   }
-  writer_flush(wbuf, fill, a.segs, a.ring);
+  writer_flush<kRing>(wbuf, fill, a.segs, a.ring);
 }
 
 // Staged mode, second kernel: the evaporation of the handed-over events the
 // cascade kernel's waves did not evaporate themselves (the chunks listed
 // after the hand-over records), as a persistent work-queue kernel.
-template <int kExt>
+template <int kExt, bool kRing>
 __global__ void __launch_bounds__(256) k_evap_persistent(KernelArgs a) {
   // usually nothing is left: the cascade waves evaporated what they handed over
   uint32_t* left = (uint32_t*)(a.mid + a.n);
@@ -596,8 +597,8 @@ __global__ void __launch_bounds__(256) k_evap_persistent(KernelArgs a) {
   uint32_t* wbuf = (uint32_t*)(lds + sizeof(MassTab)) + (threadIdx.x / 64) * (kWriterCapEvap * kRecWords);
   int fill = 0;
   LeftChunks src = {left, count};
-  evap_events<kWriterCapEvap, kExt>(a, smt, wbuf, fill, src);
-  writer_flush(wbuf, fill, a.segs, a.ring);
+  evap_events<kWriterCapEvap, kExt, kRing>(a, smt, wbuf, fill, src);
+  writer_flush<kRing>(wbuf, fill, a.segs, a.ring);
 }
 
 // Evaporation alone (Sec. 2.4) of given excited nuclei: each nucleus becomes a
@@ -841,7 +842,7 @@ __global__ void __launch_bounds__(256) k_vertex(KernelArgs a, VertexArgs v) {
             ++nsec;
           }
         }
-        writer_append<kCap>(wbuf, fill, a.segs, a.ring, em.on, er.local, kind_of(em.kind, er), em.T, em.u);
+        writer_append<false, kCap>(wbuf, fill, a.segs, a.ring, em.on, er.local, kind_of(em.kind, er), em.T, em.u);
       }
     } else {
       const NucTab& nt = snt[live ? tgt : 0];
@@ -862,7 +863,7 @@ __global__ void __launch_bounds__(256) k_vertex(KernelArgs a, VertexArgs v) {
               act = false;
             }
           }
-          writer_append(wbuf, fill, a.segs, a.ring, em.on, er.local, kind_of(em.kind, er), em.T, em.u);
+          writer_append<false>(wbuf, fill, a.segs, a.ring, em.on, er.local, kind_of(em.kind, er), em.T, em.u);
         }
       } else if constexpr (kType == kVTent) {
         if (live) next = tent_step(c, rng, nt, sxs, a.opt) == kStKin ? kVKin : kVFlight;
@@ -876,7 +877,7 @@ __global__ void __launch_bounds__(256) k_vertex(KernelArgs a, VertexArgs v) {
     if (live && next != kVFree) vstore(v.slots[slot], c, rng, nu, er, T0, Ex_casc, tgt, nsec);
     vpush<kStage>(v, live, next, cur, slot);
   }
-  writer_flush(wbuf, fill, a.segs, a.ring);
+  writer_flush<false>(wbuf, fill, a.segs, a.ring);
 }
 
 // REFILL: every freed slot takes the next event of the launch (in start
@@ -976,11 +977,11 @@ int stack_levels(int mode, int n_targets, int block, int waves_per_cu, int xs_la
   const size_t base = lds_bytes(n_targets, block, xs_layout, 0);
   int occ = 0;
   const bool pairs = xs_layout == kXsPairs;
-  const void* fn = mode == INC_MODE_PLAIN        ? (const void*)k_cascade_plain
-                   : mode == INC_MODE_PERSISTENT ? (pairs ? (const void*)k_persistent<true, true, false>
-                                                          : (const void*)k_persistent<true, false, false>)
-                                                 : (pairs ? (const void*)k_persistent<false, true, false>
-                                                          : (const void*)k_persistent<false, false, false>);
+  const void* fn = mode == INC_MODE_PLAIN        ? (const void*)k_cascade_plain<false>
+                   : mode == INC_MODE_PERSISTENT ? (pairs ? (const void*)k_persistent<true, true, 0, false>
+                                                          : (const void*)k_persistent<true, false, 0, false>)
+                                                 : (pairs ? (const void*)k_persistent<false, true, 0, false>
+                                                          : (const void*)k_persistent<false, false, 0, false>);
   if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, fn, block, base) != hipSuccess || occ < 1) return 0;
   int blocks = occ;
   if (mode != INC_MODE_PLAIN) {
@@ -996,7 +997,7 @@ int stack_levels(int mode, int n_targets, int block, int waves_per_cu, int xs_la
 
 int evap_blocks_per_cu(int block) {
   int occ = 0;
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, (const void*)k_evap_persistent<0>, block,
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, (const void*)k_evap_persistent<0, false>, block,
                                                    lds_bytes(0, block, kXsNone, 0)) != hipSuccess ||
       occ < 1)
     return 1;
@@ -1036,27 +1037,29 @@ static KernelArgs kernel_args(const LaunchDesc& L) {
   return a;
 }
 
-// The evaporation options' instantiations (kExt != 0) take the columns layout.
-template <int kExt>
+// The evaporation options' instantiations (kExt != 0) and the ring's (kRing)
+// take the columns layout.
+template <int kExt, bool kRing>
 static void launch_ext(const LaunchDesc& L, const KernelArgs& a, hipStream_t s) {
   const int block = L.block;
   if (L.mode == INC_MODE_PLAIN) {
     const unsigned grid = (unsigned)((L.n + block - 1) / block);
-    hipLaunchKernelGGL(k_cascade_plain, dim3(grid), dim3(block),
+    hipLaunchKernelGGL(k_cascade_plain<kRing>, dim3(grid), dim3(block),
                        lds_bytes(L.n_targets, block, kXsColumns, L.stack_lds), s, a);
-    hipLaunchKernelGGL(k_evap_plain<kExt>, dim3(grid), dim3(block), lds_bytes(0, block, kXsNone, 0), s, a);
+    hipLaunchKernelGGL((k_evap_plain<kExt, kRing>), dim3(grid), dim3(block), lds_bytes(0, block, kXsNone, 0), s, a);
     return;
   }
+  constexpr bool kCols = kExt != 0 || kRing;
   const dim3 grid(L.persistent_blocks);
-  const size_t lds = lds_bytes(L.n_targets, block, L.xs_pairs && kExt == 0 ? kXsPairs : kXsColumns, L.stack_lds);
+  const size_t lds = lds_bytes(L.n_targets, block, L.xs_pairs && !kCols ? kXsPairs : kXsColumns, L.stack_lds);
   if (L.mode == INC_MODE_STAGED) {
-    if (kExt == 0 && L.xs_pairs) hipLaunchKernelGGL((k_persistent<false, true, 0>), grid, dim3(block), lds, s, a);
-    else hipLaunchKernelGGL((k_persistent<false, false, kExt>), grid, dim3(block), lds, s, a);
-    hipLaunchKernelGGL(k_evap_persistent<kExt>, dim3(L.evap_blocks), dim3(block), lds_bytes(0, block, kXsNone, 0), s,
-                       a);
+    if (!kCols && L.xs_pairs) hipLaunchKernelGGL((k_persistent<false, true, 0, false>), grid, dim3(block), lds, s, a);
+    else hipLaunchKernelGGL((k_persistent<false, false, kExt, kRing>), grid, dim3(block), lds, s, a);
+    hipLaunchKernelGGL((k_evap_persistent<kExt, kRing>), dim3(L.evap_blocks), dim3(block),
+                       lds_bytes(0, block, kXsNone, 0), s, a);
   } else {
-    if (kExt == 0 && L.xs_pairs) hipLaunchKernelGGL((k_persistent<true, true, 0>), grid, dim3(block), lds, s, a);
-    else hipLaunchKernelGGL((k_persistent<true, false, kExt>), grid, dim3(block), lds, s, a);
+    if (!kCols && L.xs_pairs) hipLaunchKernelGGL((k_persistent<true, true, 0, false>), grid, dim3(block), lds, s, a);
+    else hipLaunchKernelGGL((k_persistent<true, false, kExt, kRing>), grid, dim3(block), lds, s, a);
   }
 }
 
@@ -1066,11 +1069,14 @@ hipError_t launch_events(const LaunchDesc& L, hipStream_t s) {
   const KernelArgs a = kernel_args(L);
   hipLaunchKernelGGL(k_zero_counters, dim3((L.n_seg + 63) / 64), dim3(64), 0, s, L.segs, L.n_seg, L.queue,
                      L.mode == INC_MODE_STAGED ? (uint32_t*)(L.mid + L.n) : nullptr);
+  const bool ring = L.ring.tag || L.ring.done;
   switch (ext_of(L)) {
-    case 0: launch_ext<0>(L, a, s); break;
-    case kExtPhoton: launch_ext<kExtPhoton>(L, a, s); break;
-    case kExtHeavy: launch_ext<kExtHeavy>(L, a, s); break;
-    default: launch_ext<kExtPhoton | kExtHeavy>(L, a, s); break;
+    case 0: ring ? launch_ext<0, true>(L, a, s) : launch_ext<0, false>(L, a, s); break;
+    case kExtPhoton: ring ? launch_ext<kExtPhoton, true>(L, a, s) : launch_ext<kExtPhoton, false>(L, a, s); break;
+    case kExtHeavy: ring ? launch_ext<kExtHeavy, true>(L, a, s) : launch_ext<kExtHeavy, false>(L, a, s); break;
+    default:
+      ring ? launch_ext<kExtPhoton | kExtHeavy, true>(L, a, s) : launch_ext<kExtPhoton | kExtHeavy, false>(L, a, s);
+      break;
   }
   return hipGetLastError();
 }
@@ -1083,10 +1089,10 @@ hipError_t launch_evaporation(const LaunchDesc& L, const ExcitedDesc& x, hipStre
   const dim3 grid(L.evap_blocks), block(L.block);
   const size_t lds = lds_bytes(0, L.block, kXsNone, 0);
   switch (ext_of(L)) {
-    case 0: hipLaunchKernelGGL(k_evap_persistent<0>, grid, block, lds, s, a); break;
-    case kExtPhoton: hipLaunchKernelGGL(k_evap_persistent<kExtPhoton>, grid, block, lds, s, a); break;
-    case kExtHeavy: hipLaunchKernelGGL(k_evap_persistent<kExtHeavy>, grid, block, lds, s, a); break;
-    default: hipLaunchKernelGGL(k_evap_persistent<kExtPhoton | kExtHeavy>, grid, block, lds, s, a); break;
+    case 0: hipLaunchKernelGGL((k_evap_persistent<0, false>), grid, block, lds, s, a); break;
+    case kExtPhoton: hipLaunchKernelGGL((k_evap_persistent<kExtPhoton, false>), grid, block, lds, s, a); break;
+    case kExtHeavy: hipLaunchKernelGGL((k_evap_persistent<kExtHeavy, false>), grid, block, lds, s, a); break;
+    default: hipLaunchKernelGGL((k_evap_persistent<kExtPhoton | kExtHeavy, false>), grid, block, lds, s, a); break;
   }
   return hipGetLastError();
 }
