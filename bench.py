@@ -670,7 +670,7 @@ def main(argv=None):
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--events", type=int, default=2_000_000, help="events per step (split O/Ca)")
     ap.add_argument("--mode", default="staged", choices=["staged", "persistent", "plain"])
-    ap.add_argument("--inflight", type=int, default=2,
+    ap.add_argument("--inflight", type=int, default=3,
                     help="batches on the device at once in the timed steps (each with its own context, "
                          "buffers and stream); the roofline's kernel time is always one batch at a time")
     ap.add_argument("--cpu-sample", type=int, default=1_000_000)

@@ -77,7 +77,7 @@ typedef struct {
   int evap_threshold;    /* persistent kernel: lanes waiting in a state that */
   int tent_threshold;    /* make a wave run that state's step next (1..64): */
   int kin_threshold;     /* evaporation, tentative collision, kinematics     */
-  int waves_per_cu;      /* persistent kernel: resident waves per CU         */
+  int waves_per_cu;      /* persistent kernel: resident waves per CU (0 = 16)*/
   int stack_levels;      /* entries of each lane's LIFO kept in LDS (deeper  */
                          /* ones in private memory): 0 = as many as fit     */
                          /* beside the tables at the launch's occupancy, up */

@@ -40,7 +40,7 @@ from typing import Optional
 import numpy as np
 
 DEFAULT_DIMENSIONS = {
-    "launch": tuple(dict(block_size=b, waves_per_cu=w) for b in (128, 256) for w in (8, 12)),
+    "launch": tuple(dict(block_size=b, waves_per_cu=w) for b in (128, 256) for w in (8, 12, 16)),
     # (kinematics, tentative collision, flight start) lane thresholds
     "thresholds": tuple(dict(kin_threshold=k, tent_threshold=t, start_threshold=s)
                         for k, t, s in ((24, 24, 8), (24, 32, 8), (16, 32, 8), (16, 16, 8), (24, 12, 4), (16, 8, 8))),

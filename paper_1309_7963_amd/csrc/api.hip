@@ -349,7 +349,7 @@ int inc_ctx_create(const inc_nucleus* targets, int n_targets, const inc_options*
   c->tent_threshold = o.tent_threshold ? o.tent_threshold : 24;
   c->kin_threshold = o.kin_threshold ? o.kin_threshold : 24;
   c->start_threshold = o.start_threshold ? o.start_threshold : 8;
-  c->waves_per_cu = o.waves_per_cu ? o.waves_per_cu : 12;
+  c->waves_per_cu = o.waves_per_cu ? o.waves_per_cu : 16;
   int amax = 0, zmax = 0;
   for (int t = 0; t < n_targets; ++t) {
     c->AZ[2 * t] = targets[t].A;

@@ -384,8 +384,10 @@ __device__ __forceinline__ void evap_events(const KernelArgs& a, const MassTab& 
   }
 }
 
-// 3 waves per SIMD (<= 168 VGPRs): the lane scheduler needs many events in
-// flight per CU more than it needs extra registers.
+// 4 waves per SIMD (<= 128 VGPRs, 16 per CU): the lane scheduler needs many
+// events in flight per CU more than it needs extra registers (measured: 3
+// waves per SIMD at 138 VGPRs took 12.3 ms for the 2x10^6-event batch, 4 at
+// 128 VGPRs with one VGPR spilled 11.1 ms).
 // kFused: the evaporation runs in the same loop as a fifth lane state;
 // otherwise (staged mode) the loop hands each finished cascade over and has
 // no evaporation state, which leaves it fewer live registers; the wave
@@ -393,7 +395,7 @@ __device__ __forceinline__ void evap_events(const KernelArgs& a, const MassTab& 
 // kPairs: the NN table in LDS as node pairs (XsPairs) instead of columns.
 // kExt: the evaporation's optional channels (kExtPhoton, kExtHeavy bits).
 template <bool kFused, bool kPairs, int kExt, bool kRing>
-__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) k_persistent(KernelArgs a) {
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) k_persistent(KernelArgs a) {
   using XS = typename std::conditional<kPairs, XsPairs, XsLds>::type;
   constexpr int kLayout = kPairs ? kXsPairs : kXsColumns;
   extern __shared__ __align__(16) char lds[];
