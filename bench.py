@@ -287,8 +287,8 @@ def _workloads(n_events: int):
 
 
 def _time_gpu(w, mode, steps, warmup, seed=1, inflight=1, **ctx_opts):
-    """Time `steps` batches of workload w (after `warmup` untimed ones), each
-    on new event ids.  inflight = 1: one batch at a time on torch's current
+    """Time `steps` batches of workload w (after `warmup` untimed ones, at
+    least one per in-flight context), each on new event ids.  inflight = 1: one batch at a time on torch's current
     stream, launch_ms = each launch's duration (HIP events on that stream).
     inflight = k > 1: batch i goes to context, output buffers and stream
     i mod k (default priority), so up to k batches are on the device at once
@@ -304,7 +304,10 @@ def _time_gpu(w, mode, steps, warmup, seed=1, inflight=1, **ctx_opts):
     n = int(T0.shape[0])
     outs = [inc.DeviceOutput.allocate(n, ctxs[0].default_capacity(n)) for _ in range(inflight)]
     streams = [torch.cuda.current_stream()] if inflight == 1 else [torch.cuda.Stream() for _ in range(inflight)]
-    for k in range(warmup):
+    # every in-flight context gets at least one untimed launch, which
+    # allocates its start-order and hand-over buffers outside the timed steps
+    n_warm = max(warmup, inflight)
+    for k in range(n_warm):
         i = k % inflight
         ctxs[i].simulate(T0, seed=seed, target_idx=tidx, mode=mode, out=outs[i], first_event_id=k * n,
                          stream=streams[i])
@@ -315,7 +318,7 @@ def _time_gpu(w, mode, steps, warmup, seed=1, inflight=1, **ctx_opts):
     for k in range(steps):
         i = k % inflight
         starts[k].record(streams[i])
-        ctxs[i].simulate(T0, seed=seed, target_idx=tidx, mode=mode, out=outs[i], first_event_id=(warmup + k) * n,
+        ctxs[i].simulate(T0, seed=seed, target_idx=tidx, mode=mode, out=outs[i], first_event_id=(n_warm + k) * n,
                          stream=streams[i])
         ends[k].record(streams[i])
     torch.cuda.synchronize()

@@ -101,6 +101,17 @@ struct Opts {
   int evap_threshold, tent_threshold, kin_threshold, start_threshold;
   int same_stream;       // every event uses its segment's first id
 };
+// The test hooks of Opts (fixed impact parameter, constant cross-section, no
+// Pauli blocking, stop after the first collision) at their neutral values, as
+// compile-time constants: the kernels of contexts that set none of them are
+// instantiated with this type, so that they hold none of the hooks' code or
+// registers.
+struct NoHooks {
+  static constexpr float fixed_b = -1.0f;
+  static constexpr float const_sigma_mb = 0.0f;
+  static constexpr int no_pauli = 0;
+  static constexpr int stop_after_first = 0;
+};
 
 // Evaporation constants of one nucleus (A, Z) (Sec. 2.4), computed once per
 // context from the binding table: per channel j the separation energy S_j
@@ -355,8 +366,8 @@ __device__ __forceinline__ float xs_lerp(const float* col, int k, float f) {
 // Majorant flight cross-sections (fm^2) for a particle of species sp with
 // excess energy eps: smallest own momentum (at the smallest E_F) against the
 // largest Fermi momentum of each target species.
-template <class XS>
-__device__ __forceinline__ void majorant(const NucTab& nt, const XS& xs, const Opts& o, int sp, float eps,
+template <class XS, class O>
+__device__ __forceinline__ void majorant(const NucTab& nt, const XS& xs, const O& o, int sp, float eps,
                                          float& sh0, float& sh1) {
   const float mx = nucleon_mass(sp);
   const float T = eps + nt.EFmin[sp];

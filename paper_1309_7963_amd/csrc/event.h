@@ -113,9 +113,9 @@ __device__ __forceinline__ void cascade_init(Cascade& c, const NucTab& nt) {
 
 // Entry (reading): impact parameter uniform over the disc of radius R,
 // incidence along +z, inward refraction at R; then the first optical depth.
-template <class XS>
+template <class XS, class O>
 __device__ __forceinline__ void cascade_entry(Cascade& c, Rng& rng, const NucTab& nt, const XS& xs,
-                                              const Opts& o, float T0) {
+                                              const O& o, float T0) {
   const float ub = rng.next();
   const float uphi = rng.next();
   float b, z;
@@ -150,9 +150,9 @@ __device__ __forceinline__ void capture(Cascade& c, float eps, int sp) {
 
 // Take the next particle from the stack or end the cascade.  Returns false
 // when the cascade is over.
-template <class XS>
+template <class XS, class O>
 __device__ __forceinline__ bool next_particle(Cascade& c, StackEntry* stk, Rng& rng, const NucTab& nt,
-                                              const XS& xs, const Opts& o) {
+                                              const XS& xs, const O& o) {
   if (c.top == 0) return false;
   pop(stk, c);
   majorant(nt, xs, o, c.sp, c.eps, c.sh0, c.sh1);
@@ -175,9 +175,9 @@ __device__ __forceinline__ float flight_weight(const Cascade& c, const NucTab& n
 // nucleus (impact parameter, refraction, majorant, first optical depth);
 // otherwise the particle in hand has escaped and the next one comes from the
 // stack (kStDone when it is empty).  Draws at most 3 uniforms.
-template <class XS>
+template <class XS, class O>
 __device__ __forceinline__ int start_step(Cascade& c, StackEntry* stk, Rng& rng, const NucTab& nt, const XS& xs,
-                                          const Opts& o, float T0) {
+                                          const O& o, float T0) {
   rng.ensure(3);
   if (!c.started) {
     cascade_entry(c, rng, nt, xs, o, T0);
@@ -257,9 +257,9 @@ __device__ __forceinline__ int flight_core(Cascade& c, StackEntry* stk, const Nu
 // not started, one segment, and after an escape the next particle.  Returns
 // kStFlight, kStTent or kStDone; a transparent pass returns kStFlight with the
 // entry left for the next call.
-template <class XS>
+template <class XS, class O>
 __device__ __forceinline__ int flight_step(Cascade& c, StackEntry* stk, Rng& rng, const NucTab& nt, const XS& xs,
-                                           const Opts& o, float T0, Emit& em) {
+                                           const O& o, float T0, Emit& em) {
   if (!c.started) start_step(c, stk, rng, nt, xs, o, T0);
   int st = flight_core(c, stk, nt, em);
   if (st == kStStart) st = c.started ? start_step(c, stk, rng, nt, xs, o, T0) : kStFlight;
@@ -293,8 +293,8 @@ __device__ __forceinline__ Pair pair_of(const Cascade& c, const NucTab& nt, int 
 // (Sec. 2.2), accept with sigma(p_lab) / sigma_hat.  A rejected (null)
 // collision draws a fresh optical depth and the flight goes on (-> FLIGHT);
 // an accepted one goes to KIN.  Draws at most 6 uniforms.
-template <class XS>
-__device__ __forceinline__ int tent_step(Cascade& c, Rng& rng, const NucTab& nt, const XS& xs, const Opts& o) {
+template <class XS, class O>
+__device__ __forceinline__ int tent_step(Cascade& c, Rng& rng, const NucTab& nt, const XS& xs, const O& o) {
   rng.ensure(6);
   const int s = c.shell;
   c.hsh = c.hsh * 3u + (uint32_t)(s + 1);
@@ -326,9 +326,9 @@ __device__ __forceinline__ int tent_step(Cascade& c, Rng& rng, const NucTab& nt,
 // boosts to the lab, Pauli test on both products, hole energy, cutoff
 // capture, LIFO push of the struck nucleon.  Returns the next state (kStDone
 // when the cascade is over).  Draws at most 4 uniforms.
-template <class XS>
+template <class XS, class O>
 __device__ __forceinline__ int kin_step(Cascade& c, StackEntry* stk, Rng& rng, const NucTab& nt, const XS& xs,
-                                        const Opts& o) {
+                                        const O& o) {
   rng.ensure(4);
   const int s = c.shell;
   const int y = c.ytgt;

@@ -141,8 +141,10 @@ __device__ __forceinline__ void put_hist_cascade(const KernelArgs& a, EventRef e
 // the wave loop advances every live lane by one flight segment together with
 // the tentative collision and kinematics it may end in, then the wave writes
 // the escaping particles through the compacted writer.
-template <bool kRing>
+template <bool kRing, bool kHooks>
 __global__ void __launch_bounds__(256) k_cascade_plain(KernelArgs a) {
+  typename std::conditional<kHooks, Opts, NoHooks>::type op{};
+  if constexpr (kHooks) op = a.opt;
   extern __shared__ __align__(16) char lds[];
   stage_tables(lds, a, a.n_targets, kXsColumns);
   const NucTab* snt = (const NucTab*)lds;
@@ -183,9 +185,9 @@ __global__ void __launch_bounds__(256) k_cascade_plain(KernelArgs a) {
     Emit em;
     em.on = false;
     if (live) {
-      int st = flight_step(c, stk, rng, nt, sxs, a.opt, T0, em);
-      if (st == kStTent) st = tent_step(c, rng, nt, sxs, a.opt);
-      if (st == kStKin) st = kin_step(c, stk, rng, nt, sxs, a.opt);
+      int st = flight_step(c, stk, rng, nt, sxs, op, T0, em);
+      if (st == kStTent) st = tent_step(c, rng, nt, sxs, op);
+      if (st == kStKin) st = kin_step(c, stk, rng, nt, sxs, op);
       if (st == kStDone) {
         const Nucleus r = cascade_residual(c, nt, T0);
         put_hist_cascade(a, er, c);
@@ -394,9 +396,11 @@ __device__ __forceinline__ void evap_events(const KernelArgs& a, const MassTab& 
 // evaporates its hand-overs in a second loop once its cascades are over.
 // kPairs: the NN table in LDS as node pairs (XsPairs) instead of columns.
 // kExt: the evaporation's optional channels (kExtPhoton, kExtHeavy bits).
-template <bool kFused, bool kPairs, int kExt, bool kRing>
+template <bool kFused, bool kPairs, int kExt, bool kRing, bool kHooks>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) k_persistent(KernelArgs a) {
   using XS = typename std::conditional<kPairs, XsPairs, XsLds>::type;
+  typename std::conditional<kHooks, Opts, NoHooks>::type op{};
+  if constexpr (kHooks) op = a.opt;
   constexpr int kLayout = kPairs ? kXsPairs : kXsColumns;
   extern __shared__ __align__(16) char lds[];
   stage_tables(lds, a, a.n_targets, kLayout);
@@ -530,9 +534,9 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) k
       const NucTab& nt = snt[tgt];
       int ns;
       if (run == kStFlight) ns = flight_core(c, stk, nt, em);
-      else if (run == kStStart) ns = start_step(c, stk, rng, nt, sxs, a.opt, T0);
-      else if (run == kStTent) ns = tent_step(c, rng, nt, sxs, a.opt);
-      else ns = kin_step(c, stk, rng, nt, sxs, a.opt);
+      else if (run == kStStart) ns = start_step(c, stk, rng, nt, sxs, op, T0);
+      else if (run == kStTent) ns = tent_step(c, rng, nt, sxs, op);
+      else ns = kin_step(c, stk, rng, nt, sxs, op);
       if (em.on) ++nsec;
       if (ns == kStDone) {
         nu = cascade_residual(c, nt, T0);
@@ -979,11 +983,11 @@ int stack_levels(int mode, int n_targets, int block, int waves_per_cu, int xs_la
   const size_t base = lds_bytes(n_targets, block, xs_layout, 0);
   int occ = 0;
   const bool pairs = xs_layout == kXsPairs;
-  const void* fn = mode == INC_MODE_PLAIN        ? (const void*)k_cascade_plain<false>
-                   : mode == INC_MODE_PERSISTENT ? (pairs ? (const void*)k_persistent<true, true, 0, false>
-                                                          : (const void*)k_persistent<true, false, 0, false>)
-                                                 : (pairs ? (const void*)k_persistent<false, true, 0, false>
-                                                          : (const void*)k_persistent<false, false, 0, false>);
+  const void* fn = mode == INC_MODE_PLAIN        ? (const void*)k_cascade_plain<false, false>
+                   : mode == INC_MODE_PERSISTENT ? (pairs ? (const void*)k_persistent<true, true, 0, false, false>
+                                                          : (const void*)k_persistent<true, false, 0, false, false>)
+                                                 : (pairs ? (const void*)k_persistent<false, true, 0, false, false>
+                                                          : (const void*)k_persistent<false, false, 0, false, false>);
   if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, fn, block, base) != hipSuccess || occ < 1) return 0;
   int blocks = occ;
   if (mode != INC_MODE_PLAIN) {
@@ -1039,30 +1043,46 @@ static KernelArgs kernel_args(const LaunchDesc& L) {
   return a;
 }
 
-// The evaporation options' instantiations (kExt != 0) and the ring's (kRing)
-// take the columns layout.
-template <int kExt, bool kRing>
+// The kernels of the default model without test hooks carry neither the
+// hooks (kHooks) nor the ring (kRing); a context with hooks set, or a ring
+// launch, takes the instances with the runtime hooks.  The evaporation
+// options' instantiations (kExt != 0), the hooks' and the ring's take the
+// columns layout.
+template <int kExt, bool kRing, bool kHooks>
 static void launch_ext(const LaunchDesc& L, const KernelArgs& a, hipStream_t s) {
   const int block = L.block;
   if (L.mode == INC_MODE_PLAIN) {
     const unsigned grid = (unsigned)((L.n + block - 1) / block);
-    hipLaunchKernelGGL(k_cascade_plain<kRing>, dim3(grid), dim3(block),
+    hipLaunchKernelGGL((k_cascade_plain<kRing, kHooks>), dim3(grid), dim3(block),
                        lds_bytes(L.n_targets, block, kXsColumns, L.stack_lds), s, a);
     hipLaunchKernelGGL((k_evap_plain<kExt, kRing>), dim3(grid), dim3(block), lds_bytes(0, block, kXsNone, 0), s, a);
     return;
   }
-  constexpr bool kCols = kExt != 0 || kRing;
+  constexpr bool kCols = kExt != 0 || kRing || kHooks;
   const dim3 grid(L.persistent_blocks);
   const size_t lds = lds_bytes(L.n_targets, block, L.xs_pairs && !kCols ? kXsPairs : kXsColumns, L.stack_lds);
   if (L.mode == INC_MODE_STAGED) {
-    if (!kCols && L.xs_pairs) hipLaunchKernelGGL((k_persistent<false, true, 0, false>), grid, dim3(block), lds, s, a);
-    else hipLaunchKernelGGL((k_persistent<false, false, kExt, kRing>), grid, dim3(block), lds, s, a);
+    if (!kCols && L.xs_pairs)
+      hipLaunchKernelGGL((k_persistent<false, true, 0, false, false>), grid, dim3(block), lds, s, a);
+    else
+      hipLaunchKernelGGL((k_persistent<false, false, kExt, kRing, kHooks>), grid, dim3(block), lds, s, a);
     hipLaunchKernelGGL((k_evap_persistent<kExt, kRing>), dim3(L.evap_blocks), dim3(block),
                        lds_bytes(0, block, kXsNone, 0), s, a);
   } else {
-    if (!kCols && L.xs_pairs) hipLaunchKernelGGL((k_persistent<true, true, 0, false>), grid, dim3(block), lds, s, a);
-    else hipLaunchKernelGGL((k_persistent<true, false, kExt, kRing>), grid, dim3(block), lds, s, a);
+    if (!kCols && L.xs_pairs)
+      hipLaunchKernelGGL((k_persistent<true, true, 0, false, false>), grid, dim3(block), lds, s, a);
+    else
+      hipLaunchKernelGGL((k_persistent<true, false, kExt, kRing, kHooks>), grid, dim3(block), lds, s, a);
   }
+}
+
+template <int kExt>
+static void launch_ext_out(const LaunchDesc& L, const KernelArgs& a, hipStream_t s) {
+  const bool ring = L.ring.tag || L.ring.done;
+  const bool hooks = L.opt.no_pauli || L.opt.stop_after_first || L.opt.const_sigma_mb > 0.0f || L.fixed_b_set;
+  if (ring) launch_ext<kExt, true, true>(L, a, s);
+  else if (hooks) launch_ext<kExt, false, true>(L, a, s);
+  else launch_ext<kExt, false, false>(L, a, s);
 }
 
 static int ext_of(const LaunchDesc& L) { return (L.photon ? kExtPhoton : 0) | (L.heavy ? kExtHeavy : 0); }
@@ -1071,14 +1091,11 @@ hipError_t launch_events(const LaunchDesc& L, hipStream_t s) {
   const KernelArgs a = kernel_args(L);
   hipLaunchKernelGGL(k_zero_counters, dim3((L.n_seg + 63) / 64), dim3(64), 0, s, L.segs, L.n_seg, L.queue,
                      L.mode == INC_MODE_STAGED ? (uint32_t*)(L.mid + L.n) : nullptr);
-  const bool ring = L.ring.tag || L.ring.done;
   switch (ext_of(L)) {
-    case 0: ring ? launch_ext<0, true>(L, a, s) : launch_ext<0, false>(L, a, s); break;
-    case kExtPhoton: ring ? launch_ext<kExtPhoton, true>(L, a, s) : launch_ext<kExtPhoton, false>(L, a, s); break;
-    case kExtHeavy: ring ? launch_ext<kExtHeavy, true>(L, a, s) : launch_ext<kExtHeavy, false>(L, a, s); break;
-    default:
-      ring ? launch_ext<kExtPhoton | kExtHeavy, true>(L, a, s) : launch_ext<kExtPhoton | kExtHeavy, false>(L, a, s);
-      break;
+    case 0: launch_ext_out<0>(L, a, s); break;
+    case kExtPhoton: launch_ext_out<kExtPhoton>(L, a, s); break;
+    case kExtHeavy: launch_ext_out<kExtHeavy>(L, a, s); break;
+    default: launch_ext_out<kExtPhoton | kExtHeavy>(L, a, s); break;
   }
   return hipGetLastError();
 }
