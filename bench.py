@@ -304,9 +304,10 @@ def _time_gpu(w, mode, steps, warmup, seed=1, inflight=1, **ctx_opts):
     n = int(T0.shape[0])
     outs = [inc.DeviceOutput.allocate(n, ctxs[0].default_capacity(n)) for _ in range(inflight)]
     streams = [torch.cuda.current_stream()] if inflight == 1 else [torch.cuda.Stream() for _ in range(inflight)]
-    # every in-flight context gets at least one untimed launch, which
-    # allocates its start-order and hand-over buffers outside the timed steps
-    n_warm = max(warmup, inflight)
+    # with several batches in flight every context gets at least one untimed
+    # launch, which allocates its start-order and hand-over buffers outside
+    # the timed steps
+    n_warm = warmup if inflight == 1 else max(warmup, inflight)
     for k in range(n_warm):
         i = k % inflight
         ctxs[i].simulate(T0, seed=seed, target_idx=tidx, mode=mode, out=outs[i], first_event_id=k * n,
@@ -737,7 +738,7 @@ def main(argv=None):
         return 0
     if args.same_stream:
         w = wl["o16_200"]
-        e = _time_gpu(w, args.mode, args.steps, 0, same_stream=1)
+        e = _time_gpu(w, args.mode, args.steps, 0, same_stream=1)  # no warm-up: launch k replays id k n
         print(json.dumps(dict(same_stream=True, workload=w["label"], kernel=KERNELS[args.mode],
                               events_per_launch=e["n"], first_ids=[k * e["n"] for k in range(args.steps)],
                               launch_ms=e["launch_ms"])))
