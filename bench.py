@@ -240,17 +240,19 @@ def step_counts(res) -> dict:
     with an entry, a majorant and an optical depth; each null or blocked
     tentative collision draws a new optical depth; each accepted collision and
     each escape starts a new flight (majorant and optical depth) except the
-    one that ends its event; a retried (transparent) pass records nothing."""
+    one that ends its event (an event the segment guard ends has none); a
+    retried (transparent) pass records nothing."""
     n = len(res)
     tent = int(res["n_tent"].sum())
     coll = int(res["n_coll"].sum())
     evap = int(res["n_evap"].sum())
     passes = n + int(res["n_retry"].sum())
     escapes = int(res["n_sec"].sum()) - evap
-    return {"draw": int(res["n_draw"].sum()), "tau": passes + tent + escapes - n,
+    ended = n - int(np.count_nonzero(res["flags"] & 2))  # events ended by a collision or an escape
+    return {"draw": int(res["n_draw"].sum()), "tau": passes + tent + escapes - ended,
             "segment": int(res["n_seg"].sum()), "crossing": int(res["n_seg"].sum()) - tent,
             "tentative": tent, "kinematics": coll + int(res["n_pauli"].sum()), "collision": coll,
-            "majorant": passes + coll + escapes - n, "entry": passes, "escape": escapes,
+            "majorant": passes + coll + escapes - ended, "entry": passes, "escape": escapes,
             "evap_channels": evap + n, "evap_emit": evap}
 
 

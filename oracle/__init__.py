@@ -84,6 +84,7 @@ class Result(C.Structure):
         ("n_draw", C.c_int),
         ("first_z", C.c_double),
         ("sea", C.c_int * 2), ("sea_min", C.c_int), ("tent_shells", C.c_uint32),
+        ("n_tau", C.c_int), ("n_majorant", C.c_int),
     ]
 
 
@@ -101,6 +102,7 @@ RESULT_DTYPE = np.dtype(
         ("n_sec", "i4"), ("flags", "i4"), ("n_retry", "i4"), ("n_coll", "i4"),
         ("n_tent", "i4"), ("n_pauli", "i4"), ("n_seg", "i4"), ("n_evap", "i4"),
         ("n_draw", "i4"), ("first_z", "f8"), ("sea", "i4", 2), ("sea_min", "i4"), ("tent_shells", "u4"),
+        ("n_tau", "i4"), ("n_majorant", "i4"),
     ],
     align=True,
 )

@@ -581,6 +581,7 @@ struct Event {
 
   /* majorant for a flight of species x with excess energy eps (reading) */
   void set_majorant(const Particle& q) {
+    res.n_majorant++;
     const double mx = nucleon_mass(q.sp);
     double EFmin = nu.EF[q.sp][0];
     for (int i = 1; i < ORC_NSHELL; ++i) EFmin = std::min(EFmin, nu.EF[q.sp][i]);
@@ -593,6 +594,12 @@ struct Event {
       const double s_mb = opt.const_sigma_mb > 0 ? opt.const_sigma_mb : sigma_hat(q.sp == y, pmin);
       sh[y] = s_mb * kMbToFm2;
     }
+  }
+
+  /* optical depth of a new flight segment sequence (reading): -ln u */
+  double new_tau() {
+    res.n_tau++;
+    return -std::log(rng.next());
   }
 
   double weight(int y, int shell) const {
@@ -647,7 +654,7 @@ struct Event {
       refract(cur.d, n, T0, cur.eps + nu.EF[1][ORC_NSHELL - 1], kMassP);
     }
     set_majorant(cur);
-    double tau = -std::log(rng.next());
+    double tau = new_tau();
     bool have = true;
 
     while (have) {
@@ -699,7 +706,7 @@ struct Event {
         const double sig = (opt.const_sigma_mb > 0 ? opt.const_sigma_mb : sigma(like, plab / 1000.0)) * kMbToFm2;
         const double u_acc = rng.next();
         if (!(u_acc < sig / sh[y])) {
-          tau = -std::log(rng.next());
+          tau = new_tau();
           continue;
         }
         const double u_th = rng.next(), u_ph = rng.next();
@@ -713,7 +720,7 @@ struct Event {
         const CollisionOutcome oc = collision_outcome(nu, s, cur.sp, y, Txn, Ttn, Tt, !opt.no_pauli);
         if (oc.blocked) {
           res.n_pauli++;
-          tau = -std::log(rng.next());
+          tau = new_tau();
           continue;
         }
         /* accepted collision: the struck nucleon leaves the sea */
@@ -756,7 +763,7 @@ struct Event {
           stack.pop_back();
         }
         set_majorant(cur);
-        tau = -std::log(rng.next());
+        tau = new_tau();
         continue;
       }
       /* reach the boundary */
@@ -778,7 +785,7 @@ struct Event {
           cur = stack.back();
           stack.pop_back();
           set_majorant(cur);
-          tau = -std::log(rng.next());
+          tau = new_tau();
         }
       } else {
         if (refract(cur.d, n, T_from, cur.eps + nu.EF[cur.sp][dest], m)) cur.shell = dest;

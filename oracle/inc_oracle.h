@@ -78,6 +78,9 @@ typedef struct {
   uint32_t tent_shells;   /* h = 3 h + shell + 1 over the tentative collisions
                              in order, from h = 0 (mod 2^32): where they
                              happened, a fingerprint of the event's path      */
+  int n_tau;              /* optical depths drawn, over all passes (each new
+                             flight and each null or blocked collision)       */
+  int n_majorant;         /* flight majorants evaluated (each new flight)     */
 } orc_result;
 
 typedef struct {
