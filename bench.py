@@ -5,7 +5,7 @@ Default workload (one step): 10^6 events of 200 MeV p + 16O and 10^6 events of
 200 MeV p + 40Ca, synthetic inputs already resident in HBM, generated in the
 staged mode: the persistent cascade kernel, then the persistent evaporation
 kernel, back to back on one stream.  The timed steps are consecutive batches
-(each on new event ids) with four on the device at once, each with its own
+(each on new event ids) with three on the device at once, each with its own
 context, buffers and stream (--inflight), so that a batch's start fills the
 CUs its predecessor's end frees (a launch ends waiting for its slowest
 events); `value` is the whole job's events over its wall time, and
@@ -676,7 +676,7 @@ def main(argv=None):
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--events", type=int, default=2_000_000, help="events per step (split O/Ca)")
     ap.add_argument("--mode", default="staged", choices=["staged", "persistent", "plain"])
-    ap.add_argument("--inflight", type=int, default=4,
+    ap.add_argument("--inflight", type=int, default=3,
                     help="batches on the device at once in the timed steps (each with its own context, "
                          "buffers and stream); the roofline's kernel time is always one batch at a time")
     ap.add_argument("--cpu-sample", type=int, default=1_000_000)
