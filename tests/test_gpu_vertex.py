@@ -70,3 +70,23 @@ def test_vertex_window_validated():
             inc.Context([(16, 8)], vertex_window=bad)
     with pytest.raises(inc.IncError):
         inc.Context([(16, 8)], vertex_launch=2)
+
+
+def test_vertex_mode_is_not_offered_where_unsupported():
+    # the allocation-free entry point and the ring take the three kernel
+    # modes only; the vertex pipeline needs its own buffers
+    import torch
+
+    import paper_1309_7963_amd as inc
+
+    ctx = inc.Context([(16, 8)])
+    T0 = torch.full((1000,), 200.0, dtype=torch.float32, device="cuda")
+    out = inc.DeviceOutput.allocate(1000, ctx.default_capacity(1000))
+    with pytest.raises(inc.IncError) as e:
+        ctx.simulate_noalloc(T0, seed=1, out=out, mode="vertex")
+    assert e.value.code == inc.INC_ERR_ARG
+    ring = inc.Ring(ctx, slots=1 << 12, chunk=1 << 10)
+    with pytest.raises(inc.IncError):
+        ring.simulate(T0, seed=1, mode="vertex")
+    ring.close()
+    ctx.close()
