@@ -607,6 +607,10 @@ __device__ __forceinline__ float photon_sample_s(float Y, float u) {
 constexpr int kWriterCap = 128;      // records per wave buffer (cascade kernels)
 constexpr int kWriterCapEvap = 256;  // records per wave buffer (evaporation kernels)
 constexpr int kRecWords = 6;     // event, species | stage << 8 | segment << 16, T, ux, uy, uz
+// One append adds up to a record per lane after at most one flush, so a wave's
+// buffer must hold a full wave of records (a smaller one would overflow into
+// the next wave's LDS).
+static_assert(kWriterCap >= 64 && kWriterCapEvap >= 64, "writer buffer below one wave of records");
 
 // One segment of a launch: a request with its own event ids and output
 // buffers (all segments of a launch share the launch's random-stream key).
