@@ -144,12 +144,6 @@ typedef struct {
                          /* one replay of a graph captured for the call (0, */
                          /* default) or as separate kernel launches (1).     */
                          /* Results do not depend on it.                     */
-  int merge_lanes;       /* INC_MODE_STAGED: once no event is left to start, */
-                         /* a wave with at most this many live cascades     */
-                         /* hands them to other waves of its workgroup that */
-                         /* have free lanes, through a pool in the LDS left */
-                         /* beside the tables and LIFO levels (1..64; 0 =   */
-                         /* 16; -1 = never).  Results do not depend on it.   */
 } inc_options;
 
 /* One residual nucleus per event, 32 bytes: the excited nucleus the cascade
@@ -245,15 +239,6 @@ int inc_ctx_tables(const inc_ctx* ctx, float* host_out);
  * const_sigma_mb set, both sigma columns and their maxima hold that value.
  * Synchronous.  Returns INC_ERR_ARG for a NULL context or out-param. */
 int inc_ctx_xs_table(const inc_ctx* ctx, float* host_out, int* n_nodes, float* p_lo, float* p_hi);
-
-/* Diagnostic of the staged kernel's drain (the scheduling of Sec. 3 on this
- * hardware, see merge_lanes): *moved receives the number of events of the
- * context's last launch whose cascades ended in another wave than the one
- * that started them and were not already final, 0 when that launch was not
- * a staged launch on the context's own buffers (inc_simulate_dev; not the
- * allocation-free or ring calls).  Waits for the device.  Returns INC_ERR_ARG
- * for a NULL context or out-param. */
-int inc_ctx_moved_events(inc_ctx* ctx, unsigned long long* moved);
 
 /* Launch modes (Sec. 3.1-3.3 organise the work as one cascade, then one
  * de-excitation, per thread) */

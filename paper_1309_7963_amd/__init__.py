@@ -155,14 +155,6 @@ class Context:
         _lib.check(_lib.load().inc_ctx_tables(self._h, out.ctypes.data), "inc_ctx_tables")
         return out
 
-    def moved_events(self) -> int:
-        """Events of the context's last staged launch whose cascades ended in
-        another wave than the one that started them (inc_ctx_moved_events;
-        waits for the device)."""
-        v = C.c_ulonglong()
-        _lib.check(_lib.load().inc_ctx_moved_events(self._h, C.byref(v)), "inc_ctx_moved_events")
-        return int(v.value)
-
     def xs_table(self) -> dict:
         """The context's NN elastic table (inc_ctx_xs_table): node momenta
         p_lab (GeV/c, float64 from the float32 grid ends) and per column

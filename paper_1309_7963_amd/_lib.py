@@ -27,7 +27,6 @@ MODE_VERTEX = 3
 # exported symbols, in the order include/inc.h declares them
 SYMBOLS = (
     "inc_strerror", "inc_ctx_create", "inc_ctx_destroy", "inc_ctx_tables", "inc_ctx_xs_table",
-    "inc_ctx_moved_events",
     "inc_simulate_dev", "inc_simulate_dev_noalloc", "inc_evaporate_dev", "inc_simulate", "inc_server_create", "inc_server_destroy",
     "inc_server_submit", "inc_server_poll", "inc_server_wait", "inc_server_fetch",
     "inc_server_stats_get", "inc_server_stats_reset", "inc_server_hold", "inc_server_replay", "inc_ring_create",
@@ -56,7 +55,6 @@ class Options(C.Structure):
         ("heavy_fragments", C.c_int),
         ("vertex_window", C.c_int),
         ("vertex_launch", C.c_int),
-        ("merge_lanes", C.c_int),
     ]
 
 
@@ -170,8 +168,6 @@ def load():
         L.inc_ctx_xs_table.argtypes = [C.c_void_p, C.c_void_p, C.POINTER(C.c_int), C.POINTER(C.c_float),
                                        C.POINTER(C.c_float)]
         L.inc_ctx_xs_table.restype = C.c_int
-        L.inc_ctx_moved_events.argtypes = [C.c_void_p, C.POINTER(C.c_ulonglong)]
-        L.inc_ctx_moved_events.restype = C.c_int
         L.inc_simulate_dev.argtypes = [C.c_void_p, C.POINTER(Batch), C.POINTER(Output), C.c_void_p, C.c_int]
         L.inc_simulate_dev.restype = C.c_int
         L.inc_simulate_dev_noalloc.argtypes = [C.c_void_p, C.POINTER(Batch), C.POINTER(Output), C.c_void_p, C.c_int]

@@ -167,8 +167,6 @@ LaunchDesc launch_desc(const inc_ctx* ctx, size_t n, int mode, int max_blocks) {
   L.kin_threshold = ctx->kin_threshold;
   L.start_threshold = ctx->start_threshold;
   L.stack_lds = ctx->stack_lds[mode == INC_MODE_PLAIN ? 0 : 1];
-  L.merge_slots = mode == INC_MODE_STAGED ? ctx->merge_slots : 0;
-  L.merge_lanes = ctx->opt.merge_lanes ? ctx->opt.merge_lanes : kMergeLanesDefault;
   L.chunk = ctx->opt.chunk_events ? ctx->opt.chunk_events : kChunkEvents;
   L.xs_pairs = ctx->opt.table_layout;
   L.photon = ctx->opt.photon_evaporation;
@@ -253,7 +251,6 @@ int inc_launch_segments(inc_ctx* ctx, size_t n, const uint8_t* tidx, const float
     perm = order;
   }
   LaunchDesc L = launch_desc(ctx, n, mode, max_blocks);
-  ctx->last_left = own && !ws && mode == INC_MODE_STAGED ? (const uint32_t*)(ctx->d_mid + n) : nullptr;
   L.perm = perm;
   L.tidx = tidx;
   L.T0 = T0;
@@ -325,7 +322,7 @@ int inc_ctx_create(const inc_nucleus* targets, int n_targets, const inc_options*
       o.table_layout < 0 || o.table_layout > 1 || o.heavy_fragments < 0 || o.heavy_fragments > 1 ||
       (o.vertex_window && (o.vertex_window < 1024 || o.vertex_window > (1 << 20) ||
                            (o.vertex_window & (o.vertex_window - 1)))) ||
-      o.vertex_launch < 0 || o.vertex_launch > 1 || o.merge_lanes < -1 || o.merge_lanes > 64 ||
+      o.vertex_launch < 0 || o.vertex_launch > 1 ||
       (o.chunk_events && (o.chunk_events < kChunkMin || o.chunk_events > kChunkMax || o.chunk_events % kChunkMin)))
     return INC_ERR_ARG;
   if (!(o.const_sigma_mb >= 0.0f) || o.const_sigma_mb > 1e5f) return INC_ERR_ARG;
@@ -398,13 +395,6 @@ int inc_ctx_create(const inc_nucleus* targets, int n_targets, const inc_options*
       else if (o.stack_levels > 0 && o.stack_levels < lv) lv = o.stack_levels;
       c->stack_lds[m] = lv;
     }
-    {
-      const int layout = o.table_layout ? kXsPairs : kXsColumns;
-      c->merge_slots = o.merge_lanes < 0 ? 0
-                       : o.fast_math ? fast::merge_slots(n_targets, c->block, c->waves_per_cu, layout, c->stack_lds[1])
-                                     : precise::merge_slots(n_targets, c->block, c->waves_per_cu, layout,
-                                                            c->stack_lds[1]);
-    }
     c->evap_blocks = n_cu * (o.fast_math ? fast::evap_blocks_per_cu(c->block) : precise::evap_blocks_per_cu(c->block));
   } while (false);
   if (d_AZ) (void)hipFree(d_AZ);
@@ -443,18 +433,6 @@ int inc_ctx_tables(const inc_ctx* ctx, float* host_out) {
     o[106] = tabs[t].EC;
     o[107] = tabs[t].R;
   }
-  return INC_OK;
-}
-
-int inc_ctx_moved_events(inc_ctx* ctx, unsigned long long* moved) {
-  if (!ctx || !moved) return INC_ERR_ARG;
-  *moved = 0;
-  if (!ctx->last_left) return INC_OK;
-  uint32_t v = 0;
-  hipError_t e = hipDeviceSynchronize();
-  if (e == hipSuccess) e = hipMemcpy(&v, ctx->last_left + 2, sizeof(v), hipMemcpyDeviceToHost);
-  if (e != hipSuccess) return map_err(e);
-  *moved = v;
   return INC_OK;
 }
 

@@ -30,8 +30,6 @@ struct inc_ctx {
   int n_cu;
   int block, evap_threshold, tent_threshold, kin_threshold, start_threshold, waves_per_cu;
   int stack_lds[2];  // LIFO entries per lane in LDS: [plain, persistent]
-  int merge_slots;   // staged mode: events of the drain-time pool (0: none)
-  const uint32_t* last_left;  // last staged launch on d_mid: its list of left work (NULL: none)
   int evap_blocks;   // staged mode: evaporation kernel grid (full occupancy)
   incdev::VertexBuf vtx;  // INC_MODE_VERTEX buffers (allocated on first use; slots NULL until then)
 };

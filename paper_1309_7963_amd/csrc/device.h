@@ -31,9 +31,6 @@ constexpr float kPhi = 1.5f;         // GeV/c; NN argument ceiling
 constexpr uint16_t kFlagStack = 1, kFlagSegments = 2, kFlagEmpty = 4, kFlagRange = 0x8000;
 // hand-over only (never in a residual): the residual is already written
 constexpr uint16_t kMidFinal = 0x4000;
-// hand-over only: the event's cascade moved to another wave of its
-// workgroup, which lists it for the evaporation kernel (staged mode)
-constexpr uint16_t kMidMoved = 0x2000;
 
 // --------------------------------------------------------------- tables
 // One target nucleus: 15 shells (Sec. 2.2).  Index [species][shell], species
@@ -103,7 +100,6 @@ struct Opts {
   float fixed_b;         // >= 0 fixes the impact parameter
   int evap_threshold, tent_threshold, kin_threshold, start_threshold;
   int same_stream;       // every event uses its segment's first id
-  int merge_lanes;       // staged drain: a wave with at most this many live events hands them over (0: never)
 };
 // The test hooks of Opts (fixed impact parameter, constant cross-section, no
 // Pauli blocking, stop after the first collision) at their neutral values, as
@@ -608,7 +604,7 @@ __device__ __forceinline__ float photon_sample_s(float Y, float u) {
 // at (fill + rank among emitting lanes); when the buffer could overflow, the
 // wave reserves space with one global atomic and all 64 lanes copy the
 // buffer out contiguously into the SoA arrays.
-constexpr int kWriterCap = 64;       // records per wave buffer (cascade kernels; the least that holds a wave's)
+constexpr int kWriterCap = 128;      // records per wave buffer (cascade kernels)
 constexpr int kWriterCapEvap = 256;  // records per wave buffer (evaporation kernels)
 constexpr int kRecWords = 6;     // event, species | stage << 8 | segment << 16, T, ux, uy, uz
 // One append adds up to a record per lane after at most one flush, so a wave's

@@ -109,11 +109,6 @@ __device__ __forceinline__ void cascade_init(Cascade& c, const NucTab& nt) {
   c.ncoll = c.nretry = c.nseg = c.flags = c.top = 0;
   c.hsh = 0u;
   c.started = 0;
-  // set by the entry and the first tentative collision; defined from the
-  // start so that an event can be handed to another wave before either
-  c.sp = 0;
-  c.shell = 0;
-  c.ytgt = 0;
 }
 
 // Entry (reading): impact parameter uniform over the disc of radius R,

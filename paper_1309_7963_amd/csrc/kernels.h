@@ -34,26 +34,13 @@ __host__ __device__ constexpr size_t xs_lds_bytes(int layout) {
 }
 
 // Hand-over buffer of a plain or staged launch of n events: n MidState
-// records, then (staged) the evaporation work left to the evaporation kernel:
-// [0] chunks listed, [1] chunks claimed by the evaporation kernel, [2] moved
-// events listed, [3] moved events claimed; then the first event of each
-// listed chunk (room for chunks as small as kChunkMin); then the events whose
-// cascades ended in another wave than the one that started them (room for
-// all n).
-constexpr size_t left_chunk_room(size_t n) { return (n + kChunkMin - 1) / kChunkMin; }
+// records, then (staged) the chunks whose evaporation is left to the
+// evaporation kernel: [0] chunks listed, [1] chunks claimed by the
+// evaporation kernel, [2], [3] unused, then the first event of each listed
+// chunk (room for chunks as small as kChunkMin).
 constexpr size_t mid_bytes(size_t n) {
-  return sizeof(MidState) * n + sizeof(uint32_t) * (4 + left_chunk_room(n) + n);
+  return sizeof(MidState) * n + sizeof(uint32_t) * (4 + (n + kChunkMin - 1) / kChunkMin);
 }
-
-// Staged kernel, once the work queue is empty: the LDS pool through which
-// sparse waves hand their live events to waves of the workgroup with free
-// lanes.  Each pooled event takes kMergeWords words of dynamic LDS; a pool
-// holds kMergeMinSlots..kMergeMaxSlots events (fewer fit: no pool).
-constexpr int kMergeWords = 42;
-constexpr int kMergeMinSlots = 8;
-constexpr int kMergeMaxSlots = 64;
-constexpr int kMergeLanesDefault = 16;
-constexpr size_t merge_pool_bytes(int slots) { return sizeof(uint32_t) * kMergeWords * (size_t)(slots > 0 ? slots : 0); }
 
 struct LaunchDesc {
   int mode;
@@ -62,8 +49,6 @@ struct LaunchDesc {
   int evap_blocks;       // staged mode: grid of the evaporation kernel
   int evap_threshold, tent_threshold, kin_threshold, start_threshold;
   int stack_lds;         // stack entries per lane held in LDS (stack_levels)
-  int merge_slots;       // staged mode: events the drain-time pool holds (0: no pool)
-  int merge_lanes;       // staged mode: live events at or below which a wave hands them over
   int chunk;             // events per work-queue claim (0: kChunkEvents)
   int xs_pairs;          // persistent kernels: NN table in LDS as node pairs
   int photon;            // the evaporation has the photon channel (instantiation)
@@ -112,9 +97,6 @@ constexpr float kMaxExcitation = 500.0f;  // MeV
 //                 to share a CU, with the NN table in xs_layout (the plain
 //                 kernel always uses columns; the kernel's own occupancy limit
 //                 applies too); 0 when none fit;
-//   merge_slots   events the staged kernel's drain-time pool holds in the LDS
-//                 left beside the tables and stack_levels LIFO levels
-//                 (kMergeMinSlots..kMergeMaxSlots; 0 when fewer fit);
 //   evap_blocks_per_cu  resident blocks per CU of the staged evaporation
 //                 kernel (its own occupancy: it needs fewer registers);
 //   launch_events zero the counters, then launch the event kernel(s) of L.mode.
@@ -147,7 +129,6 @@ size_t vertex_queue_words(size_t window);
 hipError_t launch_vertex(const LaunchDesc& L, const VertexBuf& vb, hipStream_t s);
 size_t lds_bytes(int n_targets, int block, int xs_layout, int stack_levels);
 int stack_levels(int mode, int n_targets, int block, int waves_per_cu, int xs_layout);
-int merge_slots(int n_targets, int block, int waves_per_cu, int xs_layout, int stack_levels);
 int evap_blocks_per_cu(int block);
 hipError_t launch_events(const LaunchDesc& L, hipStream_t s);
 hipError_t launch_evaporation(const LaunchDesc& L, const ExcitedDesc& x, hipStream_t s);
@@ -159,7 +140,6 @@ size_t vertex_queue_words(size_t window);
 hipError_t launch_vertex(const LaunchDesc& L, const VertexBuf& vb, hipStream_t s);
 size_t lds_bytes(int n_targets, int block, int xs_layout, int stack_levels);
 int stack_levels(int mode, int n_targets, int block, int waves_per_cu, int xs_layout);
-int merge_slots(int n_targets, int block, int waves_per_cu, int xs_layout, int stack_levels);
 int evap_blocks_per_cu(int block);
 hipError_t launch_events(const LaunchDesc& L, hipStream_t s);
 hipError_t launch_evaporation(const LaunchDesc& L, const ExcitedDesc& x, hipStream_t s);

@@ -42,14 +42,13 @@ struct KernelArgs {
   RingDev ring;              // streaming output (rec == NULL: segment arrays)
   int stack_lds;             // stack entries per lane held in LDS
   int chunk;                 // events per work-queue claim
-  int merge_slots;           // staged mode: events of the drain-time pool (0: none)
 };
 
 __device__ __forceinline__ bool energy_ok(float T0) { return T0 >= 20.0f && T0 <= 250.0f; }
 
 // LDS layout of the event kernels: [n_targets NucTab][NN table][MassTab]
 // [writer buffers of the block's waves][LIFO levels: per wave stack_lds x 2 x
-// 64 float4][staged kernel: the drain-time pool].  The NN table is XsLds (columns) or XsPairs (node pairs), see
+// 64 float4].  The NN table is XsLds (columns) or XsPairs (node pairs), see
 // xs_lds_bytes.  The evaporation kernels stage only the MassTab (n_targets =
 // 0, no NN table: kXsNone), have no stack and larger writer buffers
 // (kWriterCapEvap records per wave: nearly every lane emits every step).
@@ -63,12 +62,6 @@ __device__ __forceinline__ int lds_stack_base(int n_targets, int xs_layout, int 
                 (blockDim.x / 64) * (kWriterCap * kRecWords * sizeof(uint32_t))) /
                sizeof(float4)) +
          (int)(threadIdx.x / 64) * levels * 128 + (int)(threadIdx.x % 64);
-}
-// Byte offset of the staged kernel's drain-time pool (after the LIFO levels).
-__device__ __forceinline__ size_t lds_merge_offset(int n_targets, int xs_layout, int levels) {
-  return lds_mass_offset(n_targets, xs_layout) + sizeof(MassTab) +
-         (blockDim.x / 64) * (kWriterCap * kRecWords * sizeof(uint32_t)) +
-         (size_t)(blockDim.x / 64) * levels * 128 * sizeof(float4);
 }
 __device__ __forceinline__ void stage_tables(char* lds, const KernelArgs& a, int n_targets, int xs_layout) {
   uint32_t* dst = (uint32_t*)lds;
@@ -291,72 +284,31 @@ __global__ void __launch_bounds__(256) k_evap_plain(KernelArgs a) {
 // states wait, so every step runs with many lanes together; each lane still
 // consumes its own random stream in order, so results do not depend on the
 // schedule.
-// Sources of evaporation work.  A source hands out ranges [base, end) of
-// positions and maps a position to a launch event.  Chunk sources hand out
-// chunks of a.chunk consecutive queue positions (the launch's start order)
-// and skip the events whose cascades moved to another wave (kMidMoved); the
-// moved events are listed on their own.
-__device__ __forceinline__ void chunk_range(const KernelArgs& a, uint32_t first, unsigned long long& base,
-                                            unsigned long long& end) {
-  base = first;
-  end = base + a.chunk < a.n ? base + a.chunk : a.n;
-}
-// The chunks listed after the hand-over records (mid_bytes): those of waves
-// that took more chunks than they keep (evaporation kernel).
+// Sources of evaporation work: chunks of a.chunk consecutive launch events.
+// The evaporation kernel takes the chunks listed after the hand-over records
+// (mid_bytes): those of waves that took more chunks than they keep.
 struct LeftChunks {
-  static constexpr bool kMoved = false;
   uint32_t* left;
   uint32_t count;
-  __device__ __forceinline__ bool claim(const KernelArgs& a, unsigned long long& base, unsigned long long& end) {
+  __device__ __forceinline__ bool claim(unsigned long long& base) {
     uint32_t b = 0;
     if (lane_id() == 0) b = atomicAdd(&left[1], 1u);
     b = (uint32_t)__shfl((int)b, 0);
     if (b >= count) return false;
-    chunk_range(a, left[4 + b], base, end);
+    base = left[4 + b];
     return true;
-  }
-  __device__ __forceinline__ size_t event(const KernelArgs& a, unsigned long long pos) const {
-    return a.perm ? (size_t)a.perm[pos] : (size_t)pos;
   }
 };
 // A wave's own list: the chunks it took through the cascade, whose hand-over
 // records its own lanes wrote.
 struct OwnChunks {
-  static constexpr bool kMoved = false;
   uint32_t list;  // lane i: first event of the wave's i-th chunk
   int count, next;
-  __device__ __forceinline__ bool claim(const KernelArgs& a, unsigned long long& base, unsigned long long& end) {
+  __device__ __forceinline__ bool claim(unsigned long long& base) {
     if (next >= count) return false;
-    chunk_range(a, (uint32_t)__shfl((int)list, next), base, end);
+    base = (unsigned long long)(uint32_t)__shfl((int)list, next);
     ++next;
     return true;
-  }
-  __device__ __forceinline__ size_t event(const KernelArgs& a, unsigned long long pos) const {
-    return a.perm ? (size_t)a.perm[pos] : (size_t)pos;
-  }
-};
-// The events whose cascades ended in another wave than the one that started
-// them (staged drain), listed by launch event after the chunk list
-// (evaporation kernel), 64 at a time.
-__device__ __forceinline__ uint32_t* moved_list(const KernelArgs& a) {
-  return (uint32_t*)(a.mid + a.n) + 4 + left_chunk_room(a.n);
-}
-struct MovedEvents {
-  static constexpr bool kMoved = true;
-  uint32_t* left;
-  const uint32_t* list;
-  uint32_t count;
-  __device__ __forceinline__ bool claim(const KernelArgs&, unsigned long long& base, unsigned long long& end) {
-    uint32_t b = 0;
-    if (lane_id() == 0) b = atomicAdd(&left[3], 64u);
-    b = (uint32_t)__shfl((int)b, 0);
-    if (b >= count) return false;
-    base = b;
-    end = b + 64u < count ? b + 64u : count;
-    return true;
-  }
-  __device__ __forceinline__ size_t event(const KernelArgs&, unsigned long long pos) const {
-    return (size_t)list[pos];
   }
 };
 
@@ -380,10 +332,10 @@ __device__ __forceinline__ void evap_events(const KernelArgs& a, const MassTab& 
     const uint64_t need = __ballot(!busy);
     if (need && !exhausted) {
       if (chunk_next == chunk_end) {
-        unsigned long long base = 0, end = 0;
-        if (src.claim(a, base, end)) {
+        unsigned long long base = 0;
+        if (src.claim(base)) {
           chunk_next = base;
-          chunk_end = end;
+          chunk_end = base + a.chunk < a.n ? base + a.chunk : a.n;
         } else {
           exhausted = true;
           chunk_next = chunk_end = 0;
@@ -392,9 +344,10 @@ __device__ __forceinline__ void evap_events(const KernelArgs& a, const MassTab& 
       const unsigned long long avail = chunk_end - chunk_next;
       const uint32_t r = rank_in(need);
       if (!busy && r < avail) {
-        const size_t ev = src.event(a, chunk_next + r);
+        const size_t pos = (size_t)(chunk_next + r);
+        const size_t ev = a.perm ? (size_t)a.perm[pos] : pos;
         const MidState m = a.mid[ev];
-        if (!(m.flags & kMidFinal) && (Src::kMoved || !(m.flags & kMidMoved))) {
+        if (!(m.flags & kMidFinal)) {
           er = event_ref(a, ev);
           nu.A = m.A;
           nu.Z = m.Z;
@@ -402,7 +355,7 @@ __device__ __forceinline__ void evap_events(const KernelArgs& a, const MassTab& 
           nu.P = {m.P[0], m.P[1], m.P[2]};
           Ex_casc = m.E;
           nsec = m.nsec;
-          flags = m.flags & ~kMidMoved;
+          flags = m.flags;
           ncoll = m.ncoll;
           nretry = m.nretry;
           init_stream(rng, a, er);
@@ -433,178 +386,6 @@ __device__ __forceinline__ void evap_events(const KernelArgs& a, const MassTab& 
   }
 }
 
-// Drain-time merge of the staged kernel.  Once the work queue is empty a
-// wave's live events thin out while each of its iterations still costs a
-// full wave's issue slots.  A wave whose live events have dropped to
-// a.opt.merge_lanes or fewer posts them to its workgroup's pool in LDS and
-// leaves for its evaporation work; waves of the workgroup with free lanes
-// take them over.  No wave waits for another: a wave that cannot post or
-// claim this iteration carries on, and a wave without live events leaves
-// unless it is the last one taking events while the pool is not empty.
-// Control word: bits 0-7 waves still taking events, 8-9 the pool's state,
-// 16-23 events posted, 24-31 events claimed; word 1 counts events read out.
-constexpr uint32_t kPoolEmpty = 0u, kPoolFilling = 1u, kPoolFull = 2u;
-// A lane's secondary count carries this bit while its event is one that
-// another wave started (the count itself stays below 2^16: records and
-// residuals keep its low 16 bits).
-constexpr int kNsecMoved = 1 << 30;
-__device__ __forceinline__ uint32_t pool_active(uint32_t w) { return w & 0xffu; }
-__device__ __forceinline__ uint32_t pool_state(uint32_t w) { return (w >> 8) & 3u; }
-__device__ __forceinline__ uint32_t pool_count(uint32_t w) { return (w >> 16) & 0xffu; }
-__device__ __forceinline__ uint32_t pool_claimed(uint32_t w) { return w >> 24; }
-__device__ __forceinline__ uint32_t pool_load(uint32_t* ctl) {
-  return __hip_atomic_load(ctl, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_WORKGROUP);
-}
-// The pool's slots | merge_lanes << 8 word (an atomic load, so that it is
-// read where it is used rather than kept in a register).
-__device__ __forceinline__ uint32_t pool_config(uint32_t* hdr) {
-  return __builtin_amdgcn_readfirstlane(__hip_atomic_load(hdr + 3, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP));
-}
-__device__ __forceinline__ bool pool_cas(uint32_t* ctl, uint32_t& old, uint32_t nw) {
-  return __hip_atomic_compare_exchange_strong(ctl, &old, nw, __ATOMIC_ACQ_REL, __ATOMIC_ACQUIRE,
-                                              __HIP_MEMORY_SCOPE_WORKGROUP);
-}
-// Each of the following makes one attempt (lane 0); a wave whose attempt
-// fails, because another wave changed the control word meanwhile, tries
-// again at its next iteration.
-// Start posting n events: the pool is empty and another wave still takes
-// events.  The posting wave no longer counts as taking events.
-__device__ __forceinline__ bool pool_begin_post(uint32_t* ctl, uint32_t n) {
-  uint32_t old = pool_load(ctl);
-  if (pool_state(old) != kPoolEmpty || pool_active(old) < 2u) return false;
-  return pool_cas(ctl, old, old - 1u + (kPoolFilling << 8) + (n << 16));
-}
-// Claim up to `want` posted events: their number, `first` the first slot.
-__device__ __forceinline__ uint32_t pool_claim(uint32_t* ctl, uint32_t want, uint32_t& first) {
-  uint32_t old = pool_load(ctl);
-  if (pool_state(old) != kPoolFull) return 0u;
-  const uint32_t rest = pool_count(old) - pool_claimed(old);
-  const uint32_t k = want < rest ? want : rest;
-  if (k == 0u || !pool_cas(ctl, old, old + (k << 24))) return 0u;
-  first = pool_claimed(old);
-  return k;
-}
-// After the wave's lanes read k claimed events out: the reader that
-// completes the count empties the pool.
-__device__ __forceinline__ void pool_release(uint32_t* ctl, uint32_t k) {
-  const uint32_t done = __hip_atomic_fetch_add(ctl + 1, k, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_WORKGROUP) + k;
-  const uint32_t n = pool_count(pool_load(ctl));
-  if (done == n) {
-    __hip_atomic_store(ctl + 1, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-    __hip_atomic_fetch_sub(ctl, (kPoolFull << 8) | (n << 16) | (n << 24), __ATOMIC_RELEASE,
-                           __HIP_MEMORY_SCOPE_WORKGROUP);
-  }
-}
-// A wave without live events leaves, unless it is the last one taking events
-// while the pool holds events.
-__device__ __forceinline__ bool pool_leave(uint32_t* ctl) {
-  uint32_t old = pool_load(ctl);
-  if (pool_active(old) < 2u && pool_state(old) != kPoolEmpty) return false;
-  return pool_cas(ctl, old, old - 1u);
-}
-// An event in the pool: kMergeWords words, word w of slot k at slots[w * P + k].
-__device__ __forceinline__ void pool_put(uint32_t* slots, int P, uint32_t k, int st, const Cascade& c, const Rng& rng,
-                                         EventRef er, uint32_t ev, float T0, int tgt, int nsec) {
-  uint32_t* q = slots + k;
-  q[0 * P] = __float_as_uint(c.pos.x);
-  q[1 * P] = __float_as_uint(c.pos.y);
-  q[2 * P] = __float_as_uint(c.pos.z);
-  q[3 * P] = __float_as_uint(c.dir.x);
-  q[4 * P] = __float_as_uint(c.dir.y);
-  q[5 * P] = __float_as_uint(c.dir.z);
-  q[6 * P] = __float_as_uint(c.eps);
-  q[7 * P] = __float_as_uint(c.tau);
-  q[8 * P] = __float_as_uint(c.sh0);
-  q[9 * P] = __float_as_uint(c.sh1);
-  q[10 * P] = __float_as_uint(c.Ex);
-  q[11 * P] = __float_as_uint(c.pesc.x);
-  q[12 * P] = __float_as_uint(c.pesc.y);
-  q[13 * P] = __float_as_uint(c.pesc.z);
-  q[14 * P] = __float_as_uint(c.pt.x);
-  q[15 * P] = __float_as_uint(c.pt.y);
-  q[16 * P] = __float_as_uint(c.pt.z);
-  q[17 * P] = __float_as_uint(c.ptm);
-  q[18 * P] = (uint32_t)c.ncoll;
-  q[19 * P] = (uint32_t)c.nretry;
-  q[20 * P] = (uint32_t)c.nseg;
-  q[21 * P] = c.hsh;
-  q[22 * P] = (uint32_t)c.stk_base;
-  // small fields share a word, each masked to its width
-  q[23 * P] = ((uint32_t)c.sp & 1u) | ((uint32_t)c.shell & 15u) << 1 | ((uint32_t)c.ytgt & 1u) << 5 |
-              ((uint32_t)c.started & 1u) << 6 | ((uint32_t)c.top & 127u) << 7 | ((uint32_t)c.flags & 0xffffu) << 16;
-  q[24 * P] = ((uint32_t)c.nesc0 & 0xffu) | ((uint32_t)c.nesc1 & 0xffu) << 8 | ((uint32_t)c.avail0 & 0xffu) << 16 |
-              ((uint32_t)c.avail1 & 0xffu) << 24;
-  q[25 * P] = rng.id0;
-  q[26 * P] = rng.id1;
-  q[27 * P] = rng.blk;
-  q[28 * P] = (rng.pos & 0xffu) | rng.nb << 8;
-  q[29 * P] = rng.a[0];
-  q[30 * P] = rng.a[1];
-  q[31 * P] = rng.a[2];
-  q[32 * P] = rng.a[3];
-  q[33 * P] = rng.b[0];
-  q[34 * P] = rng.b[1];
-  q[35 * P] = rng.b[2];
-  q[36 * P] = rng.b[3];
-  q[37 * P] = (uint32_t)er.seg;
-  q[38 * P] = er.local;
-  q[39 * P] = ev;
-  q[40 * P] = __float_as_uint(T0);
-  q[41 * P] = ((uint32_t)tgt & 0xffu) | ((uint32_t)st & 0xffu) << 8 | ((uint32_t)nsec & 0xffffu) << 16;
-}
-__device__ __forceinline__ void pool_get(const uint32_t* slots, int P, uint32_t k, int& st, Cascade& c, Rng& rng,
-                                         EventRef& er, uint32_t& ev, float& T0, int& tgt, int& nsec) {
-  const uint32_t* q = slots + k;
-  c.pos = {__uint_as_float(q[0 * P]), __uint_as_float(q[1 * P]), __uint_as_float(q[2 * P])};
-  c.dir = {__uint_as_float(q[3 * P]), __uint_as_float(q[4 * P]), __uint_as_float(q[5 * P])};
-  c.eps = __uint_as_float(q[6 * P]);
-  c.tau = __uint_as_float(q[7 * P]);
-  c.sh0 = __uint_as_float(q[8 * P]);
-  c.sh1 = __uint_as_float(q[9 * P]);
-  c.Ex = __uint_as_float(q[10 * P]);
-  c.pesc = {__uint_as_float(q[11 * P]), __uint_as_float(q[12 * P]), __uint_as_float(q[13 * P])};
-  c.pt = {__uint_as_float(q[14 * P]), __uint_as_float(q[15 * P]), __uint_as_float(q[16 * P])};
-  c.ptm = __uint_as_float(q[17 * P]);
-  c.ncoll = (int)q[18 * P];
-  c.nretry = (int)q[19 * P];
-  c.nseg = (int)q[20 * P];
-  c.hsh = q[21 * P];
-  c.stk_base = (int)q[22 * P];
-  const uint32_t w23 = q[23 * P], w24 = q[24 * P];
-  c.sp = (int)(w23 & 1u);
-  c.shell = (int)((w23 >> 1) & 15u);
-  c.ytgt = (int)((w23 >> 5) & 1u);
-  c.started = (int)((w23 >> 6) & 1u);
-  c.top = (int)((w23 >> 7) & 127u);
-  c.flags = (int)(w23 >> 16);
-  c.nesc0 = (int)(w24 & 0xffu);
-  c.nesc1 = (int)((w24 >> 8) & 0xffu);
-  c.avail0 = (int)((w24 >> 16) & 0xffu);
-  c.avail1 = (int)(w24 >> 24);
-  rng.id0 = q[25 * P];
-  rng.id1 = q[26 * P];
-  rng.blk = q[27 * P];
-  rng.pos = q[28 * P] & 0xffu;
-  rng.nb = q[28 * P] >> 8;
-  rng.a[0] = q[29 * P];
-  rng.a[1] = q[30 * P];
-  rng.a[2] = q[31 * P];
-  rng.a[3] = q[32 * P];
-  rng.b[0] = q[33 * P];
-  rng.b[1] = q[34 * P];
-  rng.b[2] = q[35 * P];
-  rng.b[3] = q[36 * P];
-  er.seg = (int)q[37 * P];
-  er.local = q[38 * P];
-  ev = q[39 * P];
-  T0 = __uint_as_float(q[40 * P]);
-  const uint32_t w41 = q[41 * P];
-  tgt = (int)(w41 & 0xffu);
-  st = (int)((w41 >> 8) & 0xffu);
-  nsec = (int)(w41 >> 16);
-}
-static_assert(kMergeWords == 42, "pool_put / pool_get word count");
-
 // 4 waves per SIMD (<= 128 VGPRs, 16 per CU): the lane scheduler needs many
 // events in flight per CU more than it needs extra registers (measured: 3
 // waves per SIMD at 138 VGPRs took 12.3 ms for the 2x10^6-event batch, 4 at
@@ -622,19 +403,6 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) k
   if constexpr (kHooks) op = a.opt;
   constexpr int kLayout = kPairs ? kXsPairs : kXsColumns;
   extern __shared__ __align__(16) char lds[];
-  // staged mode: the drain-time pool.  Its header is static LDS (a fixed
-  // address) and holds the pool's size and place, so that nothing about the
-  // pool occupies registers through the loop: [0] control word, [1] events
-  // read out, [2] byte offset of the slots in the dynamic LDS, [3] slots |
-  // merge_lanes << 8 (0 slots: no pool).
-  __shared__ uint32_t mhdr[4];
-  bool posted = false;  // this wave handed its live events over (wave-uniform)
-  if (!kFused && threadIdx.x == 0) {
-    mhdr[0] = blockDim.x / 64;
-    mhdr[1] = 0u;
-    mhdr[2] = (uint32_t)lds_merge_offset(a.n_targets, kLayout, a.stack_lds);
-    mhdr[3] = (uint32_t)a.merge_slots | (uint32_t)a.opt.merge_lanes << 8;
-  }
   stage_tables(lds, a, a.n_targets, kLayout);
   const NucTab* snt = (const NucTab*)lds;
   const XS& sxs = *(const XS*)(lds + a.n_targets * sizeof(NucTab));
@@ -720,71 +488,14 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) k
       chunk_next += cnt < avail ? cnt : avail;
     }
     if (exhausted && st == kStDone) st = kStIdle;
-    if constexpr (!kFused) {
-      const uint32_t mcfg = exhausted && !posted ? pool_config(mhdr) : 0u;
-      if (mcfg & 0xffu) {
-        // drain-time merge: post this wave's few live events and leave, or
-        // take posted events into free lanes
-        const int mslots = (int)(mcfg & 0xffu);
-        uint32_t* mpool = (uint32_t*)(lds + pool_load(mhdr + 2));
-        const uint64_t live = __ballot(st != kStIdle);
-        const uint32_t nlive = (uint32_t)__popcll(live);
-        const uint32_t cw = __builtin_amdgcn_readfirstlane(pool_load(mhdr));
-        if (nlive > 0u && nlive <= (mcfg >> 8) && nlive <= (uint32_t)mslots && pool_state(cw) == kPoolEmpty &&
-            pool_active(cw) >= 2u && __ballot(st != kStIdle && c.top > c.stk_levels) == 0) {
-          // (an event with LIFO entries in private memory stays: only the
-          // LDS levels, addressed through c.stk_base, travel with it)
-          int ok = 0;
-          if (lane_id() == 0) ok = pool_begin_post(mhdr, nlive) ? 1 : 0;
-          if (__shfl(ok, 0)) {
-            if (st != kStIdle) {
-              pool_put(mpool, mslots, rank_in(live), st, c, rng, er, ev_idx, T0, tgt, nsec);
-              a.mid[ev_idx].flags = kMidMoved;  // its chunk's evaporation skips it
-            }
-            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
-            if (lane_id() == 0)
-              __hip_atomic_fetch_add(mhdr, (kPoolFull - kPoolFilling) << 8, __ATOMIC_RELEASE,
-                                     __HIP_MEMORY_SCOPE_WORKGROUP);
-            st = kStIdle;  // every lane idle: the wave leaves below
-            posted = true;
-          }
-        }
-        if (!posted && pool_state(cw) == kPoolFull && pool_claimed(cw) < pool_count(cw) && nlive < 64u) {
-          uint32_t first = 0u, got = 0u;
-          if (lane_id() == 0) got = pool_claim(mhdr, 64u - nlive, first);
-          got = (uint32_t)__shfl((int)got, 0);
-          if (got) {
-            first = (uint32_t)__shfl((int)first, 0);
-            const uint32_t r = rank_in(~live);
-            if (st == kStIdle && r < got) {
-              pool_get(mpool, mslots, first + r, st, c, rng, er, ev_idx, T0, tgt, nsec);
-              nsec |= kNsecMoved;
-            }
-            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
-            if (lane_id() == 0) pool_release(mhdr, got);
-          }
-        }
-      }
-    }
     const int nF = __popcll(__ballot(st == kStFlight));
     const int nT = __popcll(__ballot(st == kStTent));
     const int nK = __popcll(__ballot(st == kStKin));
     const int nE = kFused ? __popcll(__ballot(st == kStEvap)) : 0;
     const int nS = __popcll(__ballot(st == kStStart));
     if (nF + nT + nK + nE + nS == 0) {
-      bool leave = exhausted;
-      if constexpr (!kFused) {
-        // a wave that posted its events no longer counts as taking events;
-        // the last one taking events stays while the pool holds some
-        if (exhausted && !posted && (pool_config(mhdr) & 0xffu)) {
-          int l = 0;
-          if (lane_id() == 0) l = pool_leave(mhdr) ? 1 : 0;
-          leave = __shfl(l, 0) != 0;
-        }
-      }
-      if (leave) break;
-      if (!exhausted) continue;
-      // (staying: no lane runs this iteration)
+      if (exhausted) break;
+      continue;
     }
     // ---- state selection (wave-uniform)
     int run;
@@ -843,8 +554,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) k
           MidState m;
           m.A = (int16_t)nu.A;
           m.Z = (int16_t)nu.Z;
-          const bool moved = (nsec & kNsecMoved) != 0;
-          m.flags = (uint16_t)(c.flags | (final ? kMidFinal : 0) | (moved ? kMidMoved : 0));
+          m.flags = (uint16_t)(c.flags | (final ? kMidFinal : 0));
           m.ncoll = (uint16_t)min(c.ncoll, 65535);
           m.nretry = (uint16_t)min(c.nretry, 65535);
           m.nsec = (uint16_t)nsec;
@@ -854,11 +564,6 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) k
           m.P[2] = nu.P.z;
           m.drawn = rng.drawn();
           a.mid[ev_idx] = m;
-          if (moved && !final) {
-            // listed for the evaporation kernel
-            uint32_t* left = (uint32_t*)(a.mid + a.n);
-            moved_list(a)[atomicAdd(&left[2], 1u)] = ev_idx;
-          }
           st = kStDone;
         } else {
           st = final ? kStDone : kStEvap;
@@ -885,28 +590,20 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) k
 
 // Staged mode, second kernel: the evaporation of the handed-over events the
 // cascade kernel's waves did not evaporate themselves (the chunks listed
-// after the hand-over records, then the events whose cascades moved to
-// another wave), as a persistent work-queue kernel.
+// after the hand-over records), as a persistent work-queue kernel.
 template <int kExt, bool kRing>
 __global__ void __launch_bounds__(256) k_evap_persistent(KernelArgs a) {
-  // usually little is left: the cascade waves evaporated what they handed over
+  // usually nothing is left: the cascade waves evaporated what they handed over
   uint32_t* left = (uint32_t*)(a.mid + a.n);
   const uint32_t count = __hip_atomic_load(&left[0], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-  const uint32_t moved = __hip_atomic_load(&left[2], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-  if (count == 0 && moved == 0) return;
+  if (count == 0) return;
   extern __shared__ __align__(16) char lds[];
   stage_tables(lds, a, 0, kXsNone);
   const MassTab& smt = *(const MassTab*)lds;
   uint32_t* wbuf = (uint32_t*)(lds + sizeof(MassTab)) + (threadIdx.x / 64) * (kWriterCapEvap * kRecWords);
   int fill = 0;
-  if (count) {
-    LeftChunks src = {left, count};
-    evap_events<kWriterCapEvap, kExt, kRing>(a, smt, wbuf, fill, src);
-  }
-  if (moved) {
-    MovedEvents src = {left, moved_list(a), moved};
-    evap_events<kWriterCapEvap, kExt, kRing>(a, smt, wbuf, fill, src);
-  }
+  LeftChunks src = {left, count};
+  evap_events<kWriterCapEvap, kExt, kRing>(a, smt, wbuf, fill, src);
   writer_flush<kRing>(wbuf, fill, a.segs, a.ring);
 }
 
@@ -921,7 +618,7 @@ __global__ void k_excited_setup(KernelArgs a, ExcitedDesc x) {
   uint32_t* left = (uint32_t*)(a.mid + a.n);
   if (i == 0) {
     left[0] = (uint32_t)((a.n + a.chunk - 1) / a.chunk);
-    left[1] = left[2] = left[3] = 0u;
+    left[1] = 0u;
   }
   if (i >= a.n) return;
   if (i % a.chunk == 0) left[4 + i / a.chunk] = (uint32_t)i;
@@ -968,7 +665,7 @@ __global__ void k_zero_counters(const Segment* segs, int n_seg, unsigned long lo
   if (i == 0) {
     queue[0] = 0ull;
     queue[1] = 0ull;
-    if (left) left[0] = left[1] = left[2] = left[3] = 0u;
+    if (left) left[0] = left[1] = 0u;
   }
 }
 
@@ -1276,14 +973,13 @@ size_t lds_bytes(int n_targets, int block, int xs_layout, int stack_levels) {
          (size_t)stack_levels * 2 * block * sizeof(float4);
 }
 
-// LDS one workgroup of the event kernel of `mode` may take when the kernel's
-// own occupancy and `waves_per_cu` set how many share a CU (0: unknown).
-static size_t lds_budget(int mode, int n_targets, int block, int waves_per_cu, int xs_layout) {
+int stack_levels(int mode, int n_targets, int block, int waves_per_cu, int xs_layout) {
   int dev = 0, lds_cu = 0;
   if (hipGetDevice(&dev) != hipSuccess ||
       hipDeviceGetAttribute(&lds_cu, hipDeviceAttributeMaxSharedMemoryPerMultiprocessor, dev) != hipSuccess ||
       lds_cu <= 0)
     return 0;
+  if (mode == INC_MODE_PLAIN) xs_layout = kXsColumns;
   const size_t base = lds_bytes(n_targets, block, xs_layout, 0);
   int occ = 0;
   const bool pairs = xs_layout == kXsPairs;
@@ -1298,26 +994,11 @@ static size_t lds_budget(int mode, int n_targets, int block, int waves_per_cu, i
     const int want = (waves_per_cu * 64 + block - 1) / block;
     if (want < blocks) blocks = want < 1 ? 1 : want;
   }
-  return (size_t)lds_cu / blocks;
-}
-
-int stack_levels(int mode, int n_targets, int block, int waves_per_cu, int xs_layout) {
-  if (mode == INC_MODE_PLAIN) xs_layout = kXsColumns;
-  const size_t base = lds_bytes(n_targets, block, xs_layout, 0);
-  const size_t budget = lds_budget(mode, n_targets, block, waves_per_cu, xs_layout);
   // keep a 1 KiB allocation margin per workgroup
+  const size_t budget = (size_t)lds_cu / blocks;
   if (budget < base + 1024) return 0;
   const size_t levels = (budget - base - 1024) / (2 * (size_t)block * sizeof(float4));
   return levels > (size_t)kStackLdsMax ? kStackLdsMax : (int)levels;
-}
-
-int merge_slots(int n_targets, int block, int waves_per_cu, int xs_layout, int levels) {
-  if (block < 128) return 0;  // one wave per workgroup: nobody to merge with
-  const size_t used = lds_bytes(n_targets, block, xs_layout, levels) + 1024;
-  const size_t budget = lds_budget(INC_MODE_STAGED, n_targets, block, waves_per_cu, xs_layout);
-  if (budget < used + merge_pool_bytes(kMergeMinSlots)) return 0;
-  const size_t slots = (budget - used) / (sizeof(uint32_t) * kMergeWords);
-  return slots > (size_t)kMergeMaxSlots ? kMergeMaxSlots : (int)slots;
 }
 
 int evap_blocks_per_cu(int block) {
@@ -1359,8 +1040,6 @@ static KernelArgs kernel_args(const LaunchDesc& L) {
   a.ring = L.ring;
   a.stack_lds = L.stack_lds;
   a.chunk = L.chunk > 0 ? L.chunk : kChunkEvents;
-  a.merge_slots = L.mode == INC_MODE_STAGED ? L.merge_slots : 0;
-  a.opt.merge_lanes = L.merge_lanes;
   return a;
 }
 
@@ -1383,11 +1062,10 @@ static void launch_ext(const LaunchDesc& L, const KernelArgs& a, hipStream_t s) 
   const dim3 grid(L.persistent_blocks);
   const size_t lds = lds_bytes(L.n_targets, block, L.xs_pairs && !kCols ? kXsPairs : kXsColumns, L.stack_lds);
   if (L.mode == INC_MODE_STAGED) {
-    const size_t lds_staged = lds + merge_pool_bytes(a.merge_slots);
     if (!kCols && L.xs_pairs)
-      hipLaunchKernelGGL((k_persistent<false, true, 0, false, false>), grid, dim3(block), lds_staged, s, a);
+      hipLaunchKernelGGL((k_persistent<false, true, 0, false, false>), grid, dim3(block), lds, s, a);
     else
-      hipLaunchKernelGGL((k_persistent<false, false, kExt, kRing, kHooks>), grid, dim3(block), lds_staged, s, a);
+      hipLaunchKernelGGL((k_persistent<false, false, kExt, kRing, kHooks>), grid, dim3(block), lds, s, a);
     hipLaunchKernelGGL((k_evap_persistent<kExt, kRing>), dim3(L.evap_blocks), dim3(block),
                        lds_bytes(0, block, kXsNone, 0), s, a);
   } else {
